@@ -1,0 +1,220 @@
+"""Benchmark of the KDE hot path on one MI355X.
+
+One step is one pass of the whole path over the paper-scale workload
+(1,048,576 particles drawn from (1 + 0.5 cos(0.5 x)) / L on L = 4 pi,
+M = 256 grid nodes):
+
+  1. CV scan on the first 65,536 particles over 32 concentrations
+     log-spaced in [1, 1e4] (pack + sort, O(N^2) pair sums, finalize, argmin);
+  2. pilot deposit of all particles at the chosen kappa*;
+  3. particle-wise widths from the pilot (Silverman, alpha = 0.5);
+  4. adaptive deposit with those widths;
+  5. gather of the adaptive density back to all particles.
+
+Inputs are resident in HBM before the timed region; workspaces and outputs
+are allocated once, outside it. The only host round trip inside a step is
+reading kappa* (4 bytes) after the scan, which the following calls take as
+an argument.
+
+Prints one JSON line. ``value`` is the whole step's throughput in CV
+pair-evaluations per second: B * n_cv (n_cv - 1) / 2 per step over the step
+time. Per-phase kernel times come from the library's HIP-event timing of
+its dominant kernels, on the stream they are launched on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CV pair-evals/s, particles/s at 1e-6 rel err; p50/p99 solve latency vs plain"
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 vector lane-operations/s
+# (FP64 and non-packed FP32 alike); HBM3E 8 TB/s.
+PEAK_VALU_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8.0e12
+
+# Algorithmic VALU operations per evaluated (pair, kappa) term of the CV
+# pair sums, large-argument branch, counted from the formulas: both terms'
+# exponent products, two exponentials, the Bessel polynomial and the
+# products and accumulations. An exponential counts as its range reduction
+# plus polynomial (15 operations) in double and as one transcendental
+# issued at a quarter of the VALU rate (4) in float; compensated float
+# accumulation counts 4 per add.
+OPS_PER_TERM = {"f64": 51, "f32": 28}
+SKIP_EXPONENT = 70.0
+
+
+def count_evaluated_terms(x, L, kappas):
+    """Exact number of (pair, kappa) terms whose convolution exponent
+    -2 kappa (1 - cos(pi d / L)) is at least -70 (the terms the pair kernel
+    must evaluate), from the sorted positions by binary search."""
+    xs = np.sort(np.asarray(x, dtype=np.float64) % L)
+    n = xs.shape[0]
+    ext = np.concatenate([xs, xs + L])
+    total = 0
+    for k in kappas:
+        lim = SKIP_EXPONENT / (2.0 * k)
+        if lim >= 1.0:
+            total += n * (n - 1) // 2
+            continue
+        dmax = (L / math.pi) * math.acos(1.0 - lim)       # circular distance bound
+        dmax = min(dmax, L / 2)
+        hi = np.searchsorted(ext, xs + dmax, side="right")
+        cnt = np.minimum(hi - np.arange(n) - 1, n - 1)     # partners ahead within dmax
+        # every unordered pair within dmax is counted once from each side when
+        # the window wraps less than half the circle
+        total += int(cnt.sum())
+    return total
+
+
+def cpu_baseline(x, L, kappas, budget_s=12.0):
+    """The oracle's direct pair sums timed on a bounded sample of the same
+    scan: the first m particles, with m chosen for about budget_s seconds."""
+    from oracle import cv as ocv
+    # calibrate on a small block
+    m0 = 512
+    t0 = time.perf_counter()
+    ocv.pair_sums(x[:m0], L, kappas)
+    dt0 = time.perf_counter() - t0
+    rate0 = len(kappas) * m0 * (m0 - 1) / 2 / max(dt0, 1e-9)
+    m = int(math.sqrt(2 * budget_s * rate0 / len(kappas)))
+    m = max(m0, min(m, x.shape[0]))
+    t0 = time.perf_counter()
+    ocv.pair_sums(x[:m], L, kappas)
+    dt = time.perf_counter() - t0
+    evals = len(kappas) * m * (m - 1) / 2
+    return {"value": evals / dt, "unit": "CV pair-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"direct FP64 pair sums (NumPy/SciPy, one thread) over the first {m} particles "
+                      f"x {len(kappas)} kappas: {evals:.3e} pair-evals in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--json-out", default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
+              "path is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1804_11174_amd as kde
+    import workloads as W
+
+    kde.require_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = W.plain_paper_scale()
+    L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
+    tdt = torch.float64 if args.prec == "f64" else torch.float32
+    prec = kde.KDE_F64 if args.prec == "f64" else kde.KDE_F32
+    x = torch.from_numpy(prob.x).to(dev).to(tdt).contiguous()
+    x_cv = x[:n_cv]
+    B = len(kappas)
+
+    dom_cv = kde.kde_domain(L, M, prec)
+    dom = kde.kde_domain(L, M, prec)
+    ws_cv, ws_dep, ws_ad = kde.Workspace(dev), kde.Workspace(dev), kde.Workspace(dev)
+    p_cv, b_cv = ws_cv.get(kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom_cv, n_cv, B))
+    p_dep, b_dep = ws_dep.get(kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom, n))
+    p_ad, b_ad = ws_ad.get(kde.kde_workspace_size(kde.KDE_OP_ADAPT, dom, n))
+    cv = torch.empty(B, dtype=torch.float64, device=dev)
+    sums = torch.empty(2 * B, dtype=torch.float64, device=dev)
+    am = torch.empty(1, dtype=torch.int32, device=dev)
+    am_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    pilot = torch.empty(M, dtype=torch.float64, device=dev)
+    rho = torch.empty(M, dtype=torch.float64, device=dev)
+    k_i = torch.empty(n, dtype=tdt, device=dev)
+    G = torch.empty(n, dtype=tdt, device=dev)
+    lg = torch.empty(1, dtype=torch.float64, device=dev)
+    nf = torch.empty(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        kde.kde_cv_scan(dom_cv, n_cv, x_cv, kappas, cv, sums, am, p_cv, b_cv, stream)
+        am_h.copy_(am, non_blocking=True)
+        stream.synchronize()
+        kstar = float(kappas[int(am_h[0])])
+        kde.kde_deposit(dom, n, x, None, kstar, pilot, p_dep, b_dep, stream)
+        kde.kde_adapt_widths(dom, n, x, pilot, kstar, 0.5, k_i, lg, nf, p_ad, b_ad, stream)
+        kde.kde_deposit(dom, n, x, k_i, 0.0, rho, p_dep, b_dep, stream)
+        kde.kde_gather(dom, n, x, k_i, 0.0, rho, G, None, 0, stream)
+        return kstar
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kde.kde_timing_reset()
+    kde.kde_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        kstar = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kde.kde_timing_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    kern = {}
+    for name, kid in (("cv_pairs", kde.KDE_KERNEL_CV_PAIRS), ("deposit", kde.KDE_KERNEL_DEPOSIT),
+                      ("gather", kde.KDE_KERNEL_GATHER), ("adapt", kde.KDE_KERNEL_ADAPT)):
+        tot, cnt = kde.kde_timing_read(kid)
+        kern[name] = {"launches": cnt, "avg_ms": tot / cnt if cnt else None}
+
+    pair_evals = B * n_cv * (n_cv - 1) / 2
+    value = pair_evals / (ms_step * 1e-3)
+    evaluated = count_evaluated_terms(prob.x[:n_cv], L, kappas)
+    pair_ms = kern["cv_pairs"]["avg_ms"]
+    achieved = evaluated * OPS_PER_TERM[args.prec] / (pair_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": "cv_pairs_kernel", "achieved": achieved / 1e12,
+                "peak": PEAK_VALU_OPS / 1e12, "unit": "Top/s (VALU lane-ops)",
+                "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+                "evaluated_terms_per_launch": evaluated, "ops_per_term": OPS_PER_TERM[args.prec],
+                "kernel_avg_ms": pair_ms}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "CV pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "plain KDE at paper scale: N=1,048,576 (CV on first 65,536), L=4pi, "
+                               "M=256, 32 kappas in [1,1e4], f=(1+0.5cos(0.5x))/L",
+                   "n": n, "n_cv": n_cv, "M": M, "B": B, "prec": args.prec, "parallelism": "single GPU"},
+        "particles_per_s": n / (ms_step * 1e-3),
+        "kappa_star": kstar,
+        "kernels": kern,
+        "cv_pair_kernel_pair_evals_per_s": pair_evals / (pair_ms * 1e-3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob.x[:n_cv], L, kappas)
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+if __name__ == "__main__":
+    main()

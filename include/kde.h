@@ -1,0 +1,234 @@
+/*
+ * kde.h -- C ABI of the MI355X von Mises KDE library (libkdepic.so).
+ *
+ * The library computes the data-parallel hot path of kernel-density-
+ * estimation noise reduction for 1D periodic electrostatic particle-in-cell
+ * (Wu & Qin, "Reducing Noise for PIC Simulations Using Kernel Density
+ * Estimation Algorithm"):
+ *
+ *   - the least-squares cross-validation objective over a batch of candidate
+ *     kernel concentrations (Sec. II.B, Eq. cv_def) and its argmin;
+ *   - deposition of particles onto the grid with the von Mises kernel
+ *     (Sec. II.A Eq. vonMises, Sec. II.B Eq. kde), with one global or a
+ *     per-particle concentration (Sec. II.C, step 3);
+ *   - interpolation of a grid field back to the particles with the same
+ *     kernels (the field gather of the PIC step, Sec. III.A);
+ *   - Silverman's particle-wise widths from a pilot density
+ *     (Sec. II.C, Eq. adaptive_width and the geometric mean that follows).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Domain. Positions live on the periodic interval [0, L). The kernel of
+ *   concentration kappa is the von Mises law written as a density in x:
+ *       K_kappa(d) = exp(-2 kappa sin^2(pi d / L)) / (L * I0e(kappa)),
+ *   I0e(k) = exp(-k) I0(k). Width h and concentration are related by
+ *   kappa = (L / (2 pi h))^2. The grid has M nodes x_g = g L / M and every
+ *   grid quantity is a point value at the nodes.
+ * Memory. Pointers named *_h are HOST pointers; every other pointer is a
+ *   DEVICE pointer (HBM of the current HIP device). The caller owns all
+ *   memory: inputs, outputs and the workspace. The library never allocates
+ *   or frees device memory.
+ * Precision. kde_domain.prec selects the element type of particle arrays
+ *   (positions, per-particle concentrations, gathered values): KDE_F64 =
+ *   double, KDE_F32 = float. Grid arrays and scalar results are always
+ *   double. In the KDE_F32 form the per-pair and per-node kernel arithmetic
+ *   runs in float with compensated per-thread sums; Bessel normalisers,
+ *   cross-block reductions and the final CV combination stay in double.
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream). Every call only enqueues work on it and returns; results are
+ *   valid once that work has completed. No call synchronises the device.
+ * Positions. Positions outside [0, L) are wrapped on the device
+ *   (x - L floor(x / L)); they are not rejected. Non-finite positions or
+ *   concentrations propagate as NaN into the results.
+ * Errors. Every entry point returns a kde_status. Arguments are checked on
+ *   the host before anything is enqueued; on error nothing is enqueued and
+ *   kde_last_error() returns a message (thread-local) naming the problem.
+ *   The library never aborts and never throws across this interface.
+ * Determinism. Reductions use fixed slots and a fixed order, with no
+ *   floating-point atomics: the same inputs give bitwise identical results
+ *   on every run.
+ */
+#ifndef KDE_H
+#define KDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KDE_ABI_VERSION 1
+
+typedef int32_t kde_status;
+
+enum kde_status_code {
+  KDE_OK = 0,
+  KDE_E_INVALID_ARG = 1,   /* an argument breaks the rule stated for it        */
+  KDE_E_WORKSPACE = 2,     /* workspace pointer NULL or smaller than required  */
+  KDE_E_BUDGET = 3,        /* request larger than a serving budget            */
+  KDE_E_AGAIN = 4,         /* result not ready yet                             */
+  KDE_E_NOT_FOUND = 5,     /* unknown handle or ticket                         */
+  KDE_E_HIP = 6,           /* a HIP runtime call failed; message has its text  */
+  KDE_E_NUMERIC = 7,       /* non-finite value where a finite one is needed    */
+  KDE_E_INTERNAL = 8       /* broken internal invariant                        */
+};
+
+enum kde_precision { KDE_F64 = 0, KDE_F32 = 1 };
+
+/* Operation codes for kde_workspace_size. */
+enum kde_op {
+  KDE_OP_CV_SCAN = 0,
+  KDE_OP_DEPOSIT = 1,
+  KDE_OP_GATHER = 2,
+  KDE_OP_ADAPT = 3
+};
+
+/* The periodic domain [0, L), its M-node grid and the particle precision.
+ * Rules: L finite and > 0; 2 <= M <= 4096; prec a kde_precision value. */
+typedef struct kde_domain {
+  double L;
+  int32_t M;
+  int32_t prec;
+} kde_domain;
+
+/* Largest number of candidate concentrations one kde_cv_scan accepts. */
+#define KDE_MAX_KAPPAS 64
+
+/* Version of this interface (KDE_ABI_VERSION of the built library). */
+int32_t kde_abi_version(void);
+
+/* Text of a status code (static storage). */
+const char* kde_status_str(kde_status s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* kde_last_error(void);
+
+/*
+ * kde_workspace_size -- bytes of device workspace an operation needs.
+ *   op     : a kde_op value.
+ *   dom    : domain (host pointer); M and prec matter for every op.
+ *   N      : number of particles (>= 1; >= 2 for KDE_OP_CV_SCAN).
+ *   B      : number of concentrations for KDE_OP_CV_SCAN (1..KDE_MAX_KAPPAS),
+ *            ignored otherwise.
+ *   bytes_h: receives the size; the workspace must be 256-byte aligned.
+ * The size depends only on (op, M, prec, N, B). A workspace may be reused by
+ * later calls once the work enqueued with it has completed (or on the same
+ * stream, right away).
+ */
+kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int32_t B,
+                              size_t* bytes_h);
+
+/*
+ * kde_cv_scan -- least-squares cross-validation over candidate
+ * concentrations (Sec. II.B, Eq. cv_def, with the two-fold convolution Kbar
+ * of the kernel; the leave-one-out estimator of Eq. Ehat in the second term).
+ *
+ * For each b in [0, B):
+ *   S1[b] = sum_{i<j} Kbar_{kappa_b}(x_i - x_j),
+ *   S2[b] = sum_{i<j} K_{kappa_b}(x_i - x_j),
+ *   cv[b] = (N Kbar_b(0) + 2 S1[b]) / N^2 - 4 S2[b] / (N (N - 1)),
+ * where for the von Mises kernel
+ *   Kbar_kappa(d) = I0(2 kappa |cos(pi d / L)|) / (L I0(kappa)^2).
+ * argmin receives the smallest b with cv[b] == min cv (first minimum).
+ *
+ *   dom      : domain (host). M is not used by this op.
+ *   N        : particles (>= 2).
+ *   x        : device array of N positions, element type by dom->prec.
+ *   B        : number of candidates, 1..KDE_MAX_KAPPAS.
+ *   kappas_h : host array of B finite concentrations >= 0, strictly ascending.
+ *   cv       : device, B doubles (output).
+ *   sums     : device, 2B doubles [S1[0..B), S2[0..B)] (output) or NULL.
+ *   argmin   : device, 1 int32 (output) or NULL.
+ *   ws, ws_bytes: device workspace of at least
+ *              kde_workspace_size(KDE_OP_CV_SCAN, dom, N, B) bytes.
+ *   stream   : hipStream_t or NULL.
+ * Terms whose exponent lies below -70 (each smaller than e^-70 times the
+ * largest term of its sum) are not evaluated.
+ */
+kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t B,
+                       const double* kappas_h, double* cv, double* sums, int32_t* argmin,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kde_deposit -- kernel density estimate at the grid nodes (Sec. II.B
+ * Eq. kde; with per-particle concentrations the adaptive estimate of
+ * Sec. II.C, step 3, each kernel normalised on its own):
+ *   rho[g] = (1/N) sum_i K_{kappa_i}(x_g - x_i),  g = 0..M-1.
+ *
+ *   dom     : domain (host).
+ *   N       : particles (>= 1).
+ *   x       : device, N positions (dom->prec).
+ *   kappa_i : device, N per-particle concentrations (dom->prec, each finite
+ *             and >= 0), or NULL to use `kappa` for every particle.
+ *   kappa   : global concentration (finite, >= 0), used when kappa_i is NULL.
+ *   rho     : device, M doubles (output).
+ *   ws, ws_bytes: workspace of kde_workspace_size(KDE_OP_DEPOSIT, dom, N, 0).
+ */
+kde_status kde_deposit(const kde_domain* dom, int64_t N, const void* x, const void* kappa_i,
+                       double kappa, double* rho, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kde_gather -- a grid field at the particles with each particle's kernel:
+ *   out[i] = (L/M) sum_g field[g] K_{kappa_i}(x_g - x_i).
+ * It is the adjoint of kde_deposit: (L/M) sum_g F_g rho_g = mean_i out_i.
+ *
+ *   field : device, M doubles.
+ *   out   : device, N values in dom->prec, in the order of x.
+ *   other arguments as for kde_deposit; workspace from
+ *   kde_workspace_size(KDE_OP_GATHER, dom, N, 0) (may be 0 bytes; ws may
+ *   then be NULL).
+ */
+kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const void* kappa_i,
+                      double kappa, const double* field, void* out, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/*
+ * kde_adapt_widths -- Silverman's particle-wise widths from a pilot grid
+ * density (Sec. II.C, Eq. adaptive_width and the geometric mean g), in
+ * concentration form:
+ *   f_i     = (1 - t) pilot[j] + t pilot[(j + 1) mod M],  j = floor(x_i/dx),
+ *             t = x_i/dx - j (periodic linear interpolation of the pilot),
+ *             floored at the smallest positive normal number of dom->prec;
+ *   log g   = (1/N) sum_i log f_i;
+ *   kappa_i = kappa_star * exp(2 alpha (log f_i - log g))
+ * (the width factor (f_i/g)^(-alpha) on h becomes its inverse square on
+ * kappa).
+ *
+ *   pilot      : device, M doubles (the pilot density on the grid).
+ *   kappa_star : finite, > 0.      alpha : finite, >= 0 (0.5 in the paper).
+ *   kappa_out  : device, N values in dom->prec (output).
+ *   log_geomean: device, 1 double (output) or NULL.
+ *   n_floored  : device, 1 int64 (output: particles whose pilot value was
+ *                floored) or NULL.
+ *   ws, ws_bytes: workspace of kde_workspace_size(KDE_OP_ADAPT, dom, N, 0).
+ */
+kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, const double* pilot,
+                            double kappa_star, double alpha, void* kappa_out, double* log_geomean,
+                            int64_t* n_floored, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Kernel timing (diagnostics). While enabled, the library brackets every
+ * launch of the kernels named below with a pair of HIP events recorded on
+ * the launching call's stream. kde_timing_read waits for the recorded
+ * events, adds their elapsed times to the kernel's running total and
+ * returns it with the number of launches; kde_timing_reset clears all
+ * totals. Events are host-side HIP objects: no device memory is
+ * allocated. Enabling costs two event records per bracketed launch.
+ */
+enum kde_kernel_id {
+  KDE_KERNEL_CV_PAIRS = 0,   /* the O(N^2) pair-sum kernel of kde_cv_scan   */
+  KDE_KERNEL_DEPOSIT = 1,    /* the per-chunk grid kernel of kde_deposit     */
+  KDE_KERNEL_GATHER = 2,     /* the per-particle kernel of kde_gather        */
+  KDE_KERNEL_ADAPT = 3,      /* both per-particle passes of kde_adapt_widths */
+  KDE_KERNEL_COUNT = 4
+};
+kde_status kde_timing_enable(int32_t on);
+kde_status kde_timing_reset(void);
+kde_status kde_timing_read(int32_t kernel_id, double* total_ms_h, int64_t* launches_h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDE_H */

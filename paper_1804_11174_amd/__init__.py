@@ -1,0 +1,289 @@
+"""Python binding of libkdepic.so: the MI355X von Mises KDE hot path.
+
+The functions named ``kde_*`` mirror the C entry points of ``include/kde.h``
+one to one: they only marshal arguments (torch tensors on the GPU supply
+device pointers, torch's current stream supplies the HIP stream) and raise
+``KdeError`` when a call returns a non-zero status. Every step of the path
+runs in the library's HIP kernels; there is no fallback of any kind. If the
+shared library has not been built, ``require_library()`` (called by every
+entry point) raises.
+
+Convenience wrappers (``cv_scan``, ``deposit``, ``gather``,
+``adapt_widths``) allocate outputs and workspace with torch and call the
+``kde_*`` functions.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libkdepic.so")
+
+KDE_F64, KDE_F32 = 0, 1
+KDE_OP_CV_SCAN, KDE_OP_DEPOSIT, KDE_OP_GATHER, KDE_OP_ADAPT = 0, 1, 2, 3
+KDE_MAX_KAPPAS = 64
+
+_lib = None
+
+
+class KdeError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status} ({message})")
+        self.status = status
+
+
+class kde_domain(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("M", ctypes.c_int32), ("prec", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_sz = ctypes.c_size_t
+_dom_p = ctypes.POINTER(kde_domain)
+
+_SIGNATURES = {
+    "kde_abi_version": (_i32, []),
+    "kde_status_str": (ctypes.c_char_p, [_i32]),
+    "kde_last_error": (ctypes.c_char_p, []),
+    "kde_workspace_size": (_i32, [_i32, _dom_p, _i64, _i32, ctypes.POINTER(_sz)]),
+    "kde_cv_scan": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kde_deposit": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _vp, _vp, _sz, _vp]),
+    "kde_gather": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _sz, _vp]),
+    "kde_adapt_widths": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kde_timing_enable": (_i32, [_i32]),
+    "kde_timing_reset": (_i32, []),
+    "kde_timing_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
+}
+
+KDE_KERNEL_CV_PAIRS, KDE_KERNEL_DEPOSIT, KDE_KERNEL_GATHER, KDE_KERNEL_ADAPT = 0, 1, 2, 3
+
+EXPORTED = tuple(_SIGNATURES)
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def require_library():
+    """Load libkdepic.so (once) and return it; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libkdepic.so is not built ({LIB_PATH}); run "
+                           "`python -m paper_1804_11174_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        lib = require_library()
+        msg = lib.kde_last_error().decode() or lib.kde_status_str(status).decode()
+        raise KdeError(status, where, msg)
+
+
+# ------------------------------------------------------------ marshalling
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _domain(L: float, M: int, prec: int) -> kde_domain:
+    return kde_domain(float(L), int(M), int(prec))
+
+
+def prec_of(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return KDE_F64
+    if t.dtype == torch.float32:
+        return KDE_F32
+    raise ValueError(f"particle arrays must be float64 or float32 (got {t.dtype})")
+
+
+# ------------------------------------------------------- C entry points
+
+def kde_abi_version() -> int:
+    return int(require_library().kde_abi_version())
+
+
+def kde_status_str(status: int) -> str:
+    return require_library().kde_status_str(int(status)).decode()
+
+
+def kde_last_error() -> str:
+    return require_library().kde_last_error().decode()
+
+
+def kde_workspace_size(op: int, dom: kde_domain, N: int, B: int = 0) -> int:
+    lib = require_library()
+    out = _sz(0)
+    _check(lib.kde_workspace_size(int(op), ctypes.byref(dom), int(N), int(B), ctypes.byref(out)),
+           "kde_workspace_size")
+    return int(out.value)
+
+
+def kde_cv_scan(dom, N, x, kappas_h, cv, sums, argmin, ws, ws_bytes, stream=None):
+    lib = require_library()
+    k = np.ascontiguousarray(np.asarray(kappas_h, dtype=np.float64))
+    kp = k.ctypes.data_as(ctypes.POINTER(_dbl))
+    _check(lib.kde_cv_scan(ctypes.byref(dom), int(N), _ptr(x), int(k.shape[0]), kp, _ptr(cv), _ptr(sums),
+                           _ptr(argmin), ws, int(ws_bytes), _stream(stream)), "kde_cv_scan")
+
+
+def kde_deposit(dom, N, x, kappa_i, kappa, rho, ws, ws_bytes, stream=None):
+    lib = require_library()
+    _check(lib.kde_deposit(ctypes.byref(dom), int(N), _ptr(x), _ptr(kappa_i), float(kappa), _ptr(rho), ws,
+                           int(ws_bytes), _stream(stream)), "kde_deposit")
+
+
+def kde_gather(dom, N, x, kappa_i, kappa, field, out, ws, ws_bytes, stream=None):
+    lib = require_library()
+    _check(lib.kde_gather(ctypes.byref(dom), int(N), _ptr(x), _ptr(kappa_i), float(kappa), _ptr(field), _ptr(out),
+                          ws, int(ws_bytes), _stream(stream)), "kde_gather")
+
+
+def kde_adapt_widths(dom, N, x, pilot, kappa_star, alpha, kappa_out, log_geomean, n_floored, ws, ws_bytes,
+                     stream=None):
+    lib = require_library()
+    _check(lib.kde_adapt_widths(ctypes.byref(dom), int(N), _ptr(x), _ptr(pilot), float(kappa_star), float(alpha),
+                                _ptr(kappa_out), _ptr(log_geomean), _ptr(n_floored), ws, int(ws_bytes),
+                                _stream(stream)), "kde_adapt_widths")
+
+
+def kde_timing_enable(on: bool):
+    _check(require_library().kde_timing_enable(1 if on else 0), "kde_timing_enable")
+
+
+def kde_timing_reset():
+    _check(require_library().kde_timing_reset(), "kde_timing_reset")
+
+
+def kde_timing_read(kernel_id: int) -> Tuple[float, int]:
+    """``(total_ms, launches)`` accumulated for one kernel since the last reset."""
+    ms = _dbl(0.0)
+    n = _i64(0)
+    _check(require_library().kde_timing_read(int(kernel_id), ctypes.byref(ms), ctypes.byref(n)), "kde_timing_read")
+    return float(ms.value), int(n.value)
+
+
+# ------------------------------------------------------- workspace helper
+
+class Workspace:
+    """A 256-byte aligned device buffer that grows on demand (torch memory)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self._buf = None
+        self.ptr = None
+        self.bytes = 0
+
+    def get(self, nbytes: int) -> Tuple[Optional[int], int]:
+        import torch
+        if nbytes == 0:
+            return None, 0
+        if nbytes > self.bytes:
+            self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._buf.data_ptr()
+            self.ptr = (base + 255) // 256 * 256
+            self.bytes = nbytes
+        return self.ptr, self.bytes
+
+
+_default_ws = {}
+
+
+def _ws(nbytes: int, device) -> Tuple[Optional[int], int]:
+    import torch
+    key = torch.device(device).index if torch.device(device).index is not None else torch.cuda.current_device()
+    w = _default_ws.setdefault(key, Workspace(f"cuda:{key}"))
+    return w.get(nbytes)
+
+
+# ------------------------------------------------------ convenience layer
+
+def cv_scan(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None):
+    """CV objective over ``kappas`` (ascending) for positions ``x`` (GPU
+    tensor, float64 or float32). Returns ``(cv[B], sums[2B], argmin[1])`` as
+    GPU tensors (float64, float64, int32)."""
+    import torch
+    k = np.asarray(kappas, dtype=np.float64)
+    dom = _domain(L, 2, prec_of(x))
+    n = x.shape[0]
+    cv = torch.empty(k.shape[0], dtype=torch.float64, device=x.device)
+    sums = torch.empty(2 * k.shape[0], dtype=torch.float64, device=x.device)
+    am = torch.empty(1, dtype=torch.int32, device=x.device)
+    nbytes = kde_workspace_size(KDE_OP_CV_SCAN, dom, n, k.shape[0])
+    ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
+    kde_cv_scan(dom, n, x, k, cv, sums, am, ptr, cap, stream)
+    return cv, sums, am
+
+
+def deposit(x, L: float, M: int, kappa: float = 0.0, kappa_i=None, ws: Optional[Workspace] = None,
+            stream=None):
+    """Grid density (M float64 values) with a global ``kappa`` or per-particle
+    ``kappa_i`` (same dtype as ``x``)."""
+    import torch
+    dom = _domain(L, M, prec_of(x))
+    n = x.shape[0]
+    rho = torch.empty(M, dtype=torch.float64, device=x.device)
+    nbytes = kde_workspace_size(KDE_OP_DEPOSIT, dom, n)
+    ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
+    kde_deposit(dom, n, x, kappa_i, kappa, rho, ptr, cap, stream)
+    return rho
+
+
+def gather(x, L: float, field, kappa: float = 0.0, kappa_i=None, stream=None):
+    """Field (M float64 values) interpolated to the particles (dtype of x)."""
+    import torch
+    M = field.shape[0]
+    dom = _domain(L, M, prec_of(x))
+    n = x.shape[0]
+    out = torch.empty(n, dtype=x.dtype, device=x.device)
+    kde_gather(dom, n, x, kappa_i, kappa, field, out, None, 0, stream)
+    return out
+
+
+def adapt_widths(x, L: float, pilot, kappa_star: float, alpha: float = 0.5, ws: Optional[Workspace] = None,
+                 stream=None):
+    """Per-particle concentrations from a pilot grid. Returns
+    ``(kappa_i, log_geomean[1], n_floored[1])``."""
+    import torch
+    M = pilot.shape[0]
+    dom = _domain(L, M, prec_of(x))
+    n = x.shape[0]
+    kout = torch.empty(n, dtype=x.dtype, device=x.device)
+    lg = torch.empty(1, dtype=torch.float64, device=x.device)
+    nf = torch.empty(1, dtype=torch.int64, device=x.device)
+    nbytes = kde_workspace_size(KDE_OP_ADAPT, dom, n)
+    ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
+    kde_adapt_widths(dom, n, x, pilot, kappa_star, alpha, kout, lg, nf, ptr, cap, stream)
+    return kout, lg, nf

@@ -1,0 +1,190 @@
+// The library's C ABI (include/kde.h): argument validation on the host,
+// workspace sizing, and dispatch to the kernels. Nothing is enqueued when a
+// check fails; the message is kept per thread for kde_last_error().
+#include <cmath>
+#include <cstring>
+
+#include "kde_internal.hpp"
+
+namespace kde {
+
+// implemented in cv.hip / density.hip
+size_t cv_workspace_bytes(int64_t n, int B, int prec);
+kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
+                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s);
+size_t deposit_workspace_bytes(int64_t n, int M);
+size_t adapt_workspace_bytes(int64_t n);
+kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
+                   void* ws, size_t ws_bytes, hipStream_t s);
+kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
+                  const double* field, void* out, hipStream_t s);
+kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
+                        double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
+                        hipStream_t s);
+
+static thread_local char g_err[512];
+
+kde_status fail(kde_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+size_t elem_size(int prec) { return prec == KDE_F64 ? sizeof(double) : sizeof(float); }
+
+kde_status check_domain(const kde_domain* dom, bool need_grid) {
+  if (!dom) return fail(KDE_E_INVALID_ARG, "domain pointer is NULL");
+  if (!std::isfinite(dom->L) || !(dom->L > 0.0)) return fail(KDE_E_INVALID_ARG, "L must be finite and > 0 (got %g)", dom->L);
+  if (dom->prec != KDE_F64 && dom->prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32 (got %d)", dom->prec);
+  if (need_grid && (dom->M < 2 || dom->M > kMaxM)) return fail(KDE_E_INVALID_ARG, "M must lie in [2, %d] (got %d)", kMaxM, dom->M);
+  return KDE_OK;
+}
+
+kde_status check_workspace(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return KDE_OK;
+  if (!ws) return fail(KDE_E_WORKSPACE, "workspace pointer is NULL (%zu bytes needed)", need);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(KDE_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(KDE_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  return KDE_OK;
+}
+
+kde_status check_lds(size_t bytes) {
+  static thread_local int cached_dev = -1;
+  static thread_local int cached_lds = 0;
+  int dev = 0;
+  KDE_TRY_HIP(hipGetDevice(&dev));
+  if (dev != cached_dev) {
+    int v = 0;
+    KDE_TRY_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    cached_dev = dev;
+    cached_lds = v;
+  }
+  if (bytes > size_t(cached_lds))
+    return fail(KDE_E_INVALID_ARG, "grid of this size needs %zu bytes of LDS per workgroup; the device offers %d",
+                bytes, cached_lds);
+  return KDE_OK;
+}
+
+static kde_status check_n(int64_t N, int64_t lo) {
+  if (N < lo || N > kMaxN) return fail(KDE_E_INVALID_ARG, "N must lie in [%lld, %lld] (got %lld)", (long long)lo, (long long)kMaxN, (long long)N);
+  return KDE_OK;
+}
+
+static kde_status check_kappa(double k, const char* what) {
+  if (!std::isfinite(k) || k < 0.0) return fail(KDE_E_INVALID_ARG, "%s must be finite and >= 0 (got %g)", what, k);
+  return KDE_OK;
+}
+
+}  // namespace kde
+
+using namespace kde;
+
+extern "C" {
+
+int32_t kde_abi_version(void) { return KDE_ABI_VERSION; }
+
+const char* kde_status_str(kde_status s) {
+  switch (s) {
+    case KDE_OK: return "ok";
+    case KDE_E_INVALID_ARG: return "invalid argument";
+    case KDE_E_WORKSPACE: return "workspace missing or too small";
+    case KDE_E_BUDGET: return "request exceeds budget";
+    case KDE_E_AGAIN: return "not ready";
+    case KDE_E_NOT_FOUND: return "unknown handle or ticket";
+    case KDE_E_HIP: return "HIP runtime error";
+    case KDE_E_NUMERIC: return "non-finite value";
+    case KDE_E_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char* kde_last_error(void) { return g_err; }
+
+kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int32_t B, size_t* bytes_h) {
+  clear_error();
+  if (!bytes_h) return fail(KDE_E_INVALID_ARG, "bytes_h is NULL");
+  switch (op) {
+    case KDE_OP_CV_SCAN:
+      KDE_RETURN_IF(check_domain(dom, false));
+      KDE_RETURN_IF(check_n(N, 2));
+      if (B < 1 || B > KDE_MAX_KAPPAS) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d] (got %d)", KDE_MAX_KAPPAS, B);
+      *bytes_h = cv_workspace_bytes(N, B, dom->prec);
+      return KDE_OK;
+    case KDE_OP_DEPOSIT:
+      KDE_RETURN_IF(check_domain(dom, true));
+      KDE_RETURN_IF(check_n(N, 1));
+      *bytes_h = deposit_workspace_bytes(N, dom->M);
+      return KDE_OK;
+    case KDE_OP_GATHER:
+      KDE_RETURN_IF(check_domain(dom, true));
+      KDE_RETURN_IF(check_n(N, 1));
+      *bytes_h = 0;
+      return KDE_OK;
+    case KDE_OP_ADAPT:
+      KDE_RETURN_IF(check_domain(dom, true));
+      KDE_RETURN_IF(check_n(N, 1));
+      *bytes_h = adapt_workspace_bytes(N);
+      return KDE_OK;
+    default:
+      return fail(KDE_E_INVALID_ARG, "unknown op %d", op);
+  }
+}
+
+kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t B, const double* kappas_h,
+                       double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  KDE_RETURN_IF(check_domain(dom, false));
+  KDE_RETURN_IF(check_n(N, 2));
+  if (B < 1 || B > KDE_MAX_KAPPAS) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d] (got %d)", KDE_MAX_KAPPAS, B);
+  if (!x || !cv) return fail(KDE_E_INVALID_ARG, "x and cv must not be NULL");
+  if (!kappas_h) return fail(KDE_E_INVALID_ARG, "kappas_h is NULL");
+  for (int b = 0; b < B; ++b) {
+    KDE_RETURN_IF(check_kappa(kappas_h[b], "every kappa"));
+    if (b > 0 && !(kappas_h[b] > kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending (index %d)", b);
+  }
+  KDE_RETURN_IF(check_workspace(ws, ws_bytes, cv_workspace_bytes(N, B, dom->prec)));
+  return cv_scan(dom, N, x, B, kappas_h, cv, sums, argmin, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+kde_status kde_deposit(const kde_domain* dom, int64_t N, const void* x, const void* kappa_i, double kappa,
+                       double* rho, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  KDE_RETURN_IF(check_domain(dom, true));
+  KDE_RETURN_IF(check_n(N, 1));
+  if (!x || !rho) return fail(KDE_E_INVALID_ARG, "x and rho must not be NULL");
+  if (!kappa_i) KDE_RETURN_IF(check_kappa(kappa, "kappa"));
+  KDE_RETURN_IF(check_workspace(ws, ws_bytes, deposit_workspace_bytes(N, dom->M)));
+  return deposit(dom, N, x, kappa_i, kappa, rho, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const void* kappa_i, double kappa,
+                      const double* field, void* out, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  (void)ws;
+  (void)ws_bytes;
+  KDE_RETURN_IF(check_domain(dom, true));
+  KDE_RETURN_IF(check_n(N, 1));
+  if (!x || !field || !out) return fail(KDE_E_INVALID_ARG, "x, field and out must not be NULL");
+  if (!kappa_i) KDE_RETURN_IF(check_kappa(kappa, "kappa"));
+  return gather(dom, N, x, kappa_i, kappa, field, out, static_cast<hipStream_t>(stream));
+}
+
+kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, const double* pilot,
+                            double kappa_star, double alpha, void* kappa_out, double* log_geomean,
+                            int64_t* n_floored, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  KDE_RETURN_IF(check_domain(dom, true));
+  KDE_RETURN_IF(check_n(N, 1));
+  if (!x || !pilot || !kappa_out) return fail(KDE_E_INVALID_ARG, "x, pilot and kappa_out must not be NULL");
+  if (!std::isfinite(kappa_star) || !(kappa_star > 0.0)) return fail(KDE_E_INVALID_ARG, "kappa_star must be finite and > 0 (got %g)", kappa_star);
+  if (!std::isfinite(alpha) || alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0 (got %g)", alpha);
+  KDE_RETURN_IF(check_workspace(ws, ws_bytes, adapt_workspace_bytes(N)));
+  return adapt_widths(dom, N, x, pilot, kappa_star, alpha, kappa_out, log_geomean, n_floored, ws, ws_bytes,
+                      static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

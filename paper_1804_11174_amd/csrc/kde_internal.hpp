@@ -1,0 +1,161 @@
+// Internal definitions shared by the library's translation units: status
+// plumbing, workspace carving, launch geometry and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <type_traits>
+
+#include "../../include/kde.h"
+
+namespace kde {
+
+// ----------------------------------------------------------------- status
+
+// Record a message for kde_last_error() on this thread and return `code`.
+kde_status fail(kde_status code, const char* fmt, ...);
+void clear_error();
+
+#define KDE_TRY_HIP(expr)                                                          \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return ::kde::fail(KDE_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+#define KDE_CHECK_LAUNCH()                                                         \
+  do {                                                                             \
+    hipError_t _e = hipGetLastError();                                             \
+    if (_e != hipSuccess)                                                          \
+      return ::kde::fail(KDE_E_HIP, "kernel launch failed: %s", hipGetErrorString(_e)); \
+  } while (0)
+
+#define KDE_RETURN_IF(st)          \
+  do {                             \
+    kde_status _s = (st);          \
+    if (_s != KDE_OK) return _s;   \
+  } while (0)
+
+// ------------------------------------------------------------- constants
+
+constexpr int kBlock = 256;               // threads per workgroup for every kernel
+constexpr int kCvTile = 256;              // particles per CV tile (one per thread)
+constexpr int kCvChunk = 16;              // concentrations per pass of the pair kernel
+constexpr double kSkipExponent = 70.0;    // terms below exp(-70) of their sum's scale are skipped
+constexpr int64_t kMaxN = int64_t(1) << 30;
+constexpr int kMaxM = 4096;
+
+// ------------------------------------------------------------ workspace
+
+// Bump allocator over a caller-provided device buffer; every block is
+// 256-byte aligned. In "measure" mode (base == nullptr) it only counts.
+struct Carver {
+  char* base;
+  size_t cap;
+  size_t used = 0;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+  bool fits() const { return used <= cap; }
+};
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ timing
+
+// Brackets the launches made during its lifetime with HIP events when
+// kernel timing is enabled (kde_timing_enable); a no-op otherwise.
+class TimedLaunch {
+ public:
+  TimedLaunch(int id, hipStream_t s);
+  ~TimedLaunch();
+  TimedLaunch(const TimedLaunch&) = delete;
+  TimedLaunch& operator=(const TimedLaunch&) = delete;
+
+ private:
+  int id_;
+  hipStream_t s_;
+  hipEvent_t start_{}, stop_{};
+  bool active_ = false;
+};
+
+// ----------------------------------------------------- argument checking
+
+kde_status check_domain(const kde_domain* dom, bool need_grid);
+// Fails (without launching) when a kernel would need more LDS per workgroup
+// than the current device provides.
+kde_status check_lds(size_t bytes);
+kde_status check_workspace(void* ws, size_t ws_bytes, size_t need);
+size_t elem_size(int prec);
+
+// ----------------------------------------------------- shared launch plans
+
+// Counting sort of CV particles by angular cell.
+struct SortPlan {
+  int64_t n;
+  int cells;       // angular cells
+  int blocks;      // histogram/scatter blocks
+  int64_t chunk;   // particles per block
+};
+SortPlan make_sort_plan(int64_t n);
+
+// ------------------------------------------------------------- launchers
+
+// Packed particle element of the pair kernels: for double, two values per
+// particle (cos(pi x/L), sin(pi x/L)); for float, one 32-bit fixed-point
+// phase round(x/L * 2^32) mod 2^32.
+template <typename T>
+struct Packed;
+template <>
+struct Packed<double> {
+  using type = double;
+  static constexpr int per_particle = 2;
+};
+template <>
+struct Packed<float> {
+  using type = uint32_t;
+  static constexpr int per_particle = 1;
+};
+
+// Wrap, pack and sort by cell, stably. `packed` receives
+// n * Packed<T>::per_particle elements.
+template <typename T>
+kde_status launch_pack_sorted(const T* x, int64_t n, double L, const SortPlan& plan,
+                              int32_t* hist, typename Packed<T>::type* packed, int32_t* perm,
+                              hipStream_t s);
+
+// Deterministic column sums: out[c] = scale * sum_r in[r][c], fixed order.
+// `scratch` must hold column_sum_scratch(rows, cols) bytes.
+kde_status launch_column_sum(const double* in, int64_t rows, int cols, double* scratch,
+                             double* out, hipStream_t s, double scale = 1.0);
+size_t column_sum_scratch(int64_t rows, int cols);
+
+// ----------------------------------------------------------- device helpers
+
+template <typename T>
+__device__ __forceinline__ T wrap_position(T x, T L) {
+  T y = x - L * floor(x / L);
+  return (y >= L) ? T(0) : y;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+
+// Sum over the 64 lanes of a wave (butterfly; every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+  return v;
+}
+
+}  // namespace kde

@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/kde.h declares, sizes workspaces, and rejects bad
+arguments before enqueuing anything."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1804_11174_amd as kde
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(kde_[a-z_0-9]+)\s*\(", src))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return kde.require_library()
+
+
+def test_library_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert {"kde_cv_scan", "kde_deposit", "kde_gather", "kde_adapt_widths", "kde_workspace_size"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    # the binding covers every declared function with the same name
+    for n in names:
+        assert hasattr(kde, n), n
+
+
+def test_abi_version_and_status_text(lib):
+    assert kde.kde_abi_version() == 1
+    assert kde.kde_status_str(0) == "ok"
+    assert "argument" in kde.kde_status_str(1)
+
+
+def dom(L=4 * math.pi, M=64, prec=kde.KDE_F64):
+    return kde.kde_domain(L, M, prec)
+
+
+def test_workspace_sizes_grow_with_n():
+    a = kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(), 4096, 8)
+    b = kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(), 65536, 32)
+    assert 0 < a < b
+    assert kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom(M=256), 1 << 20) > 0
+    assert kde.kde_workspace_size(kde.KDE_OP_GATHER, dom(), 1000) == 0
+    assert kde.kde_workspace_size(kde.KDE_OP_ADAPT, dom(), 1000) > 0
+    # float form needs less room for the packed particles
+    assert kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(prec=kde.KDE_F32), 65536, 32) < b
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(L=-1.0), "L must"), (dict(L=float("nan")), "L must"), (dict(M=1), "M must"),
+    (dict(M=5000), "M must"), (dict(prec=7), "prec"),
+])
+def test_workspace_size_rejects_bad_domain(bad, msg):
+    d = dict(L=1.0, M=64, prec=kde.KDE_F64)
+    d.update(bad)
+    with pytest.raises(kde.KdeError) as e:
+        kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, kde.kde_domain(d["L"], d["M"], d["prec"]), 100)
+    assert msg in str(e.value) and e.value.status == 1
+
+
+def _call_cv(lib, N, kappas, ws=None, ws_bytes=0, x=1):
+    k = np.asarray(kappas, dtype=np.float64)
+    d = dom()
+    return lib.kde_cv_scan(ctypes.byref(d), N, x, len(k), k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           1, None, None, ws, ws_bytes, None)
+
+
+def test_cv_scan_argument_checks(lib):
+    # every failing case returns before touching the device (fake pointers)
+    assert _call_cv(lib, 1, [1.0]) == 1 and "N must" in kde.kde_last_error()
+    assert _call_cv(lib, 10, [2.0, 1.0]) == 1 and "ascending" in kde.kde_last_error()
+    assert _call_cv(lib, 10, [-1.0]) == 1 and "kappa" in kde.kde_last_error()
+    assert _call_cv(lib, 10, [float("inf")]) == 1
+    assert _call_cv(lib, 10, list(range(1, 66))) == 1 and "B must" in kde.kde_last_error()
+    # missing or unaligned or short workspace
+    assert _call_cv(lib, 10, [1.0]) == 2
+    assert _call_cv(lib, 10, [1.0], ws=256 + 8, ws_bytes=1 << 20) == 2 and "aligned" in kde.kde_last_error()
+    assert _call_cv(lib, 10, [1.0], ws=4096, ws_bytes=16) == 2 and "too small" in kde.kde_last_error()
+
+
+def test_deposit_gather_adapt_argument_checks(lib):
+    d = dom()
+    assert lib.kde_deposit(ctypes.byref(d), 10, None, None, 1.0, 1, None, 0, None) == 1
+    assert lib.kde_deposit(ctypes.byref(d), 10, 1, None, -1.0, 1, None, 0, None) == 1
+    assert lib.kde_gather(ctypes.byref(d), 0, 1, None, 1.0, 1, 1, None, 0, None) == 1
+    assert lib.kde_adapt_widths(ctypes.byref(d), 10, 1, 1, 0.0, 0.5, 1, None, None, None, 0, None) == 1
+    assert "kappa_star" in kde.kde_last_error()
+    assert lib.kde_adapt_widths(ctypes.byref(d), 10, 1, 1, 3.0, -0.5, 1, None, None, None, 0, None) == 1
+    assert lib.kde_workspace_size(99, ctypes.byref(d), 10, 0, ctypes.byref(ctypes.c_size_t())) == 1
+
+
+def test_last_error_is_cleared_by_a_good_call():
+    with pytest.raises(kde.KdeError):
+        kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom(M=1), 100)
+    assert kde.kde_last_error() != ""
+    kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom(), 100)
+    assert kde.kde_last_error() == ""
