@@ -208,6 +208,62 @@ kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, con
                             int64_t* n_floored, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batching form. Many independent particle sets, each taken through the
+ * whole path -- kde_cv_scan over one shared list of B concentrations (all N
+ * particles of the set), kde_deposit at the set's kappa* (the pilot),
+ * kde_adapt_widths with `alpha`, and kde_deposit with the resulting
+ * per-particle concentrations -- in one hipGraph launch. The graph holds one
+ * persistent kernel per phase; their workgroups pull work units (a set, a
+ * tile pair, a particle chunk, a row block) from per-phase device counters,
+ * largest sets first. Each set's outputs are bitwise identical to those of
+ * the one-set calls on the same set.
+ */
+typedef struct kde_batch_set {
+  int64_t N;          /* particles, >= 2                                        */
+  const void* x;      /* device, N positions (element type: the batch's prec)   */
+  double L;           /* period, finite and > 0                                 */
+  int32_t M;          /* grid nodes, 2..4096                                    */
+  int32_t reserved;   /* set to 0                                               */
+  double* cv;         /* device, B doubles: the CV objective (output) or NULL   */
+  double* pilot;      /* device, M doubles: pilot density at kappa* (output) or NULL */
+  double* rho;        /* device, M doubles: adaptive density (output)           */
+  void* kappa_i;      /* device, N values (prec): adaptive widths (output) or NULL */
+  double* kappa_star; /* device, 1 double: the chosen concentration (output) or NULL */
+} kde_batch_set;
+
+typedef struct kde_batch kde_batch;
+
+/* Plan a batch (host work only). The set array is copied; the device
+ * buffers it points to must stay valid while the batch is run. Rules as
+ * for the one-set calls: N >= 2, L finite > 0, 2 <= M <= 4096, x and rho
+ * not NULL, 1 <= B <= KDE_MAX_KAPPAS finite ascending kappas >= 0, alpha
+ * finite >= 0. *out_h receives the handle (NULL on error). */
+kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t prec, int32_t B,
+                          const double* kappas_h, double alpha, kde_batch** out_h);
+/* Device workspace the batch needs (256-byte aligned). */
+kde_status kde_batch_workspace_size(const kde_batch* b, size_t* bytes_h);
+/* Enqueue the whole batch on `stream` as one graph launch. The first run
+ * with a given workspace uploads the set descriptors into it (a blocking
+ * copy) and captures the graph; later runs with the same workspace only
+ * launch the graph. The workspace belongs to the batch between runs. */
+kde_status kde_batch_run(kde_batch* b, void* ws, size_t ws_bytes, void* stream);
+kde_status kde_batch_destroy(kde_batch* b);
+
+/*
+ * Tuning of the CV pair kernel: the number of concentrations it evaluates
+ * per pass (4, 8 or 16), by particle count. Entry k applies to
+ * N <= n_max_h[k] (ascending); the last entry covers every larger N. The
+ * choice changes speed only: each concentration accumulates the same terms
+ * in the same order whatever the pass size, so results are bitwise equal.
+ * The table is process-wide; set it before launching work, not while calls
+ * on other threads are running. kde_tune_get returns the pass size used for
+ * N. The default is 16 for every N until a table is set (the Python binding
+ * installs the autotuned table shipped with the package).
+ */
+kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h);
+kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h);
+
+/*
  * Kernel timing (diagnostics). While enabled, the library brackets every
  * launch of the kernels named below with a pair of HIP events recorded on
  * the launching call's stream. kde_timing_read waits for the recorded

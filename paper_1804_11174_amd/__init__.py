@@ -40,6 +40,12 @@ class kde_domain(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("M", ctypes.c_int32), ("prec", ctypes.c_int32)]
 
 
+class kde_batch_set(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("x", ctypes.c_void_p), ("L", ctypes.c_double), ("M", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("cv", ctypes.c_void_p), ("pilot", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p), ("kappa_i", ctypes.c_void_p), ("kappa_star", ctypes.c_void_p)]
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -59,7 +65,16 @@ _SIGNATURES = {
     "kde_timing_enable": (_i32, [_i32]),
     "kde_timing_reset": (_i32, []),
     "kde_timing_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
+    "kde_tune_set": (_i32, [_i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "kde_tune_get": (_i32, [_i32, _i64, ctypes.POINTER(_i32)]),
+    "kde_batch_plan": (_i32, [ctypes.POINTER(kde_batch_set), _i32, _i32, _i32, ctypes.POINTER(_dbl), _dbl,
+                              ctypes.POINTER(_vp)]),
+    "kde_batch_workspace_size": (_i32, [_vp, ctypes.POINTER(_sz)]),
+    "kde_batch_run": (_i32, [_vp, _vp, _sz, _vp]),
+    "kde_batch_destroy": (_i32, [_vp]),
 }
+
+TUNE_FILE = os.path.join(HERE, "tune_gfx950.json")
 
 KDE_KERNEL_CV_PAIRS, KDE_KERNEL_DEPOSIT, KDE_KERNEL_GATHER, KDE_KERNEL_ADAPT = 0, 1, 2, 3
 
@@ -84,7 +99,20 @@ def require_library():
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    if os.path.exists(TUNE_FILE):
+        load_tuning(TUNE_FILE)
     return lib
+
+
+def load_tuning(path: str):
+    """Install an autotuned pass-size table (JSON written by autotune.py)."""
+    import json
+    with open(path) as f:
+        table = json.load(f)
+    for name, prec in (("f64", KDE_F64), ("f32", KDE_F32)):
+        rows = table.get(name)
+        if rows:
+            kde_tune_set(prec, [r["n_max"] for r in rows], [r["chunk"] for r in rows])
 
 
 def _check(status: int, where: str):
@@ -177,6 +205,91 @@ def kde_adapt_widths(dom, N, x, pilot, kappa_star, alpha, kappa_out, log_geomean
     _check(lib.kde_adapt_widths(ctypes.byref(dom), int(N), _ptr(x), _ptr(pilot), float(kappa_star), float(alpha),
                                 _ptr(kappa_out), _ptr(log_geomean), _ptr(n_floored), ws, int(ws_bytes),
                                 _stream(stream)), "kde_adapt_widths")
+
+
+def kde_tune_set(prec: int, n_max, chunk):
+    lib = require_library()
+    n = len(n_max)
+    a = (_i64 * n)(*[int(v) for v in n_max])
+    b = (_i32 * n)(*[int(v) for v in chunk])
+    _check(lib.kde_tune_set(int(prec), n, a, b), "kde_tune_set")
+
+
+def kde_tune_get(prec: int, N: int) -> int:
+    out = _i32(0)
+    _check(require_library().kde_tune_get(int(prec), int(N), ctypes.byref(out)), "kde_tune_get")
+    return int(out.value)
+
+
+def kde_batch_plan(sets, prec: int, kappas, alpha: float = 0.5) -> int:
+    """Plan a batch from a list of ``kde_batch_set``; returns the handle."""
+    lib = require_library()
+    arr = (kde_batch_set * len(sets))(*sets)
+    k = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
+    h = _vp()
+    _check(lib.kde_batch_plan(arr, len(sets), int(prec), int(k.shape[0]), k.ctypes.data_as(ctypes.POINTER(_dbl)),
+                              float(alpha), ctypes.byref(h)), "kde_batch_plan")
+    return h.value
+
+
+def kde_batch_workspace_size(handle: int) -> int:
+    out = _sz(0)
+    _check(require_library().kde_batch_workspace_size(handle, ctypes.byref(out)), "kde_batch_workspace_size")
+    return int(out.value)
+
+
+def kde_batch_run(handle: int, ws, ws_bytes: int, stream=None):
+    _check(require_library().kde_batch_run(handle, ws, int(ws_bytes), _stream(stream)), "kde_batch_run")
+
+
+def kde_batch_destroy(handle: int):
+    _check(require_library().kde_batch_destroy(handle), "kde_batch_destroy")
+
+
+class Batch:
+    """Many particle sets through the whole path in one graph launch.
+
+    ``xs`` are GPU tensors (all float64 or all float32), ``Ls`` and ``Ms``
+    their periods and grids. Outputs are allocated here: ``cv[s]`` (B),
+    ``pilot[s]`` (M), ``rho[s]`` (M), ``kappa_i[s]`` (N), ``kappa_star``
+    (one per set)."""
+
+    def __init__(self, xs, Ls, Ms, kappas, alpha: float = 0.5):
+        import torch
+        self.prec = prec_of(xs[0])
+        dev = xs[0].device
+        self.kappas = np.asarray(kappas, dtype=np.float64)
+        B = self.kappas.shape[0]
+        self.xs = list(xs)
+        self.cv = [torch.empty(B, dtype=torch.float64, device=dev) for _ in xs]
+        self.pilot = [torch.empty(int(M), dtype=torch.float64, device=dev) for M in Ms]
+        self.rho = [torch.empty(int(M), dtype=torch.float64, device=dev) for M in Ms]
+        self.kappa_i = [torch.empty(x.shape[0], dtype=x.dtype, device=dev) for x in xs]
+        self.kappa_star = torch.empty(len(xs), dtype=torch.float64, device=dev)
+        sets = []
+        for s, (x, L, M) in enumerate(zip(xs, Ls, Ms)):
+            if prec_of(x) != self.prec:
+                raise ValueError("all sets of a batch share one precision")
+            sets.append(kde_batch_set(int(x.shape[0]), _ptr(x), float(L), int(M), 0, _ptr(self.cv[s]),
+                                      _ptr(self.pilot[s]), _ptr(self.rho[s]), _ptr(self.kappa_i[s]),
+                                      self.kappa_star.data_ptr() + 8 * s))
+        self.handle = kde_batch_plan(sets, self.prec, self.kappas, alpha)
+        self.ws = Workspace(dev)
+        self.ws.get(kde_batch_workspace_size(self.handle))
+
+    def run(self, stream=None):
+        kde_batch_run(self.handle, self.ws.ptr, self.ws.bytes, stream)
+
+    def close(self):
+        if self.handle:
+            kde_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def kde_timing_enable(on: bool):

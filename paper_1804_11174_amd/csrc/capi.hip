@@ -134,6 +134,21 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
   }
 }
 
+kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h) {
+  clear_error();
+  if (prec != KDE_F64 && prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
+  if (count < 1 || count > 64 || !n_max_h || !chunk_h) return fail(KDE_E_INVALID_ARG, "count must lie in [1, 64] with both arrays given");
+  return set_tuning(prec, count, n_max_h, chunk_h);
+}
+
+kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h) {
+  clear_error();
+  if (prec != KDE_F64 && prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
+  if (!chunk_h) return fail(KDE_E_INVALID_ARG, "chunk_h is NULL");
+  *chunk_h = tuned_chunk(prec, N);
+  return KDE_OK;
+}
+
 kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t B, const double* kappas_h,
                        double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes, void* stream) {
   clear_error();

@@ -1,0 +1,348 @@
+#pragma once
+// Device pieces of the least-squares cross-validation over a batch of
+// concentrations (Sec. II.B, Eq. cv_def): the O(N^2) pair sums and the final
+// combination. Shared by the one-set kernels of cv.hip and the batched engine.
+//
+// For the von Mises kernel both pair terms depend on a pair only through
+// its half-angle difference phi = pi (x_i - x_j) / L, via s = sin(phi) and
+// c = |cos(phi)|:
+//   K-term    exp(-2 kappa s^2)                           (kernel, unnormalised)
+//   Kbar-term exp(-2 kappa (1 - c)) I0e(2 kappa c)        (two-fold convolution)
+// Both exponents are formed without cancellation:
+//   double: from half-angle vectors (a, b) = (cos(pi x/L), sin(pi x/L)),
+//           c = |a_i a_j + b_i b_j|, s = b_i a_j - a_i b_j, 1 - c = s^2 / (1 + c);
+//   float : from 32-bit fixed-point phases, whose wrapped integer difference
+//           gives phi in [-pi/2, pi/2) exactly up to one conversion; then
+//           1 - c = phi^2 R(phi^2) with R the Taylor series of
+//           (1 - cos phi) / phi^2 (7 terms, below float rounding on that
+//           range) and s^2 = (1 - c)(1 + c) = q (2 - q). Normalisers 1/(L I0e(kappa)) and
+// 1/(L I0e(kappa)^2) are applied once, in double, by the finalize kernel.
+//
+// Work decomposition: particles (sorted by angular cell) are cut into tiles
+// of 256; one workgroup takes one tile pair (I <= J), one i-particle per
+// thread against the J tile staged in LDS (every lane reads the same j:
+// an LDS broadcast). Concentrations are processed in chunks of 16, each
+// with per-thread accumulators; at the end of a chunk the 256 per-thread
+// sums are reduced in double in a fixed order and the workgroup writes its
+// 2B partial sums to its own slot. No floating-point atomics are used.
+//
+// Terms whose exponent is below -70 are not evaluated: each is below
+// e^-70 (4e-31) times the largest term of its sum (the pair at distance 0
+// has exponent 0 and I0e <= 1). Concentrations are ascending and the
+// exponent scales with kappa, so once every lane of a wave is below the
+// bound for one concentration, the wave skips the rest for that j.
+#include "device_bessel.hpp"
+#include "kde_internal.hpp"
+
+namespace kde {
+
+
+template <typename T>
+struct CvConsts {
+  T A[KDE_MAX_KAPPAS];     // -2 kappa (double) or -2 kappa log2(e) (float)
+  T invk[KDE_MAX_KAPPAS];  // 1 / kappa
+  T rsk[KDE_MAX_KAPPAS];   // 1 / sqrt(kappa)
+  T em2k[KDE_MAX_KAPPAS];  // exp(-2 kappa) for the small-argument branch
+  T twok[KDE_MAX_KAPPAS];  // 2 kappa
+  int B;
+  int nsmall;  // leading concentrations that may need the small-argument I0e branch
+  T skip;      // exponent bound (in the unit of A)
+};
+
+template <typename T>
+struct Acc;
+
+template <>
+struct Acc<double> {
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(double v) { s += v; }
+  __device__ __forceinline__ double value() const { return s; }
+};
+
+// Compensated (Kahan) float accumulator.
+template <>
+struct Acc<float> {
+  float s, c;
+  __device__ __forceinline__ void zero() { s = 0.0f; c = 0.0f; }
+  __device__ __forceinline__ void add(float v) {
+    float y = v - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return double(s) - double(c); }
+};
+
+__device__ __forceinline__ double exp_unit(double a) { return exp_nonpos_f64(a); }
+__device__ __forceinline__ float exp_unit(float a) { return __builtin_amdgcn_exp2f(a); }
+
+__device__ __forceinline__ double rcp_unit(double a) { return 1.0 / a; }
+__device__ __forceinline__ float rcp_unit(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double rsqrt_unit(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ float rsqrt_unit(float a) { return __builtin_amdgcn_rsqf(a); }
+
+__device__ __forceinline__ double i0_series(double y) { return i0_series_f64(y); }
+__device__ __forceinline__ float i0_series(float y) { return i0_series_f32(y); }
+__device__ __forceinline__ double i0e_sqrt_large(double t) { return i0e_sqrt_large_f64(t); }
+__device__ __forceinline__ float i0e_sqrt_large(float t) { return i0e_sqrt_large_f32(t); }
+
+template <typename T>
+struct I0eBounds;
+template <>
+struct I0eBounds<double> {
+  static constexpr double X0 = KDE_I0E_F64_X0;
+};
+template <>
+struct I0eBounds<float> {
+  static constexpr float X0 = KDE_I0E_F32_X0;
+};
+
+// Decode the J-major triangular index p -> (I, J), I <= J.
+__device__ __forceinline__ void tri_decode(int64_t p, int& I, int& J) {
+  int64_t j = int64_t((sqrt(8.0 * double(p) + 1.0) - 1.0) * 0.5);
+  while (j * (j + 1) / 2 > p) --j;
+  while ((j + 1) * (j + 2) / 2 <= p) ++j;
+  J = int(j);
+  I = int(p - j * (j + 1) / 2);
+}
+
+// Geometry of one pair: s^2, q = 1 - c, c, 1/(2c), 1/sqrt(2c).
+template <typename T>
+struct Geo {
+  T s2, q, c, inv2c, rs2c;
+};
+
+// i-particle state held in registers.
+template <typename T>
+struct IPart;
+template <>
+struct IPart<double> {
+  double a, b;
+};
+template <>
+struct IPart<float> {
+  uint32_t u;
+};
+
+__device__ __forceinline__ IPart<double> load_i(const double* __restrict__ packed, int64_t i, bool valid) {
+  return IPart<double>{valid ? packed[2 * i] : 1.0, valid ? packed[2 * i + 1] : 0.0};
+}
+__device__ __forceinline__ IPart<float> load_i(const uint32_t* __restrict__ packed, int64_t i, bool valid) {
+  return IPart<float>{valid ? packed[i] : 0u};
+}
+
+__device__ __forceinline__ Geo<double> pair_geo(const IPart<double>& p, const double* __restrict__ tj, int jj) {
+  const double aj = tj[2 * jj], bj = tj[2 * jj + 1];
+  const double c = fabs(p.a * aj + p.b * bj);
+  const double s = p.b * aj - p.a * bj;
+  Geo<double> g;
+  g.s2 = s * s;
+  g.q = g.s2 / (1.0 + c);
+  g.c = c;
+  g.inv2c = 1.0 / (2.0 * c);
+  g.rs2c = 1.0 / sqrt(2.0 * c);
+  return g;
+}
+
+__device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint32_t* __restrict__ tj, int jj) {
+  // pi / 2^32 turns a wrapped phase difference into the half-angle difference
+  const float phi = float(int32_t(p.u - tj[jj])) * 7.3145904152e-10f;
+  const float y = phi * phi;
+  float r = 1.0f / 87178291200.0f;
+  r = fmaf(r, y, -1.0f / 479001600.0f);
+  r = fmaf(r, y, 1.0f / 3628800.0f);
+  r = fmaf(r, y, -1.0f / 40320.0f);
+  r = fmaf(r, y, 1.0f / 720.0f);
+  r = fmaf(r, y, -1.0f / 24.0f);
+  r = fmaf(r, y, 0.5f);
+  Geo<float> g;
+  g.q = y * r;
+  g.c = 1.0f - g.q;
+  g.s2 = g.q * (2.0f - g.q);
+  g.inv2c = __builtin_amdgcn_rcpf(2.0f * g.c);
+  g.rs2c = __builtin_amdgcn_rsqf(2.0f * g.c);
+  return g;
+}
+
+template <typename T, int BC, bool MASKED>
+__device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
+                                           const IPart<T>& ip, bool valid_i, bool diag, int b0,
+                                           const CvConsts<T>& K, Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
+  const int nb = min(BC, K.B - b0);
+  const T X0 = I0eBounds<T>::X0;
+  const T tmin = T(1) / X0;
+  const T rsmax = T(1) / sqrt(X0);
+  for (int jj = 0; jj < nj; ++jj) {
+    const Geo<T> g = pair_geo(ip, tj, jj);
+    bool live = true;
+    if (MASKED) live = valid_i && (!diag || jj > int(threadIdx.x));
+    // `go` is uniform across the wave: it turns false at the first
+    // concentration for which every live pair of the wave is negligible
+    bool go = true;
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      const int b = b0 + bb;
+      go = go && (bb < nb);
+      T A = T(0), Aq = T(0);
+      if (go) {
+        A = K.A[b];
+        Aq = A * g.q;
+        go = !__all(!live || Aq < K.skip);
+      }
+      if (go) {
+        T t2 = exp_unit(A * g.s2);
+        T t1;
+        if (b < K.nsmall) {
+          const T R = K.twok[b] * g.c;
+          if (R < X0) {
+            t1 = K.em2k[b] * i0_series(R * R);
+          } else {
+            t1 = exp_unit(Aq) * i0e_sqrt_large(g.inv2c * K.invk[b]) * (g.rs2c * K.rsk[b]);
+          }
+        } else {
+          const T t = fmin(g.inv2c * K.invk[b], tmin);
+          const T rs = fmin(g.rs2c * K.rsk[b], rsmax);
+          t1 = exp_unit(Aq) * i0e_sqrt_large(t) * rs;
+        }
+        if (MASKED) {
+          t1 = live ? t1 : T(0);
+          t2 = live ? t2 : T(0);
+        }
+        acc1[bb].add(t1);
+        acc2[bb].add(t2);
+      }
+    }
+  }
+}
+
+// Shared memory of one tile-pair unit.
+template <typename T, int BC>
+struct CvSmem {
+  typename Packed<T>::type tj[Packed<T>::per_particle * kCvTile];
+  double red[kBlock / 64][2 * BC];
+  double unit_acc[2 * KDE_MAX_KAPPAS];
+};
+
+// One unit of the pair sums: tile I (one i per thread) against tile J
+// (staged in LDS), every concentration; writes the unit's 2B partial sums
+// [Kbar sums | K sums] to `out`. Used by the one-set kernel below and by the
+// batched engine. Ends with a barrier, so the caller may reuse `sm`.
+template <typename T, int BC>
+__device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __restrict__ packed, int64_t n,
+                                             int I, int J, const CvConsts<T>& K, double* __restrict__ out,
+                                             CvSmem<T, BC>& sm) {
+  constexpr int per = Packed<T>::per_particle;
+  const int tid = threadIdx.x;
+  const int64_t j0 = int64_t(J) * kCvTile;
+  const int nj = int(min(int64_t(kCvTile), n - j0));
+  for (int k = tid; k < per * nj; k += kBlock) sm.tj[k] = packed[per * j0 + k];
+  const int64_t i = int64_t(I) * kCvTile + tid;
+  const bool valid_i = i < n;
+  const IPart<T> ip = load_i(packed, i, valid_i);
+  const bool diag = (I == J);
+  const bool masked = diag || (int64_t(I + 1) * kCvTile > n);
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int b0 = 0; b0 < K.B; b0 += BC) {
+    Acc<T> s1[BC], s2[BC];
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      s1[bb].zero();
+      s2[bb].zero();
+    }
+    if (masked)
+      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, K, s1, s2);
+    else
+      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, K, s1, s2);
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      double v1 = wave_sum(s1[bb].value());
+      double v2 = wave_sum(s2[bb].value());
+      if (lane == 0) {
+        sm.red[wave][bb] = v1;
+        sm.red[wave][BC + bb] = v2;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * BC) {
+      const int bb = tid % BC;
+      const int which = tid / BC;  // 0: Kbar sums, 1: K sums
+      if (b0 + bb < K.B) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
+        sm.unit_acc[which * K.B + b0 + bb] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = sm.unit_acc[k];
+  __syncthreads();
+}
+
+// Per-concentration constants of the pair kernel, computed on the host.
+template <typename T>
+inline CvConsts<T> make_consts(const double* kappas, int B) {
+  CvConsts<T> K{};
+  const double log2e = 1.4426950408889634;
+  const double unit = std::is_same<T, float>::value ? log2e : 1.0;
+  const double X0 = double(I0eBounds<T>::X0);
+  K.B = B;
+  K.nsmall = 0;
+  for (int b = 0; b < B; ++b) {
+    const double k = kappas[b];
+    K.A[b] = T(-2.0 * k * unit);
+    K.invk[b] = T(1.0 / k);
+    K.rsk[b] = T(1.0 / std::sqrt(k));
+    K.em2k[b] = T(std::exp(-2.0 * k));
+    K.twok[b] = T(2.0 * k);
+    // an argument 2 kappa |c| below X0 carries weight exp(-2 kappa (1 - |c|))
+    // <= exp(-(2 kappa - X0)); beyond the skip bound it is negligible
+    if (2.0 * k - X0 <= kSkipExponent) K.nsmall = b + 1;
+  }
+  K.skip = T(-kSkipExponent * unit);
+  return K;
+}
+
+struct KappaList {
+  double k[KDE_MAX_KAPPAS];
+};
+
+// The objective from the unordered pair sums of one set, by one workgroup
+// (thread b handles concentration b): raw[0..B) = sum_{i<j} exp(-2k(1-c))
+// I0e(2kc), raw[B..2B) = sum_{i<j} exp(-2k s^2). Normalisers in double;
+// writes cv[B], optional sums[2B] (normalised), and returns nothing; the
+// first-minimum index is written by thread 0 into *argmin (if not NULL)
+// and into `v` (LDS, B doubles) the objective values.
+__device__ __forceinline__ void cv_finalize_block(const double* __restrict__ raw, int B, double n, double L,
+                                                  const KappaList& kap, double* __restrict__ cv,
+                                                  double* __restrict__ sums, int32_t* __restrict__ argmin,
+                                                  double* v, int* best_out) {
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const double k = kap.k[b];
+    const double ik = i0e_f64(k);
+    const double i2k = i0e_f64(2.0 * k);
+    const double S1 = raw[b] / (L * ik * ik);
+    const double S2 = raw[B + b] / (L * ik);
+    const double kbar0 = i2k / (L * ik * ik);
+    const double val = (n * kbar0 + 2.0 * S1) / (n * n) - 4.0 * S2 / (n * (n - 1.0));
+    if (cv) cv[b] = val;
+    v[b] = val;
+    if (sums) {
+      sums[b] = S1;
+      sums[B + b] = S2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int t = 1; t < B; ++t)
+      if (v[t] < v[best]) best = t;
+    if (argmin) *argmin = best;
+    if (best_out) *best_out = best;
+  }
+  __syncthreads();
+}
+
+}  // namespace kde

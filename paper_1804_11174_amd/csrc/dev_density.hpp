@@ -1,0 +1,295 @@
+#pragma once
+// Device pieces of the grid density, field gather and adaptive widths with
+// von Mises kernels, shared by density.hip and the batched engine.
+//
+// Deposit (Sec. II.B Eq. kde; Sec. II.C step 3 for per-particle widths):
+//   rho[g] = (1/N) sum_i w_i exp(-2 kappa_i s_ig^2),
+//   s_ig = sin(pi (x_g - x_i) / L),  w_i = 1 / (L I0e(kappa_i)).
+// The grid is small (M <= 4096) and every particle touches every node, so
+// a workgroup owns the whole grid for one contiguous chunk of particles:
+// the chunk is staged in LDS (half-angle vector, exponent scale, weight)
+// and read by all lanes at the same address (broadcast), each thread
+// accumulating its own node(s). Per-chunk grids go to fixed slots and are
+// summed in a fixed order. The cost is one exponential per (particle, node):
+// transcendental-bound, not HBM-bound, at every grid size used here.
+//
+// Gather (field interpolation of Sec. III.A with the same kernels):
+//   out[i] = (L/M) w_i sum_g F_g exp(-2 kappa_i s_ig^2),
+// one thread per particle with the node table in LDS.
+//
+// Adaptive widths (Sec. II.C, Eq. adaptive_width): the pilot grid is
+// interpolated linearly at each particle, its logarithms are averaged in
+// double (fixed-order reduction), and kappa_i = kappa* exp(2 alpha (log f_i
+// - log g)) is written per particle.
+#include <cfloat>
+
+#include "device_bessel.hpp"
+#include "kde_internal.hpp"
+
+namespace kde {
+
+
+template <typename T>
+struct Flt;
+template <>
+struct Flt<double> {
+  static __device__ __forceinline__ double ex(double a) { return exp_nonpos_f64(a); }  // a = natural exponent <= 0
+  static constexpr double unit = 1.0;
+  static constexpr double tiny = DBL_MIN;
+};
+template <>
+struct Flt<float> {
+  static __device__ __forceinline__ float ex(float a) { return __builtin_amdgcn_exp2f(a); }  // base 2
+  static constexpr double unit = 1.4426950408889634;
+  static constexpr float tiny = FLT_MIN;
+};
+
+template <typename T>
+struct SumOf;
+template <>
+struct SumOf<double> {
+  double s = 0.0;
+  __device__ __forceinline__ void add(double v) { s += v; }
+  __device__ __forceinline__ double value() const { return s; }
+};
+template <>
+struct SumOf<float> {
+  float s = 0.0f, c = 0.0f;
+  __device__ __forceinline__ void add(float v) {
+    float y = v - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return double(s) - double(c); }
+};
+
+constexpr int kDepMaxChunk = 512;
+
+// Geometry of a (node, particle) pair. Both forms give s = sin(pi (x_g - x_i) / L):
+//   double: global half-angle vectors, s = sin(pi g/M) a_i - cos(pi g/M) b_i with
+//           (a_i, b_i) = (cos(pi x_i/L), sin(pi x_i/L));
+//   float : node-relative, with the particle at v = x_i M / L split as v = g0 + d
+//           (g0 the nearest node, |d| <= 1/2) and beta = pi d / M:
+//           s = sin(pi k/M) cos(beta) - cos(pi k/M) sin(beta), k = (g - g0) mod M,
+//           from a table over k. Near nodes have small k and small beta, so s
+//           keeps float relative accuracy where the kernel is largest (the
+//           global form would carry the absolute rounding of a_i, b_i).
+template <typename T>
+struct PGeo;
+template <>
+struct PGeo<double> {
+  double a, b;
+};
+template <>
+struct PGeo<float> {
+  int g0;
+  float cb, sb;
+};
+
+__device__ __forceinline__ void make_geo(double xw, double L, int M, PGeo<double>& p) {
+  double sp, cp;
+  sincospi(xw / L, &sp, &cp);
+  p.a = cp;
+  p.b = sp;
+}
+
+__device__ __forceinline__ void make_geo(double xw, double L, int M, PGeo<float>& p) {
+  const double v = xw * (double(M) / L);
+  double g0 = floor(v + 0.5);
+  const double d = v - g0;
+  if (g0 >= double(M)) g0 -= double(M);
+  double sb, cb;
+  sincospi(d / double(M), &sb, &cb);
+  p.g0 = int(g0);
+  p.cb = float(cb);
+  p.sb = float(sb);
+}
+
+template <typename T, bool PER>
+__device__ __forceinline__ void particle_terms(const T* __restrict__ x, const T* __restrict__ kap, double kappa_g,
+                                               int64_t i, double L, int M, PGeo<T>& g, T& A, T& w) {
+  const double xi = double(x[i]);
+  const double xw = xi - L * floor(xi / L);
+  make_geo(xw, L, M, g);
+  const double k = PER ? double(kap[i]) : kappa_g;
+  A = T(-2.0 * k * Flt<T>::unit);
+  w = PER ? T(1.0 / (L * i0e_f64(k))) : T(1);
+}
+
+// s for node g of a particle; `ts`/`tc` hold sin/cos(pi g/M) (double form,
+// indexed by g) or sin/cos(pi k/M) (float form, indexed by k = g - g0 mod M).
+__device__ __forceinline__ double node_s(const PGeo<double>& p, int g, int M, const double* ts, const double* tc) {
+  return ts[g] * p.a - tc[g] * p.b;
+}
+__device__ __forceinline__ float node_s(const PGeo<float>& p, int g, int M, const float* ts, const float* tc) {
+  int k = g - p.g0;
+  k += (k < 0) ? M : 0;
+  return ts[k] * p.cb - tc[k] * p.sb;
+}
+
+// Shared memory of one deposit chunk (the node table is separate: dynamic
+// LDS of 2 M values of T).
+template <typename T>
+struct DepSmem {
+  PGeo<T> pg[kDepMaxChunk];
+  T pA[kDepMaxChunk], pw[kDepMaxChunk];
+  double red[kBlock];
+};
+
+// Fill the node table: ts[k] = sin(pi k/M), tc[k] = cos(pi k/M).
+template <typename T>
+__device__ __forceinline__ void node_table(int M, T* ts, T* tc) {
+  for (int k = threadIdx.x; k < M; k += kBlock) {
+    double sv, cv;
+    sincospi(double(k) / double(M), &sv, &cv);
+    ts[k] = T(sv);
+    tc[k] = T(cv);
+  }
+}
+
+// One deposit chunk: particles [lo, lo + cnt) onto all M nodes, written to
+// out[M] (the chunk's partial grid, unnormalised by N). The node table must
+// be filled and visible. Ends with a barrier.
+// M <= 256: S = 256 / M sub-streams share a node, thread t -> node t % M,
+//           sub-stream t / M (threads beyond S*M idle);
+// M  > 256: thread t -> nodes t, t + 256, ... (G per thread).
+template <typename T, bool PER, int G>
+__device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* __restrict__ kap, double kappa_g,
+                                              int M, double L, int64_t lo, int cnt, double* __restrict__ out,
+                                              const T* ts, const T* tc, DepSmem<T>& sm) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < cnt; k += kBlock) particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.pg[k], sm.pA[k], sm.pw[k]);
+  __syncthreads();
+  if (M <= kBlock) {
+    const int S = kBlock / M;
+    const int g = tid % M, sub = tid / M;
+    double tot = 0.0;
+    if (sub < S) {
+      SumOf<T> acc;
+      for (int p = sub; p < cnt; p += S) {
+        const T s = node_s(sm.pg[p], g, M, ts, tc);
+        const T e = Flt<T>::ex(sm.pA[p] * (s * s));
+        acc.add(PER ? sm.pw[p] * e : e);
+      }
+      tot = acc.value();
+    }
+    sm.red[tid] = tot;
+    __syncthreads();
+    if (tid < M) {
+      double v = 0.0;
+      for (int q = 0; q < S; ++q) v += sm.red[q * M + tid];
+      out[tid] = PER ? v : v * (1.0 / (L * i0e_f64(kappa_g)));
+    }
+  } else {
+    SumOf<T> acc[G];
+    for (int p = 0; p < cnt; ++p) {
+      const PGeo<T> gp = sm.pg[p];
+      const T A = sm.pA[p], w = sm.pw[p];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int g = tid + k * kBlock;
+        if (g < M) {
+          const T s = node_s(gp, g, M, ts, tc);
+          const T e = Flt<T>::ex(A * (s * s));
+          acc[k].add(PER ? w * e : e);
+        }
+      }
+    }
+    const double scale = PER ? 1.0 : 1.0 / (L * i0e_f64(kappa_g));
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = tid + k * kBlock;
+      if (g < M) out[g] = acc[k].value() * scale;
+    }
+  }
+  __syncthreads();
+}
+
+// Particles per deposit chunk for N particles (the chunk grid is what the
+// fixed-order reduction sums, so every user must cut the same chunks).
+__host__ __device__ inline int deposit_chunk(int64_t n) {
+  int64_t c = (n + 2047) / 2048;
+  if (c < 64) c = 64;
+  if (c > kDepMaxChunk) c = kDepMaxChunk;
+  return int(c);
+}
+
+// Pilot density at a particle: periodic linear interpolation between the
+// two nodes around it, floored at the smallest normal number of T. A
+// non-finite position yields NaN (and is not counted as floored). The
+// arithmetic is double in both precisions: this step reads and writes a
+// few bytes per particle and is bound by memory traffic, not arithmetic.
+template <typename T>
+__device__ __forceinline__ double pilot_at(T xv, double L, int M, const double* __restrict__ pilot, bool& floored) {
+  const double xi = double(xv);
+  floored = false;
+  if (!isfinite(xi)) return NAN;
+  const double xw = xi - L * floor(xi / L);
+  double u = xw * (double(M) / L);
+  if (!(u >= 0.0)) u = 0.0;
+  int j = int(floor(u));
+  double t = u - double(j);
+  if (j >= M) {  // x rounded up to L: the node at 0
+    j = 0;
+    t = 0.0;
+  }
+  const int j1 = (j + 1 == M) ? 0 : j + 1;
+  double f = (1.0 - t) * pilot[j] + t * pilot[j1];
+  if (f < double(Flt<T>::tiny)) {  // NaN stays NaN
+    floored = true;
+    f = double(Flt<T>::tiny);
+  }
+  return f;
+}
+
+// Block b of the log-sum pass: particles [256 b, 256 b + 256); writes
+// (sum of log f, floored count) to out[0..2). `r0`, `r1`: kBlock/64 doubles
+// of LDS each.
+template <typename T>
+__device__ __forceinline__ void adapt_logsum_block(const T* __restrict__ x, int64_t n, int M, double L,
+                                                   const double* __restrict__ pilot, int64_t b,
+                                                   double* __restrict__ out, double* r0, double* r1) {
+  const int64_t i = b * kBlock + threadIdx.x;
+  double lsum = 0.0, fl = 0.0;
+  if (i < n) {
+    bool floored;
+    lsum = log(pilot_at<T>(x[i], L, M, pilot, floored));
+    fl = floored ? 1.0 : 0.0;
+  }
+  lsum = wave_sum(lsum);
+  fl = wave_sum(fl);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    r0[wave] = lsum;
+    r1[wave] = fl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      a += r0[w];
+      c += r1[w];
+    }
+    out[0] = a;
+    out[1] = c;
+  }
+  __syncthreads();
+}
+
+// Block b of the width pass: kappa_i = kappa* exp(2 alpha (log f_i - log g))
+// with log g = sums[0] / n.
+template <typename T>
+__device__ __forceinline__ void adapt_apply_block(const T* __restrict__ x, int64_t n, int M, double L,
+                                                  const double* __restrict__ pilot, double kappa_star, double alpha,
+                                                  const double* __restrict__ sums, int64_t b, T* __restrict__ kout) {
+  const double log_g = sums[0] / double(n);
+  const int64_t i = b * kBlock + threadIdx.x;
+  if (i < n) {
+    bool floored;
+    const double lf = log(pilot_at<T>(x[i], L, M, pilot, floored));
+    kout[i] = T(kappa_star * exp(2.0 * alpha * (lf - log_g)));
+  }
+}
+
+}  // namespace kde

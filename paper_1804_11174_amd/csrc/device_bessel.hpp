@@ -17,25 +17,44 @@ namespace kde {
 
 // ---------------------------------------------------------------- double
 
-__host__ __device__ __forceinline__ double i0_series_f64(double y) {
+// a * b + c in double as one three-operand v_fma_f64. The compiler's
+// two-address form (v_fmac) overwrites its addend, so a polynomial
+// coefficient kept in a register needs a copy before every use in register-
+// heavy loops; the three-operand form needs none.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// The same with the addend (a polynomial coefficient) in a scalar register
+// pair, which keeps coefficient tables out of the vector register file.
+__device__ __forceinline__ double fma3s(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+}
+
+
+__device__ __forceinline__ double i0_series_f64(double y) {
   constexpr double c[KDE_I0E_F64_NSERIES] = KDE_I0E_F64_SERIES;
   double r = c[KDE_I0E_F64_NSERIES - 1];
 #pragma unroll
-  for (int k = KDE_I0E_F64_NSERIES - 2; k >= 0; --k) r = fma(r, y, c[k]);
+  for (int k = KDE_I0E_F64_NSERIES - 2; k >= 0; --k) r = fma3(r, y, c[k]);
   return r;
 }
 
 // sqrt(x) * I0e(x) for x >= X0, given t = 1/x.
-__host__ __device__ __forceinline__ double i0e_sqrt_large_f64(double t) {
+__device__ __forceinline__ double i0e_sqrt_large_f64(double t) {
   constexpr double c[KDE_I0E_F64_NFIT] = KDE_I0E_F64_FIT;
   const double u = (t - KDE_I0E_F64_C) * (1.0 / KDE_I0E_F64_H);
   double r = c[KDE_I0E_F64_NFIT - 1];
 #pragma unroll
-  for (int k = KDE_I0E_F64_NFIT - 2; k >= 0; --k) r = fma(r, u, c[k]);
+  for (int k = KDE_I0E_F64_NFIT - 2; k >= 0; --k) r = fma3(r, u, c[k]);
   return r;
 }
 
-__host__ __device__ __forceinline__ double i0e_f64(double x) {
+__device__ __forceinline__ double i0e_f64(double x) {
   x = fabs(x);
   if (x < KDE_I0E_F64_X0) return exp(-x) * i0_series_f64(x * x);
   return i0e_sqrt_large_f64(1.0 / x) / sqrt(x);
@@ -58,6 +77,33 @@ __device__ __forceinline__ float i0e_sqrt_large_f32(float t) {
 #pragma unroll
   for (int k = KDE_I0E_F32_NFIT - 2; k >= 0; --k) r = fmaf(r, u, c[k]);
   return r;
+}
+
+// exp(x) for x <= 0 in double: x = n ln2 + r with |r| <= ln2/2 (two-part
+// ln2, Cody and Waite), e^r by its Taylor series to degree 13 (remainder
+// below 5e-18 relative), then scaled by 2^n. Arguments below about -745
+// give 0 through the scaling (they are clamped to -1000 first); NaN gives
+// NaN. Callers pass non-positive arguments.
+__device__ __forceinline__ double exp_nonpos_f64(double x) {
+  x = (x < -1000.0) ? -1000.0 : x;  // far below the underflow limit; NaN passes through
+  const double n = __builtin_rint(x * 1.4426950408889634);
+  double r = fma(-n, 0.6931471805599453094, x);
+  r = fma(-n, 2.3190468138462996e-17, r);
+  double p = 1.0 / 6227020800.0;
+  p = fma3(p, r, 1.0 / 479001600.0);
+  p = fma3(p, r, 1.0 / 39916800.0);
+  p = fma3(p, r, 1.0 / 3628800.0);
+  p = fma3(p, r, 1.0 / 362880.0);
+  p = fma3(p, r, 1.0 / 40320.0);
+  p = fma3(p, r, 1.0 / 5040.0);
+  p = fma3(p, r, 1.0 / 720.0);
+  p = fma3(p, r, 1.0 / 120.0);
+  p = fma3(p, r, 1.0 / 24.0);
+  p = fma3(p, r, 1.0 / 6.0);
+  p = fma3(p, r, 0.5);
+  p = fma3(p, r, 1.0);
+  p = fma3(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, int(n));
 }
 
 }  // namespace kde

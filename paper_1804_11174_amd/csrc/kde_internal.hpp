@@ -46,7 +46,6 @@ void clear_error();
 
 constexpr int kBlock = 256;               // threads per workgroup for every kernel
 constexpr int kCvTile = 256;              // particles per CV tile (one per thread)
-constexpr int kCvChunk = 16;              // concentrations per pass of the pair kernel
 constexpr double kSkipExponent = 70.0;    // terms below exp(-70) of their sum's scale are skipped
 constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int kMaxM = 4096;
@@ -98,6 +97,10 @@ kde_status check_domain(const kde_domain* dom, bool need_grid);
 kde_status check_lds(size_t bytes);
 kde_status check_workspace(void* ws, size_t ws_bytes, size_t need);
 size_t elem_size(int prec);
+
+// Concentrations per pass of the pair kernel for (precision, N).
+int tuned_chunk(int prec, int64_t n);
+kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk);
 
 // ----------------------------------------------------- shared launch plans
 

@@ -109,3 +109,21 @@ def test_last_error_is_cleared_by_a_good_call():
     assert kde.kde_last_error() != ""
     kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom(), 100)
     assert kde.kde_last_error() == ""
+
+
+def test_tuning_table_round_trip():
+    kde.kde_tune_set(kde.KDE_F64, [1000, 50000, 1 << 40], [4, 8, 16])
+    assert kde.kde_tune_get(kde.KDE_F64, 10) == 4
+    assert kde.kde_tune_get(kde.KDE_F64, 1000) == 4
+    assert kde.kde_tune_get(kde.KDE_F64, 1001) == 8
+    assert kde.kde_tune_get(kde.KDE_F64, 10 ** 9) == 16
+    assert kde.kde_tune_get(kde.KDE_F64, 1 << 50) == 16   # last entry covers everything larger
+    with pytest.raises(kde.KdeError):
+        kde.kde_tune_set(kde.KDE_F64, [10], [5])
+    with pytest.raises(kde.KdeError):
+        kde.kde_tune_set(kde.KDE_F64, [10, 5], [4, 8])
+    # restore the shipped table (or the built-in default)
+    if os.path.exists(kde.TUNE_FILE):
+        kde.load_tuning(kde.TUNE_FILE)
+    else:
+        kde.kde_tune_set(kde.KDE_F64, [1 << 62], [16])

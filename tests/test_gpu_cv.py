@@ -163,3 +163,25 @@ def test_bad_arguments_raise(gpu):
         gpu.cv_scan(x[:1], 1.0, [1.0])
     with pytest.raises(ValueError):
         gpu.cv_scan(x.to(torch.int32), 1.0, [1.0])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pass_size_changes_nothing(gpu, dtype):
+    """The tuned pass size (concentrations per pass) must not change any bit."""
+    import torch
+    p = W.plain_small()
+    prec = gpu.KDE_F64 if dtype == "f64" else gpu.KDE_F32
+    x = p.x if dtype == "f64" else p.x.astype(np.float32)
+    kap = W.log_kappas(1.0, 1e4, 20)
+    outs = []
+    try:
+        for c in (4, 8, 16):
+            gpu.kde_tune_set(prec, [1 << 62], [c])
+            outs.append(run_gpu_cv(gpu, x, p.L, kap, dtype))
+    finally:
+        if __import__("os").path.exists(gpu.TUNE_FILE):
+            gpu.load_tuning(gpu.TUNE_FILE)
+        else:
+            gpu.kde_tune_set(prec, [1 << 62], [16])
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
