@@ -103,9 +103,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--prec", choices=["f64", "f32"], default=None,
+                    help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--form", choices=["plain", "batch"], default="plain",
+                    help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets")
+    ap.add_argument("--sets", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
@@ -119,6 +123,10 @@ def main():
     kde.require_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.form == "batch":
+        args.prec = args.prec or "f32"
+        return bench_batch(args, kde, W, torch, dev)
+    args.prec = args.prec or "f64"
     prob = W.plain_paper_scale()
     L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
     tdt = torch.float64 if args.prec == "f64" else torch.float32
@@ -209,6 +217,85 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob.x[:n_cv], L, kappas)
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+def bench_batch(args, kde, W, torch, dev):
+    """The batching form on independent sets (N log-uniform in [1e3, 1e5],
+    alpha ~ U[0.01, 0.5], k in {0.5, 1, 2}, L = 2 pi / k, M in {64, 128, 256};
+    16 kappas in [1, 1e4]; float form by default): one graph launch per step,
+    against the same sets through the one-set calls, one set after another
+    (the plain path: per set a CV scan, the host reading kappa*, the pilot
+    deposit, the widths and the adaptive deposit)."""
+    prec_name = args.prec
+    tdt = torch.float64 if prec_name == "f64" else torch.float32
+    sets = W.batch_sets(args.sets)
+    kappas = sets[0].problem.kappas
+    xs = [torch.from_numpy(s.problem.x).to(dev).to(tdt).contiguous() for s in sets]
+    Ls = [s.problem.L for s in sets]
+    Ms = [s.problem.M for s in sets]
+    ns = np.array([x.shape[0] for x in xs], dtype=np.float64)
+    B = len(kappas)
+    pair_evals = float(B * np.sum(ns * (ns - 1) / 2))
+    bt = kde.Batch(xs, Ls, Ms, kappas)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        bt.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.run(stream)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # the plain path: one set after another through the one-set calls
+    ws_cv, ws_dep, ws_ad = kde.Workspace(dev), kde.Workspace(dev), kde.Workspace(dev)
+    prec = kde.KDE_F64 if prec_name == "f64" else kde.KDE_F32
+    cv = torch.empty(B, dtype=torch.float64, device=dev)
+    am = torch.empty(1, dtype=torch.int32, device=dev)
+    am_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    outs = []
+    for x, L, M in zip(xs, Ls, Ms):
+        outs.append((torch.empty(M, dtype=torch.float64, device=dev), torch.empty(M, dtype=torch.float64, device=dev),
+                     torch.empty(x.shape[0], dtype=tdt, device=dev)))
+
+    def plain_all():
+        for x, L, M, (pil, rho, k_i) in zip(xs, Ls, Ms, outs):
+            n = x.shape[0]
+            d = kde.kde_domain(L, M, prec)
+            p1, b1 = ws_cv.get(kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, d, n, B))
+            kde.kde_cv_scan(d, n, x, kappas, cv, None, am, p1, b1, stream)
+            am_h.copy_(am, non_blocking=True)
+            stream.synchronize()
+            kstar = float(kappas[int(am_h[0])])
+            p2, b2 = ws_dep.get(kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, d, n))
+            kde.kde_deposit(d, n, x, None, kstar, pil, p2, b2, stream)
+            p3, b3 = ws_ad.get(kde.kde_workspace_size(kde.KDE_OP_ADAPT, d, n))
+            kde.kde_adapt_widths(d, n, x, pil, kstar, 0.5, k_i, None, None, p3, b3, stream)
+            kde.kde_deposit(d, n, x, k_i, 0.0, rho, p2, b2, stream)
+
+    plain_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_all()
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3
+    same = all(torch.equal(bt.rho[s], outs[s][1]) for s in range(len(xs)))
+    line = {"metric": METRIC, "form": "batch", "value": pair_evals / (ms_batch * 1e-3), "unit": "CV pair-evals/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec_name,
+            "data": "synthetic",
+            "config": {"workload": f"batching form: {len(xs)} sets, N log-uniform in [1e3,1e5], M in {{64,128,256}}, "
+                                   "16 kappas in [1,1e4]; CV scan + pilot + widths + adaptive deposit per set",
+                       "sets": len(xs), "particles": int(ns.sum()), "B": B},
+            "particles_per_s": float(ns.sum()) / (ms_batch * 1e-3),
+            "plain_path_ms": ms_plain, "batched_over_plain_speedup": ms_plain / ms_batch,
+            "batched_equals_plain_bitwise": bool(same)}
+    bt.close()
     out = json.dumps(line)
     print(out, flush=True)
     if args.json_out:

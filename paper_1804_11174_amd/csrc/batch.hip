@@ -25,9 +25,13 @@ namespace kde {
 
 // Phase counters (zeroed by the first kernel of every launch).
 enum Phase {
-  PH_PACK, PH_PAIRS, PH_CV_L1, PH_CV_FIN, PH_PIL_DEP, PH_PIL_L1, PH_PIL_L2, PH_AD_LOG, PH_AD_L1, PH_AD_L2,
+  PH_PACK, PH_CV_L1, PH_CV_FIN, PH_PIL_DEP, PH_PIL_L1, PH_PIL_L2, PH_AD_LOG, PH_AD_L1, PH_AD_L2,
   PH_AD_APPLY, PH_RHO_DEP, PH_RHO_L1, PH_RHO_L2, PH_COUNT
 };
+// The pair phase runs once per pass-size bucket, bucket k on counter
+// PH_COUNT + k.
+constexpr int kMaxBuckets = 64;
+constexpr int kCounters = PH_COUNT + kMaxBuckets;
 
 // Per-set description as the kernels see it (lives in the workspace).
 struct SetDev {
@@ -83,8 +87,8 @@ __device__ __forceinline__ int64_t claim(unsigned long long* counter, int64_t* s
   return u;
 }
 
-__global__ void __launch_bounds__(64) batch_zero_kernel(unsigned long long* counters) {
-  if (threadIdx.x < PH_COUNT) counters[threadIdx.x] = 0ull;
+__global__ void __launch_bounds__(kBlock) batch_zero_kernel(unsigned long long* counters) {
+  if (threadIdx.x < kCounters) counters[threadIdx.x] = 0ull;
 }
 
 template <typename T>
@@ -102,16 +106,17 @@ __global__ void __launch_bounds__(kBlock) batch_pack_kernel(BatchArgs a) {
   }
 }
 
+// Pair units [u_lo, u_hi) of the flattened list (one pass-size bucket).
 template <typename T, int BC>
-__global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvConsts<T> K) {
+__global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvConsts<T> K, int phase, int64_t u_lo,
+                                                            int64_t u_hi) {
   using P = typename Packed<T>::type;
   __shared__ int64_t slot;
   __shared__ CvSmem<T, BC> sm;
   const int64_t* pf = a.prefix + PF_PAIRS * (a.nsets + 1);
-  const int64_t total = pf[a.nsets];
   for (;;) {
-    const int64_t u = claim(&a.counters[PH_PAIRS], &slot);
-    if (u >= total) break;
+    const int64_t u = u_lo + claim(&a.counters[phase], &slot);
+    if (u >= u_hi) break;
     const int si = find_set(pf, a.nsets, u);
     const SetDev& s = a.sets[si];
     const int64_t p = u - pf[si];
@@ -257,7 +262,8 @@ struct BatchImpl {
   std::vector<int> order;           // LPT order -> caller index
   int max_M = 0, max_cells = 1;
   int64_t max_n = 0;
-  int bc = 16;
+  // pass-size buckets over the LPT order: sets [bucket_begin[k], bucket_begin[k+1]) use bucket_bc[k]
+  std::vector<int> bucket_begin, bucket_bc;
   size_t ws_need = 0;
   // graph
   void* ws_bound = nullptr;
@@ -278,7 +284,7 @@ static size_t layout_batch(const BatchImpl& b, void* ws, std::vector<SetDev>* de
                            unsigned long long** counters, SetDev** dev_sets, int64_t** dev_prefix) {
   Carver c(ws, ~size_t(0));
   const int ns = int(b.sets.size());
-  unsigned long long* cnt = c.take<unsigned long long>(PH_COUNT);
+  unsigned long long* cnt = c.take<unsigned long long>(kCounters);
   SetDev* ds = c.take<SetDev>(ns);
   int64_t* dp = c.take<int64_t>(size_t(PF_COUNT) * (ns + 1));
   if (descs) descs->assign(ns, SetDev{});
@@ -345,7 +351,7 @@ static unsigned persistent_grid(K kernel, size_t dyn_lds, int64_t units) {
   return unsigned(g < 1 ? 1 : g);
 }
 
-template <typename T, int BC, int G>
+template <typename T, int G>
 static kde_status enqueue_batch(BatchImpl& b, const BatchArgs& a, const std::vector<int64_t>& prefix, hipStream_t s) {
   const int ns = int(b.sets.size());
   auto total = [&](int pf) { return prefix[size_t(pf) * (ns + 1) + ns]; };
@@ -355,14 +361,31 @@ static kde_status enqueue_batch(BatchImpl& b, const BatchArgs& a, const std::vec
   const size_t dep_lds = 2 * size_t(b.max_M) * sizeof(T);
   const size_t pack_lds = size_t(b.max_cells) * sizeof(int);
 
-  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(64), 0, s, a.counters);
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(kBlock), 0, s, a.counters);
   KDE_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_pack_kernel<T>, dim3(persistent_grid(batch_pack_kernel<T>, pack_lds, ns)), dim3(kBlock),
                      pack_lds, s, a);
   KDE_CHECK_LAUNCH();
-  hipLaunchKernelGGL((batch_pairs_kernel<T, BC>), dim3(persistent_grid(batch_pairs_kernel<T, BC>, 0, total(PF_PAIRS))),
-                     dim3(kBlock), 0, s, a, K);
-  KDE_CHECK_LAUNCH();
+  for (size_t k = 0; k < b.bucket_bc.size(); ++k) {
+    const int64_t lo = prefix[size_t(PF_PAIRS) * (ns + 1) + b.bucket_begin[k]];
+    const int64_t hi = prefix[size_t(PF_PAIRS) * (ns + 1) + b.bucket_begin[k + 1]];
+    const int ph = int(PH_COUNT + k);
+    switch (b.bucket_bc[k]) {
+      case 4:
+        hipLaunchKernelGGL((batch_pairs_kernel<T, 4>), dim3(persistent_grid(batch_pairs_kernel<T, 4>, 0, hi - lo)),
+                           dim3(kBlock), 0, s, a, K, ph, lo, hi);
+        break;
+      case 8:
+        hipLaunchKernelGGL((batch_pairs_kernel<T, 8>), dim3(persistent_grid(batch_pairs_kernel<T, 8>, 0, hi - lo)),
+                           dim3(kBlock), 0, s, a, K, ph, lo, hi);
+        break;
+      default:
+        hipLaunchKernelGGL((batch_pairs_kernel<T, 16>), dim3(persistent_grid(batch_pairs_kernel<T, 16>, 0, hi - lo)),
+                           dim3(kBlock), 0, s, a, K, ph, lo, hi);
+        break;
+    }
+    KDE_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(batch_level1_kernel<SRC_CV>,
                      dim3(persistent_grid(batch_level1_kernel<SRC_CV>, 0, total(PF_CV_L1))), dim3(kBlock), 0, s, a,
                      int(PH_CV_L1), int(PF_CV_L1));
@@ -414,23 +437,14 @@ static kde_status enqueue_batch(BatchImpl& b, const BatchArgs& a, const std::vec
   return KDE_OK;
 }
 
-template <typename T, int BC>
-static kde_status enqueue_batch_g(BatchImpl& b, const BatchArgs& a, const std::vector<int64_t>& pf, hipStream_t s) {
-  const int g = int(ceil_div(b.max_M, kBlock));
-  if (g <= 1) return enqueue_batch<T, BC, 1>(b, a, pf, s);
-  if (g <= 2) return enqueue_batch<T, BC, 2>(b, a, pf, s);
-  if (g <= 4) return enqueue_batch<T, BC, 4>(b, a, pf, s);
-  if (g <= 8) return enqueue_batch<T, BC, 8>(b, a, pf, s);
-  return enqueue_batch<T, BC, 16>(b, a, pf, s);
-}
-
 template <typename T>
 static kde_status enqueue_batch_t(BatchImpl& b, const BatchArgs& a, const std::vector<int64_t>& pf, hipStream_t s) {
-  switch (b.bc) {
-    case 4: return enqueue_batch_g<T, 4>(b, a, pf, s);
-    case 8: return enqueue_batch_g<T, 8>(b, a, pf, s);
-    default: return enqueue_batch_g<T, 16>(b, a, pf, s);
-  }
+  const int g = int(ceil_div(b.max_M, kBlock));
+  if (g <= 1) return enqueue_batch<T, 1>(b, a, pf, s);
+  if (g <= 2) return enqueue_batch<T, 2>(b, a, pf, s);
+  if (g <= 4) return enqueue_batch<T, 4>(b, a, pf, s);
+  if (g <= 8) return enqueue_batch<T, 8>(b, a, pf, s);
+  return enqueue_batch<T, 16>(b, a, pf, s);
 }
 
 // Upload descriptors and capture the graph for workspace `ws`.
@@ -515,7 +529,17 @@ kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t pr
   // largest pair-sum work first (stable, so equal sets keep caller order)
   std::stable_sort(im.order.begin(), im.order.end(),
                    [&](int a, int c) { return im.sets[a].N > im.sets[c].N; });
-  im.bc = tuned_chunk(prec, im.max_n);
+  // contiguous runs of equal tuned pass size along the LPT order (at most
+  // one per entry of the tuning table, as N decreases along the order)
+  for (int r = 0; r < nsets; ++r) {
+    const int bc = tuned_chunk(prec, im.sets[im.order[r]].N);
+    if (im.bucket_bc.empty() || im.bucket_bc.back() != bc) {
+      if (int(im.bucket_bc.size()) == kMaxBuckets) return fail(KDE_E_INTERNAL, "too many pass-size buckets");
+      im.bucket_begin.push_back(r);
+      im.bucket_bc.push_back(bc);
+    }
+  }
+  im.bucket_begin.push_back(nsets);
   im.ws_need = layout_batch(im, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   *out_h = b.release();
   return KDE_OK;

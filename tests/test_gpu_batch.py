@@ -108,3 +108,42 @@ def test_batch_rejects_bad_sets(gpu):
         gpu.Batch([x], [1.0], [1], [1.0, 2.0])
     with pytest.raises(gpu.KdeError):
         gpu.Batch([x], [1.0], [8], [2.0, 1.0])
+
+
+def test_batching_workload_full_size(gpu):
+    """The batching workload at its real size (512 sets, N log-uniform in
+    [1e3, 1e5], float form, 16 kappas): four sets spread over the cost order
+    are compared bitwise with the one-set calls and with the oracle (CV by
+    the Fourier-moment route, adaptive density at sampled nodes)."""
+    import torch
+    sets = W.batch_sets(512)
+    kappas = sets[0].problem.kappas
+    xs = [to_gpu(s.problem.x.astype(np.float32)) for s in sets]
+    announce("batching workload 512 sets f32")
+    bt = gpu.Batch(xs, [s.problem.L for s in sets], [s.problem.M for s in sets], kappas)
+    try:
+        bt.run()
+        torch.cuda.synchronize()
+        ks = host(bt.kappa_star)
+        for si in (0, 128, 256, 384):
+            p = sets[si].problem
+            x32 = p.x.astype(np.float32)
+            cv, kstar, pilot, k_i, rho = plain(gpu, xs[si], p.L, p.M, kappas)
+            assert np.array_equal(host(bt.cv[si]), cv) and ks[si] == kstar
+            assert np.array_equal(host(bt.rho[si]), rho)
+            ref_cv, S1, S2 = ocv.cv_curve_fourier(x32.astype(np.float64), p.L, kappas)
+            n = len(x32)
+            from oracle.vonmises import conv2_at_zero
+            first = (n * conv2_at_zero(kappas, p.L) + 2 * S1) / n ** 2
+            assert np.all(np.abs(cv - ref_cv) <= 1e-6 * np.maximum(np.abs(ref_cv), first))
+            b = ocv.cv_argmin(ref_cv)
+            if kappas[b] != kstar:   # tie band of the float form
+                assert abs(ref_cv[list(kappas).index(kstar)] - ref_cv[b]) <= 2e-6 * np.abs(ref_cv).max()
+            from oracle.vonmises import kernel
+            ki = k_i.astype(np.float64)
+            x64 = x32.astype(np.float64)
+            nodes = np.arange(0, p.M, max(1, p.M // 8))
+            ref_r = np.array([kernel(g * p.L / p.M - x64, ki, p.L).mean() for g in nodes])
+            assert rel_err(rho[nodes], ref_r).max() <= 1e-6
+    finally:
+        bt.close()
