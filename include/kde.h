@@ -209,8 +209,8 @@ kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, con
 
 /*
  * Batching form. Many independent particle sets, each taken through the
- * whole path -- kde_cv_scan over one shared list of B concentrations (all N
- * particles of the set), kde_deposit at the set's kappa* (the pilot),
+ * whole path -- kde_cv_scan over one shared list of B concentrations (on the
+ * set's first n_cv particles), kde_deposit at the set's kappa* (the pilot),
  * kde_adapt_widths with `alpha`, and kde_deposit with the resulting
  * per-particle concentrations -- in one hipGraph launch. The graph holds one
  * persistent kernel per phase; their workgroups pull work units (a set, a
@@ -224,6 +224,7 @@ typedef struct kde_batch_set {
   double L;           /* period, finite and > 0                                 */
   int32_t M;          /* grid nodes, 2..4096                                    */
   int32_t reserved;   /* set to 0                                               */
+  int64_t n_cv;       /* the CV scan uses the first n_cv particles (2..N); 0 = N */
   double* cv;         /* device, B doubles: the CV objective (output) or NULL   */
   double* pilot;      /* device, M doubles: pilot density at kappa* (output) or NULL */
   double* rho;        /* device, M doubles: adaptive density (output)           */
@@ -248,6 +249,128 @@ kde_status kde_batch_workspace_size(const kde_batch* b, size_t* bytes_h);
  * launch the graph. The workspace belongs to the batch between runs. */
 kde_status kde_batch_run(kde_batch* b, void* ws, size_t ws_bytes, void* stream);
 kde_status kde_batch_destroy(kde_batch* b);
+
+/*
+ * Resident PIC sessions (serving form). A session keeps one electron
+ * population in HBM (inside a caller-owned arena) and advances it by the
+ * KDE-PIC cycle of Sec. III.A with the width-update rule of Sec. II.D:
+ * deposit with kappa_i -> net charge 1 - L rho -> three-point periodic
+ * Poisson equation solved exactly by FFT (the mean mode dropped) ->
+ * centred field -> gather with kappa_i -> leapfrog push (electrons,
+ * q/m = -1; v <- v - E dt, then x <- x + v dt, wrapped) -> Anderson-Darling
+ * statistic of x/L against the uniform law, read by the host, whose
+ * p-value drives the update rule (p > 2 thr: p_th = 2 thr; else p < p_th/2:
+ * CV scan on the first n_cv particles gives h_target and p_th = p; then
+ * always h_opt <- rate h_target + (1 - rate) h_opt) -> pilot deposit at
+ * kappa* = (L / (2 pi h_opt))^2 -> adaptive widths for the next step.
+ * Units follow the Birdsall convention (plasma frequency 1). Creation runs
+ * the CV scan at t = 0 (h_opt = h_target at its optimum, p_th = 2 thr).
+ * Every step waits once for the A^2 value (one 8-byte device-to-host copy)
+ * and, when the rule fires, for the scan's argmin.
+ */
+typedef struct kde_pic_params {
+  int64_t N;             /* particles, >= 2                                       */
+  double L;              /* period, finite and > 0                                */
+  int32_t M;             /* grid nodes, a power of two in [2, 2048]               */
+  int32_t prec;          /* KDE_F64 or KDE_F32 (positions, velocities, widths)    */
+  double dt;             /* time step, > 0                                        */
+  int32_t B;             /* candidate concentrations of the CV scan, 1..64         */
+  int32_t n_cv;          /* the scan uses the first n_cv particles, 2..N          */
+  const double* kappas_h;/* host, B finite ascending concentrations > 0 (copied)  */
+  double alpha;          /* Silverman sensitivity (0.5 in the paper)              */
+  double p_threshold;    /* significance threshold of the test (0.01)             */
+  double adjust_rate;    /* relaxation rate of the width (0.05)                   */
+} kde_pic_params;
+
+typedef struct kde_session_info {
+  int64_t step;          /* steps taken                                           */
+  double p_th, h_opt, h_target;  /* update-rule state                             */
+  double kappa_star;     /* concentration of the current pilot                    */
+  double last_a2, last_p;/* last A^2 and its p-value                              */
+  int64_t fired;         /* CV scans triggered by the rule after t = 0            */
+} kde_session_info;
+
+enum kde_session_field { KDE_SESSION_X = 0, KDE_SESSION_V = 1, KDE_SESSION_KAPPA = 2, KDE_SESSION_RHO = 3,
+                         KDE_SESSION_E = 4 };
+
+typedef struct kde_session kde_session;
+
+/* Arena bytes a session with these parameters needs (256-byte aligned). */
+kde_status kde_session_bytes(const kde_pic_params* p, size_t* bytes_h);
+/* Create a session in `arena`: copies x0 and v0 (device, N values in
+ * prec; positions in [0, L)), runs the t = 0 scan and widths, and returns
+ * when that work is done. The session owns one HIP stream (default
+ * priority). The arena must stay valid until kde_session_destroy. */
+kde_status kde_session_create(const kde_pic_params* p, const void* x0, const void* v0, void* arena,
+                              size_t arena_bytes, kde_session** out_h);
+/* Advance nsteps steps (returns when they are done). */
+kde_status kde_session_step(kde_session* s, int32_t nsteps);
+kde_status kde_session_state(const kde_session* s, kde_session_info* info_h);
+/* Copy a field to `dst` (device): X, V, KAPPA (N values in prec), RHO, E (M doubles). */
+kde_status kde_session_read(kde_session* s, int32_t what, void* dst);
+/* Checkpoint to a host blob (blob_h NULL: *bytes_h receives the size) and
+ * restore into a session of the same N, M and prec; a restored session
+ * continues bitwise identically. */
+kde_status kde_session_save(kde_session* s, void* blob_h, size_t* bytes_h);
+kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes);
+kde_status kde_session_destroy(kde_session* s);
+
+/*
+ * Request server (serving form): continuous batching of KDE solves. A
+ * request is one particle set (a kde_batch_set: positions, grid, outputs)
+ * taken through the whole path like one set of a batch; the CV scan uses
+ * min(N, request n_cv, config n_cv) leading particles (0 = no limit).
+ * Requests queue in FIFO order; a scheduler thread admits them into
+ * `nslots` slots (each a HIP stream of default priority), up to max_batch
+ * requests per admission, whenever a slot is free and their workspaces fit
+ * in the free part of the caller's arena (the HBM budget). Slots run
+ * concurrently. A request that alone needs more than the whole budget is
+ * refused by kde_server_submit with KDE_E_BUDGET. Results are bitwise the
+ * same whatever the mix. Latency = completion noticed by the scheduler
+ * minus submission, host steady clock. The request's device buffers must
+ * stay valid until its ticket completes; the arena until destroy.
+ */
+typedef struct kde_server_config {
+  int32_t prec;          /* KDE_F64 or KDE_F32 for every request                  */
+  int32_t B;             /* candidate concentrations, 1..64                       */
+  const double* kappas_h;/* host, B finite ascending >= 0 (copied)                */
+  double alpha;          /* Silverman sensitivity                                 */
+  int64_t n_cv;          /* cap on the CV subsample (0 = none)                    */
+  int32_t nslots;        /* concurrent slots, 1..64                               */
+  int32_t max_batch;     /* requests per admission, 1..1024                       */
+} kde_server_config;
+
+typedef struct kde_result {
+  int32_t status;        /* KDE_OK                                                */
+  int32_t batch_size;    /* requests admitted together with this one              */
+  double latency_s, queue_s, run_s;  /* total, waiting, on the device             */
+} kde_result;
+
+typedef struct kde_server_stats_t {
+  int64_t submitted, completed, rejected, launches;
+  double mean_batch;     /* requests per admission                                */
+  double p50_s, p99_s, mean_s, max_s;  /* latency of completed requests          */
+  double wall_s;         /* first submission to last completion                   */
+  double requests_per_s, pair_evals, particles;
+} kde_server_stats_t;
+
+typedef struct kde_server kde_server;
+
+kde_status kde_server_create(const kde_server_config* cfg, void* arena, size_t budget_bytes, kde_server** out_h);
+/* Workspace bytes one request needs when admitted alone. */
+kde_status kde_server_request_bytes(const kde_server* s, const kde_batch_set* req_h, size_t* bytes_h);
+kde_status kde_server_submit(kde_server* s, const kde_batch_set* req_h, uint64_t* ticket_h);
+/* KDE_OK and the result once done, KDE_E_AGAIN while pending. */
+kde_status kde_server_poll(kde_server* s, uint64_t ticket, kde_result* res_h);
+/* Wait until every submitted request has completed. */
+kde_status kde_server_drain(kde_server* s);
+kde_status kde_server_stats(kde_server* s, kde_server_stats_t* st_h);
+kde_status kde_server_destroy(kde_server* s);
+
+/* Upper-tail p-value of an Anderson-Darling statistic under its limiting
+ * law for a fully specified distribution (Anderson and Darling 1954),
+ * computed on the host. */
+kde_status kde_ad_pvalue(double a2, double* p_h);
 
 /*
  * Tuning of the CV pair kernel: the number of concentrations it evaluates

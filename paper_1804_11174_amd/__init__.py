@@ -42,8 +42,40 @@ class kde_domain(ctypes.Structure):
 
 class kde_batch_set(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("x", ctypes.c_void_p), ("L", ctypes.c_double), ("M", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("cv", ctypes.c_void_p), ("pilot", ctypes.c_void_p),
+                ("reserved", ctypes.c_int32), ("n_cv", ctypes.c_int64), ("cv", ctypes.c_void_p), ("pilot", ctypes.c_void_p),
                 ("rho", ctypes.c_void_p), ("kappa_i", ctypes.c_void_p), ("kappa_star", ctypes.c_void_p)]
+
+
+class kde_pic_params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("L", ctypes.c_double), ("M", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("B", ctypes.c_int32), ("n_cv", ctypes.c_int32),
+                ("kappas_h", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.c_double),
+                ("p_threshold", ctypes.c_double), ("adjust_rate", ctypes.c_double)]
+
+
+class kde_session_info(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("p_th", ctypes.c_double), ("h_opt", ctypes.c_double),
+                ("h_target", ctypes.c_double), ("kappa_star", ctypes.c_double), ("last_a2", ctypes.c_double),
+                ("last_p", ctypes.c_double), ("fired", ctypes.c_int64)]
+
+
+class kde_server_config(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("B", ctypes.c_int32), ("kappas_h", ctypes.POINTER(ctypes.c_double)),
+                ("alpha", ctypes.c_double), ("n_cv", ctypes.c_int64), ("nslots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+class kde_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("latency_s", ctypes.c_double),
+                ("queue_s", ctypes.c_double), ("run_s", ctypes.c_double)]
+
+
+class kde_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("p50_s", ctypes.c_double),
+                ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("requests_per_s", ctypes.c_double), ("pair_evals", ctypes.c_double),
+                ("particles", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -72,7 +104,26 @@ _SIGNATURES = {
     "kde_batch_workspace_size": (_i32, [_vp, ctypes.POINTER(_sz)]),
     "kde_batch_run": (_i32, [_vp, _vp, _sz, _vp]),
     "kde_batch_destroy": (_i32, [_vp]),
+    "kde_session_bytes": (_i32, [ctypes.POINTER(kde_pic_params), ctypes.POINTER(_sz)]),
+    "kde_session_create": (_i32, [ctypes.POINTER(kde_pic_params), _vp, _vp, _vp, _sz, ctypes.POINTER(_vp)]),
+    "kde_session_step": (_i32, [_vp, _i32]),
+    "kde_session_state": (_i32, [_vp, ctypes.POINTER(kde_session_info)]),
+    "kde_session_read": (_i32, [_vp, _i32, _vp]),
+    "kde_session_save": (_i32, [_vp, _vp, ctypes.POINTER(_sz)]),
+    "kde_session_restore": (_i32, [_vp, _vp, _sz]),
+    "kde_session_destroy": (_i32, [_vp]),
+    "kde_ad_pvalue": (_i32, [_dbl, ctypes.POINTER(_dbl)]),
+    "kde_server_create": (_i32, [ctypes.POINTER(kde_server_config), _vp, _sz, ctypes.POINTER(_vp)]),
+    "kde_server_request_bytes": (_i32, [_vp, ctypes.POINTER(kde_batch_set), ctypes.POINTER(_sz)]),
+    "kde_server_submit": (_i32, [_vp, ctypes.POINTER(kde_batch_set), ctypes.POINTER(ctypes.c_uint64)]),
+    "kde_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(kde_result)]),
+    "kde_server_drain": (_i32, [_vp]),
+    "kde_server_stats": (_i32, [_vp, ctypes.POINTER(kde_server_stats_t)]),
+    "kde_server_destroy": (_i32, [_vp]),
 }
+
+KDE_SESSION_X, KDE_SESSION_V, KDE_SESSION_KAPPA, KDE_SESSION_RHO, KDE_SESSION_E = 0, 1, 2, 3, 4
+KDE_E_AGAIN, KDE_E_BUDGET = 4, 3
 
 TUNE_FILE = os.path.join(HERE, "tune_gfx950.json")
 
@@ -254,7 +305,7 @@ class Batch:
     ``pilot[s]`` (M), ``rho[s]`` (M), ``kappa_i[s]`` (N), ``kappa_star``
     (one per set)."""
 
-    def __init__(self, xs, Ls, Ms, kappas, alpha: float = 0.5):
+    def __init__(self, xs, Ls, Ms, kappas, alpha: float = 0.5, n_cv=None):
         import torch
         self.prec = prec_of(xs[0])
         dev = xs[0].device
@@ -270,7 +321,8 @@ class Batch:
         for s, (x, L, M) in enumerate(zip(xs, Ls, Ms)):
             if prec_of(x) != self.prec:
                 raise ValueError("all sets of a batch share one precision")
-            sets.append(kde_batch_set(int(x.shape[0]), _ptr(x), float(L), int(M), 0, _ptr(self.cv[s]),
+            ncv = 0 if n_cv is None else min(int(n_cv), int(x.shape[0]))
+            sets.append(kde_batch_set(int(x.shape[0]), _ptr(x), float(L), int(M), 0, ncv, _ptr(self.cv[s]),
                                       _ptr(self.pilot[s]), _ptr(self.rho[s]), _ptr(self.kappa_i[s]),
                                       self.kappa_star.data_ptr() + 8 * s))
         self.handle = kde_batch_plan(sets, self.prec, self.kappas, alpha)
@@ -283,6 +335,203 @@ class Batch:
     def close(self):
         if self.handle:
             kde_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- sessions
+
+def _params(N, L, M, prec, dt, kappas, n_cv, alpha=0.5, p_threshold=0.01, adjust_rate=0.05):
+    k = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
+    p = kde_pic_params(int(N), float(L), int(M), int(prec), float(dt), int(k.shape[0]), int(n_cv),
+                       k.ctypes.data_as(ctypes.POINTER(_dbl)), float(alpha), float(p_threshold), float(adjust_rate))
+    return p, k
+
+
+def kde_session_bytes(params) -> int:
+    out = _sz(0)
+    _check(require_library().kde_session_bytes(ctypes.byref(params), ctypes.byref(out)), "kde_session_bytes")
+    return int(out.value)
+
+
+def kde_session_create(params, x0, v0, arena, arena_bytes) -> int:
+    h = _vp()
+    _check(require_library().kde_session_create(ctypes.byref(params), _ptr(x0), _ptr(v0), arena, int(arena_bytes),
+                                                ctypes.byref(h)), "kde_session_create")
+    return h.value
+
+
+def kde_session_step(handle, nsteps: int = 1):
+    _check(require_library().kde_session_step(handle, int(nsteps)), "kde_session_step")
+
+
+def kde_session_state(handle) -> dict:
+    info = kde_session_info()
+    _check(require_library().kde_session_state(handle, ctypes.byref(info)), "kde_session_state")
+    return {f: getattr(info, f) for f, _ in kde_session_info._fields_}
+
+
+def kde_session_read(handle, what: int, dst):
+    _check(require_library().kde_session_read(handle, int(what), _ptr(dst)), "kde_session_read")
+
+
+def kde_session_save(handle) -> bytes:
+    lib = require_library()
+    n = _sz(0)
+    _check(lib.kde_session_save(handle, None, ctypes.byref(n)), "kde_session_save")
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib.kde_session_save(handle, buf, ctypes.byref(n)), "kde_session_save")
+    return buf.raw[:n.value]
+
+
+def kde_session_restore(handle, blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(require_library().kde_session_restore(handle, buf, len(blob)), "kde_session_restore")
+
+
+def kde_session_destroy(handle):
+    _check(require_library().kde_session_destroy(handle), "kde_session_destroy")
+
+
+def kde_ad_pvalue(a2: float) -> float:
+    out = _dbl(0.0)
+    _check(require_library().kde_ad_pvalue(float(a2), ctypes.byref(out)), "kde_ad_pvalue")
+    return float(out.value)
+
+
+class Session:
+    """A resident PIC session; x0, v0 are GPU tensors (float64 or float32)."""
+
+    def __init__(self, x0, v0, L, M, dt, kappas, n_cv, alpha=0.5, p_threshold=0.01, adjust_rate=0.05):
+        import torch
+        self.N, self.M, self.dtype, self.device = x0.shape[0], int(M), x0.dtype, x0.device
+        self.params, self._k = _params(self.N, L, M, prec_of(x0), dt, kappas, n_cv, alpha, p_threshold, adjust_rate)
+        nbytes = kde_session_bytes(self.params)
+        self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=x0.device)
+        base = self._arena.data_ptr()
+        self.handle = kde_session_create(self.params, x0, v0, (base + 255) // 256 * 256, nbytes)
+
+    def step(self, n=1):
+        kde_session_step(self.handle, n)
+
+    def state(self):
+        return kde_session_state(self.handle)
+
+    def read(self, what):
+        import torch
+        if what in (KDE_SESSION_RHO, KDE_SESSION_E):
+            out = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        else:
+            out = torch.empty(self.N, dtype=self.dtype, device=self.device)
+        kde_session_read(self.handle, what, out)
+        return out
+
+    def save(self):
+        return kde_session_save(self.handle)
+
+    def restore(self, blob):
+        kde_session_restore(self.handle, blob)
+
+    def close(self):
+        if self.handle:
+            kde_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- server
+
+def kde_server_create(cfg, arena, budget) -> int:
+    h = _vp()
+    _check(require_library().kde_server_create(ctypes.byref(cfg), arena, int(budget), ctypes.byref(h)),
+           "kde_server_create")
+    return h.value
+
+
+def kde_server_request_bytes(handle, req) -> int:
+    out = _sz(0)
+    _check(require_library().kde_server_request_bytes(handle, ctypes.byref(req), ctypes.byref(out)),
+           "kde_server_request_bytes")
+    return int(out.value)
+
+
+def kde_server_submit(handle, req) -> int:
+    t = ctypes.c_uint64(0)
+    _check(require_library().kde_server_submit(handle, ctypes.byref(req), ctypes.byref(t)), "kde_server_submit")
+    return int(t.value)
+
+
+def kde_server_poll(handle, ticket: int):
+    """The result as a dict once done, else None."""
+    r = kde_result()
+    st = require_library().kde_server_poll(handle, ctypes.c_uint64(ticket), ctypes.byref(r))
+    if st == KDE_E_AGAIN:
+        return None
+    _check(st, "kde_server_poll")
+    return {f: getattr(r, f) for f, _ in kde_result._fields_}
+
+
+def kde_server_drain(handle):
+    _check(require_library().kde_server_drain(handle), "kde_server_drain")
+
+
+def kde_server_stats(handle) -> dict:
+    st = kde_server_stats_t()
+    _check(require_library().kde_server_stats(handle, ctypes.byref(st)), "kde_server_stats")
+    return {f: getattr(st, f) for f, _ in kde_server_stats_t._fields_}
+
+
+def kde_server_destroy(handle):
+    _check(require_library().kde_server_destroy(handle), "kde_server_destroy")
+
+
+class Server:
+    """Continuous-batching server of KDE solves over a torch-owned arena."""
+
+    def __init__(self, kappas, prec=KDE_F32, budget_bytes=256 << 20, nslots=4, max_batch=16, n_cv=65536,
+                 alpha=0.5, device="cuda"):
+        import torch
+        self._k = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
+        self.cfg = kde_server_config(int(prec), int(self._k.shape[0]), self._k.ctypes.data_as(ctypes.POINTER(_dbl)),
+                                     float(alpha), int(n_cv), int(nslots), int(max_batch))
+        self._arena = torch.empty(int(budget_bytes) + 256, dtype=torch.uint8, device=device)
+        base = self._arena.data_ptr()
+        self.handle = kde_server_create(self.cfg, (base + 255) // 256 * 256, int(budget_bytes))
+        self.B = int(self._k.shape[0])
+
+    @staticmethod
+    def request(x, L, M, outputs, n_cv=0):
+        """A kde_batch_set for positions x with output tensors
+        (cv[B], pilot[M], rho[M], kappa_i[N], kappa_star[1])."""
+        cv, pilot, rho, k_i, ks = outputs
+        return kde_batch_set(int(x.shape[0]), _ptr(x), float(L), int(M), 0, int(n_cv), _ptr(cv), _ptr(pilot),
+                             _ptr(rho), _ptr(k_i), _ptr(ks))
+
+    def submit(self, req) -> int:
+        return kde_server_submit(self.handle, req)
+
+    def poll(self, ticket):
+        return kde_server_poll(self.handle, ticket)
+
+    def drain(self):
+        kde_server_drain(self.handle)
+
+    def stats(self):
+        return kde_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            kde_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

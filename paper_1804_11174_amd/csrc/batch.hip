@@ -20,6 +20,8 @@
 #include "dev_density.hpp"
 #include "dev_layout.hpp"
 #include "dev_reduce.hpp"
+#include "batch_internal.hpp"
+#include <cstring>
 
 namespace kde {
 
@@ -36,6 +38,7 @@ constexpr int kCounters = PH_COUNT + kMaxBuckets;
 // Per-set description as the kernels see it (lives in the workspace).
 struct SetDev {
   int64_t n;
+  int64_t n_cv;  // particles the CV scan uses (a prefix)
   const void* x;
   double L;
   int M, cells, chunk, pad;
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) batch_pack_kernel(BatchArgs a) {
     const int64_t u = claim(&a.counters[PH_PACK], &slot);
     if (u >= a.nsets) break;
     const SetDev& s = a.sets[u];
-    sort_set_one_block<T, P>(static_cast<const T*>(s.x), s.n, s.L, s.cells, base, tot, static_cast<P*>(s.packed));
+    sort_set_one_block<T, P>(static_cast<const T*>(s.x), s.n_cv, s.L, s.cells, base, tot, static_cast<P*>(s.packed));
     __syncthreads();
   }
 }
@@ -122,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvCons
     const int64_t p = u - pf[si];
     int I, J;
     tri_decode(p, I, J);
-    cv_tile_pair<T, BC>(static_cast<const P*>(s.packed), s.n, I, J, K, s.partials + p * 2 * K.B, sm);
+    cv_tile_pair<T, BC>(static_cast<const P*>(s.packed), s.n_cv, I, J, K, s.partials + p * 2 * K.B, sm);
   }
 }
 
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) batch_cv_finalize_kernel(BatchArgs a, 
     const SetDev& s = a.sets[u];
     for (int c = threadIdx.x; c < 2 * a.B; c += kBlock) raw[c] = colsum_level2(s.cv_l1, s.g_cv, 2 * a.B, c, 1.0);
     __syncthreads();
-    cv_finalize_block(raw, a.B, double(s.n), s.L, kap, s.cv, nullptr, nullptr, v, &best);
+    cv_finalize_block(raw, a.B, double(s.n_cv), s.L, kap, s.cv, nullptr, nullptr, v, &best);
     if (threadIdx.x == 0) {
       *s.kstar = kap.k[best];
       if (s.kstar_user) *s.kstar_user = kap.k[best];
@@ -253,34 +256,9 @@ __global__ void __launch_bounds__(kBlock) batch_adapt_apply_kernel(BatchArgs a) 
 
 // ------------------------------------------------------------------ host
 
-struct BatchImpl {
-  int prec = KDE_F64;
-  int B = 0;
-  double alpha = 0.5;
-  std::vector<double> kappas;
-  std::vector<kde_batch_set> sets;  // caller order
-  std::vector<int> order;           // LPT order -> caller index
-  int max_M = 0, max_cells = 1;
-  int64_t max_n = 0;
-  // pass-size buckets over the LPT order: sets [bucket_begin[k], bucket_begin[k+1]) use bucket_bc[k]
-  std::vector<int> bucket_begin, bucket_bc;
-  size_t ws_need = 0;
-  // graph
-  void* ws_bound = nullptr;
-  size_t ws_bytes_bound = 0;
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~BatchImpl() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap) (void)hipStreamDestroy(cap);
-  }
-};
-
 // Lay out the workspace; with ws == nullptr only sizes it. Fills host
 // images of the descriptors and prefix arrays.
-static size_t layout_batch(const BatchImpl& b, void* ws, std::vector<SetDev>* descs, std::vector<int64_t>* prefix,
+static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* descs, std::vector<int64_t>* prefix,
                            unsigned long long** counters, SetDev** dev_sets, int64_t** dev_prefix) {
   Carver c(ws, ~size_t(0));
   const int ns = int(b.sets.size());
@@ -295,21 +273,22 @@ static size_t layout_batch(const BatchImpl& b, void* ws, std::vector<SetDev>* de
     const kde_batch_set& in = b.sets[b.order[r]];
     SetDev d{};
     d.n = in.N;
+    d.n_cv = in.n_cv ? in.n_cv : in.N;
     d.x = in.x;
     d.L = in.L;
     d.M = in.M;
-    const SortPlan sp = make_sort_plan(in.N);
+    const SortPlan sp = make_sort_plan(d.n_cv);
     d.cells = sp.cells;
     d.chunk = deposit_chunk(in.N);
-    const int64_t ntiles = ceil_div(in.N, kCvTile);
+    const int64_t ntiles = ceil_div(d.n_cv, kCvTile);
     d.units = ntiles * (ntiles + 1) / 2;
     d.g_cv = ceil_div(d.units, kSumRows);
     d.chunks = ceil_div(in.N, d.chunk);
     d.g_dep = ceil_div(d.chunks, kSumRows);
     d.blocks = ceil_div(in.N, kBlock);
     d.g_ad = ceil_div(d.blocks, kSumRows);
-    d.packed = b.prec == KDE_F64 ? static_cast<void*>(c.take<double>(2 * size_t(in.N)))
-                                 : static_cast<void*>(c.take<uint32_t>(size_t(in.N)));
+    d.packed = b.prec == KDE_F64 ? static_cast<void*>(c.take<double>(2 * size_t(d.n_cv)))
+                                 : static_cast<void*>(c.take<uint32_t>(size_t(d.n_cv)));
     d.partials = c.take<double>(size_t(d.units) * 2 * b.B);
     d.cv_l1 = c.take<double>(size_t(d.g_cv) * 2 * b.B);
     d.dep_part = c.take<double>(size_t(d.chunks) * in.M);
@@ -352,7 +331,7 @@ static unsigned persistent_grid(K kernel, size_t dyn_lds, int64_t units) {
 }
 
 template <typename T, int G>
-static kde_status enqueue_batch(BatchImpl& b, const BatchArgs& a, const std::vector<int64_t>& prefix, hipStream_t s) {
+static kde_status enqueue_batch(const BatchPlan& b, const BatchArgs& a, const std::vector<int64_t>& prefix, hipStream_t s) {
   const int ns = int(b.sets.size());
   auto total = [&](int pf) { return prefix[size_t(pf) * (ns + 1) + ns]; };
   const CvConsts<T> K = make_consts<T>(b.kappas.data(), b.B);
@@ -438,7 +417,7 @@ static kde_status enqueue_batch(BatchImpl& b, const BatchArgs& a, const std::vec
 }
 
 template <typename T>
-static kde_status enqueue_batch_t(BatchImpl& b, const BatchArgs& a, const std::vector<int64_t>& pf, hipStream_t s) {
+static kde_status enqueue_batch_t(const BatchPlan& b, const BatchArgs& a, const std::vector<int64_t>& pf, hipStream_t s) {
   const int g = int(ceil_div(b.max_M, kBlock));
   if (g <= 1) return enqueue_batch<T, 1>(b, a, pf, s);
   if (g <= 2) return enqueue_batch<T, 2>(b, a, pf, s);
@@ -447,58 +426,18 @@ static kde_status enqueue_batch_t(BatchImpl& b, const BatchArgs& a, const std::v
   return enqueue_batch<T, 16>(b, a, pf, s);
 }
 
-// Upload descriptors and capture the graph for workspace `ws`.
-static kde_status build_graph(BatchImpl& b, void* ws, size_t ws_bytes) {
-  std::vector<SetDev> descs;
-  std::vector<int64_t> prefix;
+// Descriptors of the plan written into `ws` (host images).
+static void batch_images(const BatchPlan& b, void* ws, std::vector<SetDev>& descs, std::vector<int64_t>& prefix,
+                         BatchArgs& a) {
   unsigned long long* counters = nullptr;
   SetDev* dsets = nullptr;
   int64_t* dpref = nullptr;
   layout_batch(b, ws, &descs, &prefix, &counters, &dsets, &dpref);
-  KDE_TRY_HIP(hipMemcpy(dsets, descs.data(), descs.size() * sizeof(SetDev), hipMemcpyHostToDevice));
-  KDE_TRY_HIP(hipMemcpy(dpref, prefix.data(), prefix.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-  if (b.exec) {
-    (void)hipGraphExecDestroy(b.exec);
-    b.exec = nullptr;
-  }
-  if (b.graph) {
-    (void)hipGraphDestroy(b.graph);
-    b.graph = nullptr;
-  }
-  if (!b.cap) KDE_TRY_HIP(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
-  BatchArgs a{dsets, dpref, counters, int(b.sets.size()), b.B, b.alpha};
-  KDE_TRY_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
-  kde_status st = b.prec == KDE_F64 ? enqueue_batch_t<double>(b, a, prefix, b.cap)
-                                    : enqueue_batch_t<float>(b, a, prefix, b.cap);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(b.cap, &g);
-  if (st != KDE_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return st;
-  }
-  if (e != hipSuccess) return fail(KDE_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-  b.graph = g;
-  KDE_TRY_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-  b.ws_bound = ws;
-  b.ws_bytes_bound = ws_bytes;
-  return KDE_OK;
+  a = BatchArgs{dsets, dpref, counters, int(b.sets.size()), b.B, b.alpha};
 }
 
-}  // namespace kde
-
-using namespace kde;
-
-struct kde_batch {
-  BatchImpl impl;
-};
-
-extern "C" {
-
-kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t prec, int32_t B,
-                          const double* kappas_h, double alpha, kde_batch** out_h) {
-  clear_error();
-  if (!out_h) return fail(KDE_E_INVALID_ARG, "out_h is NULL");
-  *out_h = nullptr;
+kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int B, const double* kappas_h,
+                           double alpha, BatchPlan& im) {
   if (!sets_h || nsets < 1) return fail(KDE_E_INVALID_ARG, "need at least one set");
   if (prec != KDE_F64 && prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
   if (B < 1 || B > KDE_MAX_KAPPAS || !kappas_h) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d]", KDE_MAX_KAPPAS);
@@ -507,17 +446,18 @@ kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t pr
     if (k > 0 && !(kappas_h[k] > kappas_h[k - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending");
   }
   if (!std::isfinite(alpha) || alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0");
-  std::unique_ptr<kde_batch> b(new kde_batch());
-  BatchImpl& im = b->impl;
+  im = BatchPlan{};
   for (int s = 0; s < nsets; ++s) {
     const kde_batch_set& in = sets_h[s];
     if (in.N < 2 || in.N > kMaxN) return fail(KDE_E_INVALID_ARG, "set %d: N must lie in [2, %lld]", s, (long long)kMaxN);
     if (!in.x || !in.rho) return fail(KDE_E_INVALID_ARG, "set %d: x and rho must not be NULL", s);
+    if (in.n_cv != 0 && (in.n_cv < 2 || in.n_cv > in.N))
+      return fail(KDE_E_INVALID_ARG, "set %d: n_cv must be 0 or lie in [2, N]", s);
     if (!std::isfinite(in.L) || !(in.L > 0.0)) return fail(KDE_E_INVALID_ARG, "set %d: L must be finite and > 0", s);
     if (in.M < 2 || in.M > kMaxM) return fail(KDE_E_INVALID_ARG, "set %d: M must lie in [2, %d]", s, kMaxM);
     im.max_M = std::max(im.max_M, int(in.M));
     im.max_n = std::max(im.max_n, in.N);
-    im.max_cells = std::max(im.max_cells, make_sort_plan(in.N).cells);
+    im.max_cells = std::max(im.max_cells, make_sort_plan(in.n_cv ? in.n_cv : in.N).cells);
   }
   im.prec = prec;
   im.B = B;
@@ -527,12 +467,12 @@ kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t pr
   im.order.resize(nsets);
   std::iota(im.order.begin(), im.order.end(), 0);
   // largest pair-sum work first (stable, so equal sets keep caller order)
-  std::stable_sort(im.order.begin(), im.order.end(),
-                   [&](int a, int c) { return im.sets[a].N > im.sets[c].N; });
+  auto ncv = [&](int i) { return im.sets[i].n_cv ? im.sets[i].n_cv : im.sets[i].N; };
+  std::stable_sort(im.order.begin(), im.order.end(), [&](int a, int c) { return ncv(a) > ncv(c); });
   // contiguous runs of equal tuned pass size along the LPT order (at most
   // one per entry of the tuning table, as N decreases along the order)
   for (int r = 0; r < nsets; ++r) {
-    const int bc = tuned_chunk(prec, im.sets[im.order[r]].N);
+    const int bc = tuned_chunk(prec, ncv(im.order[r]));
     if (im.bucket_bc.empty() || im.bucket_bc.back() != bc) {
       if (int(im.bucket_bc.size()) == kMaxBuckets) return fail(KDE_E_INTERNAL, "too many pass-size buckets");
       im.bucket_begin.push_back(r);
@@ -541,6 +481,74 @@ kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t pr
   }
   im.bucket_begin.push_back(nsets);
   im.ws_need = layout_batch(im, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return KDE_OK;
+}
+
+size_t batch_staging_bytes(const BatchPlan& b) {
+  const size_t ns = b.sets.size();
+  return ns * sizeof(SetDev) + size_t(PF_COUNT) * (ns + 1) * sizeof(int64_t) + 64;
+}
+
+kde_status batch_plan_enqueue(const BatchPlan& b, void* ws, hipStream_t s, void* staging_h) {
+  std::vector<SetDev> descs;
+  std::vector<int64_t> prefix;
+  BatchArgs a{};
+  batch_images(b, ws, descs, prefix, a);
+  const size_t db = descs.size() * sizeof(SetDev), pb = prefix.size() * sizeof(int64_t);
+  char* st = static_cast<char*>(staging_h);
+  memcpy(st, descs.data(), db);
+  memcpy(st + db, prefix.data(), pb);
+  KDE_TRY_HIP(hipMemcpyAsync(const_cast<SetDev*>(a.sets), st, db, hipMemcpyHostToDevice, s));
+  KDE_TRY_HIP(hipMemcpyAsync(const_cast<int64_t*>(a.prefix), st + db, pb, hipMemcpyHostToDevice, s));
+  return b.prec == KDE_F64 ? enqueue_batch_t<double>(b, a, prefix, s) : enqueue_batch_t<float>(b, a, prefix, s);
+}
+
+// Upload descriptors and capture the graph for workspace `ws`.
+static kde_status build_graph(kde_batch_graph& g, const BatchPlan& b, void* ws, size_t ws_bytes) {
+  std::vector<SetDev> descs;
+  std::vector<int64_t> prefix;
+  BatchArgs a{};
+  batch_images(b, ws, descs, prefix, a);
+  KDE_TRY_HIP(hipMemcpy(const_cast<SetDev*>(a.sets), descs.data(), descs.size() * sizeof(SetDev), hipMemcpyHostToDevice));
+  KDE_TRY_HIP(hipMemcpy(const_cast<int64_t*>(a.prefix), prefix.data(), prefix.size() * sizeof(int64_t),
+                        hipMemcpyHostToDevice));
+  g.reset();
+  KDE_TRY_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+  KDE_TRY_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+  kde_status st = b.prec == KDE_F64 ? enqueue_batch_t<double>(b, a, prefix, g.cap)
+                                    : enqueue_batch_t<float>(b, a, prefix, g.cap);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(g.cap, &graph);
+  if (st != KDE_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(KDE_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  g.graph = graph;
+  KDE_TRY_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  g.ws = ws;
+  g.ws_bytes = ws_bytes;
+  return KDE_OK;
+}
+
+}  // namespace kde
+
+using namespace kde;
+
+struct kde_batch {
+  BatchPlan plan;
+  kde_batch_graph graph;
+};
+
+extern "C" {
+
+kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t prec, int32_t B,
+                          const double* kappas_h, double alpha, kde_batch** out_h) {
+  clear_error();
+  if (!out_h) return fail(KDE_E_INVALID_ARG, "out_h is NULL");
+  *out_h = nullptr;
+  std::unique_ptr<kde_batch> b(new kde_batch());
+  KDE_RETURN_IF(batch_plan_make(sets_h, nsets, prec, B, kappas_h, alpha, b->plan));
   *out_h = b.release();
   return KDE_OK;
 }
@@ -548,18 +556,19 @@ kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t pr
 kde_status kde_batch_workspace_size(const kde_batch* b, size_t* bytes_h) {
   clear_error();
   if (!b || !bytes_h) return fail(KDE_E_INVALID_ARG, "batch and bytes_h must not be NULL");
-  *bytes_h = b->impl.ws_need;
+  *bytes_h = b->plan.ws_need;
   return KDE_OK;
 }
 
 kde_status kde_batch_run(kde_batch* b, void* ws, size_t ws_bytes, void* stream) {
   clear_error();
   if (!b) return fail(KDE_E_NOT_FOUND, "batch is NULL");
-  BatchImpl& im = b->impl;
+  const BatchPlan& im = b->plan;
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, im.ws_need));
   KDE_RETURN_IF(check_lds(2 * size_t(im.max_M) * elem_size(im.prec) + kDepMaxChunk * 32 + kBlock * 8));
-  if (!im.exec || im.ws_bound != ws || im.ws_bytes_bound != ws_bytes) KDE_RETURN_IF(build_graph(im, ws, ws_bytes));
-  KDE_TRY_HIP(hipGraphLaunch(im.exec, static_cast<hipStream_t>(stream)));
+  if (!b->graph.exec || b->graph.ws != ws || b->graph.ws_bytes != ws_bytes)
+    KDE_RETURN_IF(build_graph(b->graph, im, ws, ws_bytes));
+  KDE_TRY_HIP(hipGraphLaunch(b->graph.exec, static_cast<hipStream_t>(stream)));
   return KDE_OK;
 }
 

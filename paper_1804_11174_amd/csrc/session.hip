@@ -1,0 +1,390 @@
+// Resident PIC sessions: the particle set stays in HBM across steps and
+// every step runs the KDE-PIC cycle of Sec. III.A with the width-update
+// rule of Sec. II.D:
+//
+//   1. deposit with the per-particle concentrations kappa_i;
+//   2. Poisson solve and centred field on the grid (pic.hip);
+//   3. gather of the field with kappa_i; 4. leapfrog push;
+//   5. Anderson-Darling statistic of the new positions, read by the host,
+//      which turns it into a p-value and applies the update rule:
+//        p > 2 thr:          p_th = 2 thr;
+//        p < p_th / 2:       CV scan (first n_cv particles) -> h_target, p_th = p;
+//        always:             h_opt <- rate h_target + (1 - rate) h_opt;
+//      then kappa* = (L / (2 pi h_opt))^2, a pilot deposit at kappa* and the
+//      adaptive widths give the next step's kappa_i.
+//
+// The p-value is the upper tail of the limiting law of A^2 for a fully
+// specified distribution, from Anderson and Darling's (1954) series; its
+// integrals are done by the trapezoid rule after scaling out the Gaussian
+// factor (the integrand is even and analytic, so the rule converges
+// geometrically).
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "kde_internal.hpp"
+
+namespace kde {
+
+// implemented elsewhere in the library
+size_t cv_workspace_bytes(int64_t n, int B, int prec);
+size_t deposit_workspace_bytes(int64_t n, int M);
+size_t adapt_workspace_bytes(int64_t n);
+size_t ad_workspace_bytes(int64_t n, int prec);
+kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
+                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s);
+kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
+                   void* ws, size_t ws_bytes, hipStream_t s);
+kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
+                  const double* field, void* out, hipStream_t s);
+kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
+                        double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
+                        hipStream_t s);
+kde_status launch_poisson_field(const double* rho, int M, double L, double* E, double* phi, hipStream_t s);
+template <typename T>
+kde_status launch_push(T* x, T* v, const T* E_i, int64_t n, double dt, double L, hipStream_t s);
+template <typename T>
+kde_status launch_ad_statistic(const T* x, int64_t n, double L, double* a2, void* ws, size_t ws_bytes, hipStream_t s);
+size_t poisson_max_m();
+
+// --------------------------------------------------------- AD p-value
+
+static double ad_series_term(int j, double z) {
+  // binom(-1/2, j) (4j+1) exp(-(4j+1)^2 pi^2 / (8z)) * I_j, with
+  // I_j = int_0^inf exp(z / (8 (w^2 + 1)) - a w^2) dw, a = (4j+1)^2 pi^2 / (8z)
+  double binom = 1.0;
+  for (int k = 0; k < j; ++k) binom *= (-0.5 - k) / double(k + 1);
+  const double c = double(4 * j + 1);
+  const double a = c * c * M_PI * M_PI / (8.0 * z);
+  // w = t / sqrt(a): I_j = a^(-1/2) int_0^inf exp(z / (8 (t^2/a + 1)) - t^2) dt
+  const double h = 0.004;
+  double s = 0.5 * std::exp(z / 8.0);
+  for (int k = 1;; ++k) {
+    const double t = k * h;
+    const double f = std::exp(z / (8.0 * (t * t / a + 1.0)) - t * t);
+    s += f;
+    if (t > 9.0) break;
+  }
+  return binom * c * std::exp(-a) * s * h / std::sqrt(a);
+}
+
+double ad_upper_tail(double a2) {
+  if (!(a2 > 0.0)) return 1.0;
+  if (a2 > 200.0) return 0.0;
+  double total = 0.0;
+  for (int j = 0; j < 60; ++j) {
+    const double t = ad_series_term(j, a2);
+    total += t;
+    if (j > 3 && std::fabs(t) < 1e-18) break;
+  }
+  double cdf = std::sqrt(2.0 * M_PI) / a2 * total;
+  cdf = cdf < 0.0 ? 0.0 : (cdf > 1.0 ? 1.0 : cdf);
+  return 1.0 - cdf;
+}
+
+// ------------------------------------------------------------- session
+
+struct SessionState {
+  int64_t step = 0;
+  double p_th = 0.02, h_opt = 0.0, h_target = 0.0, kappa_star = 0.0;
+  double last_a2 = 0.0, last_p = 1.0;
+  int64_t fired = 0;
+};
+
+static double kappa_of_width(double h, double L) {
+  const double r = L / (2.0 * M_PI * h);
+  return r * r;
+}
+static double width_of_kappa(double k, double L) { return (L / (2.0 * M_PI)) / std::sqrt(k); }
+
+}  // namespace kde
+
+using namespace kde;
+
+struct kde_session {
+  kde_pic_params prm{};
+  std::vector<double> kappas;
+  kde_domain dom{};
+  hipStream_t s = nullptr;
+  // device buffers in the arena
+  void *x = nullptr, *v = nullptr, *kap = nullptr, *Ei = nullptr;
+  double *rho = nullptr, *E = nullptr, *pilot = nullptr, *cv = nullptr, *a2 = nullptr;
+  int32_t* argmin = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // pinned host mailbox: [a2, argmin]
+  double* mail = nullptr;
+  SessionState st;
+  ~kde_session() {
+    if (mail) (void)hipHostFree(mail);
+  }
+};
+
+namespace kde {
+
+static size_t session_ws_bytes(const kde_pic_params& p) {
+  size_t w = cv_workspace_bytes(p.n_cv, p.B, p.prec);
+  w = std::max(w, deposit_workspace_bytes(p.N, p.M));
+  w = std::max(w, adapt_workspace_bytes(p.N));
+  w = std::max(w, ad_workspace_bytes(p.N, p.prec));
+  return w;
+}
+
+static size_t carve_session(Carver& c, const kde_pic_params& p, kde_session* s) {
+  const size_t es = elem_size(p.prec);
+  void* x = c.take<char>(size_t(p.N) * es);
+  void* v = c.take<char>(size_t(p.N) * es);
+  void* kap = c.take<char>(size_t(p.N) * es);
+  void* Ei = c.take<char>(size_t(p.N) * es);
+  double* rho = c.take<double>(p.M);
+  double* E = c.take<double>(p.M);
+  double* pilot = c.take<double>(p.M);
+  double* cv = c.take<double>(p.B);
+  double* a2 = c.take<double>(1);
+  int32_t* am = c.take<int32_t>(1);
+  const size_t wsb = session_ws_bytes(p);
+  void* ws = c.take<char>(wsb);
+  if (s) {
+    s->x = x; s->v = v; s->kap = kap; s->Ei = Ei;
+    s->rho = rho; s->E = E; s->pilot = pilot; s->cv = cv; s->a2 = a2; s->argmin = am;
+    s->ws = ws; s->ws_bytes = wsb;
+  }
+  return c.used;
+}
+
+static kde_status check_params(const kde_pic_params* p) {
+  if (!p) return fail(KDE_E_INVALID_ARG, "params are NULL");
+  if (p->N < 2 || p->N > kMaxN) return fail(KDE_E_INVALID_ARG, "N must lie in [2, %lld]", (long long)kMaxN);
+  if (!std::isfinite(p->L) || !(p->L > 0.0)) return fail(KDE_E_INVALID_ARG, "L must be finite and > 0");
+  if (p->M < 2 || size_t(p->M) > poisson_max_m() || (p->M & (p->M - 1)))
+    return fail(KDE_E_INVALID_ARG, "M must be a power of two in [2, %zu]", poisson_max_m());
+  if (p->prec != KDE_F64 && p->prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
+  if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return fail(KDE_E_INVALID_ARG, "dt must be finite and > 0");
+  if (p->B < 1 || p->B > KDE_MAX_KAPPAS || !p->kappas_h) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d]", KDE_MAX_KAPPAS);
+  for (int b = 0; b < p->B; ++b) {
+    if (!std::isfinite(p->kappas_h[b]) || !(p->kappas_h[b] > 0.0)) return fail(KDE_E_INVALID_ARG, "kappas must be finite and > 0");
+    if (b > 0 && !(p->kappas_h[b] > p->kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending");
+  }
+  if (p->n_cv < 2 || p->n_cv > p->N) return fail(KDE_E_INVALID_ARG, "n_cv must lie in [2, N]");
+  if (!std::isfinite(p->alpha) || p->alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0");
+  if (!(p->p_threshold > 0.0 && p->p_threshold < 0.5)) return fail(KDE_E_INVALID_ARG, "p_threshold must lie in (0, 0.5)");
+  if (!(p->adjust_rate > 0.0 && p->adjust_rate <= 1.0)) return fail(KDE_E_INVALID_ARG, "adjust_rate must lie in (0, 1]");
+  return KDE_OK;
+}
+
+// CV scan on the first n_cv particles; returns the chosen concentration.
+static kde_status session_cv(kde_session* s, double* kstar) {
+  kde_domain d = s->dom;
+  KDE_RETURN_IF(cv_scan(&d, s->prm.n_cv, s->x, s->prm.B, s->kappas.data(), s->cv, nullptr, s->argmin, s->ws,
+                        s->ws_bytes, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(s->mail + 1, s->argmin, sizeof(int32_t), hipMemcpyDeviceToHost, s->s));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  int32_t b = 0;
+  memcpy(&b, s->mail + 1, sizeof(int32_t));
+  if (b < 0 || b >= s->prm.B) return fail(KDE_E_INTERNAL, "argmin out of range");
+  *kstar = s->kappas[b];
+  return KDE_OK;
+}
+
+// Pilot deposit at kappa* and the adaptive widths for the next step.
+static kde_status session_widths(kde_session* s, double kstar) {
+  KDE_RETURN_IF(deposit(&s->dom, s->prm.N, s->x, nullptr, kstar, s->pilot, s->ws, s->ws_bytes, s->s));
+  KDE_RETURN_IF(adapt_widths(&s->dom, s->prm.N, s->x, s->pilot, kstar, s->prm.alpha, s->kap, nullptr, nullptr, s->ws,
+                             s->ws_bytes, s->s));
+  return KDE_OK;
+}
+
+static kde_status session_step_once(kde_session* s) {
+  const kde_pic_params& p = s->prm;
+  KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s));
+  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, nullptr, s->s));
+  KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s));
+  if (p.prec == KDE_F64) {
+    KDE_RETURN_IF(launch_push<double>(static_cast<double*>(s->x), static_cast<double*>(s->v),
+                                      static_cast<const double*>(s->Ei), p.N, p.dt, p.L, s->s));
+    KDE_RETURN_IF(launch_ad_statistic<double>(static_cast<const double*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
+  } else {
+    KDE_RETURN_IF(launch_push<float>(static_cast<float*>(s->x), static_cast<float*>(s->v),
+                                     static_cast<const float*>(s->Ei), p.N, p.dt, p.L, s->s));
+    KDE_RETURN_IF(launch_ad_statistic<float>(static_cast<const float*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
+  }
+  KDE_TRY_HIP(hipMemcpyAsync(s->mail, s->a2, sizeof(double), hipMemcpyDeviceToHost, s->s));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  SessionState& st = s->st;
+  st.last_a2 = s->mail[0];
+  st.last_p = ad_upper_tail(st.last_a2);
+  const double thr = p.p_threshold;
+  if (st.last_p > 2.0 * thr) {
+    st.p_th = 2.0 * thr;
+  } else if (st.last_p < 0.5 * st.p_th) {
+    double k = 0.0;
+    KDE_RETURN_IF(session_cv(s, &k));
+    st.h_target = width_of_kappa(k, p.L);
+    st.p_th = st.last_p;
+    st.fired += 1;
+  }
+  st.h_opt = p.adjust_rate * st.h_target + (1.0 - p.adjust_rate) * st.h_opt;
+  st.kappa_star = kappa_of_width(st.h_opt, p.L);
+  KDE_RETURN_IF(session_widths(s, st.kappa_star));
+  st.step += 1;
+  return KDE_OK;
+}
+
+}  // namespace kde
+
+extern "C" {
+
+kde_status kde_ad_pvalue(double a2, double* p_h) {
+  clear_error();
+  if (!p_h) return fail(KDE_E_INVALID_ARG, "p_h is NULL");
+  *p_h = ad_upper_tail(a2);
+  return KDE_OK;
+}
+
+kde_status kde_session_bytes(const kde_pic_params* p, size_t* bytes_h) {
+  clear_error();
+  KDE_RETURN_IF(check_params(p));
+  if (!bytes_h) return fail(KDE_E_INVALID_ARG, "bytes_h is NULL");
+  Carver c(nullptr, 0);
+  *bytes_h = carve_session(c, *p, nullptr);
+  return KDE_OK;
+}
+
+kde_status kde_session_create(const kde_pic_params* p, const void* x0, const void* v0, void* arena, size_t arena_bytes,
+                              kde_session** out_h) {
+  clear_error();
+  if (!out_h) return fail(KDE_E_INVALID_ARG, "out_h is NULL");
+  *out_h = nullptr;
+  KDE_RETURN_IF(check_params(p));
+  if (!x0 || !v0) return fail(KDE_E_INVALID_ARG, "x0 and v0 must not be NULL");
+  std::unique_ptr<kde_session> s(new kde_session());
+  s->prm = *p;
+  s->kappas.assign(p->kappas_h, p->kappas_h + p->B);
+  s->prm.kappas_h = nullptr;
+  s->dom = kde_domain{p->L, p->M, p->prec};
+  Carver c(arena, arena_bytes);
+  carve_session(c, *p, s.get());
+  if (!arena || reinterpret_cast<uintptr_t>(arena) % 256 != 0) return fail(KDE_E_WORKSPACE, "arena must be 256-byte aligned");
+  if (!c.fits()) return fail(KDE_E_WORKSPACE, "arena too small: %zu < %zu bytes", arena_bytes, c.used);
+  KDE_TRY_HIP(hipStreamCreateWithFlags(&s->s, hipStreamNonBlocking));
+  KDE_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->mail), 64, hipHostMallocDefault));
+  const size_t es = elem_size(p->prec);
+  KDE_TRY_HIP(hipMemcpyAsync(s->x, x0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(s->v, v0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
+  // initial CV at t = 0: both widths at its optimum, p_th = 2 thr
+  double k0 = 0.0;
+  KDE_RETURN_IF(session_cv(s.get(), &k0));
+  s->st.p_th = 2.0 * p->p_threshold;
+  s->st.h_opt = s->st.h_target = width_of_kappa(k0, p->L);
+  s->st.kappa_star = k0;
+  KDE_RETURN_IF(session_widths(s.get(), k0));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  *out_h = s.release();
+  return KDE_OK;
+}
+
+kde_status kde_session_step(kde_session* s, int32_t nsteps) {
+  clear_error();
+  if (!s) return fail(KDE_E_NOT_FOUND, "session is NULL");
+  if (nsteps < 0) return fail(KDE_E_INVALID_ARG, "nsteps must be >= 0");
+  for (int k = 0; k < nsteps; ++k) KDE_RETURN_IF(session_step_once(s));
+  return KDE_OK;
+}
+
+kde_status kde_session_state(const kde_session* s, kde_session_info* h) {
+  clear_error();
+  if (!s || !h) return fail(KDE_E_INVALID_ARG, "session and output must not be NULL");
+  h->step = s->st.step;
+  h->p_th = s->st.p_th;
+  h->h_opt = s->st.h_opt;
+  h->h_target = s->st.h_target;
+  h->kappa_star = s->st.kappa_star;
+  h->last_a2 = s->st.last_a2;
+  h->last_p = s->st.last_p;
+  h->fired = s->st.fired;
+  return KDE_OK;
+}
+
+kde_status kde_session_read(kde_session* s, int32_t what, void* dst) {
+  clear_error();
+  if (!s || !dst) return fail(KDE_E_INVALID_ARG, "session and dst must not be NULL");
+  const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec), gm = size_t(s->prm.M) * sizeof(double);
+  const void* src = nullptr;
+  size_t bytes = 0;
+  switch (what) {
+    case KDE_SESSION_X: src = s->x; bytes = pn; break;
+    case KDE_SESSION_V: src = s->v; bytes = pn; break;
+    case KDE_SESSION_KAPPA: src = s->kap; bytes = pn; break;
+    case KDE_SESSION_RHO: src = s->rho; bytes = gm; break;
+    case KDE_SESSION_E: src = s->E; bytes = gm; break;
+    default: return fail(KDE_E_INVALID_ARG, "unknown field %d", what);
+  }
+  KDE_TRY_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->s));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  return KDE_OK;
+}
+
+// Blob: magic, version, params (N, M, prec), state, then x, v, kappa_i.
+static const uint64_t kMagic = 0x6b64657069637331ull;  // "kdepics1"
+
+kde_status kde_session_save(kde_session* s, void* blob_h, size_t* bytes_h) {
+  clear_error();
+  if (!s || !bytes_h) return fail(KDE_E_INVALID_ARG, "session and bytes_h must not be NULL");
+  const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec);
+  const size_t need = 64 + sizeof(SessionState) + 3 * pn;
+  if (!blob_h) {
+    *bytes_h = need;
+    return KDE_OK;
+  }
+  if (*bytes_h < need) return fail(KDE_E_INVALID_ARG, "blob too small: %zu < %zu", *bytes_h, need);
+  char* b = static_cast<char*>(blob_h);
+  memset(b, 0, 64);
+  memcpy(b, &kMagic, 8);
+  const int64_t hdr[3] = {s->prm.N, s->prm.M, s->prm.prec};
+  memcpy(b + 8, hdr, sizeof hdr);
+  memcpy(b + 64, &s->st, sizeof(SessionState));
+  char* p = b + 64 + sizeof(SessionState);
+  KDE_TRY_HIP(hipMemcpyAsync(p, s->x, pn, hipMemcpyDeviceToHost, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(p + pn, s->v, pn, hipMemcpyDeviceToHost, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(p + 2 * pn, s->kap, pn, hipMemcpyDeviceToHost, s->s));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  *bytes_h = need;
+  return KDE_OK;
+}
+
+kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes) {
+  clear_error();
+  if (!s || !blob_h) return fail(KDE_E_INVALID_ARG, "session and blob must not be NULL");
+  const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec);
+  const size_t need = 64 + sizeof(SessionState) + 3 * pn;
+  if (bytes < need) return fail(KDE_E_INVALID_ARG, "blob too small: %zu < %zu", bytes, need);
+  const char* b = static_cast<const char*>(blob_h);
+  uint64_t magic = 0;
+  int64_t hdr[3];
+  memcpy(&magic, b, 8);
+  memcpy(hdr, b + 8, sizeof hdr);
+  if (magic != kMagic || hdr[0] != s->prm.N || hdr[1] != s->prm.M || hdr[2] != s->prm.prec)
+    return fail(KDE_E_INVALID_ARG, "blob does not belong to a session of this shape");
+  memcpy(&s->st, b + 64, sizeof(SessionState));
+  const char* p = b + 64 + sizeof(SessionState);
+  KDE_TRY_HIP(hipMemcpyAsync(s->x, p, pn, hipMemcpyHostToDevice, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(s->v, p + pn, pn, hipMemcpyHostToDevice, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(s->kap, p + 2 * pn, pn, hipMemcpyHostToDevice, s->s));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  return KDE_OK;
+}
+
+kde_status kde_session_destroy(kde_session* s) {
+  clear_error();
+  if (s) {
+    if (s->s) {
+      (void)hipStreamSynchronize(s->s);
+      (void)hipStreamDestroy(s->s);
+    }
+    delete s;
+  }
+  return KDE_OK;
+}
+
+}  // extern "C"

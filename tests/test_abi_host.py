@@ -127,3 +127,19 @@ def test_tuning_table_round_trip():
         kde.load_tuning(kde.TUNE_FILE)
     else:
         kde.kde_tune_set(kde.KDE_F64, [1 << 62], [16])
+
+
+@pytest.mark.parametrize("a2", [0.05, 0.3, 1.0, 1.933, 2.492, 3.878, 7.0, 15.0])
+def test_ad_pvalue_host_matches_oracle(a2):
+    """The library's host p-value (its own trapezoid quadrature of the
+    Anderson-Darling series) against the oracle's (SciPy quad of the same
+    series, itself pinned to published points and a characteristic-function
+    inversion)."""
+    from oracle import adtest
+    assert abs(kde.kde_ad_pvalue(a2) - adtest.ad_pvalue(a2)) <= 1e-9
+
+
+def test_ad_pvalue_edges():
+    assert kde.kde_ad_pvalue(0.0) == 1.0
+    assert kde.kde_ad_pvalue(-1.0) == 1.0
+    assert kde.kde_ad_pvalue(500.0) == 0.0

@@ -1,0 +1,209 @@
+"""GPU checks of the serving form: resident PIC sessions against the
+oracle's KDE-PIC step and width-update rule, checkpoint/restore, and the
+request server (results identical alone and in a mix, budget admission)."""
+import math
+import threading
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adtest, cv as ocv, density as od, pic, update, vonmises as vm
+from tests.gpu_util import announce, host, rel_err, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_session(x0, v0, L, M, dt, kappas, n_cv, steps, alpha=0.5, thr=0.01, rate=0.05):
+    def solve(x):
+        c, _, _ = ocv.cv_curve(x[:n_cv], L, kappas)
+        return kappas[ocv.cv_argmin(c)]
+    k0 = solve(x0)
+    st = update.initial_state(vm.width_from_kappa(k0, L), thr)
+    pil = od.deposit(x0, L, M, kappa=k0)
+    k_i, _, _ = od.adapt_widths(x0, L, pil, k0, alpha)
+    x, v = x0.copy(), v0.copy()
+    hist = []
+    for _ in range(steps):
+        x, v, rho, E = pic.field_step(x, v, k_i, L, M, dt)
+        a2 = adtest.ad_statistic(x, L)
+        p = adtest.ad_pvalue(a2)
+        st, fired = update.step(st, p, lambda: vm.width_from_kappa(solve(x), L), thr, rate)
+        kstar = float(vm.kappa_from_width(st.h_opt, L))
+        pil = od.deposit(x, L, M, kappa=kstar)
+        k_i, _, _ = od.adapt_widths(x, L, pil, kstar, alpha)
+        hist.append(dict(a2=a2, p=p, fired=fired, kstar=kstar, rho=rho, E=E))
+    return x, v, k_i, st, hist
+
+
+@pytest.mark.parametrize("alpha_density", [0.1, 0.01])
+def test_session_steps_match_oracle(gpu, alpha_density):
+    L, M, n, dt = 4 * math.pi, 64, 2048, 0.1
+    rng = W.rng_for(5, 77)
+    x0 = W.cosine_positions(rng, n, L, alpha_density, 0.5)
+    v0 = W.maxwellian(rng, n, 1.0)
+    kappas = W.log_kappas(1.0, 1e4, 16)
+    n_cv, steps = 1024, 3
+    announce("session vs oracle", alpha_density)
+    s = gpu.Session(to_gpu(x0), to_gpu(v0), L, M, dt, kappas, n_cv)
+    try:
+        ox, ov, ok, ost, hist = oracle_session(x0, v0, L, M, dt, kappas, n_cv, steps)
+        fired = 0
+        for k in range(steps):
+            s.step(1)
+            info = s.state()
+            h = hist[k]
+            assert abs(info["last_a2"] - h["a2"]) <= 1e-10 * abs(h["a2"])
+            assert abs(info["last_p"] - h["p"]) <= 1e-9
+            fired += int(h["fired"])
+            assert info["fired"] == fired
+            assert abs(info["kappa_star"] - h["kstar"]) <= 1e-12 * h["kstar"]
+        rho = host(s.read(gpu.KDE_SESSION_RHO))
+        E = host(s.read(gpu.KDE_SESSION_E))
+        assert rel_err(rho, hist[-1]["rho"]).max() <= 1e-11
+        assert np.abs(E - hist[-1]["E"]).max() <= 1e-11 * np.abs(hist[-1]["E"]).max()
+        x = host(s.read(gpu.KDE_SESSION_X))
+        v = host(s.read(gpu.KDE_SESSION_V))
+        dx = np.abs(x - ox)
+        dx = np.minimum(dx, L - dx)
+        assert dx.max() <= 1e-11
+        assert np.abs(v - ov).max() <= 1e-11
+        assert rel_err(host(s.read(gpu.KDE_SESSION_KAPPA)), ok).max() <= 1e-10
+        assert abs(info["h_opt"] - ost.h_opt) <= 1e-12 * ost.h_opt
+        assert abs(info["p_th"] - ost.p_th) <= 1e-9
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_session_checkpoint_restore_is_bitwise(gpu, dtype):
+    import torch
+    L, M, n, dt = 4 * math.pi, 128, 8192, 0.1
+    rng = W.rng_for(5, 78)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    x0 = to_gpu(W.cosine_positions(rng, n, L, 0.05, 0.5), td)
+    v0 = to_gpu(W.maxwellian(rng, n, 1.0), td)
+    kappas = W.log_kappas(1.0, 1e4, 16)
+    a = gpu.Session(x0, v0, L, M, dt, kappas, 4096)
+    b = gpu.Session(x0, v0, L, M, dt, kappas, 4096)
+    try:
+        a.step(3)
+        blob = a.save()
+        a.step(4)
+        b.restore(blob)
+        b.step(4)
+        for f in (gpu.KDE_SESSION_X, gpu.KDE_SESSION_V, gpu.KDE_SESSION_KAPPA, gpu.KDE_SESSION_RHO,
+                  gpu.KDE_SESSION_E):
+            assert torch.equal(a.read(f), b.read(f)), f
+        assert a.state() == b.state()
+    finally:
+        a.close()
+        b.close()
+
+
+def plain_outputs(gpu, x, L, M, kappas, n_cv):
+    cv, _, am = gpu.cv_scan(x[:n_cv], L, kappas)
+    b = int(host(am)[0])
+    kstar = float(kappas[b])
+    pilot = gpu.deposit(x, L, M, kappa=kstar)
+    k_i, _, _ = gpu.adapt_widths(x, L, pilot, kstar, 0.5)
+    rho = gpu.deposit(x, L, M, kappa_i=k_i)
+    return host(cv), kstar, host(pilot), host(k_i), host(rho)
+
+
+def make_requests(count, seed, n_lo=500, n_hi=40000, dtype=None):
+    import torch
+    td = dtype or torch.float32
+    rng = np.random.default_rng([5, 1000, seed])
+    reqs = []
+    for r in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        M = int(rng.choice([64, 128, 256, 512]))
+        alpha = float(rng.uniform(0.01, 0.5))
+        L = 4 * math.pi
+        x = to_gpu(W.cosine_positions(rng, n, L, alpha, 0.5).astype(np.float32), td)
+        reqs.append((x, L, M))
+    return reqs
+
+
+def test_server_results_same_alone_and_in_mix(gpu):
+    """Requests served with several slots and batching, while a PIC session
+    steps on its own stream, give the same bits as each request alone."""
+    import torch
+    kappas = W.log_kappas(1.0, 1e4, 16)
+    n_cv = 8192
+    reqs = make_requests(40, seed=1)
+    srv = gpu.Server(kappas, prec=gpu.KDE_F32, budget_bytes=64 << 20, nslots=4, max_batch=8, n_cv=n_cv)
+    outs = []
+    for x, L, M in reqs:
+        outs.append((torch.empty(len(kappas), dtype=torch.float64, device="cuda"),
+                     torch.empty(M, dtype=torch.float64, device="cuda"),
+                     torch.empty(M, dtype=torch.float64, device="cuda"),
+                     torch.empty(x.shape[0], dtype=x.dtype, device="cuda"),
+                     torch.empty(1, dtype=torch.float64, device="cuda")))
+    rng = W.rng_for(5, 79)
+    sx = to_gpu(W.cosine_positions(rng, 16384, 4 * math.pi, 0.01, 0.5).astype(np.float32))
+    sv = to_gpu(W.maxwellian(rng, 16384, 1.0).astype(np.float32))
+    sess = gpu.Session(sx, sv, 4 * math.pi, 128, 0.1, kappas, 4096)
+    stop = threading.Event()
+
+    def stepper():
+        while not stop.is_set():
+            sess.step(1)
+
+    th = threading.Thread(target=stepper)
+    th.start()
+    try:
+        announce("server mix", len(reqs))
+        tickets = [srv.submit(gpu.Server.request(x, L, M, o)) for (x, L, M), o in zip(reqs, outs)]
+        srv.drain()
+    finally:
+        stop.set()
+        th.join()
+    try:
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["rejected"] == 0
+        assert st["p50_s"] <= st["p99_s"] <= st["max_s"]
+        batch_sizes = [srv.poll(t)["batch_size"] for t in tickets]
+        assert max(batch_sizes) > 1          # some requests were admitted together
+        for (x, L, M), o in zip(reqs, outs):
+            cv, kstar, pilot, k_i, rho = plain_outputs(gpu, x, L, M, kappas, min(n_cv, x.shape[0]))
+            assert np.array_equal(host(o[0]), cv)
+            assert host(o[4])[0] == kstar
+            assert np.array_equal(host(o[1]), pilot)
+            assert np.array_equal(host(o[3]), k_i)
+            assert np.array_equal(host(o[2]), rho)
+        assert sess.state()["step"] > 0
+    finally:
+        srv.close()
+        sess.close()
+
+
+def test_server_budget_admission(gpu):
+    import torch
+    kappas = W.log_kappas(1.0, 1e4, 16)
+    reqs = make_requests(6, seed=2, n_lo=20000, n_hi=30000)
+    outs = [(torch.empty(16, dtype=torch.float64, device="cuda"), torch.empty(M, dtype=torch.float64, device="cuda"),
+             torch.empty(M, dtype=torch.float64, device="cuda"), torch.empty(x.shape[0], dtype=x.dtype, device="cuda"),
+             torch.empty(1, dtype=torch.float64, device="cuda")) for x, L, M in reqs]
+    # a budget that holds one request at a time: admission must serialise them
+    probe = gpu.Server(kappas, budget_bytes=1 << 30, nslots=1, max_batch=1)
+    one = max(gpu.kde_server_request_bytes(probe.handle, gpu.Server.request(x, L, M, o)) for (x, L, M), o in zip(reqs, outs))
+    probe.close()
+    srv = gpu.Server(kappas, budget_bytes=one + 4096, nslots=4, max_batch=8)
+    try:
+        for (x, L, M), o in zip(reqs, outs):
+            srv.submit(gpu.Server.request(x, L, M, o))
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["mean_batch"] == 1.0
+        # a request larger than the whole budget is refused at submission
+        big = to_gpu(np.linspace(0, 10, 200000).astype(np.float32))
+        bo = (torch.empty(16, dtype=torch.float64, device="cuda"), torch.empty(64, dtype=torch.float64, device="cuda"),
+              torch.empty(64, dtype=torch.float64, device="cuda"), torch.empty(200000, dtype=torch.float32, device="cuda"),
+              torch.empty(1, dtype=torch.float64, device="cuda"))
+        with pytest.raises(gpu.KdeError) as e:
+            srv.submit(gpu.Server.request(big, 4 * math.pi, 64, bo, n_cv=200000))
+        assert e.value.status == gpu.KDE_E_BUDGET
+    finally:
+        srv.close()
