@@ -107,9 +107,19 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch"], default="plain",
-                    help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets")
+    ap.add_argument("--form", choices=["plain", "batch", "serve"], default="plain",
+                    help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
+                         "serve: the request server beside 16 resident PIC sessions")
     ap.add_argument("--sets", type=int, default=512)
+    ap.add_argument("--requests", type=int, default=2000, help="serve form: requests per load point")
+    ap.add_argument("--loads", default="0.5,0.8,0.95",
+                    help="serve form: offered loads as fractions of the plain path's capacity")
+    ap.add_argument("--slots", type=int, default=4, help="serve form: server slots (streams)")
+    ap.add_argument("--max-batch", type=int, default=16, help="serve form: requests per launch at most")
+    ap.add_argument("--budget-mb", type=int, default=4096, help="serve form: server arena budget")
+    ap.add_argument("--sessions", type=int, default=16, help="serve form: resident PIC sessions")
+    ap.add_argument("--session-period-ms", type=float, default=100.0,
+                    help="serve form: every session steps once per period")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
@@ -126,6 +136,9 @@ def main():
     if args.form == "batch":
         args.prec = args.prec or "f32"
         return bench_batch(args, kde, W, torch, dev)
+    if args.form == "serve":
+        args.prec = args.prec or "f32"
+        return bench_serve(args, kde, W, torch, dev)
     args.prec = args.prec or "f64"
     prob = W.plain_paper_scale()
     L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
@@ -296,6 +309,244 @@ def bench_batch(args, kde, W, torch, dev):
             "plain_path_ms": ms_plain, "batched_over_plain_speedup": ms_plain / ms_batch,
             "batched_equals_plain_bitwise": bool(same)}
     bt.close()
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+def _latency_summary(lat, t_end, reqs, B):
+    lat = np.asarray(lat)
+    ncv = np.array([r.problem.n_cv for r in reqs], dtype=np.float64)
+    ns = np.array([r.problem.x.shape[0] for r in reqs], dtype=np.float64)
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3),
+            "requests_per_s": len(reqs) / t_end, "pair_evals_per_s": float(B * np.sum(ncv * (ncv - 1) / 2)) / t_end,
+            "particles_per_s": float(ns.sum()) / t_end}
+
+
+class _SessionLoad:
+    """Resident PIC sessions stepped in a thread: every session advances one
+    step per period while the load runs."""
+
+    def __init__(self, sessions, period_s):
+        import threading
+        self.sessions, self.period = sessions, period_s
+        self.threading = threading
+        self.stop = threading.Event()
+        self.steps, self.step_time = 0, 0.0
+        self.error = None
+
+    def _run(self):
+        try:
+            nxt = time.perf_counter()
+            while not self.stop.is_set():
+                for s in self.sessions:
+                    t = time.perf_counter()
+                    s.step(1)
+                    self.step_time += time.perf_counter() - t
+                    self.steps += 1
+                nxt += self.period
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    self.stop.wait(d)
+                else:
+                    nxt = time.perf_counter()
+        except Exception as e:  # reported by the caller
+            self.error = e
+
+    def __enter__(self):
+        self.steps, self.step_time = 0, 0.0
+        self.stop.clear()
+        self.thread = self.threading.Thread(target=self._run, daemon=True)
+        self.t0 = time.perf_counter()
+        self.thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        self.thread.join()
+        self.wall = time.perf_counter() - self.t0
+        if self.error is not None:
+            raise self.error
+
+    def summary(self):
+        return {"session_steps": self.steps, "session_steps_per_s": self.steps / self.wall,
+                "mean_session_step_ms": self.step_time * 1e3 / max(self.steps, 1)}
+
+
+def bench_serve(args, kde, W, torch, dev):
+    """The serving form: a Poisson stream of one-shot KDE requests (N
+    log-uniform in [1e3, 1e6], M in {64, 128, 256, 512}, float form, CV on
+    min(N, 65536) particles over 16 kappas, then pilot deposit, widths and
+    adaptive deposit) beside resident PIC sessions (N = 262,144, M = 128,
+    dt = 0.1) that step on their own streams throughout.
+
+    The plain path serves the same arrival trace FIFO through the one-set
+    calls on one stream, one request at a time. Its capacity is measured
+    first (all requests waiting at time 0); each load point then replays the
+    trace at that fraction of the plain capacity through the server and
+    through the plain path. Latency is completion minus arrival on the
+    host's monotonic clock."""
+    prec = kde.KDE_F32 if args.prec == "f32" else kde.KDE_F64
+    tdt = torch.float32 if args.prec == "f32" else torch.float64
+    R = args.requests
+    t_gen = time.perf_counter()
+    trace = W.request_stream(R, 1.0)          # arrivals at rate 1, rescaled per load point
+    base_arrival = np.array([r.arrival_s for r in trace])
+    kappas = trace[0].problem.kappas
+    B = len(kappas)
+    n_cv_cap = 65536
+    xs = [torch.from_numpy(r.problem.x).to(dev).to(tdt).contiguous() for r in trace]
+
+    def outputs():
+        return [(torch.empty(B, dtype=torch.float64, device=dev), torch.empty(r.problem.M, dtype=torch.float64, device=dev),
+                 torch.empty(r.problem.M, dtype=torch.float64, device=dev),
+                 torch.empty(r.problem.x.shape[0], dtype=tdt, device=dev), torch.empty(1, dtype=torch.float64, device=dev))
+                for r in trace]
+
+    out_srv, out_pl = outputs(), outputs()
+    sess_init = [W.pic_session(i) for i in range(args.sessions)]
+    sessions = [kde.Session(torch.from_numpy(si.x).to(dev).to(tdt).contiguous(),
+                            torch.from_numpy(si.v).to(dev).to(tdt).contiguous(),
+                            si.L, si.M, si.dt, si.kappas, si.n_cv) for si in sess_init]
+    gen_s = time.perf_counter() - t_gen
+
+    # ---- plain path: FIFO, one request at a time, one stream
+    stream = torch.cuda.Stream(device=dev)
+    am = torch.empty(1, dtype=torch.int32, device=dev)
+    am_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    sz_cv = sz_dep = sz_ad = 0
+    for r in trace:
+        d = kde.kde_domain(r.problem.L, r.problem.M, prec)
+        n = r.problem.x.shape[0]
+        sz_cv = max(sz_cv, kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, d, min(n, n_cv_cap), B))
+        sz_dep = max(sz_dep, kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, d, n))
+        sz_ad = max(sz_ad, kde.kde_workspace_size(kde.KDE_OP_ADAPT, d, n))
+    ws = [kde.Workspace(dev) for _ in range(3)]
+    (p1, b1), (p2, b2), (p3, b3) = ws[0].get(sz_cv), ws[1].get(sz_dep), ws[2].get(sz_ad)
+
+    def plain_one(i):
+        r = trace[i].problem
+        x, n = xs[i], r.x.shape[0]
+        ncv = min(n, n_cv_cap)
+        cv, pil, rho, k_i, ks = out_pl[i]
+        d = kde.kde_domain(r.L, r.M, prec)
+        kde.kde_cv_scan(d, ncv, x[:ncv], kappas, cv, None, am, p1, b1, stream)
+        am_h.copy_(am, non_blocking=True)
+        stream.synchronize()
+        kstar = float(kappas[int(am_h[0])])
+        kde.kde_deposit(d, n, x, None, kstar, pil, p2, b2, stream)
+        kde.kde_adapt_widths(d, n, x, pil, kstar, 0.5, k_i, None, None, p3, b3, stream)
+        kde.kde_deposit(d, n, x, k_i, 0.0, rho, p2, b2, stream)
+        ks.fill_(kstar)
+        stream.synchronize()
+
+    def run_plain(arrival):
+        lat = np.empty(R)
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for i in range(R):
+                target = t0 + arrival[i]
+                while True:
+                    d = target - time.perf_counter()
+                    if d <= 0:
+                        break
+                    time.sleep(min(d, 2e-4))
+                plain_one(i)
+                lat[i] = time.perf_counter() - target
+        t_end = time.perf_counter() - t0
+        return lat, t_end
+
+    # ---- served path
+    srv = kde.Server(kappas, prec=prec, budget_bytes=args.budget_mb << 20, nslots=args.slots,
+                     max_batch=args.max_batch, n_cv=n_cv_cap, alpha=0.5, device=dev)
+    reqs = [kde.Server.request(xs[i], trace[i].problem.L, trace[i].problem.M, out_srv[i]) for i in range(R)]
+
+    def run_served(arrival):
+        lag = np.empty(R)
+        tickets = []
+        t0 = time.perf_counter()
+        for i in range(R):
+            target = t0 + arrival[i]
+            while True:
+                d = target - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 2e-4))
+            lag[i] = time.perf_counter() - target
+            tickets.append(srv.submit(reqs[i]))
+        srv.drain()
+        res = [srv.poll(t) for t in tickets]
+        if any(r is None or r["status"] != 0 for r in res):
+            raise RuntimeError("a served request did not complete")
+        lat = lag + np.array([r["latency_s"] for r in res])
+        t_end = float(np.max(arrival + lat))
+        batch = np.array([r["batch_size"] for r in res], dtype=np.float64)
+        return lat, t_end, float(batch.mean())
+
+    load = _SessionLoad(sessions, args.session_period_ms * 1e-3)
+    # warm-up: a few requests through both paths and one step of every session
+    zero = np.zeros(R)
+    for i in range(min(R, 32)):
+        plain_one(i)
+    warm = [srv.submit(reqs[i]) for i in range(min(R, 32))]
+    srv.drain()
+    if any(srv.poll(t) is None for t in warm):
+        raise RuntimeError("a warm-up request did not complete")
+    for s_ in sessions:
+        s_.step(1)
+    torch.cuda.synchronize()
+
+    points = []
+    with load:
+        lat, t_pl = run_plain(zero)
+    cap_plain = R / t_pl
+    sat_pl = _latency_summary(lat, t_pl, trace, B)
+    sat_pl.update(load.summary())
+    with load:
+        lat, t_sv, mb = run_served(zero)
+    sat_sv = _latency_summary(lat, t_sv, trace, B)
+    sat_sv.update(load.summary())
+    sat_sv["mean_batch"] = mb
+    same = all(torch.equal(out_srv[i][2], out_pl[i][2]) and torch.equal(out_srv[i][3], out_pl[i][3]) and
+               torch.equal(out_srv[i][4], out_pl[i][4]) for i in range(R))
+    points.append({"offered_load": "saturated (all requests waiting at t=0)", "served": sat_sv, "plain": sat_pl})
+    for f in [float(v) for v in args.loads.split(",") if v]:
+        rate = f * cap_plain
+        arrival = base_arrival / rate
+        with load:
+            lat, t_sv, mb = run_served(arrival)
+        sv = _latency_summary(lat, t_sv, trace, B)
+        sv.update(load.summary())
+        sv["mean_batch"] = mb
+        with load:
+            lat, t_pl = run_plain(arrival)
+        pl = _latency_summary(lat, t_pl, trace, B)
+        pl.update(load.summary())
+        points.append({"offered_load": f, "rate_per_s": rate, "served": sv, "plain": pl})
+        print(json.dumps({"load": f, "served_p99_ms": sv["p99_ms"], "plain_p99_ms": pl["p99_ms"]}),
+              file=sys.stderr, flush=True)
+    stats = srv.stats()
+    srv.close()
+    ns = np.array([r.problem.x.shape[0] for r in trace], dtype=np.float64)
+    line = {"metric": METRIC, "form": "serve", "value": sat_sv["pair_evals_per_s"], "unit": "CV pair-evals/s",
+            "n_gpus": 1, "steps": R, "warmup": 0, "ms_per_step": 1e3 / sat_sv["requests_per_s"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+            "data": "synthetic",
+            "config": {"workload": f"serving form: Poisson stream of {R} KDE/CV requests (N log-uniform in "
+                                   "[1e3,1e6], M in {64,128,256,512}, CV on min(N,65536), 16 kappas in [1,1e4]) "
+                                   f"beside {len(sessions)} resident PIC sessions (N=262,144, M=128, dt=0.1, "
+                                   f"one step each per {args.session_period_ms:g} ms)",
+                       "requests": R, "mean_N": float(ns.mean()), "slots": args.slots, "max_batch": args.max_batch,
+                       "budget_mb": args.budget_mb, "sessions": len(sessions)},
+            "plain_capacity_requests_per_s": cap_plain,
+            "served_over_plain_throughput": sat_sv["requests_per_s"] / sat_pl["requests_per_s"],
+            "served_equals_plain_bitwise": bool(same),
+            "load_points": points, "server_launches": stats["launches"], "input_generation_s": gen_s}
+    for s_ in sessions:
+        s_.close()
     out = json.dumps(line)
     print(out, flush=True)
     if args.json_out:

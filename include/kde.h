@@ -320,11 +320,18 @@ kde_status kde_session_destroy(kde_session* s);
  * request is one particle set (a kde_batch_set: positions, grid, outputs)
  * taken through the whole path like one set of a batch; the CV scan uses
  * min(N, request n_cv, config n_cv) leading particles (0 = no limit).
- * Requests queue in FIFO order; a scheduler thread admits them into
- * `nslots` slots (each a HIP stream of default priority), up to max_batch
- * requests per admission, whenever a slot is free and their workspaces fit
- * in the free part of the caller's arena (the HBM budget). Slots run
- * concurrently. A request that alone needs more than the whole budget is
+ * Requests queue in arrival order; a scheduler thread admits them into
+ * `nslots` slots (each a HIP stream of default priority) whenever a slot is
+ * free and their workspaces fit in the free part of the caller's arena
+ * (the HBM budget). A request's estimated work is B n_cv (n_cv - 1) / 2 CV
+ * pair terms plus 2 N M deposit terms plus 5e7; it is large from
+ * large_terms on. Large requests run alone, at most large_slots at a time,
+ * in arrival order. Otherwise the oldest small request heads a batch,
+ * joined by up to max_batch - 1 later small ones whose estimated work lies
+ * between a quarter and twice the head's; small requests may pass waiting
+ * large ones. Slots run concurrently, one workgroup per work unit, so they
+ * share the device with each other and with other streams. A request that
+ * alone needs more than the whole budget is
  * refused by kde_server_submit with KDE_E_BUDGET. Results are bitwise the
  * same whatever the mix. Latency = completion noticed by the scheduler
  * minus submission, host steady clock. The request's device buffers must
@@ -338,6 +345,8 @@ typedef struct kde_server_config {
   int64_t n_cv;          /* cap on the CV subsample (0 = none)                    */
   int32_t nslots;        /* concurrent slots, 1..64                               */
   int32_t max_batch;     /* requests per admission, 1..1024                       */
+  int32_t large_slots;   /* large requests in flight at most (0 = 1)              */
+  double large_terms;    /* estimated terms from which a request is large (0 = 2e9) */
 } kde_server_config;
 
 typedef struct kde_result {
@@ -373,18 +382,24 @@ kde_status kde_server_destroy(kde_server* s);
 kde_status kde_ad_pvalue(double a2, double* p_h);
 
 /*
- * Tuning of the CV pair kernel: the number of concentrations it evaluates
- * per pass (4, 8 or 16), by particle count. Entry k applies to
- * N <= n_max_h[k] (ascending); the last entry covers every larger N. The
- * choice changes speed only: each concentration accumulates the same terms
- * in the same order whatever the pass size, so results are bitwise equal.
- * The table is process-wide; set it before launching work, not while calls
- * on other threads are running. kde_tune_get returns the pass size used for
- * N. The default is 16 for every N until a table is set (the Python binding
+ * Tuning of the CV pair kernel, by particle count: chunk_h[k], the number
+ * of concentrations evaluated per pass over a tile pair (4, 8 or 16), and
+ * group_h[k], the number of concentrations one workgroup takes on (0 = all
+ * of them; else a multiple of chunk_h[k] up to KDE_MAX_KAPPAS), so that a
+ * tile pair is split over ceil(B / group) workgroups, which shortens the
+ * critical path of small sets. group_h may be NULL (all zero). Entry k
+ * applies to N <= n_max_h[k] (ascending); the last entry covers every
+ * larger N. The choice changes speed only: each concentration accumulates
+ * the same terms in the same order whatever the pass size or split, so
+ * results are bitwise equal. The table is process-wide; set it before
+ * launching work, not while calls on other threads are running.
+ * kde_tune_get returns the entry used for N (group_h may be NULL). The
+ * default is (16, 0) for every N until a table is set (the Python binding
  * installs the autotuned table shipped with the package).
  */
-kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h);
-kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h);
+kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h,
+                        const int32_t* group_h);
+kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h, int32_t* group_h);
 
 /*
  * Kernel timing (diagnostics). While enabled, the library brackets every

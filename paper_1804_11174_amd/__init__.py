@@ -62,7 +62,7 @@ class kde_session_info(ctypes.Structure):
 class kde_server_config(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("B", ctypes.c_int32), ("kappas_h", ctypes.POINTER(ctypes.c_double)),
                 ("alpha", ctypes.c_double), ("n_cv", ctypes.c_int64), ("nslots", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("large_slots", ctypes.c_int32), ("large_terms", ctypes.c_double)]
 
 
 class kde_result(ctypes.Structure):
@@ -97,8 +97,8 @@ _SIGNATURES = {
     "kde_timing_enable": (_i32, [_i32]),
     "kde_timing_reset": (_i32, []),
     "kde_timing_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
-    "kde_tune_set": (_i32, [_i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
-    "kde_tune_get": (_i32, [_i32, _i64, ctypes.POINTER(_i32)]),
+    "kde_tune_set": (_i32, [_i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "kde_tune_get": (_i32, [_i32, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kde_batch_plan": (_i32, [ctypes.POINTER(kde_batch_set), _i32, _i32, _i32, ctypes.POINTER(_dbl), _dbl,
                               ctypes.POINTER(_vp)]),
     "kde_batch_workspace_size": (_i32, [_vp, ctypes.POINTER(_sz)]),
@@ -156,14 +156,15 @@ def require_library():
 
 
 def load_tuning(path: str):
-    """Install an autotuned pass-size table (JSON written by autotune.py)."""
+    """Install an autotuned pair-kernel table (JSON written by autotune.py)."""
     import json
     with open(path) as f:
         table = json.load(f)
     for name, prec in (("f64", KDE_F64), ("f32", KDE_F32)):
         rows = table.get(name)
         if rows:
-            kde_tune_set(prec, [r["n_max"] for r in rows], [r["chunk"] for r in rows])
+            kde_tune_set(prec, [r["n_max"] for r in rows], [r["chunk"] for r in rows],
+                         [r.get("group", 0) for r in rows])
 
 
 def _check(status: int, where: str):
@@ -258,18 +259,23 @@ def kde_adapt_widths(dom, N, x, pilot, kappa_star, alpha, kappa_out, log_geomean
                                 _stream(stream)), "kde_adapt_widths")
 
 
-def kde_tune_set(prec: int, n_max, chunk):
+def kde_tune_set(prec: int, n_max, chunk, group=None):
+    """Pair-kernel table: entry k (N <= n_max[k]) evaluates chunk[k]
+    concentrations per pass and gives each workgroup group[k] of them
+    (0 = all)."""
     lib = require_library()
     n = len(n_max)
     a = (_i64 * n)(*[int(v) for v in n_max])
     b = (_i32 * n)(*[int(v) for v in chunk])
-    _check(lib.kde_tune_set(int(prec), n, a, b), "kde_tune_set")
+    g = None if group is None else (_i32 * n)(*[int(v) for v in group])
+    _check(lib.kde_tune_set(int(prec), n, a, b, g), "kde_tune_set")
 
 
-def kde_tune_get(prec: int, N: int) -> int:
-    out = _i32(0)
-    _check(require_library().kde_tune_get(int(prec), int(N), ctypes.byref(out)), "kde_tune_get")
-    return int(out.value)
+def kde_tune_get(prec: int, N: int) -> Tuple[int, int]:
+    """``(chunk, group)`` of the table entry used for N."""
+    c, g = _i32(0), _i32(0)
+    _check(require_library().kde_tune_get(int(prec), int(N), ctypes.byref(c), ctypes.byref(g)), "kde_tune_get")
+    return int(c.value), int(g.value)
 
 
 def kde_batch_plan(sets, prec: int, kappas, alpha: float = 0.5) -> int:
@@ -499,11 +505,12 @@ class Server:
     """Continuous-batching server of KDE solves over a torch-owned arena."""
 
     def __init__(self, kappas, prec=KDE_F32, budget_bytes=256 << 20, nslots=4, max_batch=16, n_cv=65536,
-                 alpha=0.5, device="cuda"):
+                 alpha=0.5, device="cuda", large_slots=0, large_terms=0.0):
         import torch
         self._k = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
         self.cfg = kde_server_config(int(prec), int(self._k.shape[0]), self._k.ctypes.data_as(ctypes.POINTER(_dbl)),
-                                     float(alpha), int(n_cv), int(nslots), int(max_batch))
+                                     float(alpha), int(n_cv), int(nslots), int(max_batch), int(large_slots),
+                                     float(large_terms))
         self._arena = torch.empty(int(budget_bytes) + 256, dtype=torch.uint8, device=device)
         base = self._arena.data_ptr()
         self.handle = kde_server_create(self.cfg, (base + 255) // 256 * 256, int(budget_bytes))

@@ -2,38 +2,43 @@
 // path (CV scan over a shared list of concentrations, pilot deposit at each
 // set's kappa*, adaptive widths, adaptive deposit) in one hipGraph launch.
 //
-// The graph holds one persistent kernel per phase. Each kernel runs about
-// as many workgroups as the device keeps resident and they pull work units
-// -- (set), (set, tile pair), (set, particle chunk) or (set, row block) --
-// from the phase's own device counter, sets ordered by decreasing cost so
-// that the long pair-sum work starts first. Phases follow each other in
-// the graph, so no workgroup ever waits on another. Every unit runs the
-// same device code as the one-set entry points and writes its own slot,
-// and every reduction has the one-set entry points' fixed order, so each
-// set's results are bitwise identical to running it alone.
+// The graph holds one kernel per phase over the work units of every set
+// -- (set), (set, sort block), (set, tile pair, concentration group),
+// (set, particle chunk) or (set, row block) -- with the sets ordered by
+// decreasing CV cost so that the long pair-sum work starts first. The pair
+// phase runs one workgroup per unit; the light phases run about as many
+// workgroups as the device keeps resident, pulling units from the phase's
+// own device counter. Phases follow each other in the graph, so no
+// workgroup ever waits on another. Every unit runs the same device code as
+// the one-set entry points and writes its own slot, and every reduction has
+// the one-set entry points' fixed order, so each set's results are bitwise
+// identical to running it alone.
 #include <algorithm>
+#include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
+#include "batch_internal.hpp"
 #include "dev_cv.hpp"
 #include "dev_density.hpp"
 #include "dev_layout.hpp"
 #include "dev_reduce.hpp"
-#include "batch_internal.hpp"
-#include <cstring>
 
 namespace kde {
 
-// Phase counters (zeroed by the first kernel of every launch).
+// Work counters of the phases that claim units (zeroed by the first kernel
+// of every launch).
 enum Phase {
-  PH_PACK, PH_CV_L1, PH_CV_FIN, PH_PIL_DEP, PH_PIL_L1, PH_PIL_L2, PH_AD_LOG, PH_AD_L1, PH_AD_L2,
-  PH_AD_APPLY, PH_RHO_DEP, PH_RHO_L1, PH_RHO_L2, PH_COUNT
+  PH_SORT_HIST, PH_SORT_SCAN, PH_SORT_SCATTER, PH_CV_L1, PH_CV_FIN, PH_PIL_L1, PH_PIL_L2, PH_AD_LOG, PH_AD_L1,
+  PH_AD_L2, PH_AD_APPLY, PH_RHO_L1, PH_RHO_L2, PH_COUNT
 };
-// The pair phase runs once per pass-size bucket, bucket k on counter
-// PH_COUNT + k.
+// The pair phase runs once per pass-size bucket, one workgroup per unit.
 constexpr int kMaxBuckets = 64;
-constexpr int kCounters = PH_COUNT + kMaxBuckets;
+constexpr int kCounters = PH_COUNT;
 
 // Per-set description as the kernels see it (lives in the workspace).
 struct SetDev {
@@ -41,8 +46,11 @@ struct SetDev {
   int64_t n_cv;  // particles the CV scan uses (a prefix)
   const void* x;
   double L;
-  int M, cells, chunk, pad;
-  int64_t units, g_cv, chunks, g_dep, blocks, g_ad;
+  int M, cells, chunk, sblocks;  // sblocks: blocks of the cell sort
+  int gsize, groups;              // pair units: concentrations per unit, units per tile pair
+  int64_t schunk;                 // particles per sort block
+  int64_t units, g_cv, chunks, g_dep, blocks, g_ad;  // units: tile pairs
+  int32_t* hist;      // cells x sblocks, cell-major
   void* packed;
   double* partials;   // units x 2B
   double* cv_l1;      // g_cv x 2B
@@ -60,7 +68,7 @@ struct SetDev {
 };
 
 // Unit prefix sums, one array of nsets + 1 per multi-unit phase.
-enum Prefix { PF_PAIRS, PF_CV_L1, PF_CHUNKS, PF_DEP_L1, PF_BLOCKS, PF_AD_L1, PF_COUNT };
+enum Prefix { PF_PAIRS, PF_CV_L1, PF_CHUNKS, PF_DEP_L1, PF_BLOCKS, PF_AD_L1, PF_SORT, PF_COUNT };
 
 struct BatchArgs {
   const SetDev* sets;
@@ -81,51 +89,109 @@ __device__ __forceinline__ int find_set(const int64_t* pf, int nsets, int64_t u)
   return lo;
 }
 
-// Claim the next unit of a phase for the whole workgroup.
+// Values known to be equal in every lane, moved to scalar registers (the
+// compiler cannot prove a loaded set descriptor uniform by itself).
+__device__ __forceinline__ int uni32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ P* uni_ptr(P* p) {
+  return reinterpret_cast<P*>(uni64(reinterpret_cast<int64_t>(p)));
+}
+
+// Claim the next unit of a phase for the whole workgroup. The value is
+// the same in every lane; reading it through readfirstlane lets the
+// compiler know that, so the unit's set descriptor and loop bounds live in
+// scalar registers.
 __device__ __forceinline__ int64_t claim(unsigned long long* counter, int64_t* slot) {
   if (threadIdx.x == 0) *slot = int64_t(atomicAdd(counter, 1ull));
   __syncthreads();
-  const int64_t u = *slot;
+  const int64_t v = *slot;
   __syncthreads();
-  return u;
+  return uni64(v);
 }
 
 __global__ void __launch_bounds__(kBlock) batch_zero_kernel(unsigned long long* counters) {
   if (threadIdx.x < kCounters) counters[threadIdx.x] = 0ull;
 }
 
+// The stable cell sort of every set's CV prefix in three phases, with the
+// one-set path's block decomposition: per-block histograms, one scan per
+// set, per-block scatters.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) batch_pack_kernel(BatchArgs a) {
-  using P = typename Packed<T>::type;
+__global__ void __launch_bounds__(kBlock) batch_sort_hist_kernel(BatchArgs a) {
   __shared__ int64_t slot;
-  __shared__ int tot[kBlock];
-  extern __shared__ int base[];
+  extern __shared__ int lh[];
+  const int64_t* pf = a.prefix + PF_SORT * (a.nsets + 1);
+  const int64_t total = pf[a.nsets];
   for (;;) {
-    const int64_t u = claim(&a.counters[PH_PACK], &slot);
-    if (u >= a.nsets) break;
-    const SetDev& s = a.sets[u];
-    sort_set_one_block<T, P>(static_cast<const T*>(s.x), s.n_cv, s.L, s.cells, base, tot, static_cast<P*>(s.packed));
-    __syncthreads();
+    const int64_t u = claim(&a.counters[PH_SORT_HIST], &slot);
+    if (u >= total) break;
+    const int si = find_set(pf, a.nsets, u);
+    const SetDev& s = a.sets[si];
+    const int b = int(u - pf[si]);
+    const int64_t lo = int64_t(b) * s.schunk;
+    sort_hist_block<T>(static_cast<const T*>(s.x), lo, min(s.n_cv, lo + s.schunk), s.L, s.cells, b, s.sblocks, lh,
+                       s.hist);
   }
 }
 
-// Pair units [u_lo, u_hi) of the flattened list (one pass-size bucket).
-template <typename T, int BC>
-__global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvConsts<T> K, int phase, int64_t u_lo,
-                                                            int64_t u_hi) {
+__global__ void __launch_bounds__(kBlock) batch_sort_scan_kernel(BatchArgs a) {
+  __shared__ int64_t slot;
+  __shared__ int tot[kBlock / 64];
+  for (;;) {
+    const int64_t u = claim(&a.counters[PH_SORT_SCAN], &slot);
+    if (u >= a.nsets) break;
+    const SetDev& s = a.sets[u];
+    block_scan_global(s.hist, int64_t(s.cells) * s.sblocks, tot);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) batch_sort_scatter_kernel(BatchArgs a) {
   using P = typename Packed<T>::type;
   __shared__ int64_t slot;
-  __shared__ CvSmem<T, BC> sm;
-  const int64_t* pf = a.prefix + PF_PAIRS * (a.nsets + 1);
+  extern __shared__ int base[];
+  const int64_t* pf = a.prefix + PF_SORT * (a.nsets + 1);
+  const int64_t total = pf[a.nsets];
   for (;;) {
-    const int64_t u = u_lo + claim(&a.counters[phase], &slot);
-    if (u >= u_hi) break;
+    const int64_t u = claim(&a.counters[PH_SORT_SCATTER], &slot);
+    if (u >= total) break;
     const int si = find_set(pf, a.nsets, u);
     const SetDev& s = a.sets[si];
-    const int64_t p = u - pf[si];
+    const int b = int(u - pf[si]);
+    const int64_t lo = int64_t(b) * s.schunk;
+    sort_scatter_block<T, P>(static_cast<const T*>(s.x), lo, min(s.n_cv, lo + s.schunk), s.L, s.cells, b, s.sblocks,
+                             s.hist, base, static_cast<P*>(s.packed), nullptr);
+  }
+}
+
+// Pair units [u_lo, u_hi) of the flattened list (one pass-size bucket),
+// one workgroup per unit. The list follows the cost order of the sets, and
+// workgroups are dispatched in index order, so the largest sets start
+// first without a work counter; a loop over claimed units would keep more
+// registers live and lower the occupancy of this, the heaviest phase.
+template <typename T, int BC>
+__global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvConsts<T> K, int64_t u_lo, int64_t u_hi) {
+  using P = typename Packed<T>::type;
+  __shared__ CvSmem<T, BC> sm;
+  const int64_t* pf = a.prefix + PF_PAIRS * (a.nsets + 1);
+  {
+    const int64_t u = u_lo + int64_t(blockIdx.x);
+    if (u >= u_hi) return;
+    const int si = uni32(find_set(pf, a.nsets, u));
+    const SetDev& s = a.sets[si];
+    const int64_t q = u - uni64(pf[si]);
+    const int groups = uni32(s.groups), gsize = uni32(s.gsize);
+    const int64_t p = q / groups;
+    const int b_lo = int(q - p * groups) * gsize;
     int I, J;
     tri_decode(p, I, J);
-    cv_tile_pair<T, BC>(static_cast<const P*>(s.packed), s.n_cv, I, J, K, s.partials + p * 2 * K.B, sm);
+    cv_tile_pair<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), I, J, K, b_lo,
+                        min(K.B, b_lo + gsize), uni_ptr(s.partials) + p * 2 * K.B, sm);
   }
 }
 
@@ -182,26 +248,24 @@ __global__ void __launch_bounds__(kBlock) batch_cv_finalize_kernel(BatchArgs a, 
 // Deposit chunks of every set: the pilot at kappa* (PER = false) or the
 // adaptive deposit with the set's kappa_i (PER = true).
 template <typename T, bool PER, int G>
-__global__ void __launch_bounds__(kBlock) batch_deposit_kernel(BatchArgs a, int phase) {
-  __shared__ int64_t slot;
+__global__ void __launch_bounds__(kBlock) batch_deposit_kernel(BatchArgs a) {
   __shared__ DepSmem<T> sm;
   extern __shared__ __align__(16) unsigned char dyn[];
   const int64_t* pf = a.prefix + PF_CHUNKS * (a.nsets + 1);
-  const int64_t total = pf[a.nsets];
   T* ts = reinterpret_cast<T*>(dyn);
-  for (;;) {
-    const int64_t u = claim(&a.counters[phase], &slot);
-    if (u >= total) break;
-    const int si = find_set(pf, a.nsets, u);
-    const SetDev& s = a.sets[si];
-    const int64_t c = u - pf[si];
-    T* tc = ts + s.M;
-    node_table(s.M, ts, tc);
-    const int64_t lo = c * s.chunk;
-    const int cnt = int(min(int64_t(s.chunk), s.n - lo));
-    deposit_block<T, PER, G>(static_cast<const T*>(s.x), static_cast<const T*>(s.kappa_i), PER ? 0.0 : *s.kstar,
-                             s.M, s.L, lo, cnt, s.dep_part + c * s.M, ts, tc, sm);
-  }
+  const int64_t u = int64_t(blockIdx.x);
+  if (u >= pf[a.nsets]) return;
+  const int si = uni32(find_set(pf, a.nsets, u));
+  const SetDev& s = a.sets[si];
+  const int64_t c = u - uni64(pf[si]);
+  const int M = uni32(s.M);
+  const int chunk = uni32(s.chunk);
+  T* tc = ts + M;
+  node_table(M, ts, tc);
+  const int64_t lo = c * chunk;
+  const int cnt = int(min(int64_t(chunk), uni64(s.n) - lo));
+  deposit_block<T, PER, G>(uni_ptr(static_cast<const T*>(s.x)), uni_ptr(static_cast<const T*>(s.kappa_i)),
+                           PER ? 0.0 : *s.kstar, M, s.L, lo, cnt, uni_ptr(s.dep_part) + c * M, ts, tc, sm);
 }
 
 // Level 2 of every set: the pilot (scaled by 1/N), the log sums, or rho.
@@ -279,14 +343,20 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.M = in.M;
     const SortPlan sp = make_sort_plan(d.n_cv);
     d.cells = sp.cells;
+    d.sblocks = sp.blocks;
+    d.schunk = sp.chunk;
     d.chunk = deposit_chunk(in.N);
     const int64_t ntiles = ceil_div(d.n_cv, kCvTile);
     d.units = ntiles * (ntiles + 1) / 2;
+    const PairTuning tp = tuned_pass(b.prec, d.n_cv);
+    d.gsize = pair_group_size(tp, b.B);
+    d.groups = pair_groups(tp, b.B);
     d.g_cv = ceil_div(d.units, kSumRows);
     d.chunks = ceil_div(in.N, d.chunk);
     d.g_dep = ceil_div(d.chunks, kSumRows);
     d.blocks = ceil_div(in.N, kBlock);
     d.g_ad = ceil_div(d.blocks, kSumRows);
+    d.hist = c.take<int32_t>(size_t(d.cells) * size_t(d.sblocks));
     d.packed = b.prec == KDE_F64 ? static_cast<void*>(c.take<double>(2 * size_t(d.n_cv)))
                                  : static_cast<void*>(c.take<uint32_t>(size_t(d.n_cv)));
     d.partials = c.take<double>(size_t(d.units) * 2 * b.B);
@@ -303,7 +373,7 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.kstar = c.take<double>(1);
     d.kstar_user = in.kappa_star;
     if (descs) (*descs)[r] = d;
-    const int64_t per[PF_COUNT] = {d.units, d.g_cv, d.chunks, d.g_dep, d.blocks, d.g_ad};
+    const int64_t per[PF_COUNT] = {d.units * d.groups, d.g_cv, d.chunks, d.g_dep, d.blocks, d.g_ad, int64_t(d.sblocks)};
     for (int k = 0; k < PF_COUNT; ++k) {
       if (prefix) (*prefix)[size_t(k) * (ns + 1) + r] = acc[k];
       acc[k] += per[k];
@@ -317,15 +387,31 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
   return c.used;
 }
 
-// Workgroups to launch for a persistent phase kernel: what the device keeps
-// resident, but no more than the phase has units.
-template <typename K>
-static unsigned persistent_grid(K kernel, size_t dyn_lds, int64_t units) {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+// Workgroups to launch for a phase kernel: with resident grids what the
+// device keeps resident, but no more than the phase has units; otherwise
+// one per unit. The occupancy of each (kernel, LDS, device) is queried
+// once.
+static int resident_blocks(const void* kernel, size_t dyn_lds, int dev) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int> cache;
+  const auto key = std::make_tuple(kernel, dyn_lds, dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, dyn_lds) != hipSuccess || per < 1) per = 1;
-  int64_t g = int64_t(cus) * per;
+  return cache[key] = cus * per;
+}
+
+template <typename K>
+static unsigned launch_grid(const BatchPlan& b, K kernel, size_t dyn_lds, int64_t units) {
+  int64_t g = int64_t(1) << 30;
+  if (b.resident_grids) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    g = resident_blocks(reinterpret_cast<const void*>(kernel), dyn_lds, dev);
+  }
   if (units < g) g = units;
   return unsigned(g < 1 ? 1 : g);
 }
@@ -342,74 +428,76 @@ static kde_status enqueue_batch(const BatchPlan& b, const BatchArgs& a, const st
 
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(kBlock), 0, s, a.counters);
   KDE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(batch_pack_kernel<T>, dim3(persistent_grid(batch_pack_kernel<T>, pack_lds, ns)), dim3(kBlock),
+  hipLaunchKernelGGL(batch_sort_hist_kernel<T>, dim3(launch_grid(b, batch_sort_hist_kernel<T>, pack_lds, total(PF_SORT))),
+                     dim3(kBlock), pack_lds, s, a);
+  KDE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(batch_sort_scan_kernel, dim3(launch_grid(b, batch_sort_scan_kernel, 0, ns)), dim3(kBlock), 0, s, a);
+  KDE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(batch_sort_scatter_kernel<T>,
+                     dim3(launch_grid(b, batch_sort_scatter_kernel<T>, pack_lds, total(PF_SORT))), dim3(kBlock),
                      pack_lds, s, a);
   KDE_CHECK_LAUNCH();
   for (size_t k = 0; k < b.bucket_bc.size(); ++k) {
     const int64_t lo = prefix[size_t(PF_PAIRS) * (ns + 1) + b.bucket_begin[k]];
     const int64_t hi = prefix[size_t(PF_PAIRS) * (ns + 1) + b.bucket_begin[k + 1]];
-    const int ph = int(PH_COUNT + k);
+    if (hi - lo > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "too many pair units for one launch");
+    const dim3 grid{unsigned(hi - lo)};
     switch (b.bucket_bc[k]) {
       case 4:
-        hipLaunchKernelGGL((batch_pairs_kernel<T, 4>), dim3(persistent_grid(batch_pairs_kernel<T, 4>, 0, hi - lo)),
-                           dim3(kBlock), 0, s, a, K, ph, lo, hi);
+        hipLaunchKernelGGL((batch_pairs_kernel<T, 4>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
         break;
       case 8:
-        hipLaunchKernelGGL((batch_pairs_kernel<T, 8>), dim3(persistent_grid(batch_pairs_kernel<T, 8>, 0, hi - lo)),
-                           dim3(kBlock), 0, s, a, K, ph, lo, hi);
+        hipLaunchKernelGGL((batch_pairs_kernel<T, 8>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
         break;
       default:
-        hipLaunchKernelGGL((batch_pairs_kernel<T, 16>), dim3(persistent_grid(batch_pairs_kernel<T, 16>, 0, hi - lo)),
-                           dim3(kBlock), 0, s, a, K, ph, lo, hi);
+        hipLaunchKernelGGL((batch_pairs_kernel<T, 16>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
         break;
     }
     KDE_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(batch_level1_kernel<SRC_CV>,
-                     dim3(persistent_grid(batch_level1_kernel<SRC_CV>, 0, total(PF_CV_L1))), dim3(kBlock), 0, s, a,
+                     dim3(launch_grid(b, batch_level1_kernel<SRC_CV>, 0, total(PF_CV_L1))), dim3(kBlock), 0, s, a,
                      int(PH_CV_L1), int(PF_CV_L1));
   KDE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(batch_cv_finalize_kernel, dim3(persistent_grid(batch_cv_finalize_kernel, 0, ns)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(batch_cv_finalize_kernel, dim3(launch_grid(b, batch_cv_finalize_kernel, 0, ns)), dim3(kBlock), 0,
                      s, a, kl);
   KDE_CHECK_LAUNCH();
   for (int pass = 0; pass < 2; ++pass) {
     const bool adaptive = pass == 1;
     if (adaptive) {
       hipLaunchKernelGGL(batch_adapt_log_kernel<T>,
-                         dim3(persistent_grid(batch_adapt_log_kernel<T>, 0, total(PF_BLOCKS))), dim3(kBlock), 0, s, a);
+                         dim3(launch_grid(b, batch_adapt_log_kernel<T>, 0, total(PF_BLOCKS))), dim3(kBlock), 0, s, a);
       KDE_CHECK_LAUNCH();
       hipLaunchKernelGGL(batch_level1_kernel<SRC_AD>,
-                         dim3(persistent_grid(batch_level1_kernel<SRC_AD>, 0, total(PF_AD_L1))), dim3(kBlock), 0, s,
+                         dim3(launch_grid(b, batch_level1_kernel<SRC_AD>, 0, total(PF_AD_L1))), dim3(kBlock), 0, s,
                          a, int(PH_AD_L1), int(PF_AD_L1));
       KDE_CHECK_LAUNCH();
-      hipLaunchKernelGGL(batch_level2_kernel<1>, dim3(persistent_grid(batch_level2_kernel<1>, 0, ns)), dim3(kBlock), 0,
+      hipLaunchKernelGGL(batch_level2_kernel<1>, dim3(launch_grid(b, batch_level2_kernel<1>, 0, ns)), dim3(kBlock), 0,
                          s, a, int(PH_AD_L2));
       KDE_CHECK_LAUNCH();
       hipLaunchKernelGGL(batch_adapt_apply_kernel<T>,
-                         dim3(persistent_grid(batch_adapt_apply_kernel<T>, 0, total(PF_BLOCKS))), dim3(kBlock), 0, s,
+                         dim3(launch_grid(b, batch_adapt_apply_kernel<T>, 0, total(PF_BLOCKS))), dim3(kBlock), 0, s,
                          a);
       KDE_CHECK_LAUNCH();
     }
     {
       if (adaptive)
-        hipLaunchKernelGGL((batch_deposit_kernel<T, true, G>),
-                           dim3(persistent_grid(batch_deposit_kernel<T, true, G>, dep_lds, total(PF_CHUNKS))),
-                           dim3(kBlock), dep_lds, s, a, int(PH_RHO_DEP));
+        hipLaunchKernelGGL((batch_deposit_kernel<T, true, G>), dim3(unsigned(total(PF_CHUNKS))), dim3(kBlock),
+                           dep_lds, s, a);
       else
-        hipLaunchKernelGGL((batch_deposit_kernel<T, false, G>),
-                           dim3(persistent_grid(batch_deposit_kernel<T, false, G>, dep_lds, total(PF_CHUNKS))),
-                           dim3(kBlock), dep_lds, s, a, int(PH_PIL_DEP));
+        hipLaunchKernelGGL((batch_deposit_kernel<T, false, G>), dim3(unsigned(total(PF_CHUNKS))), dim3(kBlock),
+                           dep_lds, s, a);
     }
     KDE_CHECK_LAUNCH();
     hipLaunchKernelGGL(batch_level1_kernel<SRC_DEP>,
-                       dim3(persistent_grid(batch_level1_kernel<SRC_DEP>, 0, total(PF_DEP_L1))), dim3(kBlock), 0, s, a,
+                       dim3(launch_grid(b, batch_level1_kernel<SRC_DEP>, 0, total(PF_DEP_L1))), dim3(kBlock), 0, s, a,
                        int(adaptive ? PH_RHO_L1 : PH_PIL_L1), int(PF_DEP_L1));
     KDE_CHECK_LAUNCH();
     if (adaptive)
-      hipLaunchKernelGGL(batch_level2_kernel<2>, dim3(persistent_grid(batch_level2_kernel<2>, 0, ns)), dim3(kBlock), 0,
+      hipLaunchKernelGGL(batch_level2_kernel<2>, dim3(launch_grid(b, batch_level2_kernel<2>, 0, ns)), dim3(kBlock), 0,
                          s, a, int(PH_RHO_L2));
     else
-      hipLaunchKernelGGL(batch_level2_kernel<0>, dim3(persistent_grid(batch_level2_kernel<0>, 0, ns)), dim3(kBlock), 0,
+      hipLaunchKernelGGL(batch_level2_kernel<0>, dim3(launch_grid(b, batch_level2_kernel<0>, 0, ns)), dim3(kBlock), 0,
                          s, a, int(PH_PIL_L2));
     KDE_CHECK_LAUNCH();
   }
@@ -472,7 +560,7 @@ kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int
   // contiguous runs of equal tuned pass size along the LPT order (at most
   // one per entry of the tuning table, as N decreases along the order)
   for (int r = 0; r < nsets; ++r) {
-    const int bc = tuned_chunk(prec, ncv(im.order[r]));
+    const int bc = tuned_pass(prec, ncv(im.order[r])).chunk;
     if (im.bucket_bc.empty() || im.bucket_bc.back() != bc) {
       if (int(im.bucket_bc.size()) == kMaxBuckets) return fail(KDE_E_INTERNAL, "too many pass-size buckets");
       im.bucket_begin.push_back(r);
@@ -480,6 +568,14 @@ kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int
     }
   }
   im.bucket_begin.push_back(nsets);
+  for (size_t k = 0; k + 1 < im.bucket_begin.size(); ++k) {
+    int64_t units = 0;
+    for (int r = im.bucket_begin[k]; r < im.bucket_begin[k + 1]; ++r) {
+      const int64_t nt = ceil_div(ncv(im.order[r]), kCvTile);
+      units += nt * (nt + 1) / 2 * pair_groups(tuned_pass(prec, ncv(im.order[r])), B);
+      if (units > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "too many CV pair units for one launch");
+    }
+  }
   im.ws_need = layout_batch(im, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   return KDE_OK;
 }

@@ -20,6 +20,11 @@ struct BatchPlan {
   // pass-size buckets over the cost order: sets [bucket_begin[k], bucket_begin[k+1]) use bucket_bc[k]
   std::vector<int> bucket_begin, bucket_bc;
   size_t ws_need = 0;
+  // Launch shape of the phase kernels: true, about as many workgroups as
+  // the device keeps resident, each looping over units (one stream owns the
+  // device); false, one workgroup per unit, so that kernels of other
+  // streams get compute units as workgroups retire (a server's slots).
+  bool resident_grids = true;
 };
 
 // A captured graph of a plan bound to one workspace.

@@ -134,18 +134,22 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
   }
 }
 
-kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h) {
+kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h,
+                        const int32_t* group_h) {
   clear_error();
   if (prec != KDE_F64 && prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
-  if (count < 1 || count > 64 || !n_max_h || !chunk_h) return fail(KDE_E_INVALID_ARG, "count must lie in [1, 64] with both arrays given");
-  return set_tuning(prec, count, n_max_h, chunk_h);
+  if (count < 1 || count > 64 || !n_max_h || !chunk_h)
+    return fail(KDE_E_INVALID_ARG, "count must lie in [1, 64] with n_max and chunk given");
+  return set_tuning(prec, count, n_max_h, chunk_h, group_h);
 }
 
-kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h) {
+kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h, int32_t* group_h) {
   clear_error();
   if (prec != KDE_F64 && prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
   if (!chunk_h) return fail(KDE_E_INVALID_ARG, "chunk_h is NULL");
-  *chunk_h = tuned_chunk(prec, N);
+  const PairTuning t = tuned_pass(prec, N);
+  *chunk_h = t.chunk;
+  if (group_h) *group_h = t.group;
   return KDE_OK;
 }
 

@@ -37,14 +37,18 @@
 
 namespace kde {
 
+// Block (tile pair p, concentration group g) with p = blockIdx.x / groups.
 template <typename T, int BC>
 __global__ void __launch_bounds__(kBlock) cv_pairs_kernel(const typename Packed<T>::type* __restrict__ packed,
-                                                         int64_t n, int ntiles, CvConsts<T> K,
+                                                         int64_t n, int groups, int gsize, CvConsts<T> K,
                                                          double* __restrict__ partials) {
   __shared__ CvSmem<T, BC> sm;
+  const int64_t p = int64_t(blockIdx.x) / groups;
+  const int g = int(int64_t(blockIdx.x) - p * groups);
   int I, J;
-  tri_decode(int64_t(blockIdx.x), I, J);
-  cv_tile_pair<T, BC>(packed, n, I, J, K, partials + int64_t(blockIdx.x) * 2 * K.B, sm);
+  tri_decode(p, I, J);
+  const int b_lo = g * gsize;
+  cv_tile_pair<T, BC>(packed, n, I, J, K, b_lo, min(K.B, b_lo + gsize), partials + p * 2 * K.B, sm);
 }
 
 // raw[0..B): Kbar sums, raw[B..2B): K sums (unnormalised); one block.
@@ -59,33 +63,38 @@ __global__ void __launch_bounds__(KDE_MAX_KAPPAS) cv_finalize_kernel(const doubl
 
 // ------------------------------------------------------------------ host
 
-// Concentrations per pass of the pair kernel, by precision and particle
-// count (kde_tune_set). The per-concentration sums do not depend on the
-// choice: each concentration accumulates the same terms in the same order
-// and the skip test is monotone in kappa. Defaults come from the autotuner
-// run on gfx950 (paper_1804_11174_amd/autotune.py).
+// Launch shape of the pair kernel, by precision and particle count
+// (kde_tune_set): concentrations per pass and per work unit. The
+// per-concentration sums do not depend on either: each concentration
+// accumulates the same terms in the same order and the skip test is
+// monotone in kappa. Defaults come from the autotuner run on gfx950
+// (paper_1804_11174_amd/autotune.py).
 namespace {
 struct TuneEntry {
   int64_t n_max;
-  int chunk;
+  PairTuning t;
 };
 std::mutex g_tune_mu;
-std::vector<TuneEntry> g_tune[2] = {{{INT64_MAX, 16}}, {{INT64_MAX, 16}}};
+std::vector<TuneEntry> g_tune[2] = {{{INT64_MAX, {16, 0}}}, {{INT64_MAX, {16, 0}}}};
 }  // namespace
 
-int tuned_chunk(int prec, int64_t n) {
+PairTuning tuned_pass(int prec, int64_t n) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  for (const TuneEntry& e : g_tune[prec]) if (n <= e.n_max) return e.chunk;
-  return g_tune[prec].back().chunk;
+  for (const TuneEntry& e : g_tune[prec]) if (n <= e.n_max) return e.t;
+  return g_tune[prec].back().t;
 }
 
-kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk) {
+kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk, const int32_t* group) {
   std::vector<TuneEntry> t;
   for (int k = 0; k < count; ++k) {
     if (chunk[k] != 4 && chunk[k] != 8 && chunk[k] != 16)
       return fail(KDE_E_INVALID_ARG, "chunk must be 4, 8 or 16 (entry %d is %d)", k, chunk[k]);
+    const int g = group ? group[k] : 0;
+    if (g < 0 || g > KDE_MAX_KAPPAS || g % chunk[k] != 0)
+      return fail(KDE_E_INVALID_ARG, "group must be 0 or a multiple of chunk up to %d (entry %d is %d)",
+                  KDE_MAX_KAPPAS, k, g);
     if (k > 0 && !(n_max[k] > n_max[k - 1])) return fail(KDE_E_INVALID_ARG, "n_max must be strictly ascending");
-    t.push_back(TuneEntry{n_max[k], chunk[k]});
+    t.push_back(TuneEntry{n_max[k], PairTuning{chunk[k], g}});
   }
   t.back().n_max = INT64_MAX;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -145,19 +154,24 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
   P* packed = static_cast<P*>(buf.packed);
   KDE_RETURN_IF(launch_pack_sorted<T>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s));
   CvConsts<T> K = make_consts<T>(kappas, B);
-  if (p.units > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "N too large for one CV launch");
+  const PairTuning tp = tuned_pass(dom->prec, n);
+  const int groups = pair_groups(tp, B), gsize = pair_group_size(tp, B);
+  if (p.units * groups > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "N too large for one CV launch");
   {
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
-    const dim3 grid{unsigned(p.units)}, block{unsigned(kBlock)};
-    switch (tuned_chunk(dom->prec, n)) {
+    const dim3 grid{unsigned(p.units * groups)}, block{unsigned(kBlock)};
+    switch (tp.chunk) {
       case 4:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, p.ntiles, K, buf.partials);
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, groups, gsize, K,
+                           buf.partials);
         break;
       case 8:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, p.ntiles, K, buf.partials);
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, groups, gsize, K,
+                           buf.partials);
         break;
       default:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, p.ntiles, K, buf.partials);
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, groups, gsize, K,
+                           buf.partials);
         break;
     }
   }

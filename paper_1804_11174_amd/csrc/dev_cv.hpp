@@ -167,9 +167,9 @@ __device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint
 
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
-                                           const IPart<T>& ip, bool valid_i, bool diag, int b0,
+                                           const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
                                            const CvConsts<T>& K, Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
-  const int nb = min(BC, K.B - b0);
+  const int nb = min(BC, b_end - b0);
   const T X0 = I0eBounds<T>::X0;
   const T tmin = T(1) / X0;
   const T rsmax = T(1) / sqrt(X0);
@@ -225,13 +225,16 @@ struct CvSmem {
 };
 
 // One unit of the pair sums: tile I (one i per thread) against tile J
-// (staged in LDS), every concentration; writes the unit's 2B partial sums
-// [Kbar sums | K sums] to `out`. Used by the one-set kernel below and by the
-// batched engine. Ends with a barrier, so the caller may reuse `sm`.
+// (staged in LDS), concentrations [b_lo, b_hi); writes those entries of the
+// tile pair's 2B partial sums [Kbar sums | K sums] at `out`. A tile pair may
+// be split over several units by concentration range: every concentration
+// accumulates the same terms in the same order whatever the range. Used by
+// the one-set kernel and by the batched engine. Ends with a barrier, so the
+// caller may reuse `sm`.
 template <typename T, int BC>
 __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __restrict__ packed, int64_t n,
-                                             int I, int J, const CvConsts<T>& K, double* __restrict__ out,
-                                             CvSmem<T, BC>& sm) {
+                                             int I, int J, const CvConsts<T>& K, int b_lo, int b_hi,
+                                             double* __restrict__ out, CvSmem<T, BC>& sm) {
   constexpr int per = Packed<T>::per_particle;
   const int tid = threadIdx.x;
   const int64_t j0 = int64_t(J) * kCvTile;
@@ -245,7 +248,7 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
   __syncthreads();
 
   const int lane = tid & 63, wave = tid >> 6;
-  for (int b0 = 0; b0 < K.B; b0 += BC) {
+  for (int b0 = b_lo; b0 < b_hi; b0 += BC) {
     Acc<T> s1[BC], s2[BC];
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
@@ -253,9 +256,9 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
       s2[bb].zero();
     }
     if (masked)
-      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, K, s1, s2);
+      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, b_hi, K, s1, s2);
     else
-      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, K, s1, s2);
+      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, b_hi, K, s1, s2);
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       double v1 = wave_sum(s1[bb].value());
@@ -269,7 +272,7 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
     if (tid < 2 * BC) {
       const int bb = tid % BC;
       const int which = tid / BC;  // 0: Kbar sums, 1: K sums
-      if (b0 + bb < K.B) {
+      if (b0 + bb < b_hi) {
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
         sm.unit_acc[which * K.B + b0 + bb] = v;
@@ -277,7 +280,11 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
     }
     __syncthreads();
   }
-  for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = sm.unit_acc[k];
+  const int nk = b_hi - b_lo;
+  for (int k = tid; k < 2 * nk; k += kBlock) {
+    const int e = (k / nk) * K.B + b_lo + k % nk;
+    out[e] = sm.unit_acc[e];
+  }
   __syncthreads();
 }
 

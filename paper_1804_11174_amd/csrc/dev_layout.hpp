@@ -81,47 +81,70 @@ __device__ __forceinline__ void stable_scatter(const T* __restrict__ x, int64_t 
   }
 }
 
-// Exclusive scan of `len` ints held in LDS, by one workgroup: each thread
-// scans a contiguous segment, the 256 segment totals are scanned, then each
-// segment is offset. `tot` is kBlock ints of LDS scratch.
-__device__ __forceinline__ void block_exclusive_scan(int* a, int len, int* tot) {
-  const int seg = (len + kBlock - 1) / kBlock;
-  const int lo = threadIdx.x * seg;
-  const int hi = min(len, lo + seg);
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += a[i];
-  tot[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int t = 0; t < kBlock; ++t) {
-      const int v = tot[t];
-      tot[t] = run;
-      run += v;
+// Exclusive scan of `len` ints in global memory, in place, by one
+// workgroup. The array is walked in tiles of 4 * kBlock: each lane holds
+// four consecutive elements, lane totals are scanned across the wave with
+// shuffles and the wave totals through LDS, and a running carry joins the
+// tiles. `tot` is kBlock / 64 ints of LDS. Every thread must call this.
+__device__ __forceinline__ void block_scan_global(int32_t* __restrict__ a, int64_t len, int* tot) {
+  constexpr int kWaves = kBlock / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int carry = 0;
+  for (int64_t t0 = 0; t0 < len; t0 += 4 * kBlock) {
+    const int64_t i0 = t0 + 4 * int64_t(threadIdx.x);
+    int v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (i0 + k < len) ? a[i0 + k] : 0;
+    const int own = v[0] + v[1] + v[2] + v[3];
+    int incl = own;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
     }
+    if (lane == 63) tot[wave] = incl;
+    __syncthreads();
+    int woff = 0, tile = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const int tw = tot[w];
+      if (w < wave) woff += tw;
+      tile += tw;
+    }
+    int run = carry + woff + incl - own;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < len) a[i0 + k] = run;
+      run += v[k];
+    }
+    carry += tile;
+    __syncthreads();  // tot is rewritten by the next tile
   }
-  __syncthreads();
-  int run = tot[threadIdx.x];
-  for (int i = lo; i < hi; ++i) {
-    const int v = a[i];
-    a[i] = run;
-    run += v;
-  }
-  __syncthreads();
 }
 
-// Whole-set stable sort by one workgroup: histogram into `base` (LDS,
-// `cells` ints), exclusive scan, then the scatter. `tot` is kBlock ints of
-// LDS scratch. Every thread of the block must call this.
+// Sort block `b` of `nblocks` over particles [lo, hi): its cell histogram,
+// counted in LDS `lh` (cells ints) with integer atomics, is stored as
+// column b of the cell-major [cells][nblocks] array `hist`, so that one
+// exclusive scan of `hist` gives every block its stable scatter bases.
+template <typename T>
+__device__ __forceinline__ void sort_hist_block(const T* __restrict__ x, int64_t lo, int64_t hi, double L, int cells,
+                                                int b, int nblocks, int* lh, int32_t* __restrict__ hist) {
+  for (int c = threadIdx.x; c < cells; c += kBlock) lh[c] = 0;
+  __syncthreads();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&lh[cell_of(x[i], L, cells)], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += kBlock) hist[int64_t(c) * nblocks + b] = lh[c];
+}
+
+// Sort block `b`: load its scanned bases from `hist` into LDS `base` and
+// scatter particles [lo, hi) stably.
 template <typename T, typename P>
-__device__ __forceinline__ void sort_set_one_block(const T* __restrict__ x, int64_t n, double L, int cells,
-                                                   int* base, int* tot, P* __restrict__ packed) {
-  for (int c = threadIdx.x; c < cells; c += kBlock) base[c] = 0;
+__device__ __forceinline__ void sort_scatter_block(const T* __restrict__ x, int64_t lo, int64_t hi, double L,
+                                                   int cells, int b, int nblocks, const int32_t* __restrict__ hist,
+                                                   int* base, P* __restrict__ packed, int32_t* __restrict__ perm) {
+  for (int c = threadIdx.x; c < cells; c += kBlock) base[c] = hist[int64_t(c) * nblocks + b];
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) atomicAdd(&base[cell_of(x[i], L, cells)], 1);
-  __syncthreads();
-  block_exclusive_scan(base, cells, tot);
-  stable_scatter<T, P>(x, 0, n, L, cells, base, packed, nullptr);
+  stable_scatter<T, P>(x, lo, hi, L, cells, base, packed, perm);
 }
 
 }  // namespace kde

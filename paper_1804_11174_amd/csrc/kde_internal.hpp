@@ -98,9 +98,22 @@ kde_status check_lds(size_t bytes);
 kde_status check_workspace(void* ws, size_t ws_bytes, size_t need);
 size_t elem_size(int prec);
 
-// Concentrations per pass of the pair kernel for (precision, N).
-int tuned_chunk(int prec, int64_t n);
-kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk);
+// Launch shape of the pair kernel for (precision, N): `chunk`
+// concentrations per pass, `group` concentrations per work unit (a
+// multiple of chunk; 0 = all of them).
+struct PairTuning {
+  int chunk;
+  int group;
+};
+PairTuning tuned_pass(int prec, int64_t n);
+kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk, const int32_t* group);
+
+// Concentrations per work unit, and units per tile pair, for B values.
+inline int pair_group_size(const PairTuning& t, int B) { return (t.group > 0 && t.group < B) ? t.group : B; }
+inline int pair_groups(const PairTuning& t, int B) {
+  const int g = pair_group_size(t, B);
+  return (B + g - 1) / g;
+}
 
 // ----------------------------------------------------- shared launch plans
 

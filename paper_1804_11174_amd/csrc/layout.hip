@@ -36,41 +36,13 @@ __global__ void __launch_bounds__(kBlock) sort_hist_kernel(const T* __restrict__
                                                           int cells, int64_t chunk,
                                                           int32_t* __restrict__ hist) {
   extern __shared__ int32_t lh[];
-  for (int c = threadIdx.x; c < cells; c += kBlock) lh[c] = 0;
-  __syncthreads();
   const int64_t lo = int64_t(blockIdx.x) * chunk;
-  const int64_t hi = min(n, lo + chunk);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&lh[cell_of(x[i], L, cells)], 1);
-  __syncthreads();
-  for (int c = threadIdx.x; c < cells; c += kBlock) hist[int64_t(c) * gridDim.x + blockIdx.x] = lh[c];
+  sort_hist_block<T>(x, lo, min(n, lo + chunk), L, cells, blockIdx.x, gridDim.x, lh, hist);
 }
 
-// Exclusive scan of `len` ints in place, one workgroup: each thread scans a
-// contiguous segment, then the segment totals are scanned in LDS.
 __global__ void __launch_bounds__(kBlock) exclusive_scan_kernel(int32_t* __restrict__ a, int64_t len) {
-  __shared__ int32_t tot[kBlock];
-  const int64_t seg = (len + kBlock - 1) / kBlock;
-  const int64_t lo = int64_t(threadIdx.x) * seg;
-  const int64_t hi = min(len, lo + seg);
-  int32_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += a[i];
-  tot[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int t = 0; t < kBlock; ++t) {
-      int32_t v = tot[t];
-      tot[t] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  int32_t run = tot[threadIdx.x];
-  for (int64_t i = lo; i < hi; ++i) {
-    int32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
+  __shared__ int tot[kBlock / 64];
+  block_scan_global(a, len, tot);
 }
 
 // Stable scatter: the block walks its chunk in rounds of 256 particles; a
@@ -83,10 +55,8 @@ __global__ void __launch_bounds__(kBlock) sort_scatter_kernel(const T* __restric
                                                              P* __restrict__ packed,
                                                              int32_t* __restrict__ perm) {
   extern __shared__ int32_t base[];
-  for (int c = threadIdx.x; c < cells; c += kBlock) base[c] = base_in[int64_t(c) * gridDim.x + blockIdx.x];
-  __syncthreads();
   const int64_t lo = int64_t(blockIdx.x) * chunk;
-  stable_scatter<T, P>(x, lo, min(n, lo + chunk), L, cells, base, packed, perm);
+  sort_scatter_block<T, P>(x, lo, min(n, lo + chunk), L, cells, blockIdx.x, gridDim.x, base_in, base, packed, perm);
 }
 
 template <typename T>

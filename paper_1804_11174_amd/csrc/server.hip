@@ -4,12 +4,20 @@
 // its first n_cv particles, pilot deposit at kappa*, adaptive widths,
 // adaptive deposit), exactly as one set of a batch. Requests wait in a FIFO
 // queue. A scheduler thread admits them into slots: a slot is a HIP stream
-// (default priority) with a pinned staging buffer; admission takes up to
-// `max_batch` requests from the head of the queue whose workspaces fit
-// together in the free part of the arena (first fit), plans them as one
-// batch and enqueues its phase kernels on the slot's stream, then records
-// an event. Requests that arrive while others run are admitted as soon as a
-// slot and arena space free up, and slots run concurrently on the device.
+// (default priority) with a pinned staging buffer. Requests are large or
+// small by estimated work. Large ones run alone, at most `large_slots` at
+// a time, in arrival order: sharing the device among several large solves
+// would stretch each of them, and they set the latency tail. When a slot is
+// free and no large request may start, the oldest small request heads a
+// new batch, joined by up to `max_batch - 1` later small requests of
+// comparable cost (between a quarter and twice the head's estimated work,
+// so that none waits on a much longer one inside a batch) whose workspaces
+// fit together in the free part of the arena (first fit). The batch's phase
+// kernels are enqueued on the slot's stream
+// with one workgroup per work unit, so slots, and other streams such as
+// resident PIC sessions, share the compute units as workgroups retire; then
+// an event is recorded. Requests that arrive while others run are admitted
+// as soon as a slot and arena space free up.
 // A request larger than the whole budget is refused at submission. Because
 // a set's results do not depend on the other sets of its batch, every
 // request gets the same bits alone or in any mix. Latency is completion
@@ -92,13 +100,28 @@ struct Pending {
   kde_batch_set req;
   Clock::time_point arrival;
   size_t alone_bytes;
+  double cost;  // estimated work (request_cost)
 };
+
+// Estimated work of a request in term evaluations: the CV pair sums, the
+// two deposits, and a fixed per-request overhead of about as many terms as
+// the device evaluates in 20 microseconds.
+static double request_cost(const kde_batch_set& e, int B) {
+  const double ncv = double(e.n_cv);
+  return double(B) * ncv * (ncv - 1.0) / 2.0 + 2.0 * double(e.N) * double(e.M) + 5.0e7;
+}
+
+static bool joins(double cost, double head) { return cost <= 2.0 * head && cost >= 0.25 * head; }
+
+// Requests of the queue scanned for batch partners per admission.
+constexpr size_t kAdmitScan = 256;
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   void* staging = nullptr;
   bool busy = false;
+  bool large = false;  // running a large request
   size_t off = 0, bytes = 0;
   std::vector<Pending> reqs;
   Clock::time_point started;
@@ -116,6 +139,8 @@ struct kde_server {
   std::vector<double> kappas;
   char* arena = nullptr;
   size_t budget = 0;
+  int large_slots = 1;
+  double large_terms = 2.0e9;
   ArenaAlloc alloc;
   std::vector<Slot> slots;
   std::deque<Pending> queue;
@@ -165,29 +190,53 @@ static void finish_slot(kde_server* s, Slot& sl, Clock::time_point t) {
   sl.busy = false;
 }
 
-// Admit requests from the head of the queue into free slots (lock held).
+// Admit queued requests into free slots (lock held). A large request runs
+// alone, and no more than `large_slots` of them at a time, oldest first; a
+// small request may pass queued large ones and heads a batch of small
+// partners of comparable cost. A head whose workspace does not fit waits
+// (and so do the requests of its class behind it).
 static void admit(kde_server* s) {
   for (Slot& sl : s->slots) {
     if (s->queue.empty()) return;
     if (sl.busy) continue;
+    int large_running = 0;
+    for (const Slot& o : s->slots) large_running += (o.busy && o.large) ? 1 : 0;
+    const bool large_ok = large_running < s->large_slots;
+    const size_t scan = std::min(s->queue.size(), kAdmitScan);
+    size_t h = scan;
+    for (size_t k = 0; k < scan; ++k) {
+      const bool large = s->queue[k].cost >= s->large_terms;
+      if (!large || large_ok) {
+        h = k;
+        break;
+      }
+    }
+    if (h == scan) return;  // only large requests wait, and their slots are taken
+    const bool head_large = s->queue[h].cost >= s->large_terms;
+    const double head = s->queue[h].cost;
+    const size_t room = s->alloc.largest();
     std::vector<Pending> group;
+    std::vector<size_t> taken;
     std::vector<kde_batch_set> sets;
     BatchPlan plan;
     size_t off = 0;
-    // grow the group while the plan still fits in one free block
-    for (size_t k = 0; k < s->queue.size() && int(group.size()) < s->cfg.max_batch; ++k) {
+    for (size_t k = h; k < scan && int(group.size()) < (head_large ? 1 : s->cfg.max_batch); ++k) {
+      if (k > h && (s->queue[k].cost >= s->large_terms || !joins(s->queue[k].cost, head))) continue;
       sets.push_back(s->queue[k].req);
       BatchPlan trial;
       if (batch_plan_make(sets.data(), int(sets.size()), s->cfg.prec, s->cfg.B, s->kappas.data(), s->cfg.alpha,
                           trial) != KDE_OK ||
-          trial.ws_need > s->alloc.largest() || batch_staging_bytes(trial) > kStagingBytes) {
+          trial.ws_need > room || batch_staging_bytes(trial) > kStagingBytes) {
         sets.pop_back();
-        break;
+        if (k == h) break;
+        continue;
       }
       plan = std::move(trial);
       group.push_back(s->queue[k]);
+      taken.push_back(k);
     }
-    if (group.empty()) return;  // the head waits for space (FIFO)
+    if (group.empty()) return;  // the head waits for arena space
+    plan.resident_grids = false;
     if (!s->alloc.alloc(plan.ws_need, &off)) return;
     kde_status st = batch_plan_enqueue(plan, s->arena + off, sl.stream, sl.staging);
     hipError_t e = hipEventRecord(sl.done, sl.stream);
@@ -197,8 +246,9 @@ static void admit(kde_server* s) {
       s->alloc.release(off, plan.ws_need);
       return;
     }
-    for (size_t k = 0; k < group.size(); ++k) s->queue.pop_front();
+    for (size_t k = taken.size(); k-- > 0;) s->queue.erase(s->queue.begin() + std::ptrdiff_t(taken[k]));
     sl.busy = true;
+    sl.large = head_large;
     sl.off = off;
     sl.bytes = plan.ws_need;
     sl.reqs = std::move(group);
@@ -252,10 +302,14 @@ kde_status kde_server_create(const kde_server_config* cfg, void* arena, size_t b
   if (cfg->nslots < 1 || cfg->nslots > 64) return fail(KDE_E_INVALID_ARG, "nslots must lie in [1, 64]");
   if (cfg->max_batch < 1 || cfg->max_batch > 1024) return fail(KDE_E_INVALID_ARG, "max_batch must lie in [1, 1024]");
   if (!std::isfinite(cfg->alpha) || cfg->alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0");
+  if (cfg->large_slots < 0 || !(cfg->large_terms >= 0.0) || !std::isfinite(cfg->large_terms))
+    return fail(KDE_E_INVALID_ARG, "large_slots and large_terms must be >= 0 (0 = default)");
   if (!arena || reinterpret_cast<uintptr_t>(arena) % 256 != 0 || budget_bytes < 256)
     return fail(KDE_E_WORKSPACE, "arena must be 256-byte aligned and hold at least 256 bytes");
   std::unique_ptr<kde_server> s(new kde_server());
   s->cfg = *cfg;
+  s->large_slots = cfg->large_slots > 0 ? std::min(cfg->large_slots, cfg->nslots) : 1;
+  s->large_terms = cfg->large_terms > 0.0 ? cfg->large_terms : 2.0e9;
   s->kappas.assign(cfg->kappas_h, cfg->kappas_h + cfg->B);
   s->cfg.kappas_h = nullptr;
   s->arena = static_cast<char*>(arena);
@@ -301,7 +355,7 @@ kde_status kde_server_submit(kde_server* s, const kde_batch_set* req_h, uint64_t
     s->t_first = now;
     s->have_first = true;
   }
-  Pending pe{s->next_ticket++, e, now, p.ws_need};
+  Pending pe{s->next_ticket++, e, now, p.ws_need, request_cost(e, s->cfg.B)};
   s->queue.push_back(pe);
   s->submitted += 1;
   *ticket_h = pe.ticket;

@@ -112,16 +112,22 @@ def test_last_error_is_cleared_by_a_good_call():
 
 
 def test_tuning_table_round_trip():
-    kde.kde_tune_set(kde.KDE_F64, [1000, 50000, 1 << 40], [4, 8, 16])
-    assert kde.kde_tune_get(kde.KDE_F64, 10) == 4
-    assert kde.kde_tune_get(kde.KDE_F64, 1000) == 4
-    assert kde.kde_tune_get(kde.KDE_F64, 1001) == 8
-    assert kde.kde_tune_get(kde.KDE_F64, 10 ** 9) == 16
-    assert kde.kde_tune_get(kde.KDE_F64, 1 << 50) == 16   # last entry covers everything larger
+    kde.kde_tune_set(kde.KDE_F64, [1000, 50000, 1 << 40], [4, 8, 16], [4, 0, 32])
+    assert kde.kde_tune_get(kde.KDE_F64, 10) == (4, 4)
+    assert kde.kde_tune_get(kde.KDE_F64, 1000) == (4, 4)
+    assert kde.kde_tune_get(kde.KDE_F64, 1001) == (8, 0)
+    assert kde.kde_tune_get(kde.KDE_F64, 10 ** 9) == (16, 32)
+    assert kde.kde_tune_get(kde.KDE_F64, 1 << 50) == (16, 32)   # last entry covers everything larger
+    kde.kde_tune_set(kde.KDE_F64, [1 << 40], [8])                # no group column: whole list per unit
+    assert kde.kde_tune_get(kde.KDE_F64, 10) == (8, 0)
     with pytest.raises(kde.KdeError):
         kde.kde_tune_set(kde.KDE_F64, [10], [5])
     with pytest.raises(kde.KdeError):
         kde.kde_tune_set(kde.KDE_F64, [10, 5], [4, 8])
+    with pytest.raises(kde.KdeError):                           # group not a multiple of chunk
+        kde.kde_tune_set(kde.KDE_F64, [10], [8], [12])
+    with pytest.raises(kde.KdeError):                           # group beyond the kappa limit
+        kde.kde_tune_set(kde.KDE_F64, [10], [16], [80])
     # restore the shipped table (or the built-in default)
     if os.path.exists(kde.TUNE_FILE):
         kde.load_tuning(kde.TUNE_FILE)

@@ -167,7 +167,9 @@ def test_bad_arguments_raise(gpu):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pass_size_changes_nothing(gpu, dtype):
-    """The tuned pass size (concentrations per pass) must not change any bit."""
+    """The tuned pass size (concentrations per pass) and the split of a
+    tile pair over workgroups by concentration range must not change any
+    bit (20 concentrations, so the last group is ragged)."""
     import torch
     p = W.plain_small()
     prec = gpu.KDE_F64 if dtype == "f64" else gpu.KDE_F32
@@ -175,8 +177,8 @@ def test_pass_size_changes_nothing(gpu, dtype):
     kap = W.log_kappas(1.0, 1e4, 20)
     outs = []
     try:
-        for c in (4, 8, 16):
-            gpu.kde_tune_set(prec, [1 << 62], [c])
+        for c, g in ((4, 0), (8, 0), (16, 0), (4, 4), (4, 8), (8, 8), (16, 16), (8, 24)):
+            gpu.kde_tune_set(prec, [1 << 62], [c], [g])
             outs.append(run_gpu_cv(gpu, x, p.L, kap, dtype))
     finally:
         if __import__("os").path.exists(gpu.TUNE_FILE):

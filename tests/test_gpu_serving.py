@@ -207,3 +207,32 @@ def test_server_budget_admission(gpu):
         assert e.value.status == gpu.KDE_E_BUDGET
     finally:
         srv.close()
+
+
+def test_server_large_requests_run_alone_in_order(gpu):
+    """With every request classed large (threshold of one term), requests
+    run one at a time in arrival order, each in a batch of its own, even
+    with several free slots; small ones (default threshold) still batch."""
+    import time
+    import torch
+    kappas = W.log_kappas(1.0, 1e4, 16)
+    reqs = make_requests(6, seed=3, n_lo=3000, n_hi=9000)
+    outs = [(torch.empty(16, dtype=torch.float64, device="cuda"), torch.empty(M, dtype=torch.float64, device="cuda"),
+             torch.empty(M, dtype=torch.float64, device="cuda"), torch.empty(x.shape[0], dtype=x.dtype, device="cuda"),
+             torch.empty(1, dtype=torch.float64, device="cuda")) for x, L, M in reqs]
+    srv = gpu.Server(kappas, budget_bytes=1 << 30, nslots=4, max_batch=8, large_slots=1, large_terms=1.0)
+    try:
+        sub, tickets = [], []
+        for (x, L, M), o in zip(reqs, outs):
+            sub.append(time.perf_counter())
+            tickets.append(srv.submit(gpu.Server.request(x, L, M, o)))
+        srv.drain()
+        res = [srv.poll(t) for t in tickets]
+    finally:
+        srv.close()
+    assert all(r is not None and r["status"] == 0 and r["batch_size"] == 1 for r in res)
+    start = [s + r["queue_s"] for s, r in zip(sub, res)]
+    end = [s + r["latency_s"] for s, r in zip(sub, res)]
+    assert start == sorted(start), "large requests must start in arrival order"
+    for k in range(len(res) - 1):
+        assert end[k] <= start[k + 1] + 5e-4, f"large requests {k} and {k + 1} overlapped"
