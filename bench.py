@@ -24,6 +24,7 @@ its dominant kernels, on the stream they are launched on.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -38,20 +39,55 @@ if ROOT not in sys.path:
 
 METRIC = "CV pair-evals/s, particles/s at 1e-6 rel err; p50/p99 solve latency vs plain"
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 vector lane-operations/s
-# (FP64 and non-packed FP32 alike); HBM3E 8 TB/s.
-PEAK_VALU_OPS = 256 * 64 * 2.4e9
+# MI355X published vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s,
+# counting a fused multiply-add as two flops. In lane-operations (an FMA,
+# a multiply, an add, a min or a transcendental each count one) that is
+# 39.3e12/s in double (256 CUs x 64 lanes x 2.4 GHz) and 78.6e12/s in float
+# (twice the lanes per clock, reached with packed FP32 instructions, which
+# this build does not emit). HBM3E 8 TB/s.
+PEAK_LANE_OPS = {"f64": 78.6e12 / 2, "f32": 157.3e12 / 2}
 PEAK_HBM = 8.0e12
 
-# Algorithmic VALU operations per evaluated (pair, kappa) term of the CV
-# pair sums, large-argument branch, counted from the formulas: both terms'
-# exponent products, two exponentials, the Bessel polynomial and the
-# products and accumulations. An exponential counts as its range reduction
-# plus polynomial (15 operations) in double and as one transcendental
-# issued at a quarter of the VALU rate (4) in float; compensated float
-# accumulation counts 4 per add.
-OPS_PER_TERM = {"f64": 51, "f32": 28}
+# Algorithmic lane-operations per evaluated (pair, kappa) term of the CV
+# pair sums, large-argument branch, counted from the formulas (the small-
+# argument power series of I0 is costlier, so this undercounts the work
+# for small kappa):
+#   f64: K term: exponent product 1 + exponential 18 (clamp 1, range
+#        reduction 4, degree-13 polynomial 13) = 19; Kbar term: exponent
+#        product 1 + exponential 18 + Bessel argument and its square-root
+#        factor with their clamps 4 + degree-12 polynomial 12 + two products
+#        = 37; two accumulations 2. Total 58.
+#   f32: K term: product 1 + exponential 1 = 2; Kbar term: product 1 +
+#        exponential 1 + argument and factor with clamps 4 + degree-5
+#        polynomial 5 + two products = 13; two compensated (Kahan)
+#        accumulations of 4 = 8. Total 23.
+OPS_PER_TERM = {"f64": 58, "f32": 23}
 SKIP_EXPONENT = 70.0
+
+# HBM bytes per launch of the pair kernel on the paper-scale scan, from the
+# FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
+# scaled by a 1 GiB copy's readings (bytes read = 2.0 x FETCH_SIZE, bytes
+# written = 1.0 x WRITE_SIZE); valid only for the kernel sources they were
+# taken on, identified by PAIR_KERNEL_SOURCES' digest.
+PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "device_bessel.hpp", "bessel_coeffs.inc", "dev_layout.hpp",
+                       "kde_internal.hpp")
+PAIR_TRAFFIC = {"digest": "c676dc68de44fc03",
+                "f64": {"fetch_kib": 4572.0, "write_kib": 16448.0},
+                "f32": {"fetch_kib": 1161.0, "write_kib": 16448.0}}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def pair_kernel_traffic(prec):
+    """HBM bytes per pair-kernel launch, or None once its sources differ
+    from those the counters were taken on."""
+    h = hashlib.sha256()
+    for f in PAIR_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1804_11174_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != PAIR_TRAFFIC["digest"]:
+        return None
+    c = PAIR_TRAFFIC[prec]
+    return (FETCH_SCALE * c["fetch_kib"] + WRITE_SCALE * c["write_kib"]) * 1024.0
 
 
 def count_evaluated_terms(x, L, kappas):
@@ -107,9 +143,10 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch", "serve"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "copy"], default="plain",
                     help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
-                         "serve: the request server beside 16 resident PIC sessions")
+                         "serve: the request server beside 16 resident PIC sessions; copy: a device copy of "
+                         "known size that calibrates the HBM byte counters")
     ap.add_argument("--sets", type=int, default=512)
     ap.add_argument("--requests", type=int, default=2000, help="serve form: requests per load point")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
@@ -139,6 +176,8 @@ def main():
     if args.form == "serve":
         args.prec = args.prec or "f32"
         return bench_serve(args, kde, W, torch, dev)
+    if args.form == "copy":
+        return bench_copy(args, torch, dev)
     args.prec = args.prec or "f64"
     prob = W.plain_paper_scale()
     L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
@@ -201,9 +240,11 @@ def main():
     evaluated = count_evaluated_terms(prob.x[:n_cv], L, kappas)
     pair_ms = kern["cv_pairs"]["avg_ms"]
     achieved = evaluated * OPS_PER_TERM[args.prec] / (pair_ms * 1e-3)
+    peak = PEAK_LANE_OPS[args.prec]
     roofline = {"bound": "alu", "kernel": "cv_pairs_kernel", "achieved": achieved / 1e12,
-                "peak": PEAK_VALU_OPS / 1e12, "unit": "Top/s (VALU lane-ops)",
-                "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+                "peak": peak / 1e12, "unit": "T lane-ops/s (FMA = 1)",
+                "frac": achieved / peak, "traffic": pair_kernel_traffic(args.prec),
+                "traffic_unit": "bytes per launch",
                 "evaluated_terms_per_launch": evaluated, "ops_per_term": OPS_PER_TERM[args.prec],
                 "kernel_avg_ms": pair_ms}
     line = {
@@ -314,6 +355,27 @@ def bench_batch(args, kde, W, torch, dev):
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(out + "\n")
+
+
+COPY_BYTES = 1 << 30
+
+
+def bench_copy(args, torch, dev):
+    """A device-to-device copy of COPY_BYTES (torch's copy kernel), the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters: it reads and
+    writes exactly COPY_BYTES per launch."""
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(json.dumps({"form": "copy", "bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES, "ms_per_copy": ms,
+                      "GB_per_s": 2 * COPY_BYTES / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def _latency_summary(lat, t_end, reqs, B):
@@ -464,7 +526,7 @@ def bench_serve(args, kde, W, torch, dev):
                      max_batch=args.max_batch, n_cv=n_cv_cap, alpha=0.5, device=dev)
     reqs = [kde.Server.request(xs[i], trace[i].problem.L, trace[i].problem.M, out_srv[i]) for i in range(R)]
 
-    def run_served(arrival):
+    def run_served(arrival, srv=srv):
         lag = np.empty(R)
         tickets = []
         t0 = time.perf_counter()
@@ -513,6 +575,17 @@ def bench_serve(args, kde, W, torch, dev):
     same = all(torch.equal(out_srv[i][2], out_pl[i][2]) and torch.equal(out_srv[i][3], out_pl[i][3]) and
                torch.equal(out_srv[i][4], out_pl[i][4]) for i in range(R))
     points.append({"offered_load": "saturated (all requests waiting at t=0)", "served": sat_sv, "plain": sat_pl})
+    # the same saturated trace under a throughput policy: no request is
+    # large, so every one may batch with requests of similar cost and run
+    # concurrently with other batches
+    srv_t = kde.Server(kappas, prec=prec, budget_bytes=args.budget_mb << 20, nslots=args.slots,
+                       max_batch=args.max_batch, n_cv=n_cv_cap, alpha=0.5, device=dev, large_terms=1e300)
+    with load:
+        lat, t_tp, mb = run_served(zero, srv_t)
+    sat_tp = _latency_summary(lat, t_tp, trace, B)
+    sat_tp.update(load.summary())
+    sat_tp["mean_batch"] = mb
+    srv_t.close()
     for f in [float(v) for v in args.loads.split(",") if v]:
         rate = f * cap_plain
         arrival = base_arrival / rate
@@ -543,6 +616,8 @@ def bench_serve(args, kde, W, torch, dev):
                        "budget_mb": args.budget_mb, "sessions": len(sessions)},
             "plain_capacity_requests_per_s": cap_plain,
             "served_over_plain_throughput": sat_sv["requests_per_s"] / sat_pl["requests_per_s"],
+            "saturated_throughput_policy": sat_tp,
+            "throughput_policy_over_plain": sat_tp["requests_per_s"] / sat_pl["requests_per_s"],
             "served_equals_plain_bitwise": bool(same),
             "load_points": points, "server_launches": stats["launches"], "input_generation_s": gen_s}
     for s_ in sessions:
