@@ -17,24 +17,18 @@ namespace kde {
 
 // ---------------------------------------------------------------- double
 
-// a * b + c in double as one three-operand v_fma_f64. The compiler's
-// two-address form (v_fmac) overwrites its addend, so a polynomial
-// coefficient kept in a register needs a copy before every use in register-
-// heavy loops; the three-operand form needs none.
+// a * b + c in double as one three-operand v_fma_f64 whose addend c, a
+// polynomial coefficient known at compile time, sits in a scalar register
+// pair. Left to itself the compiler keeps every coefficient of the kernel's
+// polynomials in vector registers for the whole loop (over 100 of them in
+// the pair kernel, which halves its occupancy) and uses the two-address
+// v_fmac, which needs a copy of the addend before each use. c must be the
+// same in every lane.
 __device__ __forceinline__ double fma3(double a, double b, double c) {
-  double d;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-  return d;
-}
-
-// The same with the addend (a polynomial coefficient) in a scalar register
-// pair, which keeps coefficient tables out of the vector register file.
-__device__ __forceinline__ double fma3s(double a, double b, double c) {
   double d;
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
   return d;
 }
-
 
 __device__ __forceinline__ double i0_series_f64(double y) {
   constexpr double c[KDE_I0E_F64_NSERIES] = KDE_I0E_F64_SERIES;
