@@ -28,6 +28,10 @@ Submodules:
 * ``density``  -- deposit, gather, pilot interpolation, adaptive widths.
 * ``pic``      -- Poisson solve, centred field, leapfrog push, session step.
 * ``adtest``   -- Anderson-Darling statistic and its asymptotic p-value.
+* ``mise``     -- closed-form MISE from Fourier coefficients (CV pins).
+* ``triangle`` -- first-order (triangular) kernel of adjustable width: the
+  kernel, its two-fold convolution (a scaled cubic B-spline), pair sums,
+  CV, deposit and gather.
 * ``update``   -- the width-update rule of Sec. II.D.
 * ``mise``     -- closed-form MISE of the von Mises KDE (used by pins).
 """

@@ -12,6 +12,10 @@ independent samples has coefficients ``rho_m c_m`` with
 ``E c_m = f_m`` and ``E |c_m - f_m|^2 = (1 - |f_m|^2)/n``, hence
 
     MISE = (2/L) sum_{m>=1} [ |f_m|^2 (1 - rho_m)^2 + rho_m^2 (1 - |f_m|^2)/n ].
+
+The same holds for any kernel, with its own coefficients in place of
+``rho_m`` (``mise_from_coeffs``; the triangle of ``triangle`` has
+``rho_m = sinc^2(pi m h / L)``).
 """
 from __future__ import annotations
 
@@ -33,6 +37,19 @@ def mise(kappa, n, L, f_coeffs):
     aa = np.zeros(m_max)
     aa[:len(a)] = a
     return (2.0 / L) * float(np.sum(aa * aa * (1.0 - rho) ** 2 + rho * rho * (1.0 - aa * aa) / n))
+
+
+def mise_from_coeffs(rho, n, L, f_coeffs):
+    """The same MISE for any kernel with Fourier coefficients ``rho[m-1]``
+    (m = 1..len(rho); the kernel's coefficients beyond are taken as zero,
+    so ``rho`` must run until they are negligible)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    a = np.asarray(f_coeffs, dtype=np.float64)
+    aa = np.zeros(max(len(rho), len(a)))
+    aa[:len(a)] = a
+    rr = np.zeros_like(aa)
+    rr[:len(rho)] = rho
+    return (2.0 / L) * float(np.sum(aa * aa * (1.0 - rr) ** 2 + rr * rr * (1.0 - aa * aa) / n))
 
 
 def int_f_squared(L, f_coeffs):

@@ -98,3 +98,54 @@ def test_transposed_gather(monkeypatch):
     _orig_gather = density.gather
     monkeypatch.setattr(density, "gather", bad)
     assert _fails(pins_k.test_gather_is_adjoint_of_deposit, 64)
+
+
+# ---------------------------------------------------------- triangle shape
+
+import tests.test_oracle_triangle as pins_t
+from oracle import triangle as tri
+
+
+def test_triangle_bspline_inner_piece_sign(monkeypatch):
+    def bad(u):
+        a = np.abs(np.asarray(u, dtype=np.float64))
+        out = np.zeros_like(a)
+        inner, outer = a <= 1.0, (a > 1.0) & (a < 2.0)
+        out[inner] = 2.0 / 3.0 - a[inner] ** 2 - 0.5 * a[inner] ** 3
+        out[outer] = (2.0 - a[outer]) ** 3 / 6.0
+        return out
+    monkeypatch.setattr(tri, "bspline3", bad)
+    assert _fails(pins_t.test_conv2_equals_quadrature, 0.3, 0.17)
+
+
+def test_triangle_missing_periodic_image(monkeypatch):
+    def bad(d, h, L):
+        r = tri.periodic_distance(d, L)
+        return tri.bspline3(r / h) / h
+    monkeypatch.setattr(tri, "conv2", bad)
+    assert _fails(pins_t.test_conv2_equals_quadrature, 0.45 * pins_t.L0, 0.5 * pins_t.L0)
+
+
+def test_triangle_kernel_without_normalisation(monkeypatch):
+    def bad(d, h, L):
+        return np.maximum(0.0, 1.0 - tri.periodic_distance(d, L) / h)
+    monkeypatch.setattr(tri, "kernel", bad)
+    assert _fails(pins_t.test_kernel_integrates_to_one, 0.7)
+
+
+def test_triangle_full_width_read_as_half_width(monkeypatch):
+    """Reading h as the full support width halves the triangle; the PIC
+    special case (linear weighting at h = dx) catches it."""
+    orig = tri.kernel
+
+    def bad(d, h, L):
+        return orig(d, 0.5 * np.asarray(h, dtype=np.float64), L)
+    monkeypatch.setattr(tri, "kernel", bad)
+    assert _fails(pins_t.test_width_dx_is_linear_weighting)
+
+
+def test_triangle_conv_at_zero_in_cv(monkeypatch):
+    """A wrong Tbar(0) in the first CV term shifts the objective by n Tbar(0)/n^2;
+    the unbiasedness pin against the Fourier MISE catches it."""
+    monkeypatch.setattr(tri, "conv2_at_zero", lambda h, L: 1.0 / np.asarray(h, dtype=np.float64))
+    assert _fails(pins_t.test_cv_is_unbiased_for_mise_minus_int_f2, 0.35)
