@@ -33,6 +33,5 @@ Submodules:
   kernel, its two-fold convolution (a scaled cubic B-spline), pair sums,
   CV, deposit and gather.
 * ``update``   -- the width-update rule of Sec. II.D.
-* ``mise``     -- closed-form MISE of the von Mises KDE (used by pins).
 """
-from . import vonmises, cv, density, pic, adtest, update, mise  # noqa: F401
+from . import vonmises, cv, density, pic, adtest, update, mise, triangle  # noqa: F401
