@@ -24,6 +24,17 @@
  *   I0e(k) = exp(-k) I0(k). Width h and concentration are related by
  *   kappa = (L / (2 pi h))^2. The grid has M nodes x_g = g L / M and every
  *   grid quantity is a point value at the nodes.
+ * Shape. kde_domain.shape selects the kernel. KDE_SHAPE_VONMISES is the
+ *   kernel above, parameterised by kappa. KDE_SHAPE_TRIANGLE is the
+ *   first-order weighting of standard PIC with an adjustable width (Sec. I;
+ *   Sec. IV compares it, with a CV-chosen width, against the other shapes):
+ *       T_h(d) = max(0, 1 - |d|/h) / h,   0 < h <= L/2,
+ *   |d| the periodic distance; h = L/M is standard PIC. Its two-fold
+ *   convolution is the cubic B-spline scaled to h (plus its periodic image
+ *   for h > L/4). For this shape every argument called kappa (kappa,
+ *   kappa_i, kappas_h) carries half-widths h instead, each in (0, L/2].
+ *   kde_adapt_widths, the batching form, sessions and the server are
+ *   defined for the von Mises shape only.
  * Memory. Pointers named *_h are HOST pointers; every other pointer is a
  *   DEVICE pointer (HBM of the current HIP device). The caller owns all
  *   memory: inputs, outputs and the workspace. The library never allocates
@@ -58,7 +69,7 @@
 extern "C" {
 #endif
 
-#define KDE_ABI_VERSION 1
+#define KDE_ABI_VERSION 2
 
 typedef int32_t kde_status;
 
@@ -84,12 +95,18 @@ enum kde_op {
   KDE_OP_ADAPT = 3
 };
 
-/* The periodic domain [0, L), its M-node grid and the particle precision.
- * Rules: L finite and > 0; 2 <= M <= 4096; prec a kde_precision value. */
+/* Kernel shapes (see "Shape" above). */
+enum kde_shape { KDE_SHAPE_VONMISES = 0, KDE_SHAPE_TRIANGLE = 1 };
+
+/* The periodic domain [0, L), its M-node grid, the particle precision and
+ * the kernel shape. Rules: L finite and > 0; 2 <= M <= 4096; prec a
+ * kde_precision value; shape a kde_shape value; reserved 0. */
 typedef struct kde_domain {
   double L;
   int32_t M;
   int32_t prec;
+  int32_t shape;
+  int32_t reserved;
 } kde_domain;
 
 /* Largest number of candidate concentrations one kde_cv_scan accepts. */
@@ -129,14 +146,18 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
  *   S2[b] = sum_{i<j} K_{kappa_b}(x_i - x_j),
  *   cv[b] = (N Kbar_b(0) + 2 S1[b]) / N^2 - 4 S2[b] / (N (N - 1)),
  * where for the von Mises kernel
- *   Kbar_kappa(d) = I0(2 kappa |cos(pi d / L)|) / (L I0(kappa)^2).
+ *   Kbar_kappa(d) = I0(2 kappa |cos(pi d / L)|) / (L I0(kappa)^2)
+ * and for the triangle of half-width h
+ *   Kbar_h(d) = (B(d/h) + B((L - d)/h)) / h,  Kbar_h(0) = 2 / (3 h),
+ * B the centred cubic B-spline.
  * argmin receives the smallest b with cv[b] == min cv (first minimum).
  *
  *   dom      : domain (host). M is not used by this op.
  *   N        : particles (>= 2).
  *   x        : device array of N positions, element type by dom->prec.
  *   B        : number of candidates, 1..KDE_MAX_KAPPAS.
- *   kappas_h : host array of B finite concentrations >= 0, strictly ascending.
+ *   kappas_h : host array of B finite concentrations >= 0, strictly ascending
+ *              (triangle: B half-widths in (0, L/2], strictly ascending).
  *   cv       : device, B doubles (output).
  *   sums     : device, 2B doubles [S1[0..B), S2[0..B)] (output) or NULL.
  *   argmin   : device, 1 int32 (output) or NULL.
@@ -144,7 +165,9 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
  *              kde_workspace_size(KDE_OP_CV_SCAN, dom, N, B) bytes.
  *   stream   : hipStream_t or NULL.
  * Terms whose exponent lies below -70 (each smaller than e^-70 times the
- * largest term of its sum) are not evaluated.
+ * largest term of its sum) are not evaluated. For the triangle, pairs
+ * outside the support of a width (d >= 2 h) contribute exactly 0 and are
+ * skipped.
  */
 kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t B,
                        const double* kappas_h, double* cv, double* sums, int32_t* argmin,
@@ -161,7 +184,10 @@ kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t 
  *   x       : device, N positions (dom->prec).
  *   kappa_i : device, N per-particle concentrations (dom->prec, each finite
  *             and >= 0), or NULL to use `kappa` for every particle.
- *   kappa   : global concentration (finite, >= 0), used when kappa_i is NULL.
+ *             (Triangle: half-widths in (0, L/2]; a particle with a
+ *             half-width outside that range makes the result NaN.)
+ *   kappa   : global concentration (finite, >= 0), used when kappa_i is NULL
+ *             (triangle: a half-width in (0, L/2]).
  *   rho     : device, M doubles (output).
  *   ws, ws_bytes: workspace of kde_workspace_size(KDE_OP_DEPOSIT, dom, N, 0).
  */
@@ -199,6 +225,7 @@ kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const voi
  *   kappa_star : finite, > 0.      alpha : finite, >= 0 (0.5 in the paper).
  *   kappa_out  : device, N values in dom->prec (output).
  *   log_geomean: device, 1 double (output) or NULL.
+ * dom->shape must be KDE_SHAPE_VONMISES.
  *   n_floored  : device, 1 int64 (output: particles whose pilot value was
  *                floored) or NULL.
  *   ws, ws_bytes: workspace of kde_workspace_size(KDE_OP_ADAPT, dom, N, 0).

@@ -24,6 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libkdepic.so")
 
 KDE_F64, KDE_F32 = 0, 1
+KDE_SHAPE_VONMISES, KDE_SHAPE_TRIANGLE = 0, 1
 KDE_OP_CV_SCAN, KDE_OP_DEPOSIT, KDE_OP_GATHER, KDE_OP_ADAPT = 0, 1, 2, 3
 KDE_MAX_KAPPAS = 64
 
@@ -37,7 +38,8 @@ class KdeError(RuntimeError):
 
 
 class kde_domain(ctypes.Structure):
-    _fields_ = [("L", ctypes.c_double), ("M", ctypes.c_int32), ("prec", ctypes.c_int32)]
+    _fields_ = [("L", ctypes.c_double), ("M", ctypes.c_int32), ("prec", ctypes.c_int32), ("shape", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class kde_batch_set(ctypes.Structure):
@@ -196,8 +198,8 @@ def _stream(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
-def _domain(L: float, M: int, prec: int) -> kde_domain:
-    return kde_domain(float(L), int(M), int(prec))
+def _domain(L: float, M: int, prec: int, shape: int = KDE_SHAPE_VONMISES) -> kde_domain:
+    return kde_domain(float(L), int(M), int(prec), int(shape), 0)
 
 
 def prec_of(t) -> int:
@@ -599,13 +601,14 @@ def _ws(nbytes: int, device) -> Tuple[Optional[int], int]:
 
 # ------------------------------------------------------ convenience layer
 
-def cv_scan(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None):
-    """CV objective over ``kappas`` (ascending) for positions ``x`` (GPU
-    tensor, float64 or float32). Returns ``(cv[B], sums[2B], argmin[1])`` as
-    GPU tensors (float64, float64, int32)."""
+def cv_scan(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None, shape: int = KDE_SHAPE_VONMISES):
+    """CV objective over ``kappas`` (ascending; half-widths for the
+    triangle shape) for positions ``x`` (GPU tensor, float64 or float32).
+    Returns ``(cv[B], sums[2B], argmin[1])`` as GPU tensors (float64,
+    float64, int32)."""
     import torch
     k = np.asarray(kappas, dtype=np.float64)
-    dom = _domain(L, 2, prec_of(x))
+    dom = _domain(L, 2, prec_of(x), shape)
     n = x.shape[0]
     cv = torch.empty(k.shape[0], dtype=torch.float64, device=x.device)
     sums = torch.empty(2 * k.shape[0], dtype=torch.float64, device=x.device)
@@ -617,11 +620,11 @@ def cv_scan(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None):
 
 
 def deposit(x, L: float, M: int, kappa: float = 0.0, kappa_i=None, ws: Optional[Workspace] = None,
-            stream=None):
+            stream=None, shape: int = KDE_SHAPE_VONMISES):
     """Grid density (M float64 values) with a global ``kappa`` or per-particle
-    ``kappa_i`` (same dtype as ``x``)."""
+    ``kappa_i`` (same dtype as ``x``); half-widths for the triangle shape."""
     import torch
-    dom = _domain(L, M, prec_of(x))
+    dom = _domain(L, M, prec_of(x), shape)
     n = x.shape[0]
     rho = torch.empty(M, dtype=torch.float64, device=x.device)
     nbytes = kde_workspace_size(KDE_OP_DEPOSIT, dom, n)
@@ -630,11 +633,11 @@ def deposit(x, L: float, M: int, kappa: float = 0.0, kappa_i=None, ws: Optional[
     return rho
 
 
-def gather(x, L: float, field, kappa: float = 0.0, kappa_i=None, stream=None):
+def gather(x, L: float, field, kappa: float = 0.0, kappa_i=None, stream=None, shape: int = KDE_SHAPE_VONMISES):
     """Field (M float64 values) interpolated to the particles (dtype of x)."""
     import torch
     M = field.shape[0]
-    dom = _domain(L, M, prec_of(x))
+    dom = _domain(L, M, prec_of(x), shape)
     n = x.shape[0]
     out = torch.empty(n, dtype=x.dtype, device=x.device)
     kde_gather(dom, n, x, kappa_i, kappa, field, out, None, 0, stream)
@@ -642,12 +645,13 @@ def gather(x, L: float, field, kappa: float = 0.0, kappa_i=None, stream=None):
 
 
 def adapt_widths(x, L: float, pilot, kappa_star: float, alpha: float = 0.5, ws: Optional[Workspace] = None,
-                 stream=None):
+                 stream=None, shape: int = KDE_SHAPE_VONMISES):
     """Per-particle concentrations from a pilot grid. Returns
-    ``(kappa_i, log_geomean[1], n_floored[1])``."""
+    ``(kappa_i, log_geomean[1], n_floored[1])``. Defined for the von Mises
+    shape only (another ``shape`` raises KdeError)."""
     import torch
     M = pilot.shape[0]
-    dom = _domain(L, M, prec_of(x))
+    dom = _domain(L, M, prec_of(x), shape)
     n = x.shape[0]
     kout = torch.empty(n, dtype=x.dtype, device=x.device)
     lg = torch.empty(1, dtype=torch.float64, device=x.device)

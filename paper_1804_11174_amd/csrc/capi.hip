@@ -41,6 +41,8 @@ kde_status check_domain(const kde_domain* dom, bool need_grid) {
   if (!std::isfinite(dom->L) || !(dom->L > 0.0)) return fail(KDE_E_INVALID_ARG, "L must be finite and > 0 (got %g)", dom->L);
   if (dom->prec != KDE_F64 && dom->prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32 (got %d)", dom->prec);
   if (need_grid && (dom->M < 2 || dom->M > kMaxM)) return fail(KDE_E_INVALID_ARG, "M must lie in [2, %d] (got %d)", kMaxM, dom->M);
+  if (dom->shape != KDE_SHAPE_VONMISES && dom->shape != KDE_SHAPE_TRIANGLE)
+    return fail(KDE_E_INVALID_ARG, "shape must be KDE_SHAPE_VONMISES or KDE_SHAPE_TRIANGLE (got %d)", dom->shape);
   return KDE_OK;
 }
 
@@ -74,7 +76,13 @@ static kde_status check_n(int64_t N, int64_t lo) {
   return KDE_OK;
 }
 
-static kde_status check_kappa(double k, const char* what) {
+// A shape parameter: a concentration >= 0, or a triangle half-width in (0, L/2].
+static kde_status check_kappa(const kde_domain* dom, double k, const char* what) {
+  if (dom->shape == KDE_SHAPE_TRIANGLE) {
+    if (!std::isfinite(k) || !(k > 0.0) || k > 0.5 * dom->L)
+      return fail(KDE_E_INVALID_ARG, "%s (a half-width) must lie in (0, L/2] (got %g)", what, k);
+    return KDE_OK;
+  }
   if (!std::isfinite(k) || k < 0.0) return fail(KDE_E_INVALID_ARG, "%s must be finite and >= 0 (got %g)", what, k);
   return KDE_OK;
 }
@@ -162,7 +170,7 @@ kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t 
   if (!x || !cv) return fail(KDE_E_INVALID_ARG, "x and cv must not be NULL");
   if (!kappas_h) return fail(KDE_E_INVALID_ARG, "kappas_h is NULL");
   for (int b = 0; b < B; ++b) {
-    KDE_RETURN_IF(check_kappa(kappas_h[b], "every kappa"));
+    KDE_RETURN_IF(check_kappa(dom, kappas_h[b], "every kappa"));
     if (b > 0 && !(kappas_h[b] > kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending (index %d)", b);
   }
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, cv_workspace_bytes(N, B, dom->prec)));
@@ -175,7 +183,7 @@ kde_status kde_deposit(const kde_domain* dom, int64_t N, const void* x, const vo
   KDE_RETURN_IF(check_domain(dom, true));
   KDE_RETURN_IF(check_n(N, 1));
   if (!x || !rho) return fail(KDE_E_INVALID_ARG, "x and rho must not be NULL");
-  if (!kappa_i) KDE_RETURN_IF(check_kappa(kappa, "kappa"));
+  if (!kappa_i) KDE_RETURN_IF(check_kappa(dom, kappa, "kappa"));
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, deposit_workspace_bytes(N, dom->M)));
   return deposit(dom, N, x, kappa_i, kappa, rho, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
@@ -188,7 +196,7 @@ kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const voi
   KDE_RETURN_IF(check_domain(dom, true));
   KDE_RETURN_IF(check_n(N, 1));
   if (!x || !field || !out) return fail(KDE_E_INVALID_ARG, "x, field and out must not be NULL");
-  if (!kappa_i) KDE_RETURN_IF(check_kappa(kappa, "kappa"));
+  if (!kappa_i) KDE_RETURN_IF(check_kappa(dom, kappa, "kappa"));
   return gather(dom, N, x, kappa_i, kappa, field, out, static_cast<hipStream_t>(stream));
 }
 
@@ -198,6 +206,7 @@ kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, con
   clear_error();
   KDE_RETURN_IF(check_domain(dom, true));
   KDE_RETURN_IF(check_n(N, 1));
+  if (dom->shape != KDE_SHAPE_VONMISES) return fail(KDE_E_INVALID_ARG, "adaptive widths are defined for the von Mises shape");
   if (!x || !pilot || !kappa_out) return fail(KDE_E_INVALID_ARG, "x, pilot and kappa_out must not be NULL");
   if (!std::isfinite(kappa_star) || !(kappa_star > 0.0)) return fail(KDE_E_INVALID_ARG, "kappa_star must be finite and > 0 (got %g)", kappa_star);
   if (!std::isfinite(alpha) || alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0 (got %g)", alpha);

@@ -29,13 +29,59 @@
 // has exponent 0 and I0e <= 1). Concentrations are ascending and the
 // exponent scales with kappa, so once every lane of a wave is below the
 // bound for one concentration, the wave skips the rest for that j.
+//
+// The first-order (triangular) shape of adjustable width (dev_tri.hpp)
+// takes the same path: sort, tile pairs, fixed-order sums, finalize, with
+// its own pair function and normalisation; the candidates are half-widths.
 #include <climits>
 #include <mutex>
 #include <vector>
 
 #include "dev_cv.hpp"
+#include "dev_tri.hpp"
 
 namespace kde {
+
+// Triangle shape: one workgroup per tile pair.
+template <typename T, int BC>
+__global__ void __launch_bounds__(kBlock) tri_pairs_kernel(const typename TriPacked<T>::type* __restrict__ packed,
+                                                          int64_t n, int cells, TriConsts<T> K,
+                                                          double* __restrict__ partials) {
+  __shared__ TriSmem<T, BC> sm;
+  int I, J;
+  tri_decode(int64_t(blockIdx.x), I, J);
+  tri_tile_pair<T, BC>(packed, n, cells, I, J, K, partials + int64_t(blockIdx.x) * 2 * K.B, sm);
+}
+
+// raw[0..B): 6 h Tbar sums, raw[B..2B): h T sums; widths h_b. One block.
+// S1 = raw1 / (6 h), S2 = raw2 / h, Tbar(0) = 2 / (3 h); the objective and
+// its first minimum as for the von Mises kernel.
+__global__ void __launch_bounds__(KDE_MAX_KAPPAS) tri_finalize_kernel(const double* __restrict__ raw, int B,
+                                                                     double n, KappaList widths,
+                                                                     double* __restrict__ cv,
+                                                                     double* __restrict__ sums,
+                                                                     int32_t* __restrict__ argmin) {
+  __shared__ double v[KDE_MAX_KAPPAS];
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const double h = widths.k[b];
+    const double S1 = raw[b] / (6.0 * h);
+    const double S2 = raw[B + b] / h;
+    const double val = (n * (2.0 / (3.0 * h)) + 2.0 * S1) / (n * n) - 4.0 * S2 / (n * (n - 1.0));
+    if (cv) cv[b] = val;
+    v[b] = val;
+    if (sums) {
+      sums[b] = S1;
+      sums[B + b] = S2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && argmin) {
+    int best = 0;
+    for (int t = 1; t < B; ++t)
+      if (v[t] < v[best]) best = t;
+    *argmin = best;
+  }
+}
 
 // Block (tile pair p, concentration group g) with p = blockIdx.x / groups.
 template <typename T, int BC>
@@ -185,8 +231,43 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
   return KDE_OK;
 }
 
+// Passes of the triangle pair kernel: widths per pass.
+constexpr int kTriPass = 8;
+
+template <typename T>
+static kde_status run_cv_tri(const kde_domain* dom, int64_t n, const T* x, int B, const double* widths,
+                             double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s) {
+  CvPlan p = make_cv_plan(n);
+  Carver c(ws, ws_bytes);
+  CvBuffers buf = carve_cv(c, p, n, B, dom->prec);
+  if (!c.fits()) return fail(KDE_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.used);
+  using P = typename TriPacked<T>::type;
+  P* packed = static_cast<P*>(buf.packed);
+  KDE_RETURN_IF((launch_pack_sorted_as<T, P>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s)));
+  const TriConsts<T> K = make_tri_consts<T>(widths, B, dom->L);
+  if (p.units > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "N too large for one CV launch");
+  {
+    TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
+    hipLaunchKernelGGL((tri_pairs_kernel<T, kTriPass>), dim3(unsigned(p.units)), dim3(kBlock), 0, s,
+                       (const P*)packed, n, p.sort.cells, K, buf.partials);
+  }
+  KDE_CHECK_LAUNCH();
+  KDE_RETURN_IF(launch_column_sum(buf.partials, p.units, 2 * B, buf.colsum, buf.raw, s));
+  KappaList kl{};
+  for (int b = 0; b < B; ++b) kl.k[b] = widths[b];
+  hipLaunchKernelGGL(tri_finalize_kernel, dim3(1), dim3(KDE_MAX_KAPPAS), 0, s, (const double*)buf.raw, B, double(n),
+                     kl, cv, sums, argmin);
+  KDE_CHECK_LAUNCH();
+  return KDE_OK;
+}
+
 kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
                    double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (dom->shape == KDE_SHAPE_TRIANGLE) {
+    if (dom->prec == KDE_F64)
+      return run_cv_tri<double>(dom, n, static_cast<const double*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
+    return run_cv_tri<float>(dom, n, static_cast<const float*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
+  }
   if (dom->prec == KDE_F64)
     return run_cv<double>(dom, n, static_cast<const double*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
   return run_cv<float>(dom, n, static_cast<const float*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);

@@ -19,7 +19,12 @@
 // interpolated linearly at each particle, its logarithms are averaged in
 // double (fixed-order reduction), and kappa_i = kappa* exp(2 alpha (log f_i
 // - log g)) is written per particle.
+//
+// The first-order (triangular) shape of adjustable width (dev_tri.hpp)
+// deposits and gathers with the same decomposition; its per-particle
+// parameter is the half-width h_i. Adaptive widths are von Mises only.
 #include "dev_density.hpp"
+#include "dev_tri.hpp"
 
 namespace kde {
 
@@ -105,6 +110,34 @@ __global__ void __launch_bounds__(kBlock) adapt_apply_kernel(const T* __restrict
   }
 }
 
+// First-order (triangular) shape: the same chunked deposit with triangles
+// (dev_tri.hpp), and a gather over the M nodes with the field in LDS.
+template <typename T, bool PER, int G>
+__global__ void __launch_bounds__(kBlock) tri_deposit_kernel(const T* __restrict__ x, const T* __restrict__ hi,
+                                                            double h_g, int64_t n, int M, double L, int chunk,
+                                                            double* __restrict__ partials) {
+  __shared__ TriDepSmem<T> sm;
+  const int64_t lo = int64_t(blockIdx.x) * chunk;
+  const int cnt = int(min(int64_t(chunk), n - lo));
+  tri_deposit_block<T, PER, G>(x, hi, h_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, sm);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) tri_gather_kernel(const T* __restrict__ x, const T* __restrict__ hi,
+                                                           double h_g, bool per, int64_t n, int M, double L,
+                                                           const double* __restrict__ field, T* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  T* tf = reinterpret_cast<T*>(dyn);
+  for (int k = threadIdx.x; k < M; k += kBlock) tf[k] = T(field[k]);
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const TriGeo<T> p = tri_geo<T>(double(x[i]), per ? double(hi[i]) : h_g, L, M);
+  SumOf<T> acc;
+  for (int g = 0; g < M; ++g) acc.add(tf[g] * tri_node(p, g, M));
+  out[i] = T((L / M) * double(p.w) * acc.value());
+}
+
 // ------------------------------------------------------------------ host
 
 size_t deposit_workspace_bytes(int64_t n, int M) {
@@ -148,6 +181,28 @@ static kde_status launch_deposit_t(const kde_domain* dom, int64_t n, const T* x,
   return KDE_OK;
 }
 
+template <typename T, bool PER>
+static kde_status launch_tri_deposit_t(const kde_domain* dom, int64_t n, const T* x, const T* hi, double h,
+                                       double* partials, int chunk, int64_t chunks, hipStream_t s) {
+  const int M = dom->M;
+  const dim3 grid{unsigned(chunks)}, block{unsigned(kBlock)};
+  KDE_RETURN_IF(check_lds(sizeof(TriDepSmem<T>)));
+  TimedLaunch timed(KDE_KERNEL_DEPOSIT, s);
+  if (M <= kBlock) {
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 1>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+  } else if (M <= 2 * kBlock) {
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 2>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+  } else if (M <= 4 * kBlock) {
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 4>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+  } else if (M <= 8 * kBlock) {
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 8>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+  } else {
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 16>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+  }
+  KDE_CHECK_LAUNCH();
+  return KDE_OK;
+}
+
 kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
                    void* ws, size_t ws_bytes, hipStream_t s) {
   const int chunk = deposit_chunk(n);
@@ -156,7 +211,19 @@ kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* 
   double* partials = c.take<double>(size_t(chunks) * dom->M);
   double* scratch = c.take<double>(column_sum_scratch(chunks, dom->M) / sizeof(double) + 1);
   if (!c.fits()) return fail(KDE_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.used);
-  if (dom->prec == KDE_F64) {
+  if (dom->shape == KDE_SHAPE_TRIANGLE) {
+    if (dom->prec == KDE_F64) {
+      const double* xx = static_cast<const double*>(x);
+      const double* hh = static_cast<const double*>(kap);
+      KDE_RETURN_IF((hh ? launch_tri_deposit_t<double, true>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)
+                        : launch_tri_deposit_t<double, false>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)));
+    } else {
+      const float* xx = static_cast<const float*>(x);
+      const float* hh = static_cast<const float*>(kap);
+      KDE_RETURN_IF((hh ? launch_tri_deposit_t<float, true>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)
+                        : launch_tri_deposit_t<float, false>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)));
+    }
+  } else if (dom->prec == KDE_F64) {
     const double* xx = static_cast<const double*>(x);
     const double* kk = static_cast<const double*>(kap);
     KDE_RETURN_IF((kk ? launch_deposit_t<double, true>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s)
@@ -173,6 +240,21 @@ kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* 
 kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
                   const double* field, void* out, hipStream_t s) {
   const dim3 grid{unsigned(ceil_div(n, kBlock))}, block{unsigned(kBlock)};
+  if (dom->shape == KDE_SHAPE_TRIANGLE) {
+    const size_t lds = size_t(dom->M) * elem_size(dom->prec);
+    KDE_RETURN_IF(check_lds(lds));
+    TimedLaunch timed(KDE_KERNEL_GATHER, s);
+    if (dom->prec == KDE_F64)
+      hipLaunchKernelGGL(tri_gather_kernel<double>, grid, block, lds, s, static_cast<const double*>(x),
+                         static_cast<const double*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
+                         static_cast<double*>(out));
+    else
+      hipLaunchKernelGGL(tri_gather_kernel<float>, grid, block, lds, s, static_cast<const float*>(x),
+                         static_cast<const float*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
+                         static_cast<float*>(out));
+    KDE_CHECK_LAUNCH();
+    return KDE_OK;
+  }
   const size_t lds = 3 * size_t(dom->M) * elem_size(dom->prec);
   KDE_RETURN_IF(check_lds(lds));
   TimedLaunch timed(KDE_KERNEL_GATHER, s);

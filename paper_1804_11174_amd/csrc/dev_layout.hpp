@@ -38,6 +38,8 @@ __device__ __forceinline__ void store_packed(double* packed, int64_t dest, doubl
   packed[2 * dest + 1] = sp;
 }
 
+__device__ __forceinline__ void store_packed(FracPos* packed, int64_t dest, double frac) { packed[dest].f = frac; }
+
 __device__ __forceinline__ void store_packed(uint32_t* packed, int64_t dest, double frac) {
   // frac in [0, 1): the nearest multiple of 2^-32, wrapped
   const double v = floor(frac * 4294967296.0 + 0.5);

@@ -1,0 +1,288 @@
+#pragma once
+// Device pieces of the first-order (triangular) shape of adjustable width:
+// the standard-PIC weighting function with its half-width chosen by the CV
+// objective (Sec. I, first-order weighting; Sec. IV, the comparison of
+// shapes and costs).
+//
+//   T_h(d)    = max(0, 1 - |d|/h) / h,                 0 < h <= L/2,
+//   Tbar_h(d) = (B(d/h) + B((L - d)/h)) / h,            d in [0, L/2],
+//   B(u)      = (max(0, 2 - u)^3 - 4 max(0, 1 - u)^3) / 6,  u >= 0,
+//
+// Tbar is the two-fold convolution (the triangle is a box convolved with
+// itself, so Tbar is the cubic B-spline); the second B term is the
+// periodic image, which only widths h > L/4 can reach. No transcendental
+// is needed anywhere: the pair sums are plain ALU work, and the support is
+// compact, so tile pairs farther apart than 2 h_max are skipped whole and,
+// within a pair of tiles, a wave stops at the first width (widest first)
+// for which every pair of the wave lies outside the support.
+//
+// Pair distances are periodic and in fractions of the period: from the
+// wrapped position / L in double, or from the 32-bit fixed-point phase in
+// float (the phase difference in wrapping integer arithmetic is the exact
+// periodic separation). Partial sums are raw: sum of B(u) * 6 and sum of
+// max(0, 1 - u); the finalize divides by 6 h and h.
+#include "dev_cv.hpp"
+#include "dev_density.hpp"
+
+namespace kde {
+
+// Per-width constants of the pair kernel. scale[b] turns a periodic
+// distance in the packed unit into u = d / h_b; `period` is the period in
+// that unit (1 or 2^32); `reach` is 2 h_max / L, the distance (in fractions
+// of the period) beyond which no width contributes; image bit b is set when
+// h_b > L/4.
+template <typename T>
+struct TriConsts {
+  int B;
+  uint64_t image;
+  double reach;
+  T period;
+  T scale[KDE_MAX_KAPPAS];
+};
+
+template <typename T>
+inline TriConsts<T> make_tri_consts(const double* widths, int B, double L) {
+  TriConsts<T> K{};
+  K.B = B;
+  const double unit = std::is_same<T, float>::value ? 1.0 / 4294967296.0 : 1.0;  // packed unit in periods
+  K.period = T(1.0 / unit);
+  double hmax = 0.0;
+  for (int b = 0; b < B; ++b) {
+    K.scale[b] = T(unit * L / widths[b]);
+    if (widths[b] > 0.25 * L) K.image |= (uint64_t(1) << b);
+    hmax = widths[b] > hmax ? widths[b] : hmax;
+  }
+  K.reach = 2.0 * hmax / L;
+  return K;
+}
+
+// Periodic distance of two packed particles in the packed unit.
+__device__ __forceinline__ double tri_dist(FracPos a, FracPos b) {
+  const double r = fabs(a.f - b.f);
+  return fmin(r, 1.0 - r);
+}
+__device__ __forceinline__ float tri_dist(uint32_t a, uint32_t b) {
+  const int32_t dd = int32_t(a - b);
+  const uint32_t m = dd < 0 ? uint32_t(-int64_t(dd)) : uint32_t(dd);
+  return float(m);
+}
+
+// Fraction of the period of a packed value.
+__device__ __forceinline__ double tri_frac(FracPos a) { return a.f; }
+__device__ __forceinline__ double tri_frac(uint32_t a) { return double(a) * (1.0 / 4294967296.0); }
+
+// Cubic B-spline times 6 and the triangle's raw value at u >= 0.
+template <typename T>
+__device__ __forceinline__ void tri_terms(T u, T& kb6, T& k1) {
+  const T a = fmax(T(0), T(2) - u);
+  const T c = fmax(T(0), T(1) - u);
+  kb6 = a * a * a - T(4) * (c * c * c);
+  k1 = c;
+}
+
+template <typename T, int BC>
+struct TriSmem {
+  typename TriPacked<T>::type tj[kCvTile];
+  double red[kBlock / 64][2 * BC];
+  double unit_acc[2 * KDE_MAX_KAPPAS];
+  int skip;
+};
+
+// One tile pair (I, J) of the triangle pair sums; writes all 2B raw
+// partials [Tbar sums x 6 h | T sums x h] to `out`. `cells` is the cell
+// count of the sort that ordered the packed particles: a tile spans the
+// cells of its first and last particle (the cell read back from a packed
+// value may differ from the sort's by one at a boundary, so two cells of
+// slack are added each way), which bounds the distance between two tiles
+// from below.
+// Ends with a barrier.
+template <typename T, int BC>
+__device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type* __restrict__ packed, int64_t n,
+                                              int cells, int I, int J, const TriConsts<T>& K,
+                                              double* __restrict__ out, TriSmem<T, BC>& sm) {
+  using P = typename TriPacked<T>::type;
+  const int tid = threadIdx.x;
+  const int64_t i0 = int64_t(I) * kCvTile, j0 = int64_t(J) * kCvTile;
+  const int ni = int(min(int64_t(kCvTile), n - i0));
+  const int nj = int(min(int64_t(kCvTile), n - j0));
+  if (tid == 0) {
+    // A position within a phase step of L packs to 0 although it sorts into
+    // the last cell; a tile whose last fraction is below its first one
+    // therefore reaches the end of the period.
+    const double c = double(cells);
+    const double fI0 = tri_frac(packed[i0]), fI1 = tri_frac(packed[i0 + ni - 1]);
+    const double fJ0 = tri_frac(packed[j0]), fJ1 = tri_frac(packed[j0 + nj - 1]);
+    const double loI = (floor(fI0 * c) - 2.0) / c;
+    const double hiI = (floor((fI1 < fI0 ? 1.0 : fI1) * c) + 3.0) / c;
+    const double loJ = (floor(fJ0 * c) - 2.0) / c;
+    const double hiJ = (floor((fJ1 < fJ0 ? 1.0 : fJ1) * c) + 3.0) / c;
+    const double gap = fmin(loJ - hiI, 1.0 + loI - hiJ);  // I precedes J in cell order
+    sm.skip = (I != J && gap >= K.reach) ? 1 : 0;
+  }
+  __syncthreads();
+  if (sm.skip) {
+    for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = 0.0;
+    __syncthreads();
+    return;
+  }
+  for (int k = tid; k < nj; k += kBlock) sm.tj[k] = packed[j0 + k];
+  const bool valid_i = tid < ni;
+  const P pi = valid_i ? packed[i0 + tid] : P{};
+  const bool diag = (I == J);
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6;
+  // passes of BC widths, widest first: [b_lo, b_hi) with b_hi descending
+  for (int b_hi = K.B; b_hi > 0; b_hi -= BC) {
+    const int b_lo = max(0, b_hi - BC);
+    SumOf<T> s1[BC], s2[BC];
+    for (int jj = 0; jj < nj; ++jj) {
+      const bool live = valid_i && (!diag || jj > tid);
+      const T r = tri_dist(pi, sm.tj[jj]);
+      bool go = true;  // uniform across the wave
+#pragma unroll
+      for (int bb = BC - 1; bb >= 0; --bb) {
+        const int b = b_lo + bb;
+        if (b < b_hi && go) {
+          const T u = r * K.scale[b];
+          const bool img = (K.image >> b) & 1;
+          go = img || !__all(!live || u >= T(2));
+          if (go) {
+            T kb6, k1;
+            tri_terms(u, kb6, k1);
+            if (img) {
+              T kb6i, k1i;
+              tri_terms((K.period - r) * K.scale[b], kb6i, k1i);
+              kb6 += kb6i;
+            }
+            s1[bb].add(live ? kb6 : T(0));
+            s2[bb].add(live ? k1 : T(0));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      const double v1 = wave_sum(s1[bb].value());
+      const double v2 = wave_sum(s2[bb].value());
+      if (lane == 0) {
+        sm.red[wave][bb] = v1;
+        sm.red[wave][BC + bb] = v2;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * BC) {
+      const int bb = tid % BC, which = tid / BC;
+      if (b_lo + bb < b_hi) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
+        sm.unit_acc[which * K.B + b_lo + bb] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = sm.unit_acc[k];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ grid pieces
+
+// A particle relative to the grid: v = x M / L split as v = g0 + delta with
+// g0 the nearest node and |delta| <= 1/2, q = dx / h and the weight 1/h.
+// The distance to node g in cells is then |k - delta| with k = g - g0
+// taken into [-M/2, M/2], which keeps float's relative accuracy near the
+// particle. A half-width outside (0, L/2] gives a NaN weight.
+template <typename T>
+struct TriGeo {
+  int g0;
+  T delta, q, w;
+};
+
+template <typename T>
+__device__ __forceinline__ TriGeo<T> tri_geo(double xi, double h, double L, int M) {
+  TriGeo<T> p;
+  const double xw = xi - L * floor(xi / L);
+  const double v = xw * (double(M) / L);
+  double g0 = floor(v + 0.5);
+  const double d = v - g0;
+  if (g0 >= double(M)) g0 -= double(M);
+  p.g0 = int(g0);
+  p.delta = T(d);
+  const bool ok = (h > 0.0) && (h <= 0.5 * L);
+  p.q = T((L / double(M)) / h);
+  p.w = ok ? T(1.0 / h) : T(NAN);
+  if (!isfinite(xi)) p.w = T(NAN);
+  return p;
+}
+
+// max(0, 1 - |d|/h) for node g (the raw triangle; the caller weights it).
+template <typename T>
+__device__ __forceinline__ T tri_node(const TriGeo<T>& p, int g, int M) {
+  int k = g - p.g0;
+  if (k > M / 2) k -= M;
+  if (k < -(M / 2)) k += M;
+  T d = fabs(T(k) - p.delta);
+  d = fmin(d, T(M) - d);
+  return fmax(T(0), T(1) - d * p.q);
+}
+
+template <typename T>
+struct TriDepSmem {
+  TriGeo<T> pg[kDepMaxChunk];
+  double red[kBlock];
+};
+
+// One deposit chunk with triangles (same layout of work and of the fixed-
+// order sums as the von Mises deposit): particles [lo, lo + cnt) onto all
+// M nodes, written to out[M], unnormalised by N. Ends with a barrier.
+template <typename T, bool PER, int G>
+__device__ __forceinline__ void tri_deposit_block(const T* __restrict__ x, const T* __restrict__ hi, double h_g,
+                                                  int M, double L, int64_t lo, int cnt, double* __restrict__ out,
+                                                  TriDepSmem<T>& sm) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < cnt; k += kBlock)
+    sm.pg[k] = tri_geo<T>(double(x[lo + k]), PER ? double(hi[lo + k]) : h_g, L, M);
+  __syncthreads();
+  const double gscale = PER ? 1.0 : 1.0 / h_g;
+  if (M <= kBlock) {
+    const int S = kBlock / M;
+    const int g = tid % M, sub = tid / M;
+    double tot = 0.0;
+    if (sub < S) {
+      SumOf<T> acc;
+      for (int p = sub; p < cnt; p += S) {
+        const T t = tri_node(sm.pg[p], g, M);
+        acc.add(PER ? sm.pg[p].w * t : t);
+      }
+      tot = acc.value();
+    }
+    sm.red[tid] = tot;
+    __syncthreads();
+    if (tid < M) {
+      double v = 0.0;
+      for (int q = 0; q < S; ++q) v += sm.red[q * M + tid];
+      out[tid] = v * gscale;
+    }
+  } else {
+    SumOf<T> acc[G];
+    for (int p = 0; p < cnt; ++p) {
+      const TriGeo<T> gp = sm.pg[p];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int g = tid + k * kBlock;
+        if (g < M) {
+          const T t = tri_node(gp, g, M);
+          acc[k].add(PER ? gp.w * t : t);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = tid + k * kBlock;
+      if (g < M) out[g] = acc[k].value() * gscale;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace kde

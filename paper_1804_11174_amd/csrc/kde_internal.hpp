@@ -144,12 +144,33 @@ struct Packed<float> {
   static constexpr int per_particle = 1;
 };
 
-// Wrap, pack and sort by cell, stably. `packed` receives
-// n * Packed<T>::per_particle elements.
+// Packed particle of the triangle-shape pair kernel: the wrapped position
+// as a fraction of the period in double (the float form uses the 32-bit
+// phase of Packed<float>).
+struct FracPos {
+  double f;
+};
 template <typename T>
-kde_status launch_pack_sorted(const T* x, int64_t n, double L, const SortPlan& plan,
-                              int32_t* hist, typename Packed<T>::type* packed, int32_t* perm,
-                              hipStream_t s);
+struct TriPacked;
+template <>
+struct TriPacked<double> {
+  using type = FracPos;
+};
+template <>
+struct TriPacked<float> {
+  using type = uint32_t;
+};
+
+// Wrap, pack and sort by cell, stably. `packed` receives n elements of P
+// (one P per particle; the double half-angle form takes two doubles).
+template <typename T, typename P>
+kde_status launch_pack_sorted_as(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist, P* packed,
+                                 int32_t* perm, hipStream_t s);
+template <typename T>
+inline kde_status launch_pack_sorted(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist,
+                                     typename Packed<T>::type* packed, int32_t* perm, hipStream_t s) {
+  return launch_pack_sorted_as<T, typename Packed<T>::type>(x, n, L, plan, hist, packed, perm, s);
+}
 
 // Deterministic column sums: out[c] = scale * sum_r in[r][c], fixed order.
 // `scratch` must hold column_sum_scratch(rows, cols) bytes.

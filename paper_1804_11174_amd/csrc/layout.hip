@@ -59,9 +59,9 @@ __global__ void __launch_bounds__(kBlock) sort_scatter_kernel(const T* __restric
   sort_scatter_block<T, P>(x, lo, min(n, lo + chunk), L, cells, blockIdx.x, gridDim.x, base_in, base, packed, perm);
 }
 
-template <typename T>
-kde_status launch_pack_sorted(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist,
-                              typename Packed<T>::type* packed, int32_t* perm, hipStream_t s) {
+template <typename T, typename P>
+kde_status launch_pack_sorted_as(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist, P* packed,
+                                 int32_t* perm, hipStream_t s) {
   const size_t lds = size_t(plan.cells) * sizeof(int32_t);
   hipLaunchKernelGGL(sort_hist_kernel<T>, dim3(plan.blocks), dim3(kBlock), lds, s, x, n, L,
                      plan.cells, plan.chunk, hist);
@@ -69,16 +69,18 @@ kde_status launch_pack_sorted(const T* x, int64_t n, double L, const SortPlan& p
   hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kBlock), 0, s, hist,
                      int64_t(plan.cells) * plan.blocks);
   KDE_CHECK_LAUNCH();
-  hipLaunchKernelGGL((sort_scatter_kernel<T, typename Packed<T>::type>), dim3(plan.blocks), dim3(kBlock), lds, s, x, n, L,
+  hipLaunchKernelGGL((sort_scatter_kernel<T, P>), dim3(plan.blocks), dim3(kBlock), lds, s, x, n, L,
                      plan.cells, plan.chunk, hist, packed, perm);
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }
 
-template kde_status launch_pack_sorted<double>(const double*, int64_t, double, const SortPlan&,
-                                               int32_t*, double*, int32_t*, hipStream_t);
-template kde_status launch_pack_sorted<float>(const float*, int64_t, double, const SortPlan&,
-                                              int32_t*, uint32_t*, int32_t*, hipStream_t);
+template kde_status launch_pack_sorted_as<double, double>(const double*, int64_t, double, const SortPlan&, int32_t*,
+                                                          double*, int32_t*, hipStream_t);
+template kde_status launch_pack_sorted_as<float, uint32_t>(const float*, int64_t, double, const SortPlan&, int32_t*,
+                                                           uint32_t*, int32_t*, hipStream_t);
+template kde_status launch_pack_sorted_as<double, FracPos>(const double*, int64_t, double, const SortPlan&, int32_t*,
+                                                           FracPos*, int32_t*, hipStream_t);
 
 // ------------------------------------------------------ deterministic sums
 

@@ -40,7 +40,10 @@ def test_library_exports_every_declared_function(lib):
 
 
 def test_abi_version_and_status_text(lib):
-    assert kde.kde_abi_version() == 1
+    import re
+    with open(os.path.join(ROOT, "include", "kde.h")) as f:
+        declared = int(re.search(r"#define KDE_ABI_VERSION (\d+)", f.read()).group(1))
+    assert kde.kde_abi_version() == declared
     assert kde.kde_status_str(0) == "ok"
     assert "argument" in kde.kde_status_str(1)
 
@@ -101,6 +104,33 @@ def test_deposit_gather_adapt_argument_checks(lib):
     assert "kappa_star" in kde.kde_last_error()
     assert lib.kde_adapt_widths(ctypes.byref(d), 10, 1, 1, 3.0, -0.5, 1, None, None, None, 0, None) == 1
     assert lib.kde_workspace_size(99, ctypes.byref(d), 10, 0, ctypes.byref(ctypes.c_size_t())) == 1
+
+
+def test_shape_argument_checks(lib):
+    """The triangle shape takes half-widths in (0, L/2]; an unknown shape and
+    adaptive widths with the triangle are refused (fake pointers: every case
+    fails before touching the device)."""
+    L = 4 * math.pi
+    tri = kde.kde_domain(L, 64, kde.KDE_F64, kde.KDE_SHAPE_TRIANGLE, 0)
+    bad = kde.kde_domain(L, 64, kde.KDE_F64, 7, 0)
+    with pytest.raises(kde.KdeError) as e:
+        kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, bad, 100)
+    assert "shape" in str(e.value)
+    assert kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, tri, 1000, 8) == \
+        kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(), 1000, 8)
+
+    def cv(widths):
+        k = np.asarray(widths, dtype=np.float64)
+        return lib.kde_cv_scan(ctypes.byref(tri), 10, 1, len(k), k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               1, None, None, None, 0, None)
+    assert cv([0.0, 1.0]) == 1 and "half-width" in kde.kde_last_error()
+    assert cv([1.0, 0.51 * L]) == 1 and "half-width" in kde.kde_last_error()
+    assert cv([1.0, 0.5 * L]) == 2  # valid widths: stops at the missing workspace
+    assert lib.kde_deposit(ctypes.byref(tri), 10, 1, None, 0.6 * L, 1, None, 0, None) == 1
+    assert "half-width" in kde.kde_last_error()
+    assert lib.kde_gather(ctypes.byref(tri), 10, 1, None, -1.0, 1, 1, None, 0, None) == 1
+    assert lib.kde_adapt_widths(ctypes.byref(tri), 10, 1, 1, 3.0, 0.5, 1, None, None, None, 0, None) == 1
+    assert "von Mises" in kde.kde_last_error()
 
 
 def test_last_error_is_cleared_by_a_good_call():
