@@ -143,10 +143,11 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "copy"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "copy"], default="plain",
                     help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
-                         "serve: the request server beside 16 resident PIC sessions; copy: a device copy of "
-                         "known size that calibrates the HBM byte counters")
+                         "serve: the request server beside 16 resident PIC sessions; tri: the first-order "
+                         "(triangular) shape with a CV-chosen width on the paper-scale positions; copy: a "
+                         "device copy of known size that calibrates the HBM byte counters")
     ap.add_argument("--sets", type=int, default=512)
     ap.add_argument("--requests", type=int, default=2000, help="serve form: requests per load point")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
@@ -178,6 +179,9 @@ def main():
         return bench_serve(args, kde, W, torch, dev)
     if args.form == "copy":
         return bench_copy(args, torch, dev)
+    if args.form == "tri":
+        args.prec = args.prec or "f64"
+        return bench_tri(args, kde, W, torch, dev)
     args.prec = args.prec or "f64"
     prob = W.plain_paper_scale()
     L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
@@ -271,6 +275,132 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob.x[:n_cv], L, kappas)
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+# Triangle shape, algorithmic lane-operations per evaluated (pair, width)
+# term: u = r * scale 1; max(0, 2 - u) and max(0, 1 - u) 4; their cubes 4;
+# the spline difference 1 (an FMA); two accumulations: 2 in double, two
+# Kahan adds of 4 in float. The per-pair distance (3-4 operations) is
+# shared by all widths and not counted.
+TRI_OPS_PER_TERM = {"f64": 12, "f32": 18}
+
+
+def count_tri_terms(x, L, widths):
+    """Exact number of (pair, width) terms of the triangle CV sums that are
+    not identically zero: pairs closer than 2 h_b, and every pair for
+    widths above L/4 (whose periodic image reaches back)."""
+    xs = np.sort(np.asarray(x, dtype=np.float64) % L)
+    n = xs.shape[0]
+    ext = np.concatenate([xs, xs + L])
+    total = 0
+    for h in widths:
+        if 2.0 * h >= L / 2:
+            total += n * (n - 1) // 2
+            continue
+        hi = np.searchsorted(ext, xs + 2.0 * h, side="left")
+        total += int(np.minimum(hi - np.arange(n) - 1, n - 1).sum())
+    return total
+
+
+def tri_cpu_baseline(x, L, widths, budget_s=12.0):
+    """The triangle oracle's direct pair sums timed on a bounded sample."""
+    from oracle import triangle as otri
+    m0 = 512
+    t0 = time.perf_counter()
+    otri.pair_sums(x[:m0], L, widths)
+    dt0 = time.perf_counter() - t0
+    rate0 = len(widths) * m0 * (m0 - 1) / 2 / max(dt0, 1e-9)
+    m = max(m0, min(int(math.sqrt(2 * budget_s * rate0 / len(widths))), x.shape[0]))
+    t0 = time.perf_counter()
+    otri.pair_sums(x[:m], L, widths)
+    dt = time.perf_counter() - t0
+    evals = len(widths) * m * (m - 1) / 2
+    return {"value": evals / dt, "unit": "CV pair-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"direct FP64 triangle pair sums (NumPy, one thread) over the first {m} particles "
+                      f"x {len(widths)} half-widths: {evals:.3e} pair-evals in {dt:.1f} s"}
+
+
+def bench_tri(args, kde, W, torch, dev):
+    """The first-order (triangular) shape with its half-width chosen by CV
+    on the paper-scale positions: CV scan of the first 65,536 particles
+    over 32 half-widths log-spaced in [L/(4M), L/2], the host reading h*,
+    then deposit of all 1,048,576 particles at h* and the gather of that
+    density back to them."""
+    prob = W.plain_paper_scale()
+    L, M, n, n_cv = prob.L, prob.M, prob.x.shape[0], prob.n_cv
+    widths = np.geomspace(0.25 * L / M, 0.5 * L, 32)
+    B = len(widths)
+    tdt = torch.float64 if args.prec == "f64" else torch.float32
+    prec = kde.KDE_F64 if args.prec == "f64" else kde.KDE_F32
+    x = torch.from_numpy(prob.x).to(dev).to(tdt).contiguous()
+    x_cv = x[:n_cv]
+    dom = kde.kde_domain(L, M, prec, kde.KDE_SHAPE_TRIANGLE, 0)
+    ws_cv, ws_dep = kde.Workspace(dev), kde.Workspace(dev)
+    p_cv, b_cv = ws_cv.get(kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom, n_cv, B))
+    p_dep, b_dep = ws_dep.get(kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom, n))
+    cv = torch.empty(B, dtype=torch.float64, device=dev)
+    am = torch.empty(1, dtype=torch.int32, device=dev)
+    am_h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    rho = torch.empty(M, dtype=torch.float64, device=dev)
+    G = torch.empty(n, dtype=tdt, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        kde.kde_cv_scan(dom, n_cv, x_cv, widths, cv, None, am, p_cv, b_cv, stream)
+        am_h.copy_(am, non_blocking=True)
+        stream.synchronize()
+        hstar = float(widths[int(am_h[0])])
+        kde.kde_deposit(dom, n, x, None, hstar, rho, p_dep, b_dep, stream)
+        kde.kde_gather(dom, n, x, None, hstar, rho, G, None, 0, stream)
+        return hstar
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kde.kde_timing_reset()
+    kde.kde_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hstar = step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    kde.kde_timing_enable(False)
+    kern = {}
+    for name, kid in (("tri_pairs", kde.KDE_KERNEL_CV_PAIRS), ("deposit", kde.KDE_KERNEL_DEPOSIT),
+                      ("gather", kde.KDE_KERNEL_GATHER)):
+        tot, cnt = kde.kde_timing_read(kid)
+        kern[name] = {"launches": cnt, "avg_ms": tot / cnt if cnt else None}
+    pair_evals = B * n_cv * (n_cv - 1) / 2
+    evaluated = count_tri_terms(prob.x[:n_cv], L, widths)
+    pair_ms = kern["tri_pairs"]["avg_ms"]
+    achieved = evaluated * TRI_OPS_PER_TERM[args.prec] / (pair_ms * 1e-3)
+    peak = PEAK_LANE_OPS[args.prec]
+    line = {
+        "metric": METRIC, "form": "tri",
+        "value": pair_evals / (ms_step * 1e-3), "unit": "CV pair-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "first-order (triangular) shape, CV-chosen half-width, paper-scale positions: "
+                               "N=1,048,576 (CV on first 65,536), L=4pi, M=256, 32 half-widths in [L/(4M), L/2]",
+                   "n": n, "n_cv": n_cv, "M": M, "B": B, "prec": args.prec, "parallelism": "single GPU"},
+        "particles_per_s": n / (ms_step * 1e-3),
+        "h_star": hstar,
+        "kernels": kern,
+        "tri_pair_kernel_pair_evals_per_s": pair_evals / (pair_ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "tri_pairs_kernel", "achieved": achieved / 1e12,
+                     "peak": peak / 1e12, "unit": "T lane-ops/s (FMA = 1)", "frac": achieved / peak,
+                     "traffic": None, "evaluated_terms_per_launch": evaluated,
+                     "ops_per_term": TRI_OPS_PER_TERM[args.prec], "kernel_avg_ms": pair_ms},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = tri_cpu_baseline(prob.x[:n_cv], L, widths)
     out = json.dumps(line)
     print(out, flush=True)
     if args.json_out:

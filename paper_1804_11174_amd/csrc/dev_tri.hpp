@@ -28,9 +28,9 @@ namespace kde {
 
 // Per-width constants of the pair kernel. scale[b] turns a periodic
 // distance in the packed unit into u = d / h_b; `period` is the period in
-// that unit (1 or 2^32); `reach` is 2 h_max / L, the distance (in fractions
-// of the period) beyond which no width contributes; image bit b is set when
-// h_b > L/4.
+// that unit (1 or 2^32); hfrac2[b] = 2 h_b / L is the distance (in
+// fractions of the period) from which width b contributes nothing;
+// `reach` is the largest of them; image bit b is set when h_b > L/4.
 template <typename T>
 struct TriConsts {
   int B;
@@ -38,6 +38,7 @@ struct TriConsts {
   double reach;
   T period;
   T scale[KDE_MAX_KAPPAS];
+  double hfrac2[KDE_MAX_KAPPAS];
 };
 
 template <typename T>
@@ -49,6 +50,7 @@ inline TriConsts<T> make_tri_consts(const double* widths, int B, double L) {
   double hmax = 0.0;
   for (int b = 0; b < B; ++b) {
     K.scale[b] = T(unit * L / widths[b]);
+    K.hfrac2[b] = 2.0 * widths[b] / L;
     if (widths[b] > 0.25 * L) K.image |= (uint64_t(1) << b);
     hmax = widths[b] > hmax ? widths[b] : hmax;
   }
@@ -85,59 +87,23 @@ struct TriSmem {
   typename TriPacked<T>::type tj[kCvTile];
   double red[kBlock / 64][2 * BC];
   double unit_acc[2 * KDE_MAX_KAPPAS];
-  int skip;
+  int bstart;
 };
 
-// One tile pair (I, J) of the triangle pair sums; writes all 2B raw
-// partials [Tbar sums x 6 h | T sums x h] to `out`. `cells` is the cell
-// count of the sort that ordered the packed particles: a tile spans the
-// cells of its first and last particle (the cell read back from a packed
-// value may differ from the sort's by one at a boundary, so two cells of
-// slack are added each way), which bounds the distance between two tiles
-// from below.
-// Ends with a barrier.
-template <typename T, int BC>
-__device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type* __restrict__ packed, int64_t n,
-                                              int cells, int I, int J, const TriConsts<T>& K,
-                                              double* __restrict__ out, TriSmem<T, BC>& sm) {
-  using P = typename TriPacked<T>::type;
+// The passes of one tile pair over widths [b_start, B), widest first; per
+// j the wave stops at the first width whose support no lane reaches (the
+// narrower ones are zero as well). LIVE_ALL: every (i, j) of the pair is
+// counted (an off-diagonal pair of full tiles), so no per-term mask.
+template <typename T, int BC, bool LIVE_ALL>
+__device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool valid_i, bool diag, int nj,
+                                           int b_start, const TriConsts<T>& K, TriSmem<T, BC>& sm) {
   const int tid = threadIdx.x;
-  const int64_t i0 = int64_t(I) * kCvTile, j0 = int64_t(J) * kCvTile;
-  const int ni = int(min(int64_t(kCvTile), n - i0));
-  const int nj = int(min(int64_t(kCvTile), n - j0));
-  if (tid == 0) {
-    // A position within a phase step of L packs to 0 although it sorts into
-    // the last cell; a tile whose last fraction is below its first one
-    // therefore reaches the end of the period.
-    const double c = double(cells);
-    const double fI0 = tri_frac(packed[i0]), fI1 = tri_frac(packed[i0 + ni - 1]);
-    const double fJ0 = tri_frac(packed[j0]), fJ1 = tri_frac(packed[j0 + nj - 1]);
-    const double loI = (floor(fI0 * c) - 2.0) / c;
-    const double hiI = (floor((fI1 < fI0 ? 1.0 : fI1) * c) + 3.0) / c;
-    const double loJ = (floor(fJ0 * c) - 2.0) / c;
-    const double hiJ = (floor((fJ1 < fJ0 ? 1.0 : fJ1) * c) + 3.0) / c;
-    const double gap = fmin(loJ - hiI, 1.0 + loI - hiJ);  // I precedes J in cell order
-    sm.skip = (I != J && gap >= K.reach) ? 1 : 0;
-  }
-  __syncthreads();
-  if (sm.skip) {
-    for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = 0.0;
-    __syncthreads();
-    return;
-  }
-  for (int k = tid; k < nj; k += kBlock) sm.tj[k] = packed[j0 + k];
-  const bool valid_i = tid < ni;
-  const P pi = valid_i ? packed[i0 + tid] : P{};
-  const bool diag = (I == J);
-  __syncthreads();
-
   const int lane = tid & 63, wave = tid >> 6;
-  // passes of BC widths, widest first: [b_lo, b_hi) with b_hi descending
-  for (int b_hi = K.B; b_hi > 0; b_hi -= BC) {
-    const int b_lo = max(0, b_hi - BC);
+  for (int b_hi = K.B; b_hi > b_start; b_hi -= BC) {
+    const int b_lo = max(b_start, b_hi - BC);
     SumOf<T> s1[BC], s2[BC];
     for (int jj = 0; jj < nj; ++jj) {
-      const bool live = valid_i && (!diag || jj > tid);
+      const bool live = LIVE_ALL || (valid_i && (!diag || jj > tid));
       const T r = tri_dist(pi, sm.tj[jj]);
       bool go = true;  // uniform across the wave
 #pragma unroll
@@ -155,8 +121,13 @@ __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type*
               tri_terms((K.period - r) * K.scale[b], kb6i, k1i);
               kb6 += kb6i;
             }
-            s1[bb].add(live ? kb6 : T(0));
-            s2[bb].add(live ? k1 : T(0));
+            if (LIVE_ALL) {
+              s1[bb].add(kb6);
+              s2[bb].add(k1);
+            } else {
+              s1[bb].add(live ? kb6 : T(0));
+              s2[bb].add(live ? k1 : T(0));
+            }
           }
         }
       }
@@ -181,6 +152,65 @@ __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type*
     }
     __syncthreads();
   }
+}
+
+// One tile pair (I, J) of the triangle pair sums; writes all 2B raw
+// partials [Tbar sums x 6 h | T sums x h] to `out`. `cells` is the cell
+// count of the sort that ordered the packed particles: a tile spans the
+// cells of its first and last particle (the cell read back from a packed
+// value may differ from the sort's by one at a boundary, so two cells of
+// slack are added each way), which bounds the distance between two tiles
+// from below by `gap`; widths with 2 h <= gap L contribute nothing to the
+// pair, and a pair farther apart than every support is skipped whole.
+// Ends with a barrier.
+template <typename T, int BC>
+__device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type* __restrict__ packed, int64_t n,
+                                              int cells, int I, int J, const TriConsts<T>& K,
+                                              double* __restrict__ out, TriSmem<T, BC>& sm) {
+  using P = typename TriPacked<T>::type;
+  const int tid = threadIdx.x;
+  const int64_t i0 = int64_t(I) * kCvTile, j0 = int64_t(J) * kCvTile;
+  const int ni = int(min(int64_t(kCvTile), n - i0));
+  const int nj = int(min(int64_t(kCvTile), n - j0));
+  if (tid == 0) {
+    // A position within a phase step of L packs to 0 although it sorts into
+    // the last cell; a tile whose last fraction is below its first one
+    // therefore reaches the end of the period.
+    const double c = double(cells);
+    const double fI0 = tri_frac(packed[i0]), fI1 = tri_frac(packed[i0 + ni - 1]);
+    const double fJ0 = tri_frac(packed[j0]), fJ1 = tri_frac(packed[j0 + nj - 1]);
+    const double loI = (floor(fI0 * c) - 2.0) / c;
+    const double hiI = (floor((fI1 < fI0 ? 1.0 : fI1) * c) + 3.0) / c;
+    const double loJ = (floor(fJ0 * c) - 2.0) / c;
+    const double hiJ = (floor((fJ1 < fJ0 ? 1.0 : fJ1) * c) + 3.0) / c;
+    const double gap = fmin(loJ - hiI, 1.0 + loI - hiJ);  // I precedes J in cell order
+    int bs = 0;
+    if (I != J) {
+      if (gap >= K.reach) {
+        bs = K.B;
+      } else {
+        while (bs < K.B && K.hfrac2[bs] <= gap) ++bs;
+      }
+    }
+    sm.bstart = bs;
+  }
+  for (int k = tid; k < 2 * K.B; k += kBlock) sm.unit_acc[k] = 0.0;
+  __syncthreads();
+  const int b_start = sm.bstart;
+  if (b_start >= K.B) {
+    for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = 0.0;
+    __syncthreads();
+    return;
+  }
+  for (int k = tid; k < nj; k += kBlock) sm.tj[k] = packed[j0 + k];
+  const bool valid_i = tid < ni;
+  const P pi = valid_i ? packed[i0 + tid] : P{};
+  const bool diag = (I == J);
+  __syncthreads();
+  if (!diag && ni == kCvTile)
+    tri_passes<T, BC, true>(pi, valid_i, diag, nj, b_start, K, sm);
+  else
+    tri_passes<T, BC, false>(pi, valid_i, diag, nj, b_start, K, sm);
   for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = sm.unit_acc[k];
   __syncthreads();
 }
