@@ -109,6 +109,12 @@ typedef struct kde_domain {
   int32_t reserved;
 } kde_domain;
 
+/* Largest concentration a CV scan accepts (kde_cv_scan, the batching form,
+ * sessions and requests): far beyond any resolvable width (kappa = 1e12 is
+ * a width of L / (2 pi 10^6)), and it keeps every exponent of the pair sums
+ * within the range the pair kernel's exponential handles without a clamp. */
+#define KDE_MAX_CV_KAPPA 1e12
+
 /* Largest number of candidate concentrations one kde_cv_scan accepts. */
 #define KDE_MAX_KAPPAS 64
 
@@ -156,8 +162,9 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
  *   N        : particles (>= 2).
  *   x        : device array of N positions, element type by dom->prec.
  *   B        : number of candidates, 1..KDE_MAX_KAPPAS.
- *   kappas_h : host array of B finite concentrations >= 0, strictly ascending
- *              (triangle: B half-widths in (0, L/2], strictly ascending).
+ *   kappas_h : host array of B concentrations in [0, KDE_MAX_CV_KAPPA],
+ *              strictly ascending (triangle: B half-widths in (0, L/2],
+ *              strictly ascending).
  *   cv       : device, B doubles (output).
  *   sums     : device, 2B doubles [S1[0..B), S2[0..B)] (output) or NULL.
  *   argmin   : device, 1 int32 (output) or NULL.
@@ -264,7 +271,7 @@ typedef struct kde_batch kde_batch;
 /* Plan a batch (host work only). The set array is copied; the device
  * buffers it points to must stay valid while the batch is run. Rules as
  * for the one-set calls: N >= 2, L finite > 0, 2 <= M <= 4096, x and rho
- * not NULL, 1 <= B <= KDE_MAX_KAPPAS finite ascending kappas >= 0, alpha
+ * not NULL, 1 <= B <= KDE_MAX_KAPPAS ascending kappas in [0, KDE_MAX_CV_KAPPA], alpha
  * finite >= 0. *out_h receives the handle (NULL on error). */
 kde_status kde_batch_plan(const kde_batch_set* sets_h, int32_t nsets, int32_t prec, int32_t B,
                           const double* kappas_h, double alpha, kde_batch** out_h);
@@ -303,7 +310,7 @@ typedef struct kde_pic_params {
   double dt;             /* time step, > 0                                        */
   int32_t B;             /* candidate concentrations of the CV scan, 1..64         */
   int32_t n_cv;          /* the scan uses the first n_cv particles, 2..N          */
-  const double* kappas_h;/* host, B finite ascending concentrations > 0 (copied)  */
+  const double* kappas_h;/* host, B ascending concentrations in (0, KDE_MAX_CV_KAPPA] (copied) */
   double alpha;          /* Silverman sensitivity (0.5 in the paper)              */
   double p_threshold;    /* significance threshold of the test (0.01)             */
   double adjust_rate;    /* relaxation rate of the width (0.05)                   */
@@ -367,7 +374,7 @@ kde_status kde_session_destroy(kde_session* s);
 typedef struct kde_server_config {
   int32_t prec;          /* KDE_F64 or KDE_F32 for every request                  */
   int32_t B;             /* candidate concentrations, 1..64                       */
-  const double* kappas_h;/* host, B finite ascending >= 0 (copied)                */
+  const double* kappas_h;/* host, B ascending in [0, KDE_MAX_CV_KAPPA] (copied)   */
   double alpha;          /* Silverman sensitivity                                 */
   int64_t n_cv;          /* cap on the CV subsample (0 = none)                    */
   int32_t nslots;        /* concurrent slots, 1..64                               */

@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvCons
     const int b_lo = int(q - p * groups) * gsize;
     int I, J;
     tri_decode(p, I, J);
-    cv_tile_pair<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), I, J, K, b_lo,
+    cv_tile_pair<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), uni32(s.cells), I, J, K, b_lo,
                         min(K.B, b_lo + gsize), uni_ptr(s.partials) + p * 2 * K.B, sm);
   }
 }
@@ -530,7 +530,8 @@ kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int
   if (prec != KDE_F64 && prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
   if (B < 1 || B > KDE_MAX_KAPPAS || !kappas_h) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d]", KDE_MAX_KAPPAS);
   for (int k = 0; k < B; ++k) {
-    if (!std::isfinite(kappas_h[k]) || kappas_h[k] < 0.0) return fail(KDE_E_INVALID_ARG, "kappa %d must be finite and >= 0", k);
+    if (!std::isfinite(kappas_h[k]) || kappas_h[k] < 0.0 || kappas_h[k] > KDE_MAX_CV_KAPPA)
+      return fail(KDE_E_INVALID_ARG, "kappa %d must lie in [0, %g]", k, KDE_MAX_CV_KAPPA);
     if (k > 0 && !(kappas_h[k] > kappas_h[k - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending");
   }
   if (!std::isfinite(alpha) || alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0");

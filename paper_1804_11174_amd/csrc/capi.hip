@@ -171,6 +171,8 @@ kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t 
   if (!kappas_h) return fail(KDE_E_INVALID_ARG, "kappas_h is NULL");
   for (int b = 0; b < B; ++b) {
     KDE_RETURN_IF(check_kappa(dom, kappas_h[b], "every kappa"));
+    if (dom->shape == KDE_SHAPE_VONMISES && kappas_h[b] > KDE_MAX_CV_KAPPA)
+      return fail(KDE_E_INVALID_ARG, "every kappa must be <= %g (got %g)", KDE_MAX_CV_KAPPA, kappas_h[b]);
     if (b > 0 && !(kappas_h[b] > kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending (index %d)", b);
   }
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, cv_workspace_bytes(N, B, dom->prec)));

@@ -40,7 +40,7 @@ namespace kde {
 template <typename T>
 struct CvConsts {
   T A[KDE_MAX_KAPPAS];     // -2 kappa (double) or -2 kappa log2(e) (float)
-  T invk[KDE_MAX_KAPPAS];  // 1 / kappa
+  T vk[KDE_MAX_KAPPAS];    // X0 / kappa: v = X0 / (2 kappa c) = vk / (2 c)
   T rsk[KDE_MAX_KAPPAS];   // 1 / sqrt(kappa)
   T em2k[KDE_MAX_KAPPAS];  // exp(-2 kappa) for the small-argument branch
   T twok[KDE_MAX_KAPPAS];  // 2 kappa
@@ -74,7 +74,9 @@ struct Acc<float> {
   __device__ __forceinline__ double value() const { return double(s) - double(c); }
 };
 
-__device__ __forceinline__ double exp_unit(double a) { return exp_nonpos_f64(a); }
+// Pair-kernel exponents lie in [-2 kappa, 0] with kappa <= KDE_MAX_CV_KAPPA
+// (checked on the host), inside the bounded exponential's domain.
+__device__ __forceinline__ double exp_unit(double a) { return exp_nonpos_f64_bounded(a); }
 __device__ __forceinline__ float exp_unit(float a) { return __builtin_amdgcn_exp2f(a); }
 
 __device__ __forceinline__ double rcp_unit(double a) { return 1.0 / a; }
@@ -98,6 +100,39 @@ struct I0eBounds<float> {
   static constexpr float X0 = KDE_I0E_F32_X0;
 };
 
+// Position of packed particle i as a fraction of the period, from its
+// packed form: the half-angle vector (cos(pi f), sin(pi f)) with
+// f in [0, 1], the double position fraction, or the 32-bit phase.
+__device__ __forceinline__ double packed_frac(const double* __restrict__ packed, int64_t i) {
+  return atan2(packed[2 * i + 1], packed[2 * i]) * 0.31830988618379067;  // 1/pi
+}
+__device__ __forceinline__ double packed_frac(const FracPos* __restrict__ packed, int64_t i) { return packed[i].f; }
+__device__ __forceinline__ double packed_frac(const uint32_t* __restrict__ packed, int64_t i) {
+  return double(packed[i]) * (1.0 / 4294967296.0);
+}
+
+// Lower bound, in fractions of the period, on the periodic distance between
+// any particle of tile [i0, i0 + ni) and any of tile [j0, j0 + nj), tiles of
+// a sort by cell (`cells` cells) with the first tile before the second; a
+// value <= 0 means no bound (overlapping or adjacent tiles). A tile spans the
+// cells of its first and last particle; the cell read back from a packed
+// value may differ from the sort's by one at a boundary (the packing
+// rounds), so two cells of slack are added each way. A position within one
+// phase step of L packs to 0 although it sorts into the last cell, so a
+// tile whose last fraction is below its first reaches the end of the period.
+template <typename P>
+__device__ __forceinline__ double tile_gap(const P* __restrict__ packed, int64_t i0, int ni, int64_t j0, int nj,
+                                           int cells) {
+  const double c = double(cells);
+  const double fI0 = packed_frac(packed, i0), fI1 = packed_frac(packed, i0 + ni - 1);
+  const double fJ0 = packed_frac(packed, j0), fJ1 = packed_frac(packed, j0 + nj - 1);
+  const double loI = (floor(fI0 * c) - 2.0) / c;
+  const double hiI = (floor((fI1 < fI0 ? 1.0 : fI1) * c) + 3.0) / c;
+  const double loJ = (floor(fJ0 * c) - 2.0) / c;
+  const double hiJ = (floor((fJ1 < fJ0 ? 1.0 : fJ1) * c) + 3.0) / c;
+  return fmin(loJ - hiI, 1.0 + loI - hiJ);
+}
+
 // Decode the J-major triangular index p -> (I, J), I <= J.
 __device__ __forceinline__ void tri_decode(int64_t p, int& I, int& J) {
   int64_t j = int64_t((sqrt(8.0 * double(p) + 1.0) - 1.0) * 0.5);
@@ -107,11 +142,23 @@ __device__ __forceinline__ void tri_decode(int64_t p, int& I, int& J) {
   I = int(p - j * (j + 1) / 2);
 }
 
-// Geometry of one pair: s^2, q = 1 - c, c, 1/(2c), 1/sqrt(2c).
+// Geometry of one pair: s^2, q = 1 - c, c, 1/(2c'), 1/sqrt(2c') with
+// c' = max(c, X0 / (X0 + S)), S the skip exponent. c' = c wherever the
+// large-argument Bessel fit is used for a term that is not negligible:
+// for a concentration with 2 kappa <= X0 + S (which takes that fit only
+// when 2 kappa c >= X0) c >= X0 / (2 kappa) >= X0 / (X0 + S); for one with
+// 2 kappa > X0 + S, a pair with c below the floor has exponent -2 kappa
+// (1 - c) < -S. Then v = X0 / (2 kappa c') <= 1 always, so the fit never
+// leaves its interval and needs no per-term clamp.
 template <typename T>
 struct Geo {
   T s2, q, c, inv2c, rs2c;
 };
+
+template <typename T>
+__device__ __forceinline__ T c_floor() {
+  return T(double(I0eBounds<T>::X0) / (double(I0eBounds<T>::X0) + kSkipExponent));
+}
 
 // i-particle state held in registers.
 template <typename T>
@@ -140,8 +187,9 @@ __device__ __forceinline__ Geo<double> pair_geo(const IPart<double>& p, const do
   g.s2 = s * s;
   g.q = g.s2 / (1.0 + c);
   g.c = c;
-  g.inv2c = 1.0 / (2.0 * c);
-  g.rs2c = 1.0 / sqrt(2.0 * c);
+  const double cf = fmax(c, c_floor<double>());
+  g.inv2c = 1.0 / (2.0 * cf);
+  g.rs2c = 1.0 / sqrt(2.0 * cf);
   return g;
 }
 
@@ -160,8 +208,9 @@ __device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint
   g.q = y * r;
   g.c = 1.0f - g.q;
   g.s2 = g.q * (2.0f - g.q);
-  g.inv2c = __builtin_amdgcn_rcpf(2.0f * g.c);
-  g.rs2c = __builtin_amdgcn_rsqf(2.0f * g.c);
+  const float cf = fmaxf(g.c, c_floor<float>());
+  g.inv2c = __builtin_amdgcn_rcpf(2.0f * cf);
+  g.rs2c = __builtin_amdgcn_rsqf(2.0f * cf);
   return g;
 }
 
@@ -171,8 +220,6 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
                                            const CvConsts<T>& K, Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
   const int nb = min(BC, b_end - b0);
   const T X0 = I0eBounds<T>::X0;
-  const T tmin = T(1) / X0;
-  const T rsmax = T(1) / sqrt(X0);
   for (int jj = 0; jj < nj; ++jj) {
     const Geo<T> g = pair_geo(ip, tj, jj);
     bool live = true;
@@ -198,12 +245,10 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
           if (R < X0) {
             t1 = K.em2k[b] * i0_series(R * R);
           } else {
-            t1 = exp_unit(Aq) * i0e_sqrt_large(g.inv2c * K.invk[b]) * (g.rs2c * K.rsk[b]);
+            t1 = exp_unit(Aq) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
           }
         } else {
-          const T t = fmin(g.inv2c * K.invk[b], tmin);
-          const T rs = fmin(g.rs2c * K.rsk[b], rsmax);
-          t1 = exp_unit(Aq) * i0e_sqrt_large(t) * rs;
+          t1 = exp_unit(Aq) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
         }
         if (MASKED) {
           t1 = live ? t1 : T(0);
@@ -222,6 +267,7 @@ struct CvSmem {
   typename Packed<T>::type tj[Packed<T>::per_particle * kCvTile];
   double red[kBlock / 64][2 * BC];
   double unit_acc[2 * KDE_MAX_KAPPAS];
+  int b_end;
 };
 
 // One unit of the pair sums: tile I (one i per thread) against tile J
@@ -231,24 +277,48 @@ struct CvSmem {
 // accumulates the same terms in the same order whatever the range. Used by
 // the one-set kernel and by the batched engine. Ends with a barrier, so the
 // caller may reuse `sm`.
+//
+// Concentrations are ascending, and a pair's K-bar exponent -2 kappa q
+// (q = 1 - cos(pi d / L), growing with the periodic distance d) is the
+// larger of its two exponents. With gap the lower bound on the distance
+// between the two tiles (from `cells`, the sort's cell count), every term
+// of a concentration with kappa q_min > S/2 (q_min = 1 - cos(pi gap), S the
+// skip exponent) is below the skip bound, so the unit stops before the
+// first such concentration; the margin of 1e-6 keeps this a subset of what
+// the per-term test would skip, so the sums are those of the full loop.
 template <typename T, int BC>
 __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __restrict__ packed, int64_t n,
-                                             int I, int J, const CvConsts<T>& K, int b_lo, int b_hi,
+                                             int cells, int I, int J, const CvConsts<T>& K, int b_lo, int b_hi,
                                              double* __restrict__ out, CvSmem<T, BC>& sm) {
   constexpr int per = Packed<T>::per_particle;
   const int tid = threadIdx.x;
-  const int64_t j0 = int64_t(J) * kCvTile;
+  const int64_t i0 = int64_t(I) * kCvTile, j0 = int64_t(J) * kCvTile;
   const int nj = int(min(int64_t(kCvTile), n - j0));
+  if (tid == 0) {
+    int be = b_hi;
+    if (I != J) {
+      const double gap = tile_gap(packed, i0, int(min(int64_t(kCvTile), n - i0)), j0, nj, cells);
+      if (gap > 0.0) {
+        const double sh = sinpi(0.5 * gap);
+        const double qmin = 2.0 * sh * sh;
+        be = b_lo;
+        while (be < b_hi && !(double(K.twok[be]) * qmin > 2.0 * kSkipExponent * (1.0 + 1e-6))) ++be;
+      }
+    }
+    sm.b_end = be;
+  }
+  for (int k = tid; k < 2 * KDE_MAX_KAPPAS; k += kBlock) sm.unit_acc[k] = 0.0;
   for (int k = tid; k < per * nj; k += kBlock) sm.tj[k] = packed[per * j0 + k];
-  const int64_t i = int64_t(I) * kCvTile + tid;
+  const int64_t i = i0 + tid;
   const bool valid_i = i < n;
   const IPart<T> ip = load_i(packed, i, valid_i);
   const bool diag = (I == J);
   const bool masked = diag || (int64_t(I + 1) * kCvTile > n);
   __syncthreads();
+  const int b_end = sm.b_end;
 
   const int lane = tid & 63, wave = tid >> 6;
-  for (int b0 = b_lo; b0 < b_hi; b0 += BC) {
+  for (int b0 = b_lo; b0 < b_end; b0 += BC) {
     Acc<T> s1[BC], s2[BC];
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
@@ -256,9 +326,9 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
       s2[bb].zero();
     }
     if (masked)
-      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, b_hi, K, s1, s2);
+      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, s1, s2);
     else
-      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, b_hi, K, s1, s2);
+      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, s1, s2);
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       double v1 = wave_sum(s1[bb].value());
@@ -272,7 +342,7 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
     if (tid < 2 * BC) {
       const int bb = tid % BC;
       const int which = tid / BC;  // 0: Kbar sums, 1: K sums
-      if (b0 + bb < b_hi) {
+      if (b0 + bb < b_end) {
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
         sm.unit_acc[which * K.B + b0 + bb] = v;
@@ -300,7 +370,7 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
   for (int b = 0; b < B; ++b) {
     const double k = kappas[b];
     K.A[b] = T(-2.0 * k * unit);
-    K.invk[b] = T(1.0 / k);
+    K.vk[b] = T(X0 / k);
     K.rsk[b] = T(1.0 / std::sqrt(k));
     K.em2k[b] = T(std::exp(-2.0 * k));
     K.twok[b] = T(2.0 * k);

@@ -69,10 +69,6 @@ __device__ __forceinline__ float tri_dist(uint32_t a, uint32_t b) {
   return float(m);
 }
 
-// Fraction of the period of a packed value.
-__device__ __forceinline__ double tri_frac(FracPos a) { return a.f; }
-__device__ __forceinline__ double tri_frac(uint32_t a) { return double(a) * (1.0 / 4294967296.0); }
-
 // Cubic B-spline times 6 and the triangle's raw value at u >= 0.
 template <typename T>
 __device__ __forceinline__ void tri_terms(T u, T& kb6, T& k1) {
@@ -156,12 +152,10 @@ __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool 
 
 // One tile pair (I, J) of the triangle pair sums; writes all 2B raw
 // partials [Tbar sums x 6 h | T sums x h] to `out`. `cells` is the cell
-// count of the sort that ordered the packed particles: a tile spans the
-// cells of its first and last particle (the cell read back from a packed
-// value may differ from the sort's by one at a boundary, so two cells of
-// slack are added each way), which bounds the distance between two tiles
-// from below by `gap`; widths with 2 h <= gap L contribute nothing to the
-// pair, and a pair farther apart than every support is skipped whole.
+// count of the sort that ordered the packed particles, which bounds the
+// distance between the two tiles from below by `gap` (tile_gap); widths
+// with 2 h <= gap L contribute nothing to the pair, and a pair farther
+// apart than every support is skipped whole.
 // Ends with a barrier.
 template <typename T, int BC>
 __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type* __restrict__ packed, int64_t n,
@@ -173,17 +167,7 @@ __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type*
   const int ni = int(min(int64_t(kCvTile), n - i0));
   const int nj = int(min(int64_t(kCvTile), n - j0));
   if (tid == 0) {
-    // A position within a phase step of L packs to 0 although it sorts into
-    // the last cell; a tile whose last fraction is below its first one
-    // therefore reaches the end of the period.
-    const double c = double(cells);
-    const double fI0 = tri_frac(packed[i0]), fI1 = tri_frac(packed[i0 + ni - 1]);
-    const double fJ0 = tri_frac(packed[j0]), fJ1 = tri_frac(packed[j0 + nj - 1]);
-    const double loI = (floor(fI0 * c) - 2.0) / c;
-    const double hiI = (floor((fI1 < fI0 ? 1.0 : fI1) * c) + 3.0) / c;
-    const double loJ = (floor(fJ0 * c) - 2.0) / c;
-    const double hiJ = (floor((fJ1 < fJ0 ? 1.0 : fJ1) * c) + 3.0) / c;
-    const double gap = fmin(loJ - hiI, 1.0 + loI - hiJ);  // I precedes J in cell order
+    const double gap = tile_gap(packed, i0, ni, j0, nj, cells);
     int bs = 0;
     if (I != J) {
       if (gap >= K.reach) {

@@ -4,7 +4,7 @@
 //
 // Two regimes (coefficients from gen_bessel_coeffs.py):
 //   x <  X0: I0(x) by its power series in y = x^2, sum_k y^k / (4^k (k!)^2);
-//   x >= X0: sqrt(x) I0e(x) = P(u), u = (1/x - C) / H, a fitted polynomial.
+//   x >= X0: sqrt(x) I0e(x) = P(v), v = X0 / x in [0, 1], a fitted polynomial.
 // The pieces are exposed separately so that the pair kernels can share the
 // per-pair factors 1/x and 1/sqrt(x) across concentrations.
 #pragma once
@@ -38,20 +38,19 @@ __device__ __forceinline__ double i0_series_f64(double y) {
   return r;
 }
 
-// sqrt(x) * I0e(x) for x >= X0, given t = 1/x.
-__device__ __forceinline__ double i0e_sqrt_large_f64(double t) {
+// sqrt(x) * I0e(x) for x >= X0, given v = X0 / x in [0, 1].
+__device__ __forceinline__ double i0e_sqrt_large_f64(double v) {
   constexpr double c[KDE_I0E_F64_NFIT] = KDE_I0E_F64_FIT;
-  const double u = (t - KDE_I0E_F64_C) * (1.0 / KDE_I0E_F64_H);
   double r = c[KDE_I0E_F64_NFIT - 1];
 #pragma unroll
-  for (int k = KDE_I0E_F64_NFIT - 2; k >= 0; --k) r = fma3(r, u, c[k]);
+  for (int k = KDE_I0E_F64_NFIT - 2; k >= 0; --k) r = fma3(r, v, c[k]);
   return r;
 }
 
 __device__ __forceinline__ double i0e_f64(double x) {
   x = fabs(x);
   if (x < KDE_I0E_F64_X0) return exp(-x) * i0_series_f64(x * x);
-  return i0e_sqrt_large_f64(1.0 / x) / sqrt(x);
+  return i0e_sqrt_large_f64(KDE_I0E_F64_X0 / x) / sqrt(x);
 }
 
 // ----------------------------------------------------------------- float
@@ -64,22 +63,23 @@ __device__ __forceinline__ float i0_series_f32(float y) {
   return r;
 }
 
-__device__ __forceinline__ float i0e_sqrt_large_f32(float t) {
+// sqrt(x) * I0e(x) for x >= X0, given v = X0 / x in [0, 1].
+__device__ __forceinline__ float i0e_sqrt_large_f32(float v) {
   constexpr float c[KDE_I0E_F32_NFIT] = KDE_I0E_F32_FIT;
-  const float u = (t - KDE_I0E_F32_C) * (1.0f / KDE_I0E_F32_H);
   float r = c[KDE_I0E_F32_NFIT - 1];
 #pragma unroll
-  for (int k = KDE_I0E_F32_NFIT - 2; k >= 0; --k) r = fmaf(r, u, c[k]);
+  for (int k = KDE_I0E_F32_NFIT - 2; k >= 0; --k) r = fmaf(r, v, c[k]);
   return r;
 }
 
-// exp(x) for x <= 0 in double: x = n ln2 + r with |r| <= ln2/2 (two-part
-// ln2, Cody and Waite), e^r by its Taylor series to degree 13 (remainder
-// below 5e-18 relative), then scaled by 2^n. Arguments below about -745
-// give 0 through the scaling (they are clamped to -1000 first); NaN gives
-// NaN. Callers pass non-positive arguments.
-__device__ __forceinline__ double exp_nonpos_f64(double x) {
-  x = (x < -1000.0) ? -1000.0 : x;  // far below the underflow limit; NaN passes through
+// exp(x) for -2^40 <= x <= 0 in double: x = n ln2 + r with |r| <= ln2/2
+// (two-part ln2, Cody and Waite), e^r by its Taylor series to degree 13
+// (remainder below 5e-18 relative), then scaled by 2^n. Arguments below
+// about -745 give 0 through the scaling (the exponent handed to ldexp is
+// limited to -2000, so its conversion to int never overflows; r stays in
+// the polynomial's range while x log2(e) keeps its units digit, which
+// |x| <= 2^40 leaves room for); NaN gives NaN.
+__device__ __forceinline__ double exp_nonpos_f64_bounded(double x) {
   const double n = __builtin_rint(x * 1.4426950408889634);
   double r = fma(-n, 0.6931471805599453094, x);
   r = fma(-n, 2.3190468138462996e-17, r);
@@ -97,7 +97,13 @@ __device__ __forceinline__ double exp_nonpos_f64(double x) {
   p = fma3(p, r, 0.5);
   p = fma3(p, r, 1.0);
   p = fma3(p, r, 1.0);
-  return __builtin_amdgcn_ldexp(p, int(n));
+  return __builtin_amdgcn_ldexp(p, int(fmax(n, -2000.0)));
+}
+
+// exp(x) for any x <= 0 (or NaN): arguments below -1000, far below the
+// underflow limit, are clamped first; then as exp_nonpos_f64_bounded.
+__device__ __forceinline__ double exp_nonpos_f64(double x) {
+  return exp_nonpos_f64_bounded((x < -1000.0) ? -1000.0 : x);  // NaN passes through
 }
 
 }  // namespace kde

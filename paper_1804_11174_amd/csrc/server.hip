@@ -297,8 +297,9 @@ kde_status kde_server_create(const kde_server_config* cfg, void* arena, size_t b
   if (cfg->prec != KDE_F64 && cfg->prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
   if (cfg->B < 1 || cfg->B > KDE_MAX_KAPPAS || !cfg->kappas_h) return fail(KDE_E_INVALID_ARG, "B must lie in [1, 64]");
   for (int b = 0; b < cfg->B; ++b)
-    if (!std::isfinite(cfg->kappas_h[b]) || cfg->kappas_h[b] < 0.0 || (b > 0 && !(cfg->kappas_h[b] > cfg->kappas_h[b - 1])))
-      return fail(KDE_E_INVALID_ARG, "kappas must be finite, >= 0 and strictly ascending");
+    if (!std::isfinite(cfg->kappas_h[b]) || cfg->kappas_h[b] < 0.0 || cfg->kappas_h[b] > KDE_MAX_CV_KAPPA ||
+        (b > 0 && !(cfg->kappas_h[b] > cfg->kappas_h[b - 1])))
+      return fail(KDE_E_INVALID_ARG, "kappas must lie in [0, %g] and be strictly ascending", KDE_MAX_CV_KAPPA);
   if (cfg->nslots < 1 || cfg->nslots > 64) return fail(KDE_E_INVALID_ARG, "nslots must lie in [1, 64]");
   if (cfg->max_batch < 1 || cfg->max_batch > 1024) return fail(KDE_E_INVALID_ARG, "max_batch must lie in [1, 1024]");
   if (!std::isfinite(cfg->alpha) || cfg->alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0");

@@ -163,7 +163,8 @@ static kde_status check_params(const kde_pic_params* p) {
   if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return fail(KDE_E_INVALID_ARG, "dt must be finite and > 0");
   if (p->B < 1 || p->B > KDE_MAX_KAPPAS || !p->kappas_h) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d]", KDE_MAX_KAPPAS);
   for (int b = 0; b < p->B; ++b) {
-    if (!std::isfinite(p->kappas_h[b]) || !(p->kappas_h[b] > 0.0)) return fail(KDE_E_INVALID_ARG, "kappas must be finite and > 0");
+    if (!std::isfinite(p->kappas_h[b]) || !(p->kappas_h[b] > 0.0) || p->kappas_h[b] > KDE_MAX_CV_KAPPA)
+      return fail(KDE_E_INVALID_ARG, "kappas must lie in (0, %g]", KDE_MAX_CV_KAPPA);
     if (b > 0 && !(p->kappas_h[b] > p->kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending");
   }
   if (p->n_cv < 2 || p->n_cv > p->N) return fail(KDE_E_INVALID_ARG, "n_cv must lie in [2, N]");
