@@ -8,9 +8,12 @@ Test infrastructure: see the package docstring.
   method. Here the minimiser is taken inside the bracket that a scan over a
   list of concentrations finds: with b* the first minimum of the list, the
   search runs over u = log(kappa) between the list's neighbours of b*
-  (b* - 1 and b* + 1, clipped to the list), and the objective is the plain
-  direct-sum definition (``cv.cv_curve``) at each trial kappa. The 1D
-  search itself is a library step (SciPy's bounded Brent method).
+  (b* - 1 and b* + 1, clipped to the list). The minimiser is the
+  stationary point of the objective there: the root of dCV/du, with the
+  derivative written out by direct sums over the pairs (``cv_slope``; the
+  kernels' kappa-derivatives are closed forms in I1/I0). The root search is
+  a library step (SciPy's brentq). Where dCV/du keeps one sign over the
+  bracket, the minimiser is the end with the lower objective.
 * The pilot of Silverman's adaptive estimate is the fixed-width estimate
   itself; evaluated exactly at the particles it is
   ``f_i = (1/n) sum_j K_kappa(X_i - X_j)``, all j including i (the estimate
@@ -21,15 +24,55 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy import optimize
+from scipy import optimize, special
 
 from . import cv as _cv
-from .vonmises import kernel
+from .vonmises import conv2, conv2_at_zero, kernel
 
 
 def cv_at(x, L, kappa):
     """The objective of Eq. (cv_def) at one concentration, by direct sums."""
     return float(_cv.cv_curve(x, L, [float(kappa)])[0][0])
+
+
+def _ratio1(z):
+    """I1(z) / I0(z) (SciPy's scaled Bessel functions)."""
+    z = np.asarray(z, dtype=np.float64)
+    return special.i1e(z) / special.i0e(z)
+
+
+def cv_slope(x, L, kappa, block=256):
+    """``dCV/du`` at ``u = log(kappa)``, by direct sums of the derivatives.
+
+    With K = exp(-2 kappa s^2) / (L I0e(kappa)) and
+    Kbar = I0(2 kappa c) / (L I0(kappa)^2) (s, c as in ``vonmises``):
+
+        dK/dkappa    = K (1 - 2 s^2 - I1(kappa)/I0(kappa)),
+        dKbar/dkappa = Kbar (2 c I1(2 kappa c)/I0(2 kappa c) - 2 I1(kappa)/I0(kappa)),
+
+    and dCV/dkappa is Eq. (cv_def) with each kernel replaced by its
+    derivative (the i = j term of the first sum included)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    k = float(kappa)
+    r1 = float(_ratio1(k))
+    dk_bar0 = float(conv2_at_zero(k, L)) * (2.0 * float(_ratio1(2.0 * k)) - 2.0 * r1)
+    s1 = 0.0
+    s2 = 0.0
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        d = x[i0:i1, None] - x[None, i0:]
+        mask = np.arange(i0, n)[None, :] > np.arange(i0, i1)[:, None]
+        dd = d[mask]
+        if dd.size == 0:
+            continue
+        ang = math.pi * dd / L
+        s = np.sin(ang)
+        c = np.abs(np.cos(ang))
+        s1 += float(np.sum(conv2(dd, k, L) * (2.0 * c * _ratio1(2.0 * k * c) - 2.0 * r1)))
+        s2 += float(np.sum(kernel(dd, k, L) * (1.0 - 2.0 * s * s - r1)))
+    dcv = (n * dk_bar0 + 2.0 * s1) / (n * n) - 4.0 * s2 / (n * (n - 1.0))
+    return k * dcv
 
 
 def bracket(kappas, b):
@@ -39,9 +82,10 @@ def bracket(kappas, b):
     return float(k[max(b - 1, 0)]), float(k[min(b + 1, k.shape[0] - 1)])
 
 
-def cv_minimise(x, L, kappas, xatol=1e-11):
-    """Scan ``kappas`` (ascending), then minimise the objective over
-    log(kappa) inside the bracket of the scan's first minimum.
+def cv_minimise(x, L, kappas, xtol=1e-14):
+    """Scan ``kappas`` (ascending), then find the stationary point of the
+    objective in log(kappa) inside the bracket of the scan's first minimum
+    (see the module docstring).
 
     Returns ``(kappa_min, cv_min, b_star, (lo, hi))``. A concentration of 0
     in the bracket is replaced by the smallest positive list value (log
@@ -55,16 +99,15 @@ def cv_minimise(x, L, kappas, xatol=1e-11):
         lo = float(kappas[kappas > 0.0].min())
     if hi <= lo:
         return float(kappas[b]), float(grid[b]), b, (lo, hi)
-    res = optimize.minimize_scalar(lambda u: cv_at(x, L, math.exp(u)), bounds=(math.log(lo), math.log(hi)),
-                                   method="bounded", options={"xatol": xatol, "maxiter": 500})
-    k = math.exp(res.x)
-    val = cv_at(x, L, k)
-    # the bounded search may stop short of an end point that is lower
-    for e in (lo, hi):
-        ve = cv_at(x, L, e)
-        if ve < val:
-            k, val = e, ve
-    return k, val, b, (lo, hi)
+    ua, ub = math.log(lo), math.log(hi)
+    ga, gb = cv_slope(x, L, lo), cv_slope(x, L, hi)
+    if ga < 0.0 < gb:
+        u = optimize.brentq(lambda t: cv_slope(x, L, math.exp(t)), ua, ub, xtol=xtol, rtol=4 * np.finfo(float).eps,
+                            maxiter=200)
+        k = math.exp(u)
+        return k, cv_at(x, L, k), b, (lo, hi)
+    va, vb = cv_at(x, L, lo), cv_at(x, L, hi)
+    return (lo, va, b, (lo, hi)) if va <= vb else (hi, vb, b, (lo, hi))
 
 
 def pilot_exact(x, L, kappa, block=2048):

@@ -40,7 +40,7 @@ def test_two_particle_minimiser_matches_mpmath(d):
     f = lambda u: mpmath.diff(lambda t: _cv_two_mp(mpmath.exp(t), d, L), u)
     u_mp = mpmath.findroot(f, math.log(k_o))
     assert math.log(lo) < float(u_mp) < math.log(hi)
-    assert abs(k_o / float(mpmath.exp(u_mp)) - 1) < 1e-6
+    assert abs(k_o / float(mpmath.exp(u_mp)) - 1) < 1e-12
     assert abs(v_o - float(_cv_two_mp(mpmath.exp(u_mp), d, L))) < 1e-13
 
 
@@ -52,6 +52,28 @@ def test_two_particle_minimum_at_the_list_end():
     k_o, v_o, b, _ = refine.cv_minimise(np.array([0.5, 0.5 + d]), L, kappas)
     slope = mpmath.diff(lambda t: _cv_two_mp(mpmath.exp(t), d, L), math.log(kappas[0]))
     assert b == 0 and slope > 0 and k_o == kappas[0]
+
+
+@pytest.mark.parametrize("kappa", [0.7, 12.0, 300.0, 5000.0])
+def test_slope_matches_central_differences(kappa):
+    """The direct-sum derivative against fourth-order central differences of
+    the direct-sum objective in log(kappa)."""
+    L = 4 * math.pi
+    rng = np.random.default_rng(46)
+    x = W.cosine_positions(rng, 300, L, 0.5, 0.5)
+    h = 2e-3
+    f = [refine.cv_at(x, L, kappa * math.exp(j * h)) for j in (-2, -1, 1, 2)]
+    fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+    g = refine.cv_slope(x, L, kappa)
+    assert abs(g - fd) <= 1e-9 * max(1.0, abs(fd)) + 1e-9
+
+
+def test_two_particle_slope_matches_mpmath():
+    L, d = 2 * math.pi, 0.7
+    x = np.array([1.0, 1.0 + d])
+    for kappa in (0.3, 4.0, 60.0):
+        ref = mpmath.diff(lambda t: _cv_two_mp(mpmath.exp(t), d, L), math.log(kappa))
+        assert abs(refine.cv_slope(x, L, kappa) - float(ref)) < 1e-13
 
 
 def test_minimum_is_below_the_scan_and_stationary():
@@ -85,6 +107,7 @@ def test_minimiser_agrees_with_the_fourier_route():
                                    options={"xatol": 1e-11})
     assert abs(res.x - math.log(k)) < 1e-5
     assert abs(res.fun - v) < 1e-13
+    assert abs(refine.cv_slope(x, L, k)) < 1e-14
 
 
 @pytest.mark.parametrize("kappa", [0.0, 0.8, 30.0, 900.0])
