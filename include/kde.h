@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define KDE_ABI_VERSION 2
+#define KDE_ABI_VERSION 3
 
 typedef int32_t kde_status;
 
@@ -92,7 +92,10 @@ enum kde_op {
   KDE_OP_CV_SCAN = 0,
   KDE_OP_DEPOSIT = 1,
   KDE_OP_GATHER = 2,
-  KDE_OP_ADAPT = 3
+  KDE_OP_ADAPT = 3,
+  KDE_OP_CV_FOURIER = 4,   /* kde_cv_scan_fourier    */
+  KDE_OP_CV_REFINE = 5,    /* kde_cv_refine          */
+  KDE_OP_ADAPT_EXACT = 6   /* kde_adapt_widths_exact */
 };
 
 /* Kernel shapes (see "Shape" above). */
@@ -131,8 +134,8 @@ const char* kde_last_error(void);
  * kde_workspace_size -- bytes of device workspace an operation needs.
  *   op     : a kde_op value.
  *   dom    : domain (host pointer); M and prec matter for every op.
- *   N      : number of particles (>= 1; >= 2 for KDE_OP_CV_SCAN).
- *   B      : number of concentrations for KDE_OP_CV_SCAN (1..KDE_MAX_KAPPAS),
+ *   N      : number of particles (>= 1; >= 2 for the CV ops).
+ *   B      : number of concentrations for the CV ops (1..KDE_MAX_KAPPAS),
  *            ignored otherwise.
  *   bytes_h: receives the size; the workspace must be 256-byte aligned.
  * The size depends only on (op, M, prec, N, B). A workspace may be reused by
@@ -232,14 +235,97 @@ kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const voi
  *   kappa_star : finite, > 0.      alpha : finite, >= 0 (0.5 in the paper).
  *   kappa_out  : device, N values in dom->prec (output).
  *   log_geomean: device, 1 double (output) or NULL.
- * dom->shape must be KDE_SHAPE_VONMISES.
  *   n_floored  : device, 1 int64 (output: particles whose pilot value was
  *                floored) or NULL.
  *   ws, ws_bytes: workspace of kde_workspace_size(KDE_OP_ADAPT, dom, N, 0).
+ * dom->shape must be KDE_SHAPE_VONMISES.
  */
 kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, const double* pilot,
                             double kappa_star, double alpha, void* kappa_out, double* log_geomean,
                             int64_t* n_floored, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Fourier-moment route (von Mises shape only). On the circle the kernel is
+ * the Fourier series K(d) = (1/L)(1 + 2 sum_{m>=1} rho_m cos(m 2 pi d / L)),
+ * rho_m = I_m(kappa)/I_0(kappa), and its two-fold convolution has the
+ * coefficients rho_m^2. With the sample's moments
+ *   S_m = sum_j exp(i m theta_j),  P_m = |S_m|^2,  theta_j = 2 pi x_j / L,
+ * the double sums of Eq. (cv_def) (Sec. II.B) become single sums over m:
+ *   sum_{i,j} Kbar  = (N^2 + 2 sum_m rho_m^2 P_m) / L,
+ *   sum_{i!=j} K    = (N^2 - N + 2 sum_m rho_m (P_m - N)) / L,
+ *   cv(kappa)       = (2 A / N^2 - 4 C / (N (N - 1)) - 1) / L,
+ * A = sum_m rho_m^2 P_m, C = sum_m rho_m (P_m - N): the same objective as
+ * kde_cv_scan, in O(N M) work instead of O(N^2). M is where the series is
+ * cut: the smallest m at which an upper bound on rho_m(kappa_max) (the
+ * product of Amos's bounds on I_nu/I_{nu-1}) falls below 1e-18; rho_m
+ * decreases in m and increases in kappa, so the same M serves every kappa.
+ * The moments are FP64 sums in a fixed order, the rho_m come from the
+ * backward recurrence of I_m/I_{m-1} in FP64 on the device; results are
+ * deterministic. kappa must lie in [0, KDE_MAX_FOURIER_KAPPA] (M <= 9105).
+ * The pair sums S1 = (N^2 - N + 2 sum_m rho_m^2 (P_m - N)) / (2 L) and
+ * S2 = (N^2 - N + 2 C) / (2 L) are differences; where the diagonal
+ * N Kbar(0) dominates them (few particles, narrow kernels) they carry an
+ * absolute error of a few rounding units of N Kbar(0) (resp. N K(0)).
+ */
+#define KDE_MAX_FOURIER_KAPPA 1e6
+
+/*
+ * kde_cv_scan_fourier -- the CV objective of kde_cv_scan over B
+ * concentrations through the Fourier moments (above). Arguments, outputs
+ * (cv[B], sums[2B] or NULL, argmin or NULL: first minimum), errors and
+ * synchrony as kde_cv_scan; dom->shape must be KDE_SHAPE_VONMISES, kappas
+ * in [0, KDE_MAX_FOURIER_KAPPA] strictly ascending; dom->prec selects the
+ * position type (the arithmetic is FP64 in both).
+ *   ws, ws_bytes: kde_workspace_size(KDE_OP_CV_FOURIER, dom, N, B) bytes.
+ */
+kde_status kde_cv_scan_fourier(const kde_domain* dom, int64_t N, const void* x, int32_t B,
+                               const double* kappas_h, double* cv, double* sums, int32_t* argmin,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kde_cv_refine -- the minimiser of the CV objective in concentration, not
+ * limited to the list (Sec. II.B: the paper minimises the objective with a
+ * Newton-type method). The list is scanned as by kde_cv_scan_fourier; with
+ * b* its first minimum, Newton's method on u = log(kappa) solves
+ * dCV/du = 0 between kappas[b*-1] and kappas[b*+1] (clipped to the list; a
+ * kappa of 0 there is replaced by the smallest positive list value), with
+ * bisection whenever a Newton step leaves the current bracket. dCV/dkappa
+ * and d2CV/dkappa2 are series over the same moments, with
+ *   d rho_m / d kappa = rho_{m+1} + (m / kappa) rho_m - rho_1 rho_m.
+ * Where dCV/du has one sign over the bracket, the result is the end with
+ * the lower objective. Every step runs on the device (no host round trip).
+ *   result : device, 5 doubles (output): [kappa*, cv(kappa*), dCV/du at
+ *            kappa*, Newton/bisection steps taken, b*].
+ *   cv     : device, B doubles (output: the scan) or NULL.
+ *   argmin : device, 1 int32 (output: b*) or NULL.
+ * Other arguments, errors and synchrony as kde_cv_scan_fourier.
+ *   ws, ws_bytes: kde_workspace_size(KDE_OP_CV_REFINE, dom, N, B) bytes.
+ */
+kde_status kde_cv_refine(const kde_domain* dom, int64_t N, const void* x, int32_t B,
+                         const double* kappas_h, double* result, double* cv, int32_t* argmin,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kde_adapt_widths_exact -- particle-wise concentrations as
+ * kde_adapt_widths (Sec. II.C), with the pilot evaluated exactly at each
+ * particle instead of interpolated from a grid:
+ *   f_i = (1/N) sum_j K_{kappa_star}(x_i - x_j)   (all j, i included)
+ *       = (1/L)(1 + (2/N) sum_m rho_m Re(conj(S_m) exp(i m theta_i))),
+ * through the Fourier moments (above), O(N M) work. Then, as there,
+ * f_i floored at the smallest positive normal number of dom->prec,
+ * log g = (1/N) sum_i log f_i, kappa_i = kappa_star exp(2 alpha (log f_i -
+ * log g)). The series form carries an absolute error of a few rounding
+ * units of K(0) = (1/L)(1 + 2 sum_m rho_m) in f_i.
+ *   kappa_star : in (0, KDE_MAX_FOURIER_KAPPA].   alpha : finite, >= 0.
+ *   kappa_out  : device, N values in dom->prec (output).
+ *   log_geomean: device, 1 double (output) or NULL.
+ *   n_floored  : device, 1 int64 (output) or NULL.
+ *   ws, ws_bytes: kde_workspace_size(KDE_OP_ADAPT_EXACT, dom, N, 0) bytes.
+ * dom->shape must be KDE_SHAPE_VONMISES; dom->M is not used.
+ */
+kde_status kde_adapt_widths_exact(const kde_domain* dom, int64_t N, const void* x, double kappa_star,
+                                  double alpha, void* kappa_out, double* log_geomean, int64_t* n_floored,
+                                  void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Batching form. Many independent particle sets, each taken through the
@@ -449,7 +535,8 @@ enum kde_kernel_id {
   KDE_KERNEL_DEPOSIT = 1,    /* the per-chunk grid kernel of kde_deposit     */
   KDE_KERNEL_GATHER = 2,     /* the per-particle kernel of kde_gather        */
   KDE_KERNEL_ADAPT = 3,      /* both per-particle passes of kde_adapt_widths */
-  KDE_KERNEL_COUNT = 4
+  KDE_KERNEL_MOMENTS = 4,    /* the Fourier-moment kernel of the Fourier ops  */
+  KDE_KERNEL_COUNT = 5
 };
 kde_status kde_timing_enable(int32_t on);
 kde_status kde_timing_reset(void);

@@ -26,6 +26,8 @@ LIB_PATH = os.path.join(HERE, "_lib", "libkdepic.so")
 KDE_F64, KDE_F32 = 0, 1
 KDE_SHAPE_VONMISES, KDE_SHAPE_TRIANGLE = 0, 1
 KDE_OP_CV_SCAN, KDE_OP_DEPOSIT, KDE_OP_GATHER, KDE_OP_ADAPT = 0, 1, 2, 3
+KDE_OP_CV_FOURIER, KDE_OP_CV_REFINE, KDE_OP_ADAPT_EXACT = 4, 5, 6
+KDE_MAX_FOURIER_KAPPA = 1e6
 KDE_MAX_KAPPAS = 64
 
 _lib = None
@@ -96,6 +98,9 @@ _SIGNATURES = {
     "kde_deposit": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _vp, _vp, _sz, _vp]),
     "kde_gather": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _sz, _vp]),
     "kde_adapt_widths": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kde_cv_scan_fourier": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kde_cv_refine": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kde_adapt_widths_exact": (_i32, [_dom_p, _i64, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _sz, _vp]),
     "kde_timing_enable": (_i32, [_i32]),
     "kde_timing_reset": (_i32, []),
     "kde_timing_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
@@ -130,6 +135,7 @@ KDE_E_AGAIN, KDE_E_BUDGET = 4, 3
 TUNE_FILE = os.path.join(HERE, "tune_gfx950.json")
 
 KDE_KERNEL_CV_PAIRS, KDE_KERNEL_DEPOSIT, KDE_KERNEL_GATHER, KDE_KERNEL_ADAPT = 0, 1, 2, 3
+KDE_KERNEL_MOMENTS = 4
 
 EXPORTED = tuple(_SIGNATURES)
 
@@ -239,6 +245,30 @@ def kde_cv_scan(dom, N, x, kappas_h, cv, sums, argmin, ws, ws_bytes, stream=None
     kp = k.ctypes.data_as(ctypes.POINTER(_dbl))
     _check(lib.kde_cv_scan(ctypes.byref(dom), int(N), _ptr(x), int(k.shape[0]), kp, _ptr(cv), _ptr(sums),
                            _ptr(argmin), ws, int(ws_bytes), _stream(stream)), "kde_cv_scan")
+
+
+def kde_cv_scan_fourier(dom, N, x, kappas_h, cv, sums, argmin, ws, ws_bytes, stream=None):
+    lib = require_library()
+    k = np.ascontiguousarray(np.asarray(kappas_h, dtype=np.float64))
+    kp = k.ctypes.data_as(ctypes.POINTER(_dbl))
+    _check(lib.kde_cv_scan_fourier(ctypes.byref(dom), int(N), _ptr(x), int(k.shape[0]), kp, _ptr(cv), _ptr(sums),
+                                   _ptr(argmin), ws, int(ws_bytes), _stream(stream)), "kde_cv_scan_fourier")
+
+
+def kde_cv_refine(dom, N, x, kappas_h, result, cv, argmin, ws, ws_bytes, stream=None):
+    lib = require_library()
+    k = np.ascontiguousarray(np.asarray(kappas_h, dtype=np.float64))
+    kp = k.ctypes.data_as(ctypes.POINTER(_dbl))
+    _check(lib.kde_cv_refine(ctypes.byref(dom), int(N), _ptr(x), int(k.shape[0]), kp, _ptr(result), _ptr(cv),
+                             _ptr(argmin), ws, int(ws_bytes), _stream(stream)), "kde_cv_refine")
+
+
+def kde_adapt_widths_exact(dom, N, x, kappa_star, alpha, kappa_out, log_geomean, n_floored, ws, ws_bytes,
+                           stream=None):
+    lib = require_library()
+    _check(lib.kde_adapt_widths_exact(ctypes.byref(dom), int(N), _ptr(x), float(kappa_star), float(alpha),
+                                      _ptr(kappa_out), _ptr(log_geomean), _ptr(n_floored), ws, int(ws_bytes),
+                                      _stream(stream)), "kde_adapt_widths_exact")
 
 
 def kde_deposit(dom, N, x, kappa_i, kappa, rho, ws, ws_bytes, stream=None):
@@ -617,6 +647,55 @@ def cv_scan(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None, sh
     ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
     kde_cv_scan(dom, n, x, k, cv, sums, am, ptr, cap, stream)
     return cv, sums, am
+
+
+def cv_scan_fourier(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None):
+    """The CV objective of ``cv_scan`` through the sample's Fourier moments
+    (von Mises shape). Returns ``(cv[B], sums[2B], argmin[1])``."""
+    import torch
+    k = np.asarray(kappas, dtype=np.float64)
+    dom = _domain(L, 2, prec_of(x))
+    n = x.shape[0]
+    cv = torch.empty(k.shape[0], dtype=torch.float64, device=x.device)
+    sums = torch.empty(2 * k.shape[0], dtype=torch.float64, device=x.device)
+    am = torch.empty(1, dtype=torch.int32, device=x.device)
+    nbytes = kde_workspace_size(KDE_OP_CV_FOURIER, dom, n, k.shape[0])
+    ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
+    kde_cv_scan_fourier(dom, n, x, k, cv, sums, am, ptr, cap, stream)
+    return cv, sums, am
+
+
+def cv_refine(x, L: float, kappas, ws: Optional[Workspace] = None, stream=None):
+    """Minimiser of the CV objective in concentration inside the bracket of
+    the scan's first minimum. Returns ``(result[5], cv[B], argmin[1])`` with
+    result = [kappa*, cv(kappa*), dCV/dlog(kappa) there, steps, b*]."""
+    import torch
+    k = np.asarray(kappas, dtype=np.float64)
+    dom = _domain(L, 2, prec_of(x))
+    n = x.shape[0]
+    res = torch.empty(5, dtype=torch.float64, device=x.device)
+    cv = torch.empty(k.shape[0], dtype=torch.float64, device=x.device)
+    am = torch.empty(1, dtype=torch.int32, device=x.device)
+    nbytes = kde_workspace_size(KDE_OP_CV_REFINE, dom, n, k.shape[0])
+    ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
+    kde_cv_refine(dom, n, x, k, res, cv, am, ptr, cap, stream)
+    return res, cv, am
+
+
+def adapt_widths_exact(x, L: float, kappa_star: float, alpha: float = 0.5, ws: Optional[Workspace] = None,
+                       stream=None):
+    """Per-particle concentrations from the exact pilot at the particles.
+    Returns ``(kappa_i, log_geomean[1], n_floored[1])``."""
+    import torch
+    dom = _domain(L, 2, prec_of(x))
+    n = x.shape[0]
+    kout = torch.empty(n, dtype=x.dtype, device=x.device)
+    lg = torch.empty(1, dtype=torch.float64, device=x.device)
+    nf = torch.empty(1, dtype=torch.int64, device=x.device)
+    nbytes = kde_workspace_size(KDE_OP_ADAPT_EXACT, dom, n)
+    ptr, cap = ws.get(nbytes) if ws is not None else _ws(nbytes, x.device)
+    kde_adapt_widths_exact(dom, n, x, kappa_star, alpha, kout, lg, nf, ptr, cap, stream)
+    return kout, lg, nf
 
 
 def deposit(x, L: float, M: int, kappa: float = 0.0, kappa_i=None, ws: Optional[Workspace] = None,

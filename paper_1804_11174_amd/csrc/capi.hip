@@ -137,6 +137,18 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
       KDE_RETURN_IF(check_n(N, 1));
       *bytes_h = adapt_workspace_bytes(N);
       return KDE_OK;
+    case KDE_OP_CV_FOURIER:
+    case KDE_OP_CV_REFINE:
+      KDE_RETURN_IF(check_domain(dom, false));
+      KDE_RETURN_IF(check_n(N, 2));
+      if (B < 1 || B > KDE_MAX_KAPPAS) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d] (got %d)", KDE_MAX_KAPPAS, B);
+      *bytes_h = fourier_workspace_bytes(op, N, B);
+      return KDE_OK;
+    case KDE_OP_ADAPT_EXACT:
+      KDE_RETURN_IF(check_domain(dom, false));
+      KDE_RETURN_IF(check_n(N, 1));
+      *bytes_h = fourier_workspace_bytes(op, N, 0);
+      return KDE_OK;
     default:
       return fail(KDE_E_INVALID_ARG, "unknown op %d", op);
   }

@@ -172,6 +172,10 @@ inline kde_status launch_pack_sorted(const T* x, int64_t n, double L, const Sort
   return launch_pack_sorted_as<T, typename Packed<T>::type>(x, n, L, plan, hist, packed, perm, s);
 }
 
+// Workspace of the Fourier-moment ops (KDE_OP_CV_FOURIER, _CV_REFINE,
+// _ADAPT_EXACT), sized for the largest series order the ops accept.
+size_t fourier_workspace_bytes(int op, int64_t n, int B);
+
 // Deterministic column sums: out[c] = scale * sum_r in[r][c], fixed order.
 // `scratch` must hold column_sum_scratch(rows, cols) bytes.
 kde_status launch_column_sum(const double* in, int64_t rows, int cols, double* scratch,
