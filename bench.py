@@ -143,11 +143,12 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "copy"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "fourier", "copy"], default="plain",
                     help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
                          "serve: the request server beside 16 resident PIC sessions; tri: the first-order "
-                         "(triangular) shape with a CV-chosen width on the paper-scale positions; copy: a "
-                         "device copy of known size that calibrates the HBM byte counters")
+                         "(triangular) shape with a CV-chosen width on the paper-scale positions; fourier: the "
+                         "paper-scale pipeline through the Fourier moments (refined kappa*, exact pilot); "
+                         "copy: a device copy of known size that calibrates the HBM byte counters")
     ap.add_argument("--sets", type=int, default=512)
     ap.add_argument("--requests", type=int, default=2000, help="serve form: requests per load point")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
@@ -182,6 +183,9 @@ def main():
     if args.form == "tri":
         args.prec = args.prec or "f64"
         return bench_tri(args, kde, W, torch, dev)
+    if args.form == "fourier":
+        args.prec = args.prec or "f64"
+        return bench_fourier(args, kde, W, torch, dev)
     args.prec = args.prec or "f64"
     prob = W.plain_paper_scale()
     L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
@@ -401,6 +405,120 @@ def bench_tri(args, kde, W, torch, dev):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = tri_cpu_baseline(prob.x[:n_cv], L, widths)
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+# Fourier moments, algorithmic lane-operations per (particle, m): the
+# rotation of exp(i m theta) by exp(i theta) (two products, two FMAs) and
+# the two accumulations. The exact phase at the start of each run of 16 m
+# (two sincos per particle) is not counted.
+MOMENT_OPS = 6
+
+
+def fourier_order(kmax):
+    """Series order of the Fourier route for concentrations up to kmax: the
+    smallest m where the product of Amos's bounds on I_nu/I_{nu-1} drops
+    below 1e-18 (the rule the library applies)."""
+    lg, m = 0.0, 0
+    while True:
+        m += 1
+        nu = m - 0.5
+        lg += math.log(kmax / (nu + math.sqrt(nu * nu + kmax * kmax)))
+        if lg < math.log(1e-18):
+            return m
+
+
+def bench_fourier(args, kde, W, torch, dev):
+    """The paper-scale pipeline through the Fourier moments: kde_cv_refine
+    on the first 65,536 particles (scan of 32 kappas + Newton on log kappa,
+    all on the device; the host reads kappa*), the exact pilot widths of all
+    1,048,576 particles (kde_adapt_widths_exact), the adaptive deposit and
+    the gather. Also times the Fourier scan alone against the pair-kernel
+    scan of the same positions and concentrations."""
+    prob = W.plain_paper_scale()
+    L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
+    B = len(kappas)
+    tdt = torch.float64 if args.prec == "f64" else torch.float32
+    prec = kde.KDE_F64 if args.prec == "f64" else kde.KDE_F32
+    x = torch.from_numpy(prob.x).to(dev).to(tdt).contiguous()
+    x_cv = x[:n_cv]
+    dom = kde.kde_domain(L, M, prec)
+    wsr, wsa, wsd, wss = kde.Workspace(dev), kde.Workspace(dev), kde.Workspace(dev), kde.Workspace(dev)
+    p_r, b_r = wsr.get(kde.kde_workspace_size(kde.KDE_OP_CV_REFINE, dom, n_cv, B))
+    p_a, b_a = wsa.get(kde.kde_workspace_size(kde.KDE_OP_ADAPT_EXACT, dom, n))
+    p_d, b_d = wsd.get(kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom, n))
+    p_s, b_s = wss.get(kde.kde_workspace_size(kde.KDE_OP_CV_FOURIER, dom, n_cv, B))
+    res = torch.empty(5, dtype=torch.float64, device=dev)
+    res_h = torch.empty(5, dtype=torch.float64, pin_memory=True)
+    cv = torch.empty(B, dtype=torch.float64, device=dev)
+    am = torch.empty(1, dtype=torch.int32, device=dev)
+    k_i = torch.empty(n, dtype=tdt, device=dev)
+    rho = torch.empty(M, dtype=torch.float64, device=dev)
+    G = torch.empty(n, dtype=tdt, device=dev)
+    lg = torch.empty(1, dtype=torch.float64, device=dev)
+    nf = torch.empty(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        kde.kde_cv_refine(dom, n_cv, x_cv, kappas, res, cv, am, p_r, b_r, stream)
+        res_h.copy_(res, non_blocking=True)
+        stream.synchronize()
+        kstar = float(res_h[0])
+        kde.kde_adapt_widths_exact(dom, n, x, kstar, 0.5, k_i, lg, nf, p_a, b_a, stream)
+        kde.kde_deposit(dom, n, x, k_i, 0.0, rho, p_d, b_d, stream)
+        kde.kde_gather(dom, n, x, k_i, 0.0, rho, G, None, 0, stream)
+        return kstar
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, out
+
+    scan = lambda: kde.kde_cv_scan_fourier(dom, n_cv, x_cv, kappas, cv, None, am, p_s, b_s, stream)
+    ms_scan, _ = timed(scan, max(args.steps, 10))
+    kde.kde_timing_reset()
+    kde.kde_timing_enable(True)
+    ms_step, kstar = timed(step, args.steps)
+    kde.kde_timing_enable(False)
+    kern = {}
+    for name, kid in (("moments", kde.KDE_KERNEL_MOMENTS), ("pilot_exact", kde.KDE_KERNEL_ADAPT),
+                      ("deposit", kde.KDE_KERNEL_DEPOSIT), ("gather", kde.KDE_KERNEL_GATHER)):
+        tot, cnt = kde.kde_timing_read(kid)
+        kern[name] = {"launches": cnt, "avg_ms": tot / cnt if cnt else None}
+    # the moment launches alternate between the CV subsample (series order of
+    # the list's largest kappa) and all particles (order of kappa*)
+    m_cv, m_star = fourier_order(float(kappas[-1])), fourier_order(kstar)
+    work = (n_cv * m_cv + n * m_star) * MOMENT_OPS / 2.0  # per launch, averaged over the two kinds
+    mom_ms = kern["moments"]["avg_ms"]
+    peak = PEAK_LANE_OPS["f64"]
+    achieved = work / (mom_ms * 1e-3)
+    pair_evals = B * n_cv * (n_cv - 1) / 2
+    line = {
+        "metric": METRIC, "form": "fourier",
+        "value": pair_evals / (ms_step * 1e-3), "value_kind": "equivalent CV pair-evals/s (no pairs are evaluated)",
+        "unit": "CV pair-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "paper-scale pipeline through Fourier moments: N=1,048,576 (CV refine on first "
+                               "65,536 over 32 kappas in [1,1e4]), exact pilot widths, adaptive deposit and "
+                               "gather, L=4pi, M=256", "n": n, "n_cv": n_cv, "M": M, "B": B,
+                   "positions": args.prec, "parallelism": "single GPU"},
+        "particles_per_s": n / (ms_step * 1e-3),
+        "kappa_star_refined": kstar, "refine_steps": int(res_h[3]), "kappa_star_grid": float(kappas[int(res_h[4])]),
+        "scan_ms": ms_scan, "series_order_cv": m_cv, "series_order_pilot": m_star,
+        "kernels": kern,
+        "roofline": {"bound": "alu", "kernel": "moments_kernel", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "T lane-ops/s (FMA = 1)", "frac": achieved / peak, "traffic": None,
+                     "ops_per_particle_mode": MOMENT_OPS, "kernel_avg_ms": mom_ms},
+    }
     out = json.dumps(line)
     print(out, flush=True)
     if args.json_out:

@@ -61,8 +61,11 @@ constexpr int kMomChunks = 64;          // particle chunks of the moment partial
 constexpr int kPilotRun = 64;           // rotations between exact phase restarts
 constexpr int kMaxNewton = 100;
 
+// Concentrations with their series orders (fourier_order of each; the
+// order grows with kappa, so a bracket's upper end bounds it inside).
 struct FKappas {
   double k[KDE_MAX_KAPPAS];
+  int order[KDE_MAX_KAPPAS];
 };
 
 // Smallest m at which the product of Amos's upper bounds
@@ -236,10 +239,11 @@ __global__ void __launch_bounds__(kBlock) series_kernel(const double* __restrict
   __shared__ double red[kBlock / 64];
   const int b = blockIdx.x;
   double* rho = rho_all + int64_t(b) * (M + 1);
-  if (threadIdx.x == 0) bessel_series<false>(kap.k[b], M, rho, nullptr, nullptr);
+  const int Mb = min(M, kap.order[b]);
+  if (threadIdx.x == 0) bessel_series<false>(kap.k[b], Mb, rho, nullptr, nullptr);
   __syncthreads();
   double a = 0.0, a0 = 0.0, c = 0.0;
-  for (int m = 1 + threadIdx.x; m <= M; m += kBlock) {
+  for (int m = 1 + threadIdx.x; m <= Mb; m += kBlock) {
     const double sr = S[2 * (m - 1)], si = S[2 * (m - 1) + 1];
     const double P = fma(sr, sr, si * si);
     const double q = P - n;
@@ -276,14 +280,15 @@ struct Eval {
   double cv, g, gp;
 };
 
-// Objective and its first two derivatives in u = log(kappa), all threads.
-__device__ Eval eval_u(double u, const double* __restrict__ S, int M, double n, double L, double* rho, double* d1,
+// Objective and its first two derivatives in u = log(kappa), all threads,
+// with the series cut at order Mk (that of a kappa at least as large).
+__device__ Eval eval_u(double u, const double* __restrict__ S, int Mk, double n, double L, double* rho, double* d1,
                        double* d2, double* red) {
   const double kappa = exp(u);
-  if (threadIdx.x == 0) bessel_series<true>(kappa, M, rho, d1, d2);
+  if (threadIdx.x == 0) bessel_series<true>(kappa, Mk, rho, d1, d2);
   __syncthreads();
   double A = 0.0, C = 0.0, A1 = 0.0, C1 = 0.0, A2 = 0.0, C2 = 0.0;
-  for (int m = 1 + threadIdx.x; m <= M; m += kBlock) {
+  for (int m = 1 + threadIdx.x; m <= Mk; m += kBlock) {
     const double sr = S[2 * (m - 1)], si = S[2 * (m - 1) + 1];
     const double P = fma(sr, sr, si * si);
     const double q = P - n;
@@ -324,6 +329,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
   double* d2 = rho3 + 2 * (M + 1);
   const int bs = first_min(cvgrid, B);
   if (argmin && threadIdx.x == 0) *argmin = bs;
+  const int Mk = min(M, kap.order[min(bs + 1, B - 1)]);
   double klo = kap.k[max(bs - 1, 0)], khi = kap.k[min(bs + 1, B - 1)];
   if (!(klo > 0.0)) {
     double kp = 0.0;
@@ -343,8 +349,8 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
     g_best = 0.0;
   } else {
     double ul = log(klo), uh = log(khi);
-    const Eval el = eval_u(ul, S, M, n, L, rho, d1, d2, red);
-    const Eval eh = eval_u(uh, S, M, n, L, rho, d1, d2, red);
+    const Eval el = eval_u(ul, S, Mk, n, L, rho, d1, d2, red);
+    const Eval eh = eval_u(uh, S, Mk, n, L, rho, d1, d2, red);
     steps = 2;
     if (!(el.g < 0.0 && eh.g > 0.0)) {
       const bool lo_wins = el.cv <= eh.cv;
@@ -353,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
       g_best = lo_wins ? el.g : eh.g;
     } else {
       double u = (bs > 0 && bs < B - 1 && kap.k[bs] > klo && kap.k[bs] < khi) ? log(kap.k[bs]) : 0.5 * (ul + uh);
-      Eval e = eval_u(u, S, M, n, L, rho, d1, d2, red);
+      Eval e = eval_u(u, S, Mk, n, L, rho, d1, d2, red);
       ++steps;
       for (int it = 0; it < kMaxNewton && e.g != 0.0; ++it) {
         if (e.g < 0.0)
@@ -364,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
         if (!(e.gp > 0.0) || !(un > ul && un < uh)) un = 0.5 * (ul + uh);
         const bool done = fabs(un - u) <= 1e-14 * fmax(1.0, fabs(un)) || (uh - ul) <= 1e-14 * fmax(1.0, fabs(un));
         u = un;
-        e = eval_u(u, S, M, n, L, rho, d1, d2, red);
+        e = eval_u(u, S, Mk, n, L, rho, d1, d2, red);
         ++steps;
         if (done) break;
       }
@@ -385,7 +391,9 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
 // w_m = rho_m(kappa) S_m, m = 1..M (one workgroup).
 __global__ void __launch_bounds__(kBlock) pilot_weights_kernel(const double* __restrict__ S, int M, double kappa,
                                                               double* __restrict__ rho, double* __restrict__ w) {
-  if (threadIdx.x == 0) bessel_series<false>(kappa, M, rho, nullptr, nullptr);
+  if (threadIdx.x == 0) {
+    bessel_series<false>(kappa, M, rho, nullptr, nullptr);
+  }
   __syncthreads();
   for (int m = 1 + threadIdx.x; m <= M; m += kBlock) {
     w[2 * (m - 1)] = rho[m] * S[2 * (m - 1)];
@@ -492,7 +500,10 @@ kde_status check_fourier_kappas(int B, const double* kappas_h) {
 
 FKappas to_list(const double* k, int B) {
   FKappas f{};
-  for (int b = 0; b < B; ++b) f.k[b] = k[b];
+  for (int b = 0; b < B; ++b) {
+    f.k[b] = k[b];
+    f.order[b] = fourier_order(k[b]);
+  }
   return f;
 }
 
