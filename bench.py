@@ -52,16 +52,16 @@ PEAK_HBM = 8.0e12
 # pair sums, large-argument branch, counted from the formulas (the small-
 # argument power series of I0 is costlier, so this undercounts the work
 # for small kappa):
-#   f64: K term: exponent product 1 + exponential 18 (clamp 1, range
-#        reduction 4, degree-13 polynomial 13) = 19; Kbar term: exponent
-#        product 1 + exponential 18 + Bessel argument and its square-root
-#        factor with their clamps 4 + degree-12 polynomial 12 + two products
-#        = 37; two accumulations 2. Total 58.
+#   f64: K term: exponent product 1 + exponential 18 (range reduction 4,
+#        degree-13 polynomial 13, scaling 1) = 19; Kbar term: exponent
+#        product 1 + exponential 18 + Bessel argument and square-root
+#        factor 2 + degree-11 polynomial 11 + two products = 34; two
+#        accumulations 2. Total 55.
 #   f32: K term: product 1 + exponential 1 = 2; Kbar term: product 1 +
-#        exponential 1 + argument and factor with clamps 4 + degree-5
-#        polynomial 5 + two products = 13; two compensated (Kahan)
-#        accumulations of 4 = 8. Total 23.
-OPS_PER_TERM = {"f64": 58, "f32": 23}
+#        exponential 1 + argument and factor 2 + degree-5 polynomial 5 +
+#        two products = 11; two compensated (Kahan) accumulations of 4 = 8.
+#        Total 21.
+OPS_PER_TERM = {"f64": 55, "f32": 21}
 SKIP_EXPONENT = 70.0
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
@@ -71,9 +71,9 @@ SKIP_EXPONENT = 70.0
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "device_bessel.hpp", "bessel_coeffs.inc", "dev_layout.hpp",
                        "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "531a816270c4cbfe",
-                "f64": {"fetch_kib": 4665.6875, "write_kib": 16448.0},
-                "f32": {"fetch_kib": 1161.0, "write_kib": 16448.0}}
+PAIR_TRAFFIC = {"digest": "91d72482c8f3bd43",
+                "f64": {"fetch_kib": 4808.0625, "write_kib": 16448.0},
+                "f32": {"fetch_kib": 1384.25, "write_kib": 16448.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
