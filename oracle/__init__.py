@@ -33,8 +33,11 @@ Submodules:
   kernel, its two-fold convolution (a scaled cubic B-spline), pair sums,
   CV, deposit and gather.
 * ``update``   -- the width-update rule of Sec. II.D.
+* ``landau``   -- the standard-PIC (linear weighting) step, the field
+  energy, the two-peak damping rate and the Landau root of the Maxwellian
+  dispersion relation (Sec. III.B).
 * ``refine``   -- the continuous minimiser of the CV objective inside the
   scan's bracket, and the exact pilot at the particles with the adaptive
   widths taken from it.
 """
-from . import vonmises, cv, density, pic, adtest, update, mise, triangle, refine  # noqa: F401
+from . import vonmises, cv, density, pic, adtest, update, mise, triangle, refine, landau  # noqa: F401

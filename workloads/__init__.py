@@ -211,3 +211,34 @@ def vonmises_positions(rng: np.random.Generator, n: int, L: float, mu: float,
     x = (th % (2.0 * math.pi)) * (L / (2.0 * math.pi))
     x[x >= L] = 0.0
     return x
+
+
+@dataclass
+class LandauEnsemble:
+    """One ensemble of the Landau-damping workload (Sec. III.B): positions
+    from ``(1 + amp cos(k x)) / L`` on ``L = 2 pi / k`` and unit-normal
+    velocity draws ``z``; a run at thermal velocity v_th uses ``v_th * z``,
+    so every thermal velocity and both methods share the same random
+    numbers (common random numbers)."""
+    index: int
+    x: np.ndarray
+    z: np.ndarray
+    L: float
+    M: int
+    dt: float
+    steps: int
+
+    def v(self, v_th: float) -> np.ndarray:
+        return v_th * self.z
+
+
+def landau_ensemble(index: int, n: int = 1 << 15, M: int = 256, dt: float = 0.01, steps: int = 1500,
+                    amp: float = 0.02, k: float = 1.0) -> LandauEnsemble:
+    """Ensemble ``index`` of the Landau workload: 2^15 particles, 256 nodes,
+    dt = 0.01, 1500 steps, density perturbation 0.02 cos(1.0 x) (Sec. III.B).
+    Positions first, then the velocity draws, from ``rng_for(6, index)``."""
+    L = 2.0 * math.pi / k
+    rng = rng_for(6, index)
+    x = cosine_positions(rng, n, L, amp, k)
+    z = rng.standard_normal(n)
+    return LandauEnsemble(index, x, z, L, M, dt, steps)
