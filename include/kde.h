@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define KDE_ABI_VERSION 3
+#define KDE_ABI_VERSION 4
 
 typedef int32_t kde_status;
 
@@ -387,6 +387,18 @@ kde_status kde_batch_destroy(kde_batch* b);
  * the CV scan at t = 0 (h_opt = h_target at its optimum, p_th = 2 thr).
  * Every step waits once for the A^2 value (one 8-byte device-to-host copy)
  * and, when the rule fires, for the scan's argmin.
+ *
+ * method KDE_PIC_STANDARD runs the same cycle as standard PIC, the
+ * comparison method of Sec. III: linear ("cloud-in-cell") weighting for the
+ * deposit and the gather (the triangle of half-width dx = L/M), no CV scan,
+ * no test and no width update (B, n_cv, kappas_h, alpha, p_threshold and
+ * adjust_rate are not used); its steps never wait on the host.
+ *
+ * Field energy (both methods): each step records W = (dx/2) sum_g E_g^2 of
+ * the field it computes from the positions at the start of the step, so
+ * entry n of the history is W(t_n), t_n = n dt, n = 0 .. history-1 (later
+ * steps are not recorded). Sec. III.B reads the Landau damping rate off
+ * log W (kde_damping_rate).
  */
 typedef struct kde_pic_params {
   int64_t N;             /* particles, >= 2                                       */
@@ -400,7 +412,11 @@ typedef struct kde_pic_params {
   double alpha;          /* Silverman sensitivity (0.5 in the paper)              */
   double p_threshold;    /* significance threshold of the test (0.01)             */
   double adjust_rate;    /* relaxation rate of the width (0.05)                   */
+  int32_t method;        /* KDE_PIC_KDE (0) or KDE_PIC_STANDARD (1)               */
+  int32_t history;       /* field-energy history length in steps, >= 0            */
 } kde_pic_params;
+
+enum kde_pic_method { KDE_PIC_KDE = 0, KDE_PIC_STANDARD = 1 };
 
 typedef struct kde_session_info {
   int64_t step;          /* steps taken                                           */
@@ -411,7 +427,7 @@ typedef struct kde_session_info {
 } kde_session_info;
 
 enum kde_session_field { KDE_SESSION_X = 0, KDE_SESSION_V = 1, KDE_SESSION_KAPPA = 2, KDE_SESSION_RHO = 3,
-                         KDE_SESSION_E = 4 };
+                         KDE_SESSION_E = 4, KDE_SESSION_ENERGY = 5 };
 
 typedef struct kde_session kde_session;
 
@@ -426,14 +442,29 @@ kde_status kde_session_create(const kde_pic_params* p, const void* x0, const voi
 /* Advance nsteps steps (returns when they are done). */
 kde_status kde_session_step(kde_session* s, int32_t nsteps);
 kde_status kde_session_state(const kde_session* s, kde_session_info* info_h);
-/* Copy a field to `dst` (device): X, V, KAPPA (N values in prec), RHO, E (M doubles). */
+/* Copy a field to `dst` (device): X, V, KAPPA (N values in prec; KAPPA is
+ * not kept by standard sessions), RHO, E (M doubles), ENERGY
+ * (min(steps taken, history) doubles). */
 kde_status kde_session_read(kde_session* s, int32_t what, void* dst);
 /* Checkpoint to a host blob (blob_h NULL: *bytes_h receives the size) and
- * restore into a session of the same N, M and prec; a restored session
- * continues bitwise identically. */
+ * restore into a session of the same N, M, prec, method and history; a
+ * restored session continues bitwise identically (energy history included). */
 kde_status kde_session_save(kde_session* s, void* blob_h, size_t* bytes_h);
 kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes);
 kde_status kde_session_destroy(kde_session* s);
+
+/*
+ * kde_damping_rate -- the damping rate read off a field-energy history as in
+ * Sec. III.B: the slope of log W through the first two peaks after t = 0,
+ * a peak being an index n >= 1 with W[n-1] < W[n] >= W[n+1]:
+ *   rate = (log W[p2] - log W[p1]) / ((p2 - p1) dt).
+ * The energy decays at twice the rate of the field amplitude, so the rate
+ * is 2 Im(omega) of the damped mode. Host arrays; runs on the host.
+ *   energy_h : n >= 3 finite, positive values.    dt : > 0.
+ *   rate_h   : receives the rate (NaN when W has fewer than two peaks).
+ *   peaks_h  : receives [p1, p2] (-1 when missing) or NULL.
+ */
+kde_status kde_damping_rate(const double* energy_h, int64_t n, double dt, double* rate_h, int64_t* peaks_h);
 
 /*
  * Request server (serving form): continuous batching of KDE solves. A

@@ -21,6 +21,12 @@ Test infrastructure: see the package docstring.
   k v_th matters; the root is followed by continuation in k v_th from 0.2
   (started at the Bohm-Gross frequency, where the damping is negligible),
   since Newton from that start alone diverges once the damping is strong.
+* A smoothing kernel used for both the deposit and the gather multiplies
+  the force of mode k by the square of its Fourier coefficient, rho_1^2 for
+  the von Mises kernel of concentration kappa at the box's fundamental
+  mode (rho_1 = I_1/I_0). The mode then obeys the same relation with the
+  susceptibility scaled by s = rho_1^2, ``1 + s (1 + zeta Z) / (k v_th)^2``,
+  followed by continuation in s from 1 (``response``).
 """
 from __future__ import annotations
 
@@ -74,21 +80,21 @@ def damping_rate(W, dt):
     return (math.log(W[p[1]]) - math.log(W[p[0]])) / ((p[1] - p[0]) * dt)
 
 
-def dispersion(omega, k, v_th):
-    """``1 + (1 + zeta Z(zeta)) / (k v_th)^2`` at complex omega."""
+def dispersion(omega, k, v_th, response=1.0):
+    """``1 + s (1 + zeta Z(zeta)) / (k v_th)^2`` at complex omega, s = response."""
     zeta = omega / (math.sqrt(2.0) * k * v_th)
     Z = 1j * math.sqrt(math.pi) * special.wofz(zeta)
-    return 1.0 + (1.0 + zeta * Z) / (k * v_th) ** 2
+    return 1.0 + response * (1.0 + zeta * Z) / (k * v_th) ** 2
 
 
-def _newton(w, kv, tol):
+def _newton(w, kv, tol, resp=1.0):
     s = math.sqrt(2.0) * kv
     for _ in range(100):
         zeta = w / s
         Z = 1j * math.sqrt(math.pi) * special.wofz(zeta)
-        f = 1.0 + (1.0 + zeta * Z) / (kv * kv)
+        f = 1.0 + resp * (1.0 + zeta * Z) / (kv * kv)
         dZ = -2.0 * (1.0 + zeta * Z)
-        df = (Z + zeta * dZ) / (kv * kv * s)
+        df = resp * (Z + zeta * dZ) / (kv * kv * s)
         step = f / df
         w -= step
         if abs(step) < tol * abs(w):
@@ -96,14 +102,25 @@ def _newton(w, kv, tol):
     return w
 
 
-def landau_root(k, v_th, tol=1e-14):
+def landau_root(k, v_th, response=1.0, tol=1e-14):
     """Least-damped root omega = omega_r + i gamma (gamma < 0) of
     ``dispersion``: Newton's method on the analytic function (derivative by
-    Z'(zeta) = -2 (1 + zeta Z(zeta))), continued in k v_th from 0.2."""
+    Z'(zeta) = -2 (1 + zeta Z(zeta))), continued in k v_th from 0.2, then in
+    the response from 1."""
     target = k * v_th
     kv = min(0.2, target)
     w = _newton(complex(math.sqrt(1.0 + 3.0 * kv * kv), 0.0), kv, tol)
     while kv < target:
         kv = min(target, kv + 0.02)
         w = _newton(w, kv, tol)
+    for s in np.linspace(1.0, response, 41)[1:]:
+        w = _newton(w, target, tol, float(s))
     return w
+
+
+def kernel_response(kappa):
+    """``rho_1(kappa)^2``: the factor a von Mises kernel of concentration
+    kappa, used for the deposit and the gather, puts on the fundamental
+    mode's force (SciPy's scaled Bessel functions)."""
+    r1 = special.i1e(kappa) / special.i0e(kappa)
+    return float(r1 * r1)

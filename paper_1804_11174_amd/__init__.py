@@ -54,7 +54,8 @@ class kde_pic_params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("L", ctypes.c_double), ("M", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("B", ctypes.c_int32), ("n_cv", ctypes.c_int32),
                 ("kappas_h", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.c_double),
-                ("p_threshold", ctypes.c_double), ("adjust_rate", ctypes.c_double)]
+                ("p_threshold", ctypes.c_double), ("adjust_rate", ctypes.c_double), ("method", ctypes.c_int32),
+                ("history", ctypes.c_int32)]
 
 
 class kde_session_info(ctypes.Structure):
@@ -120,6 +121,7 @@ _SIGNATURES = {
     "kde_session_restore": (_i32, [_vp, _vp, _sz]),
     "kde_session_destroy": (_i32, [_vp]),
     "kde_ad_pvalue": (_i32, [_dbl, ctypes.POINTER(_dbl)]),
+    "kde_damping_rate": (_i32, [ctypes.POINTER(_dbl), _i64, _dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "kde_server_create": (_i32, [ctypes.POINTER(kde_server_config), _vp, _sz, ctypes.POINTER(_vp)]),
     "kde_server_request_bytes": (_i32, [_vp, ctypes.POINTER(kde_batch_set), ctypes.POINTER(_sz)]),
     "kde_server_submit": (_i32, [_vp, ctypes.POINTER(kde_batch_set), ctypes.POINTER(ctypes.c_uint64)]),
@@ -130,6 +132,8 @@ _SIGNATURES = {
 }
 
 KDE_SESSION_X, KDE_SESSION_V, KDE_SESSION_KAPPA, KDE_SESSION_RHO, KDE_SESSION_E = 0, 1, 2, 3, 4
+KDE_SESSION_ENERGY = 5
+KDE_PIC_KDE, KDE_PIC_STANDARD = 0, 1
 KDE_E_AGAIN, KDE_E_BUDGET = 4, 3
 
 TUNE_FILE = os.path.join(HERE, "tune_gfx950.json")
@@ -384,11 +388,27 @@ class Batch:
 
 # ------------------------------------------------------------- sessions
 
-def _params(N, L, M, prec, dt, kappas, n_cv, alpha=0.5, p_threshold=0.01, adjust_rate=0.05):
-    k = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
+def _params(N, L, M, prec, dt, kappas, n_cv, alpha=0.5, p_threshold=0.01, adjust_rate=0.05,
+            method=KDE_PIC_KDE, history=0):
+    k = np.ascontiguousarray(np.asarray(kappas if kappas is not None else [1.0], dtype=np.float64))
     p = kde_pic_params(int(N), float(L), int(M), int(prec), float(dt), int(k.shape[0]), int(n_cv),
-                       k.ctypes.data_as(ctypes.POINTER(_dbl)), float(alpha), float(p_threshold), float(adjust_rate))
+                       k.ctypes.data_as(ctypes.POINTER(_dbl)), float(alpha), float(p_threshold), float(adjust_rate),
+                       int(method), int(history))
     return p, k
+
+
+def kde_damping_rate(energy, dt):
+    """The damping rate of a field-energy history (host array) as the
+    library computes it: ``(rate, (p1, p2))``."""
+    e = np.ascontiguousarray(np.asarray(energy, dtype=np.float64))
+    rate = _dbl(0.0)
+    peaks = (_i64 * 2)()
+    _check(require_library().kde_damping_rate(e.ctypes.data_as(ctypes.POINTER(_dbl)), int(e.shape[0]), float(dt),
+                                              ctypes.byref(rate), peaks), "kde_damping_rate")
+    return rate.value, (int(peaks[0]), int(peaks[1]))
+
+
+damping_rate = kde_damping_rate
 
 
 def kde_session_bytes(params) -> int:
@@ -445,10 +465,13 @@ def kde_ad_pvalue(a2: float) -> float:
 class Session:
     """A resident PIC session; x0, v0 are GPU tensors (float64 or float32)."""
 
-    def __init__(self, x0, v0, L, M, dt, kappas, n_cv, alpha=0.5, p_threshold=0.01, adjust_rate=0.05):
+    def __init__(self, x0, v0, L, M, dt, kappas=None, n_cv=2, alpha=0.5, p_threshold=0.01, adjust_rate=0.05,
+                 method=KDE_PIC_KDE, history=0):
         import torch
         self.N, self.M, self.dtype, self.device = x0.shape[0], int(M), x0.dtype, x0.device
-        self.params, self._k = _params(self.N, L, M, prec_of(x0), dt, kappas, n_cv, alpha, p_threshold, adjust_rate)
+        self.history = int(history)
+        self.params, self._k = _params(self.N, L, M, prec_of(x0), dt, kappas, n_cv, alpha, p_threshold, adjust_rate,
+                                       method, history)
         nbytes = kde_session_bytes(self.params)
         self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=x0.device)
         base = self._arena.data_ptr()
@@ -464,6 +487,11 @@ class Session:
         import torch
         if what in (KDE_SESSION_RHO, KDE_SESSION_E):
             out = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        elif what == KDE_SESSION_ENERGY:
+            n = min(int(self.state()["step"]), self.history)
+            out = torch.empty(n, dtype=torch.float64, device=self.device)
+            if n == 0:
+                return out
         else:
             out = torch.empty(self.N, dtype=self.dtype, device=self.device)
         kde_session_read(self.handle, what, out)

@@ -9,6 +9,10 @@
 //    One workgroup: an iterative radix-2 complex FFT in LDS, M a power of two.
 //  * Push: v <- v - E_i dt, x <- x + v dt, wrapped into [0, L) (electrons,
 //    q/m = -1), one thread per particle.
+//  * Field energy: W = (dx / 2) sum_g E_g^2 (eps0 = 1), one workgroup, the
+//    squares summed per thread in node order, then across the workgroup in
+//    a fixed order; written to one slot of a history (Sec. III.B reads the
+//    damping rate off log W).
 //  * Anderson-Darling statistic of u = x / L against the uniform law:
 //    A^2 = -N - (1/N) sum_j [(2j - 1) ln u_(j) + (2N - 2j + 1) ln(1 - u_(j))]
 //    over the sorted u (the usual form with the second logarithm's index
@@ -229,6 +233,27 @@ __global__ void ad_finish_kernel(const double* __restrict__ sum, int64_t n, doub
 // ------------------------------------------------------------------ host
 
 size_t poisson_max_m() { return kMaxFftM; }
+
+__global__ void __launch_bounds__(kBlock) field_energy_kernel(const double* __restrict__ E, int M, double half_dx,
+                                                             double* __restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  double s = 0.0;
+  for (int g = threadIdx.x; g < M; g += kBlock) s = fma(E[g], E[g], s);
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    *out = half_dx * t;
+  }
+}
+
+kde_status launch_field_energy(const double* E, int M, double L, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(field_energy_kernel, dim3(1), dim3(kBlock), 0, s, E, M, 0.5 * (L / M), out);
+  KDE_CHECK_LAUNCH();
+  return KDE_OK;
+}
 
 kde_status launch_poisson_field(const double* rho, int M, double L, double* E, double* phi, hipStream_t s) {
   int bits = 0;

@@ -1,6 +1,8 @@
 // Resident PIC sessions: the particle set stays in HBM across steps and
 // every step runs the KDE-PIC cycle of Sec. III.A with the width-update
-// rule of Sec. II.D:
+// rule of Sec. II.D (standard sessions run the same cycle with linear
+// weighting and no width update, steps 1-4 only; both record the field
+// energy of step 2 into a history):
 //
 //   1. deposit with the per-particle concentrations kappa_i;
 //   2. Poisson solve and centred field on the grid (pic.hip);
@@ -42,6 +44,7 @@ kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const d
                         double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
                         hipStream_t s);
 kde_status launch_poisson_field(const double* rho, int M, double L, double* E, double* phi, hipStream_t s);
+kde_status launch_field_energy(const double* E, int M, double L, double* out, hipStream_t s);
 template <typename T>
 kde_status launch_push(T* x, T* v, const T* E_i, int64_t n, double dt, double L, hipStream_t s);
 template <typename T>
@@ -106,10 +109,11 @@ struct kde_session {
   kde_pic_params prm{};
   std::vector<double> kappas;
   kde_domain dom{};
+  kde_domain tdom{};  // triangle of half-width dx (standard sessions)
   hipStream_t s = nullptr;
   // device buffers in the arena
   void *x = nullptr, *v = nullptr, *kap = nullptr, *Ei = nullptr;
-  double *rho = nullptr, *E = nullptr, *pilot = nullptr, *cv = nullptr, *a2 = nullptr;
+  double *rho = nullptr, *E = nullptr, *pilot = nullptr, *cv = nullptr, *a2 = nullptr, *energy = nullptr;
   int32_t* argmin = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -123,7 +127,10 @@ struct kde_session {
 
 namespace kde {
 
+static bool standard(const kde_pic_params& p) { return p.method == KDE_PIC_STANDARD; }
+
 static size_t session_ws_bytes(const kde_pic_params& p) {
+  if (standard(p)) return deposit_workspace_bytes(p.N, p.M);
   size_t w = cv_workspace_bytes(p.n_cv, p.B, p.prec);
   w = std::max(w, deposit_workspace_bytes(p.N, p.M));
   w = std::max(w, adapt_workspace_bytes(p.N));
@@ -140,14 +147,16 @@ static size_t carve_session(Carver& c, const kde_pic_params& p, kde_session* s) 
   double* rho = c.take<double>(p.M);
   double* E = c.take<double>(p.M);
   double* pilot = c.take<double>(p.M);
-  double* cv = c.take<double>(p.B);
+  double* cv = c.take<double>(standard(p) ? 1 : p.B);
   double* a2 = c.take<double>(1);
   int32_t* am = c.take<int32_t>(1);
+  double* energy = c.take<double>(size_t(std::max(p.history, 1)));
   const size_t wsb = session_ws_bytes(p);
   void* ws = c.take<char>(wsb);
   if (s) {
     s->x = x; s->v = v; s->kap = kap; s->Ei = Ei;
     s->rho = rho; s->E = E; s->pilot = pilot; s->cv = cv; s->a2 = a2; s->argmin = am;
+    s->energy = energy;
     s->ws = ws; s->ws_bytes = wsb;
   }
   return c.used;
@@ -161,6 +170,10 @@ static kde_status check_params(const kde_pic_params* p) {
     return fail(KDE_E_INVALID_ARG, "M must be a power of two in [2, %zu]", poisson_max_m());
   if (p->prec != KDE_F64 && p->prec != KDE_F32) return fail(KDE_E_INVALID_ARG, "prec must be KDE_F64 or KDE_F32");
   if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return fail(KDE_E_INVALID_ARG, "dt must be finite and > 0");
+  if (p->method != KDE_PIC_KDE && p->method != KDE_PIC_STANDARD)
+    return fail(KDE_E_INVALID_ARG, "method must be KDE_PIC_KDE or KDE_PIC_STANDARD (got %d)", p->method);
+  if (p->history < 0) return fail(KDE_E_INVALID_ARG, "history must be >= 0");
+  if (standard(*p)) return KDE_OK;
   if (p->B < 1 || p->B > KDE_MAX_KAPPAS || !p->kappas_h) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d]", KDE_MAX_KAPPAS);
   for (int b = 0; b < p->B; ++b) {
     if (!std::isfinite(p->kappas_h[b]) || !(p->kappas_h[b] > 0.0) || p->kappas_h[b] > KDE_MAX_CV_KAPPA)
@@ -196,10 +209,40 @@ static kde_status session_widths(kde_session* s, double kstar) {
   return KDE_OK;
 }
 
+static kde_status record_energy(kde_session* s) {
+  if (s->st.step < s->prm.history)
+    KDE_RETURN_IF(launch_field_energy(s->E, s->prm.M, s->prm.L, s->energy + s->st.step, s->s));
+  return KDE_OK;
+}
+
+static kde_status push_any(kde_session* s) {
+  const kde_pic_params& p = s->prm;
+  if (p.prec == KDE_F64)
+    return launch_push<double>(static_cast<double*>(s->x), static_cast<double*>(s->v),
+                               static_cast<const double*>(s->Ei), p.N, p.dt, p.L, s->s);
+  return launch_push<float>(static_cast<float*>(s->x), static_cast<float*>(s->v), static_cast<const float*>(s->Ei),
+                            p.N, p.dt, p.L, s->s);
+}
+
+// Standard PIC: linear weighting both ways, no width update; enqueue only.
+static kde_status standard_step_once(kde_session* s) {
+  const kde_pic_params& p = s->prm;
+  const double dx = p.L / double(p.M);
+  KDE_RETURN_IF(deposit(&s->tdom, p.N, s->x, nullptr, dx, s->rho, s->ws, s->ws_bytes, s->s));
+  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, nullptr, s->s));
+  KDE_RETURN_IF(record_energy(s));
+  KDE_RETURN_IF(gather(&s->tdom, p.N, s->x, nullptr, dx, s->E, s->Ei, s->s));
+  KDE_RETURN_IF(push_any(s));
+  s->st.step += 1;
+  return KDE_OK;
+}
+
 static kde_status session_step_once(kde_session* s) {
   const kde_pic_params& p = s->prm;
+  if (standard(p)) return standard_step_once(s);
   KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s));
   KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, nullptr, s->s));
+  KDE_RETURN_IF(record_energy(s));
   KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s));
   if (p.prec == KDE_F64) {
     KDE_RETURN_IF(launch_push<double>(static_cast<double*>(s->x), static_cast<double*>(s->v),
@@ -261,9 +304,10 @@ kde_status kde_session_create(const kde_pic_params* p, const void* x0, const voi
   if (!x0 || !v0) return fail(KDE_E_INVALID_ARG, "x0 and v0 must not be NULL");
   std::unique_ptr<kde_session> s(new kde_session());
   s->prm = *p;
-  s->kappas.assign(p->kappas_h, p->kappas_h + p->B);
+  if (!standard(*p)) s->kappas.assign(p->kappas_h, p->kappas_h + p->B);
   s->prm.kappas_h = nullptr;
-  s->dom = kde_domain{p->L, p->M, p->prec};
+  s->dom = kde_domain{p->L, p->M, p->prec, KDE_SHAPE_VONMISES, 0};
+  s->tdom = kde_domain{p->L, p->M, p->prec, KDE_SHAPE_TRIANGLE, 0};
   Carver c(arena, arena_bytes);
   carve_session(c, *p, s.get());
   if (!arena || reinterpret_cast<uintptr_t>(arena) % 256 != 0) return fail(KDE_E_WORKSPACE, "arena must be 256-byte aligned");
@@ -273,6 +317,11 @@ kde_status kde_session_create(const kde_pic_params* p, const void* x0, const voi
   const size_t es = elem_size(p->prec);
   KDE_TRY_HIP(hipMemcpyAsync(s->x, x0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(s->v, v0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
+  if (standard(*p)) {
+    KDE_TRY_HIP(hipStreamSynchronize(s->s));
+    *out_h = s.release();
+    return KDE_OK;
+  }
   // initial CV at t = 0: both widths at its optimum, p_th = 2 thr
   double k0 = 0.0;
   KDE_RETURN_IF(session_cv(s.get(), &k0));
@@ -290,6 +339,7 @@ kde_status kde_session_step(kde_session* s, int32_t nsteps) {
   if (!s) return fail(KDE_E_NOT_FOUND, "session is NULL");
   if (nsteps < 0) return fail(KDE_E_INVALID_ARG, "nsteps must be >= 0");
   for (int k = 0; k < nsteps; ++k) KDE_RETURN_IF(session_step_once(s));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
   return KDE_OK;
 }
 
@@ -319,21 +369,32 @@ kde_status kde_session_read(kde_session* s, int32_t what, void* dst) {
     case KDE_SESSION_KAPPA: src = s->kap; bytes = pn; break;
     case KDE_SESSION_RHO: src = s->rho; bytes = gm; break;
     case KDE_SESSION_E: src = s->E; bytes = gm; break;
+    case KDE_SESSION_ENERGY:
+      src = s->energy;
+      bytes = size_t(std::min<int64_t>(s->st.step, s->prm.history)) * sizeof(double);
+      break;
     default: return fail(KDE_E_INVALID_ARG, "unknown field %d", what);
   }
+  if (bytes == 0) return KDE_OK;
   KDE_TRY_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->s));
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
   return KDE_OK;
 }
 
-// Blob: magic, version, params (N, M, prec), state, then x, v, kappa_i.
-static const uint64_t kMagic = 0x6b64657069637331ull;  // "kdepics1"
+// Blob: magic, header (N, M, prec, method, history), state, then x, v,
+// kappa_i and the energy history.
+static const uint64_t kMagic = 0x6b64657069637332ull;  // "kdepics2"
+
+static size_t blob_bytes(const kde_session* s) {
+  const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec);
+  return 64 + sizeof(SessionState) + 3 * pn + size_t(s->prm.history) * sizeof(double);
+}
 
 kde_status kde_session_save(kde_session* s, void* blob_h, size_t* bytes_h) {
   clear_error();
   if (!s || !bytes_h) return fail(KDE_E_INVALID_ARG, "session and bytes_h must not be NULL");
   const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec);
-  const size_t need = 64 + sizeof(SessionState) + 3 * pn;
+  const size_t need = blob_bytes(s);
   if (!blob_h) {
     *bytes_h = need;
     return KDE_OK;
@@ -342,13 +403,16 @@ kde_status kde_session_save(kde_session* s, void* blob_h, size_t* bytes_h) {
   char* b = static_cast<char*>(blob_h);
   memset(b, 0, 64);
   memcpy(b, &kMagic, 8);
-  const int64_t hdr[3] = {s->prm.N, s->prm.M, s->prm.prec};
+  const int64_t hdr[5] = {s->prm.N, s->prm.M, s->prm.prec, s->prm.method, s->prm.history};
   memcpy(b + 8, hdr, sizeof hdr);
   memcpy(b + 64, &s->st, sizeof(SessionState));
   char* p = b + 64 + sizeof(SessionState);
   KDE_TRY_HIP(hipMemcpyAsync(p, s->x, pn, hipMemcpyDeviceToHost, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(p + pn, s->v, pn, hipMemcpyDeviceToHost, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(p + 2 * pn, s->kap, pn, hipMemcpyDeviceToHost, s->s));
+  if (s->prm.history > 0)
+    KDE_TRY_HIP(hipMemcpyAsync(p + 3 * pn, s->energy, size_t(s->prm.history) * sizeof(double), hipMemcpyDeviceToHost,
+                               s->s));
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
   *bytes_h = need;
   return KDE_OK;
@@ -358,21 +422,46 @@ kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes)
   clear_error();
   if (!s || !blob_h) return fail(KDE_E_INVALID_ARG, "session and blob must not be NULL");
   const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec);
-  const size_t need = 64 + sizeof(SessionState) + 3 * pn;
+  const size_t need = blob_bytes(s);
   if (bytes < need) return fail(KDE_E_INVALID_ARG, "blob too small: %zu < %zu", bytes, need);
   const char* b = static_cast<const char*>(blob_h);
   uint64_t magic = 0;
-  int64_t hdr[3];
+  int64_t hdr[5];
   memcpy(&magic, b, 8);
   memcpy(hdr, b + 8, sizeof hdr);
-  if (magic != kMagic || hdr[0] != s->prm.N || hdr[1] != s->prm.M || hdr[2] != s->prm.prec)
+  if (magic != kMagic || hdr[0] != s->prm.N || hdr[1] != s->prm.M || hdr[2] != s->prm.prec ||
+      hdr[3] != s->prm.method || hdr[4] != s->prm.history)
     return fail(KDE_E_INVALID_ARG, "blob does not belong to a session of this shape");
   memcpy(&s->st, b + 64, sizeof(SessionState));
   const char* p = b + 64 + sizeof(SessionState);
   KDE_TRY_HIP(hipMemcpyAsync(s->x, p, pn, hipMemcpyHostToDevice, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(s->v, p + pn, pn, hipMemcpyHostToDevice, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(s->kap, p + 2 * pn, pn, hipMemcpyHostToDevice, s->s));
+  if (s->prm.history > 0)
+    KDE_TRY_HIP(hipMemcpyAsync(s->energy, p + 3 * pn, size_t(s->prm.history) * sizeof(double), hipMemcpyHostToDevice,
+                               s->s));
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  return KDE_OK;
+}
+
+kde_status kde_damping_rate(const double* energy_h, int64_t n, double dt, double* rate_h, int64_t* peaks_h) {
+  clear_error();
+  if (!energy_h || !rate_h) return fail(KDE_E_INVALID_ARG, "energy_h and rate_h must not be NULL");
+  if (n < 3) return fail(KDE_E_INVALID_ARG, "need at least 3 energies (got %lld)", (long long)n);
+  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(KDE_E_INVALID_ARG, "dt must be finite and > 0");
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(energy_h[k]) || !(energy_h[k] > 0.0))
+      return fail(KDE_E_INVALID_ARG, "energies must be finite and > 0 (index %lld)", (long long)k);
+  int64_t pk[2] = {-1, -1};
+  int found = 0;
+  for (int64_t k = 1; k + 1 < n && found < 2; ++k)
+    if (energy_h[k - 1] < energy_h[k] && energy_h[k] >= energy_h[k + 1]) pk[found++] = k;
+  if (peaks_h) {
+    peaks_h[0] = pk[0];
+    peaks_h[1] = pk[1];
+  }
+  *rate_h = (found < 2) ? std::nan("")
+                        : (std::log(energy_h[pk[1]]) - std::log(energy_h[pk[0]])) / (double(pk[1] - pk[0]) * dt);
   return KDE_OK;
 }
 

@@ -179,3 +179,22 @@ def test_ad_pvalue_edges():
     assert kde.kde_ad_pvalue(0.0) == 1.0
     assert kde.kde_ad_pvalue(-1.0) == 1.0
     assert kde.kde_ad_pvalue(500.0) == 0.0
+
+
+def test_damping_rate_host_function_matches_oracle(lib):
+    """kde_damping_rate runs on the host: against the oracle's two-peak
+    slope on a noisy damped oscillation, and its argument checks."""
+    from oracle import landau
+    rng = np.random.default_rng(9)
+    dt = 0.01
+    t = np.arange(1500) * dt
+    W = np.exp(-0.13 * t) * (np.cos(1.285 * t) ** 2 + 1e-3) * (1 + 1e-3 * rng.standard_normal(t.shape[0]))
+    rate, peaks = kde.kde_damping_rate(W, dt)
+    assert peaks == tuple(landau.first_two_peaks(W))
+    assert rate == landau.damping_rate(W, dt) or abs(rate - landau.damping_rate(W, dt)) < 1e-15
+    r2, p2 = kde.kde_damping_rate(np.exp(-np.arange(10.0)), dt)
+    assert math.isnan(r2) and p2 == (-1, -1)
+    with pytest.raises(kde.KdeError):
+        kde.kde_damping_rate([1.0, 2.0], dt)
+    with pytest.raises(kde.KdeError):
+        kde.kde_damping_rate([1.0, 0.0, 1.0, 2.0], dt)

@@ -25,6 +25,25 @@ def test_landau_root_tabulated(klam, wr, wi):
     assert abs(w2 - w) < 1e-12
 
 
+@pytest.mark.parametrize("s", [0.9, 0.65, 0.4])
+def test_scaled_response_root(s):
+    """With the susceptibility scaled by s the root solves the scaled
+    relation, reduces to the plain one at s = 1, and in the cold limit
+    (k v_th -> 0) the frequency tends to sqrt(s): the plasma frequency of
+    the weakened force."""
+    w = landau.landau_root(1.0, 0.4, response=s)
+    assert abs(landau.dispersion(w, 1.0, 0.4, response=s)) < 1e-12
+    assert w.imag < landau.landau_root(1.0, 0.4).imag  # a weaker force damps faster here
+    cold = landau.landau_root(1.0, 0.05, response=s)
+    assert abs(cold.real / math.sqrt(s) - 1) < 0.02 and abs(cold.imag) < 1e-6
+    assert landau.landau_root(1.0, 0.4, response=1.0) == landau.landau_root(1.0, 0.4)
+
+
+def test_kernel_response_limits():
+    assert landau.kernel_response(0.0) == 0.0
+    assert abs(landau.kernel_response(1e4) - (1 - 0.5 / 1e4) ** 2) < 1e-8
+
+
 def test_landau_root_weak_damping_asymptote():
     kl = 0.2
     w = landau.landau_root(1.0, kl)
