@@ -143,11 +143,13 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "fourier", "copy"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "fourier", "landau", "copy"],
+                    default="plain",
                     help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
                          "serve: the request server beside 16 resident PIC sessions; tri: the first-order "
                          "(triangular) shape with a CV-chosen width on the paper-scale positions; fourier: the "
                          "paper-scale pipeline through the Fourier moments (refined kappa*, exact pilot); "
+                         "landau: Landau-damping ensembles on resident sessions, standard PIC against KDE; "
                          "copy: a device copy of known size that calibrates the HBM byte counters")
     ap.add_argument("--sets", type=int, default=512)
     ap.add_argument("--requests", type=int, default=2000, help="serve form: requests per load point")
@@ -159,6 +161,9 @@ def main():
     ap.add_argument("--sessions", type=int, default=16, help="serve form: resident PIC sessions")
     ap.add_argument("--session-period-ms", type=float, default=100.0,
                     help="serve form: every session steps once per period")
+    ap.add_argument("--ensembles", type=int, default=30, help="landau form: ensembles per thermal velocity")
+    ap.add_argument("--vths", default="0.20,0.25,0.30,0.35,0.40,0.45", help="landau form: thermal velocities")
+    ap.add_argument("--workers", type=int, default=16, help="landau form: sessions stepping at once")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
@@ -186,6 +191,9 @@ def main():
     if args.form == "fourier":
         args.prec = args.prec or "f64"
         return bench_fourier(args, kde, W, torch, dev)
+    if args.form == "landau":
+        args.prec = args.prec or "f64"
+        return bench_landau(args, kde, W, torch, dev)
     args.prec = args.prec or "f64"
     prob = W.plain_paper_scale()
     L, M, kappas, n, n_cv = prob.L, prob.M, prob.kappas, prob.x.shape[0], prob.n_cv
@@ -518,6 +526,92 @@ def bench_fourier(args, kde, W, torch, dev):
         "roofline": {"bound": "alu", "kernel": "moments_kernel", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "T lane-ops/s (FMA = 1)", "frac": achieved / peak, "traffic": None,
                      "ops_per_particle_mode": MOMENT_OPS, "kernel_avg_ms": mom_ms},
+    }
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+def bench_landau(args, kde, W, torch, dev):
+    """Linear Landau damping (Sec. III.B): for each thermal velocity, the
+    same seeded ensembles (common random numbers: the same positions and
+    unit-normal velocity draws for every v_th and both methods) run as
+    resident sessions with standard PIC (linear weighting) and with KDE
+    (CV width at t = 0 and the update rule): 2^15 particles, 256 nodes,
+    dt = 0.01, 1500 steps, density perturbation 0.02 cos x. Each run's
+    damping rate is the slope of log field energy through its first two
+    peaks (kde_damping_rate, = 2 Im(omega)); the theory is the Maxwellian
+    root, and for KDE also the root with the kernel's response rho_1^2 at
+    the kappa* in force between the peaks. Sessions step concurrently, one
+    per worker thread, each on its own stream."""
+    import concurrent.futures as cf
+    from oracle import landau as olandau
+    vths = [float(v) for v in args.vths.split(",")]
+    ens = [W.landau_ensemble(i) for i in range(args.ensembles)]
+    e0 = ens[0]
+    tdt = torch.float64 if args.prec == "f64" else torch.float32
+    kappas = W.log_kappas(1.0, 1e4, 16)
+    chunk = 100
+    xs = [torch.from_numpy(e.x).to(dev).to(tdt).contiguous() for e in ens]
+    zs = [torch.from_numpy(e.z).to(dev) for e in ens]
+
+    def run(e_idx, vth, method):
+        e = ens[e_idx]
+        v = (zs[e_idx] * vth).to(tdt).contiguous()
+        kw = dict(method=kde.KDE_PIC_STANDARD) if method == "standard" else dict(kappas=kappas, n_cv=e.x.shape[0])
+        s = kde.Session(xs[e_idx], v, e.L, e.M, e.dt, history=e.steps, **kw)
+        ks = []
+        try:
+            for _ in range(e.steps // chunk):
+                ks.append(s.state()["kappa_star"])
+                s.step(chunk)
+            Wt = s.read(kde.KDE_SESSION_ENERGY).cpu().numpy()
+        finally:
+            s.close()
+        rate, peaks = kde.kde_damping_rate(Wt, e.dt)
+        kstar = float(np.mean(ks[peaks[0] // chunk: peaks[1] // chunk + 1])) if peaks[1] > 0 else float("nan")
+        return rate, kstar
+
+    jobs = [(i, vth, m) for vth in vths for i in range(args.ensembles) for m in ("standard", "kde")]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=args.workers) as ex:
+        results = list(ex.map(lambda j: run(*j), jobs))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    table = []
+    for vth in vths:
+        theory = 2 * olandau.landau_root(1.0, vth).imag
+        row = {"v_th": vth, "theory_energy_rate": theory}
+        for m in ("standard", "kde"):
+            r = np.array([res[0] for (i, v, mm), res in zip(jobs, results) if v == vth and mm == m])
+            k = np.array([res[1] for (i, v, mm), res in zip(jobs, results) if v == vth and mm == m])
+            ok = np.isfinite(r)
+            err = r[ok] - theory
+            sd = float(np.std(r[ok], ddof=1)) if ok.sum() > 1 else float("nan")
+            entry = {"mean_rate": float(np.mean(r[ok])) if ok.any() else None, "sd": sd,
+                     "abs_error_of_mean": float(abs(np.mean(err))) if ok.any() else None,
+                     "t_stat": float(np.mean(err) / (sd / math.sqrt(ok.sum()))) if ok.sum() > 1 else None,
+                     "runs_with_two_peaks": int(ok.sum())}
+            if m == "kde":
+                kk = float(np.nanmean(k))
+                entry["mean_kappa_star"] = kk
+                entry["theory_with_kernel_response"] = 2 * olandau.landau_root(
+                    1.0, vth, response=olandau.kernel_response(kk)).imag
+            row[m] = entry
+        table.append(row)
+    steps = len(jobs) * e0.steps
+    line = {
+        "metric": METRIC, "form": "landau",
+        "value": steps * e0.x.shape[0] / wall, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": e0.steps, "warmup": 0, "ms_per_step": wall * 1e3 / e0.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "Landau damping: 2^15 particles, M=256, dt=0.01, 1500 steps, 0.02 cos x, L=2pi; "
+                               f"{args.ensembles} ensembles x {len(vths)} thermal velocities x (standard PIC, KDE)",
+                   "ensembles": args.ensembles, "vths": vths, "workers": args.workers, "parallelism": "single GPU"},
+        "session_steps_per_s": steps / wall, "wall_s": wall, "sessions": len(jobs),
+        "damping": table,
     }
     out = json.dumps(line)
     print(out, flush=True)
