@@ -49,19 +49,19 @@ PEAK_LANE_OPS = {"f64": 78.6e12 / 2, "f32": 157.3e12 / 2}
 PEAK_HBM = 8.0e12
 
 # Algorithmic lane-operations per evaluated (pair, kappa) term of the CV
-# pair sums, large-argument branch, counted from the formulas (the small-
-# argument power series of I0 is costlier, so this undercounts the work
-# for small kappa):
-#   f64: K term: exponent product 1 + exponential 18 (range reduction 4,
-#        degree-13 polynomial 13, scaling 1) = 19; Kbar term: exponent
-#        product 1 + exponential 18 + Bessel argument and square-root
-#        factor 2 + degree-11 polynomial 11 + two products = 34; two
-#        accumulations 2. Total 55.
+# pair sums, large-argument branch, counted from the formulas (the
+# small-argument branch, a degree-20 fit in double, costs 22 for the Kbar
+# term against 30 here):
+#   f64: K term: exponent product 1 + exponential 14 (Tang's table method:
+#        reduction 4, table index 3, polynomial and combination 5, scaling
+#        1, bound 1) = 15; Kbar term: exponent product 1 + exponential 14 +
+#        Bessel argument and square-root factor 2 + degree-11 polynomial 11
+#        + two products = 30; two accumulations 2. Total 47.
 #   f32: K term: product 1 + exponential 1 = 2; Kbar term: product 1 +
 #        exponential 1 + argument and factor 2 + degree-5 polynomial 5 +
 #        two products = 11; two compensated (Kahan) accumulations of 4 = 8.
 #        Total 21.
-OPS_PER_TERM = {"f64": 55, "f32": 21}
+OPS_PER_TERM = {"f64": 47, "f32": 21}
 SKIP_EXPONENT = 70.0
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the

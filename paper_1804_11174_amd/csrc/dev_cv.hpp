@@ -44,6 +44,7 @@ struct CvConsts {
   T rsk[KDE_MAX_KAPPAS];   // 1 / sqrt(kappa)
   T em2k[KDE_MAX_KAPPAS];  // exp(-2 kappa) for the small-argument branch
   T twok[KDE_MAX_KAPPAS];  // 2 kappa
+  T tk[KDE_MAX_KAPPAS];    // (2 kappa / X0)^2: t = (R / X0)^2 = tk c^2
   int B;
   int nsmall;  // leading concentrations that may need the small-argument I0e branch
   T skip;      // exponent bound (in the unit of A)
@@ -75,17 +76,21 @@ struct Acc<float> {
 };
 
 // Pair-kernel exponents lie in [-2 kappa, 0] with kappa <= KDE_MAX_CV_KAPPA
-// (checked on the host), inside the bounded exponential's domain.
-__device__ __forceinline__ double exp_unit(double a) { return exp_nonpos_f64_bounded(a); }
-__device__ __forceinline__ float exp_unit(float a) { return __builtin_amdgcn_exp2f(a); }
+// (checked on the host), inside the table exponential's domain; `tab` is
+// the unit's LDS copy of KDE_EXP_TABLE (unused in float, where the exponent
+// is in base 2 and the hardware exp2 serves).
+__device__ __forceinline__ double exp_unit(double a, const double* __restrict__ tab) {
+  return exp_nonpos_table(a, tab);
+}
+__device__ __forceinline__ float exp_unit(float a, const double* __restrict__) { return __builtin_amdgcn_exp2f(a); }
 
 __device__ __forceinline__ double rcp_unit(double a) { return 1.0 / a; }
 __device__ __forceinline__ float rcp_unit(float a) { return __builtin_amdgcn_rcpf(a); }
 __device__ __forceinline__ double rsqrt_unit(double a) { return 1.0 / sqrt(a); }
 __device__ __forceinline__ float rsqrt_unit(float a) { return __builtin_amdgcn_rsqf(a); }
 
-__device__ __forceinline__ double i0_series(double y) { return i0_series_f64(y); }
-__device__ __forceinline__ float i0_series(float y) { return i0_series_f32(y); }
+__device__ __forceinline__ double i0_small(double t) { return i0_small_f64(t); }
+__device__ __forceinline__ float i0_small(float t) { return i0_small_f32(t); }
 __device__ __forceinline__ double i0e_sqrt_large(double t) { return i0e_sqrt_large_f64(t); }
 __device__ __forceinline__ float i0e_sqrt_large(float t) { return i0e_sqrt_large_f32(t); }
 
@@ -142,7 +147,7 @@ __device__ __forceinline__ void tri_decode(int64_t p, int& I, int& J) {
   I = int(p - j * (j + 1) / 2);
 }
 
-// Geometry of one pair: s^2, q = 1 - c, c, 1/(2c'), 1/sqrt(2c') with
+// Geometry of one pair: s^2, q = 1 - c, c, c^2, 1/(2c'), 1/sqrt(2c') with
 // c' = max(c, X0 / (X0 + S)), S the skip exponent. c' = c wherever the
 // large-argument Bessel fit is used for a term that is not negligible:
 // for a concentration with 2 kappa <= X0 + S (which takes that fit only
@@ -152,7 +157,7 @@ __device__ __forceinline__ void tri_decode(int64_t p, int& I, int& J) {
 // leaves its interval and needs no per-term clamp.
 template <typename T>
 struct Geo {
-  T s2, q, c, inv2c, rs2c;
+  T s2, q, c, c2, inv2c, rs2c;
 };
 
 template <typename T>
@@ -187,6 +192,7 @@ __device__ __forceinline__ Geo<double> pair_geo(const IPart<double>& p, const do
   g.s2 = s * s;
   g.q = g.s2 / (1.0 + c);
   g.c = c;
+  g.c2 = c * c;
   const double cf = fmax(c, c_floor<double>());
   g.inv2c = 1.0 / (2.0 * cf);
   g.rs2c = 1.0 / sqrt(2.0 * cf);
@@ -208,6 +214,7 @@ __device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint
   g.q = y * r;
   g.c = 1.0f - g.q;
   g.s2 = g.q * (2.0f - g.q);
+  g.c2 = g.c * g.c;
   const float cf = fmaxf(g.c, c_floor<float>());
   g.inv2c = __builtin_amdgcn_rcpf(2.0f * cf);
   g.rs2c = __builtin_amdgcn_rsqf(2.0f * cf);
@@ -217,7 +224,8 @@ __device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
                                            const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
-                                           const CvConsts<T>& K, Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
+                                           const CvConsts<T>& K, const double* __restrict__ etab,
+                                           Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
   const int nb = min(BC, b_end - b0);
   const T X0 = I0eBounds<T>::X0;
   for (int jj = 0; jj < nj; ++jj) {
@@ -238,17 +246,17 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
         go = !__all(!live || Aq < K.skip);
       }
       if (go) {
-        T t2 = exp_unit(A * g.s2);
+        T t2 = exp_unit(A * g.s2, etab);
         T t1;
         if (b < K.nsmall) {
           const T R = K.twok[b] * g.c;
           if (R < X0) {
-            t1 = K.em2k[b] * i0_series(R * R);
+            t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
           } else {
-            t1 = exp_unit(Aq) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
+            t1 = exp_unit(Aq, etab) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
           }
         } else {
-          t1 = exp_unit(Aq) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
+          t1 = exp_unit(Aq, etab) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
         }
         if (MASKED) {
           t1 = live ? t1 : T(0);
@@ -267,6 +275,7 @@ struct CvSmem {
   typename Packed<T>::type tj[Packed<T>::per_particle * kCvTile];
   double red[kBlock / 64][2 * BC];
   double unit_acc[2 * KDE_MAX_KAPPAS];
+  double etab[std::is_same<T, double>::value ? 256 : 1];  // exponential table (double form)
   int b_end;
 };
 
@@ -308,6 +317,10 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
     sm.b_end = be;
   }
   for (int k = tid; k < 2 * KDE_MAX_KAPPAS; k += kBlock) sm.unit_acc[k] = 0.0;
+  if constexpr (std::is_same<T, double>::value) {
+    constexpr double etab_src[256] = KDE_EXP_TABLE;
+    for (int k = tid; k < 256; k += kBlock) sm.etab[k] = etab_src[k];
+  }
   for (int k = tid; k < per * nj; k += kBlock) sm.tj[k] = packed[per * j0 + k];
   const int64_t i = i0 + tid;
   const bool valid_i = i < n;
@@ -326,9 +339,9 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
       s2[bb].zero();
     }
     if (masked)
-      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, s1, s2);
+      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, sm.etab, s1, s2);
     else
-      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, s1, s2);
+      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, sm.etab, s1, s2);
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       double v1 = wave_sum(s1[bb].value());
@@ -374,6 +387,7 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
     K.rsk[b] = T(1.0 / std::sqrt(k));
     K.em2k[b] = T(std::exp(-2.0 * k));
     K.twok[b] = T(2.0 * k);
+    K.tk[b] = T((2.0 * k / X0) * (2.0 * k / X0));
     // an argument 2 kappa |c| below X0 carries weight exp(-2 kappa (1 - |c|))
     // <= exp(-(2 kappa - X0)); beyond the skip bound it is negligible
     if (2.0 * k - X0 <= kSkipExponent) K.nsmall = b + 1;

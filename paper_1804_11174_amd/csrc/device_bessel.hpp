@@ -3,7 +3,7 @@
 // of its two-fold convolution.
 //
 // Two regimes (coefficients from gen_bessel_coeffs.py):
-//   x <  X0: I0(x) by its power series in y = x^2, sum_k y^k / (4^k (k!)^2);
+//   x <  X0: I0(x) = Q(t), t = (x/X0)^2 in [0, 1], a fitted polynomial;
 //   x >= X0: sqrt(x) I0e(x) = P(v), v = X0 / x in [0, 1], a fitted polynomial.
 // The pieces are exposed separately so that the pair kernels can share the
 // per-pair factors 1/x and 1/sqrt(x) across concentrations.
@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bessel_coeffs.inc"
+#include "exp_table.inc"
 
 namespace kde {
 
@@ -30,11 +31,12 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
   return d;
 }
 
-__device__ __forceinline__ double i0_series_f64(double y) {
-  constexpr double c[KDE_I0E_F64_NSERIES] = KDE_I0E_F64_SERIES;
-  double r = c[KDE_I0E_F64_NSERIES - 1];
+// I0(x) for x < X0, given t = (x/X0)^2 in [0, 1].
+__device__ __forceinline__ double i0_small_f64(double t) {
+  constexpr double c[KDE_I0E_F64_NSMALL] = KDE_I0E_F64_SMALL;
+  double r = c[KDE_I0E_F64_NSMALL - 1];
 #pragma unroll
-  for (int k = KDE_I0E_F64_NSERIES - 2; k >= 0; --k) r = fma3(r, y, c[k]);
+  for (int k = KDE_I0E_F64_NSMALL - 2; k >= 0; --k) r = fma3(r, t, c[k]);
   return r;
 }
 
@@ -49,17 +51,21 @@ __device__ __forceinline__ double i0e_sqrt_large_f64(double v) {
 
 __device__ __forceinline__ double i0e_f64(double x) {
   x = fabs(x);
-  if (x < KDE_I0E_F64_X0) return exp(-x) * i0_series_f64(x * x);
+  if (x < KDE_I0E_F64_X0) {
+    const double u = x * (1.0 / KDE_I0E_F64_X0);
+    return exp(-x) * i0_small_f64(u * u);
+  }
   return i0e_sqrt_large_f64(KDE_I0E_F64_X0 / x) / sqrt(x);
 }
 
 // ----------------------------------------------------------------- float
 
-__device__ __forceinline__ float i0_series_f32(float y) {
-  constexpr float c[KDE_I0E_F32_NSERIES] = KDE_I0E_F32_SERIES;
-  float r = c[KDE_I0E_F32_NSERIES - 1];
+// I0(x) for x < X0, given t = (x/X0)^2 in [0, 1].
+__device__ __forceinline__ float i0_small_f32(float t) {
+  constexpr float c[KDE_I0E_F32_NSMALL] = KDE_I0E_F32_SMALL;
+  float r = c[KDE_I0E_F32_NSMALL - 1];
 #pragma unroll
-  for (int k = KDE_I0E_F32_NSERIES - 2; k >= 0; --k) r = fmaf(r, y, c[k]);
+  for (int k = KDE_I0E_F32_NSMALL - 2; k >= 0; --k) r = fmaf(r, t, c[k]);
   return r;
 }
 
@@ -98,6 +104,28 @@ __device__ __forceinline__ double exp_nonpos_f64_bounded(double x) {
   p = fma3(p, r, 1.0);
   p = fma3(p, r, 1.0);
   return __builtin_amdgcn_ldexp(p, int(fmax(n, -2000.0)));
+}
+
+// exp(x) for -2^40 <= x <= 0 (or NaN) by Tang's table method: with
+// n = rint(x 256/ln2) = 256 m + k, r = x - n ln2/256 (head and tail of
+// ln2/256, |r| <= ln2/512), exp(x) = 2^m T[k] (1 + q), T[k] = 2^(k/256) from
+// `tab` (KDE_EXP_TABLE, 256 correctly rounded values, staged in LDS by the
+// caller) and q = r (1 + r (1/2 + r (1/6 + r/24))) (remainder below 3.8e-17
+// relative); T + T q is one FMA. Error below 2 units in the last place.
+// The exponent handed to ldexp is limited to -2000 (n >= -512000), so the
+// int conversion never overflows and results below ~e^-745 are 0.
+__device__ __forceinline__ double exp_nonpos_table(double x, const double* __restrict__ tab) {
+  const double n = __builtin_rint(x * KDE_EXP_INV_LN2_256);
+  double r = fma(-n, KDE_EXP_LN2_256_HI, x);
+  r = fma(-n, KDE_EXP_LN2_256_LO, r);
+  const int ni = int(fmax(n, -512000.0));
+  const double c24 = 1.0 / 24.0;
+  double q = fma3(r, c24, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q *= r;
+  const double t = tab[ni & 255];
+  return __builtin_amdgcn_ldexp(fma(t, q, t), ni >> 8);
 }
 
 // exp(x) for any x <= 0 (or NaN): arguments below -1000, far below the
