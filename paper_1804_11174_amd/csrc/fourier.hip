@@ -17,12 +17,14 @@
 //                       exp(i theta); per-m sums reduced in the workgroup in
 //                       a fixed order into the chunk's slot; the chunks are
 //                       summed by the shared fixed-order column sum.
-//   series_kernel    -- one workgroup per concentration: thread 0 runs the
-//                       backward recurrence of the ratios r_m = I_m/I_{m-1},
+//   series_kernel    -- one workgroup per concentration: the backward
+//                       recurrence of the ratios r_m = I_m/I_{m-1},
 //                       r_m = kappa / (2 m + kappa r_{m+1}) (stable downwards,
 //                       started where the neglected tail has decayed below
-//                       e^-40), and multiplies them up to rho_m; then all
-//                       threads form the series in a fixed order.
+//                       e^-40), as a scan of Mobius maps over the workgroup
+//                       (bessel_series), the ratios multiplied up to rho_m by
+//                       a prefix scan; then all threads form the series in a
+//                       fixed order.
 //   newton_kernel    -- one workgroup: the scan's first minimum, then
 //                       Newton's method on u = log(kappa) with bisection as
 //                       the safeguard. The derivatives come from the same
@@ -189,37 +191,190 @@ __global__ void __launch_bounds__(kBlock) moments_kernel(const T* __restrict__ x
   }
 }
 
-// Thread 0: rho_m(kappa) for m = 0..M into rho[]; with DER also
-// rho'_m and rho''_m into d1[], d2[] (kappa > 0 then).
+// Shared memory of the workgroup-wide series (double-buffered scans).
+struct SeriesSmem {
+  double mat[2][kBlock][4];  // Mobius matrices (row-major 2x2)
+  double aff[2][kBlock][2];  // affine maps x -> a + b x
+  double pre[2][kBlock][3];  // segment totals (product, sum, sum)
+  double red[kBlock / 64];
+};
+
+__device__ __forceinline__ void mat_mul_norm(const double* a, const double* b, double* c) {
+  double c0 = fma(a[0], b[0], a[1] * b[2]);
+  double c1 = fma(a[0], b[1], a[1] * b[3]);
+  double c2 = fma(a[2], b[0], a[3] * b[2]);
+  double c3 = fma(a[2], b[1], a[3] * b[3]);
+  const double mx = fmax(fmax(fabs(c0), fabs(c1)), fmax(fabs(c2), fabs(c3)));
+  const int e = (mx > 0.0) ? ilogb(mx) : 0;  // exact rescaling by a power of two
+  c[0] = ldexp(c0, -e);
+  c[1] = ldexp(c1, -e);
+  c[2] = ldexp(c2, -e);
+  c[3] = ldexp(c3, -e);
+}
+
+// rho_m(kappa) for m = 0..M into rho[]; with DER also rho'_m, rho''_m into
+// d1[], d2[] (kappa > 0 then). All threads of the workgroup take part.
+//
+// The backward recurrence r_m = kappa / (2m + kappa r_{m+1}), r_{Ms+1} = 0,
+// applies the Mobius maps with matrices [[0, kappa], [kappa, 2m]] to the
+// homogeneous vector (0, 1): thread t composes the maps of its segment of m
+// (non-negative matrices, rescaled by powers of two, so no cancellation), a
+// suffix scan over the threads gives every segment the vector entering it
+// from above, and each thread walks its segment. r'_m and r''_m obey affine
+// recurrences in r'_{m+1} and r''_{m+1} (coefficients from r_m, r'_m), done
+// the same way with affine maps; rho_m, D_m and E_m are prefix products and
+// sums over m (a combined prefix scan). The composition is a reassociation
+// of the recurrence; its rounding grows with the tree depth instead of the
+// length of the chain.
 template <bool DER>
 __device__ void bessel_series(double kappa, int M, double* __restrict__ rho, double* __restrict__ d1,
-                              double* __restrict__ d2) {
+                              double* __restrict__ d2, SeriesSmem& sm) {
+  const int t = threadIdx.x;
   const int Ms = int(ceil(sqrt(double(M) * double(M) + 40.0 * kappa))) + 16;
-  double r = 0.0, rp = 0.0, rpp = 0.0;
+  const int len = (Ms + kBlock - 1) / kBlock;
+  const int lo = 1 + t * len, hi = min(Ms, (t + 1) * len);  // empty when lo > hi
   const double ik2 = DER ? 1.0 / (kappa * kappa) : 0.0;
   const double ik3 = DER ? ik2 / kappa : 0.0;
-  for (int m = Ms; m >= 1; --m) {
-    const double rn = kappa / (2.0 * double(m) + kappa * r);
-    if (DER) {
-      const double rpn = rn * rn * (2.0 * double(m) * ik2 - rp);
-      const double rppn = 2.0 * rpn * rpn / rn - rn * rn * (4.0 * double(m) * ik3 + rpp);
-      rp = rpn;
-      rpp = rppn;
-      if (m <= M) {
-        d1[m] = rp;
-        d2[m] = rpp;
+
+  // 1. Mobius composition of the segment, suffix scan, then the walk.
+  double P[4] = {1.0, 0.0, 0.0, 1.0};
+  for (int m = hi; m >= lo; --m) {
+    const double Mm[4] = {0.0, kappa, kappa, 2.0 * double(m)};
+    double Q[4];
+    mat_mul_norm(Mm, P, Q);
+    P[0] = Q[0]; P[1] = Q[1]; P[2] = Q[2]; P[3] = Q[3];
+  }
+  int cur = 0;
+  for (int k = 0; k < 4; ++k) sm.mat[0][t][k] = P[k];
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {
+    if (t + d < kBlock)
+      mat_mul_norm(sm.mat[cur][t], sm.mat[cur][t + d], sm.mat[cur ^ 1][t]);
+    else
+      for (int k = 0; k < 4; ++k) sm.mat[cur ^ 1][t][k] = sm.mat[cur][t][k];
+    __syncthreads();
+    cur ^= 1;
+  }
+  const double r_top = (t + 1 < kBlock) ? sm.mat[cur][t + 1][1] / sm.mat[cur][t + 1][3] : 0.0;
+  {
+    double r = r_top;
+    for (int m = hi; m >= lo; --m) {
+      r = kappa / (2.0 * double(m) + kappa * r);
+      if (m <= M) rho[m] = r;
+    }
+  }
+  double rp_top = 0.0, rpp_top = 0.0;
+  if (DER) {
+    // 2. r'_m = 2m r_m^2 / kappa^2 - r_m^2 r'_{m+1}.
+    double a = 0.0, b = 1.0;
+    {
+      double r = r_top;
+      for (int m = hi; m >= lo; --m) {
+        r = kappa / (2.0 * double(m) + kappa * r);
+        const double r2 = r * r;
+        a = fma(-r2, a, 2.0 * double(m) * r2 * ik2);
+        b = -r2 * b;
       }
     }
-    r = rn;
-    if (m <= M) rho[m] = r;
+    __syncthreads();  // the matrix scan's reads are done
+    sm.aff[0][t][0] = a;
+    sm.aff[0][t][1] = b;
+    __syncthreads();
+    cur = 0;
+    for (int d = 1; d < kBlock; d <<= 1) {
+      if (t + d < kBlock) {
+        sm.aff[cur ^ 1][t][0] = fma(sm.aff[cur][t][1], sm.aff[cur][t + d][0], sm.aff[cur][t][0]);
+        sm.aff[cur ^ 1][t][1] = sm.aff[cur][t][1] * sm.aff[cur][t + d][1];
+      } else {
+        sm.aff[cur ^ 1][t][0] = sm.aff[cur][t][0];
+        sm.aff[cur ^ 1][t][1] = sm.aff[cur][t][1];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    rp_top = (t + 1 < kBlock) ? sm.aff[cur][t + 1][0] : 0.0;
+    // 3. r''_m = 2 r'_m^2 / r_m - r_m^2 (4m / kappa^3 + r''_{m+1}).
+    a = 0.0;
+    b = 1.0;
+    {
+      double r = r_top, rp = rp_top;
+      for (int m = hi; m >= lo; --m) {
+        r = kappa / (2.0 * double(m) + kappa * r);
+        const double r2 = r * r;
+        rp = r2 * (2.0 * double(m) * ik2 - rp);
+        const double A = 2.0 * rp * rp / r - 4.0 * double(m) * r2 * ik3;
+        a = fma(-r2, a, A);
+        b = -r2 * b;
+        if (m <= M) d1[m] = rp;
+      }
+    }
+    __syncthreads();
+    sm.aff[0][t][0] = a;
+    sm.aff[0][t][1] = b;
+    __syncthreads();
+    cur = 0;
+    for (int d = 1; d < kBlock; d <<= 1) {
+      if (t + d < kBlock) {
+        sm.aff[cur ^ 1][t][0] = fma(sm.aff[cur][t][1], sm.aff[cur][t + d][0], sm.aff[cur][t][0]);
+        sm.aff[cur ^ 1][t][1] = sm.aff[cur][t][1] * sm.aff[cur][t + d][1];
+      } else {
+        sm.aff[cur ^ 1][t][0] = sm.aff[cur][t][0];
+        sm.aff[cur ^ 1][t][1] = sm.aff[cur][t][1];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    rpp_top = (t + 1 < kBlock) ? sm.aff[cur][t + 1][0] : 0.0;
+    {
+      double r = r_top, rp = rp_top, rpp = rpp_top;
+      for (int m = hi; m >= lo; --m) {
+        r = kappa / (2.0 * double(m) + kappa * r);
+        const double r2 = r * r;
+        rp = r2 * (2.0 * double(m) * ik2 - rp);
+        rpp = 2.0 * rp * rp / r - r2 * (4.0 * double(m) * ik3 + rpp);
+        if (m <= M) d2[m] = rpp;
+      }
+    }
   }
-  rho[0] = 1.0;
-  double p = 1.0, D = 0.0, E = 0.0;
-  if (DER) {
+  // 4. Prefix products and sums over m = 1..M (segments clipped to M).
+  const int hm = min(hi, M);
+  double sp = 1.0, sD = 0.0, sE = 0.0;
+  for (int m = lo; m <= hm; ++m) {
+    sp *= rho[m];
+    if (DER) {
+      const double q = d1[m] / rho[m];
+      sD += q;
+      sE += d2[m] / rho[m] - q * q;
+    }
+  }
+  __syncthreads();
+  sm.pre[0][t][0] = sp;
+  sm.pre[0][t][1] = sD;
+  sm.pre[0][t][2] = sE;
+  __syncthreads();
+  cur = 0;
+  for (int d = 1; d < kBlock; d <<= 1) {
+    if (t >= d) {
+      sm.pre[cur ^ 1][t][0] = sm.pre[cur][t - d][0] * sm.pre[cur][t][0];
+      sm.pre[cur ^ 1][t][1] = sm.pre[cur][t - d][1] + sm.pre[cur][t][1];
+      sm.pre[cur ^ 1][t][2] = sm.pre[cur][t - d][2] + sm.pre[cur][t][2];
+    } else {
+      sm.pre[cur ^ 1][t][0] = sm.pre[cur][t][0];
+      sm.pre[cur ^ 1][t][1] = sm.pre[cur][t][1];
+      sm.pre[cur ^ 1][t][2] = sm.pre[cur][t][2];
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  double p = (t > 0) ? sm.pre[cur][t - 1][0] : 1.0;
+  double D = (t > 0) ? sm.pre[cur][t - 1][1] : 0.0;
+  double E = (t > 0) ? sm.pre[cur][t - 1][2] : 0.0;
+  if (t == 0) rho[0] = 1.0;
+  if (DER && t == 0) {
     d1[0] = 0.0;
     d2[0] = 0.0;
   }
-  for (int m = 1; m <= M; ++m) {
+  for (int m = lo; m <= hm; ++m) {
     const double rm = rho[m];
     p *= rm;
     rho[m] = p;
@@ -231,17 +386,18 @@ __device__ void bessel_series(double kappa, int M, double* __restrict__ rho, dou
       d2[m] = p * (D * D + E);
     }
   }
+  __syncthreads();
 }
 
 __global__ void __launch_bounds__(kBlock) series_kernel(const double* __restrict__ S, int M, double n, double L,
                                                        FKappas kap, int B, double* __restrict__ rho_all,
                                                        double* __restrict__ cv, double* __restrict__ sums) {
-  __shared__ double red[kBlock / 64];
+  __shared__ SeriesSmem sm;
+  double* red = sm.red;
   const int b = blockIdx.x;
   double* rho = rho_all + int64_t(b) * (M + 1);
   const int Mb = min(M, kap.order[b]);
-  if (threadIdx.x == 0) bessel_series<false>(kap.k[b], Mb, rho, nullptr, nullptr);
-  __syncthreads();
+  bessel_series<false>(kap.k[b], Mb, rho, nullptr, nullptr, sm);
   double a = 0.0, a0 = 0.0, c = 0.0;
   for (int m = 1 + threadIdx.x; m <= Mb; m += kBlock) {
     const double sr = S[2 * (m - 1)], si = S[2 * (m - 1) + 1];
@@ -283,10 +439,10 @@ struct Eval {
 // Objective and its first two derivatives in u = log(kappa), all threads,
 // with the series cut at order Mk (that of a kappa at least as large).
 __device__ Eval eval_u(double u, const double* __restrict__ S, int Mk, double n, double L, double* rho, double* d1,
-                       double* d2, double* red) {
+                       double* d2, SeriesSmem& sm) {
   const double kappa = exp(u);
-  if (threadIdx.x == 0) bessel_series<true>(kappa, Mk, rho, d1, d2);
-  __syncthreads();
+  double* red = sm.red;
+  bessel_series<true>(kappa, Mk, rho, d1, d2, sm);
   double A = 0.0, C = 0.0, A1 = 0.0, C1 = 0.0, A2 = 0.0, C2 = 0.0;
   for (int m = 1 + threadIdx.x; m <= Mk; m += kBlock) {
     const double sr = S[2 * (m - 1)], si = S[2 * (m - 1) + 1];
@@ -323,7 +479,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
                                                        FKappas kap, int B, const double* __restrict__ cvgrid,
                                                        double* __restrict__ rho3, double* __restrict__ result,
                                                        int32_t* __restrict__ argmin) {
-  __shared__ double red[kBlock / 64];
+  __shared__ SeriesSmem sm;
   double* rho = rho3;
   double* d1 = rho3 + (M + 1);
   double* d2 = rho3 + 2 * (M + 1);
@@ -349,8 +505,8 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
     g_best = 0.0;
   } else {
     double ul = log(klo), uh = log(khi);
-    const Eval el = eval_u(ul, S, Mk, n, L, rho, d1, d2, red);
-    const Eval eh = eval_u(uh, S, Mk, n, L, rho, d1, d2, red);
+    const Eval el = eval_u(ul, S, Mk, n, L, rho, d1, d2, sm);
+    const Eval eh = eval_u(uh, S, Mk, n, L, rho, d1, d2, sm);
     steps = 2;
     if (!(el.g < 0.0 && eh.g > 0.0)) {
       const bool lo_wins = el.cv <= eh.cv;
@@ -359,7 +515,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
       g_best = lo_wins ? el.g : eh.g;
     } else {
       double u = (bs > 0 && bs < B - 1 && kap.k[bs] > klo && kap.k[bs] < khi) ? log(kap.k[bs]) : 0.5 * (ul + uh);
-      Eval e = eval_u(u, S, Mk, n, L, rho, d1, d2, red);
+      Eval e = eval_u(u, S, Mk, n, L, rho, d1, d2, sm);
       ++steps;
       for (int it = 0; it < kMaxNewton && e.g != 0.0; ++it) {
         if (e.g < 0.0)
@@ -370,7 +526,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
         if (!(e.gp > 0.0) || !(un > ul && un < uh)) un = 0.5 * (ul + uh);
         const bool done = fabs(un - u) <= 1e-14 * fmax(1.0, fabs(un)) || (uh - ul) <= 1e-14 * fmax(1.0, fabs(un));
         u = un;
-        e = eval_u(u, S, Mk, n, L, rho, d1, d2, red);
+        e = eval_u(u, S, Mk, n, L, rho, d1, d2, sm);
         ++steps;
         if (done) break;
       }
@@ -391,10 +547,8 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
 // w_m = rho_m(kappa) S_m, m = 1..M (one workgroup).
 __global__ void __launch_bounds__(kBlock) pilot_weights_kernel(const double* __restrict__ S, int M, double kappa,
                                                               double* __restrict__ rho, double* __restrict__ w) {
-  if (threadIdx.x == 0) {
-    bessel_series<false>(kappa, M, rho, nullptr, nullptr);
-  }
-  __syncthreads();
+  __shared__ SeriesSmem sm;
+  bessel_series<false>(kappa, M, rho, nullptr, nullptr, sm);
   for (int m = 1 + threadIdx.x; m <= M; m += kBlock) {
     w[2 * (m - 1)] = rho[m] * S[2 * (m - 1)];
     w[2 * (m - 1) + 1] = rho[m] * S[2 * (m - 1) + 1];
