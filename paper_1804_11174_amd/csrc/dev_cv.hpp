@@ -31,6 +31,14 @@
 // has exponent 0 and I0e <= 1). Concentrations are ascending and the
 // exponent scales with kappa, so once every lane of a wave is below the
 // bound for one concentration, the wave skips the rest for that j.
+//
+// The leading concentrations with 2 kappa < X0 (the small-argument Bessel
+// range covers every pair) run in chunks of their own through a lean loop:
+// no term can reach the skip bound, so there is no vote, and the pair
+// geometry is s^2 and c^2 alone. With only that branch's polynomial live,
+// its coefficients stay in scalar registers instead of being rebuilt for
+// every term. Which loop a concentration takes depends on kappa alone, so
+// the sums still do not depend on the chunk or group size.
 #include "device_bessel.hpp"
 #include "kde_internal.hpp"
 
@@ -46,6 +54,7 @@ struct CvConsts {
   T twok[KDE_MAX_KAPPAS];  // 2 kappa
   T tk[KDE_MAX_KAPPAS];    // (2 kappa / X0)^2: t = (R / X0)^2 = tk c^2
   int B;
+  int npure;   // leading concentrations with 2 kappa < X0: every term takes the small-argument branch
   int nsmall;  // leading concentrations that may need the small-argument I0e branch
   T skip;      // exponent bound (in the unit of A)
 };
@@ -221,6 +230,62 @@ __device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint
   return g;
 }
 
+// s^2 and c^2 of one pair: all that the small-argument terms need.
+template <typename T>
+struct GeoS {
+  T s2, c2;
+};
+__device__ __forceinline__ GeoS<double> pair_geo_small(const IPart<double>& p, const double* __restrict__ tj, int jj) {
+  const double aj = tj[2 * jj], bj = tj[2 * jj + 1];
+  const double c = p.a * aj + p.b * bj;
+  const double s = p.b * aj - p.a * bj;
+  return GeoS<double>{s * s, c * c};
+}
+__device__ __forceinline__ GeoS<float> pair_geo_small(const IPart<float>& p, const uint32_t* __restrict__ tj, int jj) {
+  const float phi = float(int32_t(p.u - tj[jj])) * 7.3145904152e-10f;
+  const float y = phi * phi;
+  float r = 1.0f / 87178291200.0f;
+  r = fmaf(r, y, -1.0f / 479001600.0f);
+  r = fmaf(r, y, 1.0f / 3628800.0f);
+  r = fmaf(r, y, -1.0f / 40320.0f);
+  r = fmaf(r, y, 1.0f / 720.0f);
+  r = fmaf(r, y, -1.0f / 24.0f);
+  r = fmaf(r, y, 0.5f);
+  const float q = y * r;
+  const float c = 1.0f - q;
+  return GeoS<float>{q * (2.0f - q), c * c};
+}
+
+// Concentrations [b0, b_end) with 2 kappa < X0: every term takes the
+// small-argument branch, and no exponent reaches -X0 > -S, so nothing is
+// skipped. Same accumulation order as pair_chunk.
+template <typename T, int BC, bool MASKED>
+__device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* __restrict__ tj, int nj,
+                                                const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
+                                                const CvConsts<T>& K, const double* __restrict__ etab,
+                                                Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
+  const int nb = min(BC, b_end - b0);
+  for (int jj = 0; jj < nj; ++jj) {
+    const GeoS<T> g = pair_geo_small(ip, tj, jj);
+    bool live = true;
+    if (MASKED) live = valid_i && (!diag || jj > int(threadIdx.x));
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      if (bb < nb) {
+        const int b = b0 + bb;
+        T t2 = exp_unit(K.A[b] * g.s2, etab);
+        T t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
+        if (MASKED) {
+          t1 = live ? t1 : T(0);
+          t2 = live ? t2 : T(0);
+        }
+        acc1[bb].add(t1);
+        acc2[bb].add(t2);
+      }
+    }
+  }
+}
+
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
                                            const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
@@ -331,17 +396,26 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
   const int b_end = sm.b_end;
 
   const int lane = tid & 63, wave = tid >> 6;
-  for (int b0 = b_lo; b0 < b_end; b0 += BC) {
+  for (int b0 = b_lo; b0 < b_end;) {
+    // chunks do not straddle the end of the pure small-argument range
+    const int bc_end = min(b0 + BC, b0 < K.npure ? min(b_end, K.npure) : b_end);
     Acc<T> s1[BC], s2[BC];
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       s1[bb].zero();
       s2[bb].zero();
     }
-    if (masked)
-      pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, sm.etab, s1, s2);
-    else
-      pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, b_end, K, sm.etab, s1, s2);
+    if (b0 < K.npure) {
+      if (masked)
+        pair_chunk_pure<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+      else
+        pair_chunk_pure<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+    } else {
+      if (masked)
+        pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+      else
+        pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+    }
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       double v1 = wave_sum(s1[bb].value());
@@ -355,13 +429,14 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
     if (tid < 2 * BC) {
       const int bb = tid % BC;
       const int which = tid / BC;  // 0: Kbar sums, 1: K sums
-      if (b0 + bb < b_end) {
+      if (b0 + bb < bc_end) {
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
         sm.unit_acc[which * K.B + b0 + bb] = v;
       }
     }
     __syncthreads();
+    b0 = bc_end;
   }
   const int nk = b_hi - b_lo;
   for (int k = tid; k < 2 * nk; k += kBlock) {
@@ -380,6 +455,7 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
   const double X0 = double(I0eBounds<T>::X0);
   K.B = B;
   K.nsmall = 0;
+  K.npure = 0;
   for (int b = 0; b < B; ++b) {
     const double k = kappas[b];
     K.A[b] = T(-2.0 * k * unit);
@@ -391,6 +467,7 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
     // an argument 2 kappa |c| below X0 carries weight exp(-2 kappa (1 - |c|))
     // <= exp(-(2 kappa - X0)); beyond the skip bound it is negligible
     if (2.0 * k - X0 <= kSkipExponent) K.nsmall = b + 1;
+    if (2.0 * k < X0) K.npure = b + 1;
   }
   K.skip = T(-kSkipExponent * unit);
   return K;

@@ -166,6 +166,38 @@ def test_bad_arguments_raise(gpu):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_small_argument_range_boundary(gpu, dtype):
+    """Concentrations with 2 kappa below the Bessel fits' switch point
+    (16 in double, 8 in float) take their own loop; values on both sides of
+    and at that point, against the oracle, on a ragged size with a diagonal
+    tile pair."""
+    L = 4 * math.pi
+    rng = np.random.default_rng(71)
+    x = W.cosine_positions(rng, 700, L, 0.4, 0.5)
+    if dtype == "f32":
+        x = x.astype(np.float32)
+    kap = np.array([0.5, 3.99, 4.0, 4.01, 7.99, 8.0, 8.01, 20.0, 60.0])
+    announce("cv small-argument boundary", dtype)
+    cv, sums, am = run_gpu_cv(gpu, x, L, kap, dtype)
+    ref_cv, S1, S2 = ocv.cv_curve(np.asarray(x, dtype=np.float64), L, kap)
+    tol = TOL[dtype]
+    n, B = len(x), len(kap)
+    if dtype == "f64":
+        from oracle.vonmises import i0e
+        assert rel_err(cv, ref_cv).max() <= tol, rel_err(cv, ref_cv)
+        skipped = math.exp(-70.0) * n * n / 2
+        for got, ref, w in ((sums[:B], S1, 1 / (L * i0e(kap) ** 2)), (sums[B:], S2, 1 / (L * i0e(kap)))):
+            assert np.all(np.abs(got - ref) <= tol * np.abs(ref) + skipped * w)
+    else:
+        first = (n * conv2_at_zero(kap, L) + 2 * S1) / n ** 2
+        scale = np.maximum(np.abs(ref_cv), first)
+        assert np.all(np.abs(cv - ref_cv) <= tol * scale)
+        assert np.all(2 * np.abs(sums[:B] - S1) / n ** 2 <= tol * scale)
+        assert np.all(4 * np.abs(sums[B:] - S2) / (n * (n - 1)) <= tol * scale)
+    assert_argmin_ok(am, ref_cv, tol)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pass_size_changes_nothing(gpu, dtype):
     """The tuned pass size (concentrations per pass) and the split of a
     tile pair over workgroups by concentration range must not change any
