@@ -59,9 +59,9 @@ PEAK_HBM = 8.0e12
 #        + two products = 30; two accumulations 2. Total 47.
 #   f32: K term: product 1 + exponential 1 = 2; Kbar term: product 1 +
 #        exponential 1 + argument and factor 2 + degree-5 polynomial 5 +
-#        two products = 11; two compensated (Kahan) accumulations of 4 = 8.
-#        Total 21.
-OPS_PER_TERM = {"f64": 47, "f32": 21}
+#        two products = 11; two accumulations into double (conversion and
+#        add) of 2 = 4. Total 17.
+OPS_PER_TERM = {"f64": 47, "f32": 17}
 SKIP_EXPONENT = 70.0
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
@@ -71,9 +71,9 @@ SKIP_EXPONENT = 70.0
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "device_bessel.hpp", "bessel_coeffs.inc", "dev_layout.hpp",
                        "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "96251c8faebf304b",
-                "f64": {"fetch_kib": 4717.6875, "write_kib": 16448.0},
-                "f32": {"fetch_kib": 1383.3125, "write_kib": 16448.0}}
+PAIR_TRAFFIC = {"digest": "f3268bec837ca2c7",
+                "f64": {"fetch_kib": 4571.375, "write_kib": 16448.0},
+                "f32": {"fetch_kib": 1399.3125, "write_kib": 16448.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
@@ -296,10 +296,10 @@ def main():
 
 # Triangle shape, algorithmic lane-operations per evaluated (pair, width)
 # term: u = r * scale 1; max(0, 2 - u) and max(0, 1 - u) 4; their cubes 4;
-# the spline difference 1 (an FMA); two accumulations: 2 in double, two
-# Kahan adds of 4 in float. The per-pair distance (3-4 operations) is
-# shared by all widths and not counted.
-TRI_OPS_PER_TERM = {"f64": 12, "f32": 18}
+# the spline difference 1 (an FMA); two accumulations: 2 in double, and in
+# float two of 2 (each term converted to double and added). The per-pair
+# distance (3-4 operations) is shared by all widths and not counted.
+TRI_OPS_PER_TERM = {"f64": 12, "f32": 14}
 
 
 def count_tri_terms(x, L, widths):

@@ -43,8 +43,9 @@
  *   (positions, per-particle concentrations, gathered values): KDE_F64 =
  *   double, KDE_F32 = float. Grid arrays and scalar results are always
  *   double. In the KDE_F32 form the per-pair and per-node kernel arithmetic
- *   runs in float with compensated per-thread sums; Bessel normalisers,
- *   cross-block reductions and the final CV combination stay in double.
+ *   runs in float, each term added to a per-thread double sum; Bessel
+ *   normalisers, cross-block reductions and the final CV combination stay
+ *   in double.
  * Streams. `stream` is a hipStream_t passed as void* (NULL = the default
  *   stream). Every call only enqueues work on it and returns; results are
  *   valid once that work has completed. No call synchronises the device.

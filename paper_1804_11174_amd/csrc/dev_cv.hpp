@@ -70,18 +70,14 @@ struct Acc<double> {
   __device__ __forceinline__ double value() const { return s; }
 };
 
-// Compensated (Kahan) float accumulator.
+// Float terms summed in double: one conversion and one double add per
+// term, fewer instructions than a compensated float sum and more accurate.
 template <>
 struct Acc<float> {
-  float s, c;
-  __device__ __forceinline__ void zero() { s = 0.0f; c = 0.0f; }
-  __device__ __forceinline__ void add(float v) {
-    float y = v - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-  __device__ __forceinline__ double value() const { return double(s) - double(c); }
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(float v) { s += double(v); }
+  __device__ __forceinline__ double value() const { return s; }
 };
 
 // Pair-kernel exponents lie in [-2 kappa, 0] with kappa <= KDE_MAX_CV_KAPPA

@@ -52,16 +52,12 @@ struct SumOf<double> {
   __device__ __forceinline__ void add(double v) { s += v; }
   __device__ __forceinline__ double value() const { return s; }
 };
+// Float terms summed in double (a conversion and a double add per term).
 template <>
 struct SumOf<float> {
-  float s = 0.0f, c = 0.0f;
-  __device__ __forceinline__ void add(float v) {
-    float y = v - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-  __device__ __forceinline__ double value() const { return double(s) - double(c); }
+  double s = 0.0;
+  __device__ __forceinline__ void add(float v) { s += double(v); }
+  __device__ __forceinline__ double value() const { return s; }
 };
 
 constexpr int kDepMaxChunk = 512;
