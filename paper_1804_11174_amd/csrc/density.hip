@@ -52,9 +52,11 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
                                                        double kappa_g, bool per, int64_t n, int M, double L,
                                                        const double* __restrict__ field, T* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ double etab[std::is_same<T, double>::value ? 256 : 1];
   T* ts = reinterpret_cast<T*>(dyn);
   T* tc = ts + M;
   T* tf = tc + M;
+  exp_table_fill<T>(etab);
   for (int k = threadIdx.x; k < M; k += kBlock) {
     double sv, cv;
     sincospi(double(k) / double(M), &sv, &cv);
@@ -77,13 +79,13 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
     int g = gp.g0;
     for (int k = 0; k < M; ++k) {
       const T s = ts[k] * gp.cb - tc[k] * gp.sb;
-      acc.add(tf[g] * Flt<T>::ex(A * (s * s)));
+      acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
       g = (g + 1 == M) ? 0 : g + 1;
     }
   } else {
     for (int g = 0; g < M; ++g) {
       const T s = node_s(gp, g, M, ts, tc);
-      acc.add(tf[g] * Flt<T>::ex(A * (s * s)));
+      acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
     }
   }
   out[i] = T(w * acc.value());

@@ -31,15 +31,17 @@ namespace kde {
 
 template <typename T>
 struct Flt;
+// ex(a, tab): exp of a kernel exponent a <= 0 (natural in double, with the
+// exponential's table `tab` in LDS; base 2 in float, where tab is unused).
 template <>
 struct Flt<double> {
-  static __device__ __forceinline__ double ex(double a) { return exp_nonpos_f64(a); }  // a = natural exponent <= 0
+  static __device__ __forceinline__ double ex(double a, const double* tab) { return exp_nonpos_table_any(a, tab); }
   static constexpr double unit = 1.0;
   static constexpr double tiny = DBL_MIN;
 };
 template <>
 struct Flt<float> {
-  static __device__ __forceinline__ float ex(float a) { return __builtin_amdgcn_exp2f(a); }  // base 2
+  static __device__ __forceinline__ float ex(float a, const double*) { return __builtin_amdgcn_exp2f(a); }
   static constexpr double unit = 1.4426950408889634;
   static constexpr float tiny = FLT_MIN;
 };
@@ -131,7 +133,17 @@ struct DepSmem {
   PGeo<T> pg[kDepMaxChunk];
   T pA[kDepMaxChunk], pw[kDepMaxChunk];
   double red[kBlock];
+  double etab[std::is_same<T, double>::value ? 256 : 1];  // exponential table (double form)
 };
+
+// Stage the double exponential's table (KDE_EXP_TABLE) in LDS; no-op in float.
+template <typename T>
+__device__ __forceinline__ void exp_table_fill(double* etab) {
+  if constexpr (std::is_same<T, double>::value) {
+    constexpr double src[256] = KDE_EXP_TABLE;
+    for (int k = threadIdx.x; k < 256; k += kBlock) etab[k] = src[k];
+  }
+}
 
 // Fill the node table: ts[k] = sin(pi k/M), tc[k] = cos(pi k/M).
 template <typename T>
@@ -156,6 +168,7 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
                                               const T* ts, const T* tc, DepSmem<T>& sm) {
   const int tid = threadIdx.x;
   for (int k = tid; k < cnt; k += kBlock) particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.pg[k], sm.pA[k], sm.pw[k]);
+  exp_table_fill<T>(sm.etab);
   __syncthreads();
   if (M <= kBlock) {
     const int S = kBlock / M;
@@ -165,7 +178,7 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
       SumOf<T> acc;
       for (int p = sub; p < cnt; p += S) {
         const T s = node_s(sm.pg[p], g, M, ts, tc);
-        const T e = Flt<T>::ex(sm.pA[p] * (s * s));
+        const T e = Flt<T>::ex(sm.pA[p] * (s * s), sm.etab);
         acc.add(PER ? sm.pw[p] * e : e);
       }
       tot = acc.value();
@@ -187,7 +200,7 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
         const int g = tid + k * kBlock;
         if (g < M) {
           const T s = node_s(gp, g, M, ts, tc);
-          const T e = Flt<T>::ex(A * (s * s));
+          const T e = Flt<T>::ex(A * (s * s), sm.etab);
           acc[k].add(PER ? w * e : e);
         }
       }

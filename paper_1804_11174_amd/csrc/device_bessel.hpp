@@ -106,7 +106,7 @@ __device__ __forceinline__ double exp_nonpos_f64_bounded(double x) {
   return __builtin_amdgcn_ldexp(p, int(fmax(n, -2000.0)));
 }
 
-// exp(x) for -2^40 <= x <= 0 (or NaN) by Tang's table method: with
+// exp(x) for -2^44 <= x <= 0 (or NaN) by Tang's table method: with
 // n = rint(x 256/ln2) = 256 m + k, r = x - n ln2/256 (head and tail of
 // ln2/256, |r| <= ln2/512), exp(x) = 2^m T[k] (1 + q), T[k] = 2^(k/256) from
 // `tab` (KDE_EXP_TABLE, 256 correctly rounded values, staged in LDS by the
@@ -126,6 +126,12 @@ __device__ __forceinline__ double exp_nonpos_table(double x, const double* __res
   q *= r;
   const double t = tab[ni & 255];
   return __builtin_amdgcn_ldexp(fma(t, q, t), ni >> 8);
+}
+
+// exp(x) for any x <= 0 (or NaN) by the table method, arguments below
+// -1000 (far below the underflow limit) clamped first.
+__device__ __forceinline__ double exp_nonpos_table_any(double x, const double* __restrict__ tab) {
+  return exp_nonpos_table((x < -1000.0) ? -1000.0 : x, tab);  // NaN passes through
 }
 
 // exp(x) for any x <= 0 (or NaN): arguments below -1000, far below the
