@@ -59,7 +59,9 @@ namespace {
 
 constexpr double kFourierTail = 1e-18;  // rho_M below this ends the series
 constexpr int kMomM = 16;               // consecutive m per moment block
-constexpr int kMomChunks = 64;          // particle chunks of the moment partials
+constexpr int kMomChunks = 64;          // moment partials' budget: kMomChunks x kMaxOrder (re, im) pairs
+constexpr int64_t kMomBlocks = 4096;    // workgroups a moment launch aims for
+constexpr int kMomPerThread = 8;        // fewest particles per thread of a moment workgroup
 constexpr int kPilotRun = 64;           // rotations between exact phase restarts
 constexpr int kMaxNewton = 100;
 
@@ -87,7 +89,24 @@ int fourier_order(double kmax) {
 
 const int kMaxOrder = fourier_order(KDE_MAX_FOURIER_KAPPA);
 
-int64_t moment_chunks(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(kMomChunks, ceil_div(n, 1024))); }
+// Moment partials' budget for N particles, in units of kMaxOrder (re, im)
+// pairs: one per kBlock x kMomPerThread particles, at least 1, at most
+// kMomChunks.
+int64_t moment_budget(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>(kMomChunks, n / (int64_t(kBlock) * kMomPerThread)));
+}
+
+// Particle chunks of the moments of N particles to order M: about
+// kMomBlocks workgroups over the ceil(M / kMomM) mode groups (a low order
+// still fills the GPU), at least kMomPerThread particles per thread (so the
+// workgroup's fixed-order reduction of 2 kMomM sums stays a small part of
+// its work), and chunks x M within the partials' budget.
+int64_t moment_chunks(int64_t n, int M) {
+  int64_t c = ceil_div(kMomBlocks, ceil_div(M, kMomM));
+  c = std::min<int64_t>(c, n / (int64_t(kBlock) * kMomPerThread));
+  c = std::min<int64_t>(c, moment_budget(n) * kMaxOrder / M);
+  return std::max<int64_t>(1, c);
+}
 
 struct FourierBufs {
   double* partials;  // [chunks][2 M]
@@ -105,9 +124,12 @@ struct FourierBufs {
 FourierBufs carve_fourier(Carver& c, int op, int64_t n, int B) {
   FourierBufs b{};
   const int M = kMaxOrder;
-  const int64_t chunks = moment_chunks(n);
-  b.partials = c.take<double>(size_t(chunks) * 2 * M);
-  b.colsum = c.take<double>(column_sum_scratch(chunks, 2 * M) / sizeof(double) + 1);
+  // any order's chunks x 2 M partials fit the budget; its column-sum
+  // scratch, ceil(chunks / R) x 2 M for R rows per level-1 block, is at
+  // most (chunks x 2 M) / R + 2 M
+  const int64_t budget = moment_budget(n);
+  b.partials = c.take<double>(size_t(budget) * 2 * M);
+  b.colsum = c.take<double>((column_sum_scratch(budget * M, 2) + column_sum_scratch(1, 2 * M)) / sizeof(double) + 1);
   b.S = c.take<double>(size_t(2) * M);
   const int slots = (op == KDE_OP_CV_FOURIER) ? B : (op == KDE_OP_CV_REFINE ? std::max(B, 3) : 1);
   b.rho = c.take<double>(size_t(slots) * (M + 1));
@@ -615,7 +637,7 @@ __global__ void __launch_bounds__(kBlock) pilot_apply_kernel(const double* __res
 
 template <typename T>
 kde_status launch_moments(const T* x, int64_t n, double L, int M, const FourierBufs& b, hipStream_t s) {
-  const int64_t chunks = moment_chunks(n);
+  const int64_t chunks = moment_chunks(n, M);
   const int64_t per = ceil_div(n, chunks);
   const dim3 grid{unsigned(chunks), unsigned(ceil_div(M, kMomM))};
   {
