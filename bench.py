@@ -113,6 +113,60 @@ def count_evaluated_terms(x, L, kappas):
     return total
 
 
+# Secondary kernels of the plain pipeline, from the library's per-launch
+# HIP-event averages. Algorithmic lane-operations per (particle, node)
+# evaluation of the deposit and gather:
+#   f64: node sine from the node table 2, square 1, exponent product 1,
+#        clamp 1, table exponential 14, weight or field product 1,
+#        accumulation 1 = 21;
+#   f32: node index wrap 2, node sine 2, square 1, exponent product 1,
+#        exp2 1, weight or field product 1, accumulation into double 2 = 10.
+# Algorithmic HBM bytes per launch: deposit reads the positions (and the
+# widths in the adaptive one; the pipeline runs one of each, so 1.5 arrays
+# on average) and writes its chunk grids (chunks x M doubles); gather reads
+# positions and widths and writes the gathered values; adapt reads the
+# positions twice (log sums, then widths) and writes the widths.
+NODE_OPS = {"f64": 21, "f32": 10}
+HBM_PEAK = 8e12
+
+
+def secondary_rooflines(prec, n, M, kern):
+    el = 8 if prec == "f64" else 4
+    chunk = min(512, max(64, -(-n // 2048)))
+    chunks = -(-n // chunk)
+    out = {}
+    for name, bytes_ in (("deposit", 1.5 * el * n + chunks * M * 8), ("gather", 3 * el * n + M * 8)):
+        ms = kern[name]["avg_ms"]
+        if not ms:
+            continue
+        alu = n * M * NODE_OPS[prec] / (ms * 1e-3)
+        bw = bytes_ / (ms * 1e-3)
+        out[name] = {"bound": "alu", "ops_per_eval": NODE_OPS[prec], "evals_per_launch": n * M,
+                     "alu_frac": alu / PEAK_LANE_OPS[prec], "hbm_gbs": bw / 1e9, "hbm_frac": bw / HBM_PEAK,
+                     "avg_ms": ms}
+    ms = kern["adapt"]["avg_ms"]
+    if ms:
+        bw = 3 * el * n / (ms * 1e-3)
+        out["adapt"] = {"bound": "hbm", "bytes_per_launch": 3 * el * n, "hbm_gbs": bw / 1e9, "hbm_frac": bw / HBM_PEAK,
+                        "avg_ms": ms}
+    return out
+
+
+def host_cores():
+    """The host the oracle ran on: logical CPUs, those this process may use,
+    and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
 def cpu_baseline(x, L, kappas, budget_s=12.0):
     """The oracle's direct pair sums timed on a bounded sample of the same
     scan: the first m particles, with m chosen for about budget_s seconds."""
@@ -131,7 +185,8 @@ def cpu_baseline(x, L, kappas, budget_s=12.0):
     evals = len(kappas) * m * (m - 1) / 2
     return {"value": evals / dt, "unit": "CV pair-evals/s", "cores": 1, "kind": "oracle",
             "sample": f"direct FP64 pair sums (NumPy/SciPy, one thread) over the first {m} particles "
-                      f"x {len(kappas)} kappas: {evals:.3e} pair-evals in {dt:.1f} s"}
+                      f"x {len(kappas)} kappas: {evals:.3e} pair-evals in {dt:.1f} s",
+            "host": host_cores()}
 
 
 def main():
@@ -239,9 +294,12 @@ def main():
     kde.kde_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_steps = []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         kstar = step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        t_steps.append((time.perf_counter() - ts) * 1e3)
     t1 = time.perf_counter()
     kde.kde_timing_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -250,6 +308,7 @@ def main():
                       ("gather", kde.KDE_KERNEL_GATHER), ("adapt", kde.KDE_KERNEL_ADAPT)):
         tot, cnt = kde.kde_timing_read(kid)
         kern[name] = {"launches": cnt, "avg_ms": tot / cnt if cnt else None}
+    secondary = secondary_rooflines(args.prec, n, M, kern)
 
     pair_evals = B * n_cv * (n_cv - 1) / 2
     value = pair_evals / (ms_step * 1e-3)
@@ -283,7 +342,10 @@ def main():
         "kappa_star": kstar,
         "kernels": kern,
         "cv_pair_kernel_pair_evals_per_s": pair_evals / (pair_ms * 1e-3),
+        "step_ms": {"p10": float(np.percentile(t_steps, 10)), "p50": float(np.percentile(t_steps, 50)),
+                    "p90": float(np.percentile(t_steps, 90))},
         "roofline": roofline,
+        "secondary": secondary,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob.x[:n_cv], L, kappas)
@@ -334,7 +396,8 @@ def tri_cpu_baseline(x, L, widths, budget_s=12.0):
     evals = len(widths) * m * (m - 1) / 2
     return {"value": evals / dt, "unit": "CV pair-evals/s", "cores": 1, "kind": "oracle",
             "sample": f"direct FP64 triangle pair sums (NumPy, one thread) over the first {m} particles "
-                      f"x {len(widths)} half-widths: {evals:.3e} pair-evals in {dt:.1f} s"}
+                      f"x {len(widths)} half-widths: {evals:.3e} pair-evals in {dt:.1f} s",
+            "host": host_cores()}
 
 
 def bench_tri(args, kde, W, torch, dev):

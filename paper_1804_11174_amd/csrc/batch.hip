@@ -662,7 +662,8 @@ kde_status kde_batch_run(kde_batch* b, void* ws, size_t ws_bytes, void* stream) 
   if (!b) return fail(KDE_E_NOT_FOUND, "batch is NULL");
   const BatchPlan& im = b->plan;
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, im.ws_need));
-  KDE_RETURN_IF(check_lds(2 * size_t(im.max_M) * elem_size(im.prec) + kDepMaxChunk * 32 + kBlock * 8));
+  KDE_RETURN_IF(check_lds(2 * size_t(im.max_M) * elem_size(im.prec) +
+                          (im.prec == KDE_F64 ? sizeof(DepSmem<double>) : sizeof(DepSmem<float>))));
   if (!b->graph.exec || b->graph.ws != ws || b->graph.ws_bytes != ws_bytes)
     KDE_RETURN_IF(build_graph(b->graph, im, ws, ws_bytes));
   KDE_TRY_HIP(hipGraphLaunch(b->graph.exec, static_cast<hipStream_t>(stream)));

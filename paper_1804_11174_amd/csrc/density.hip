@@ -82,6 +82,11 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
       g = (g + 1 == M) ? 0 : g + 1;
     }
+  } else if (__all(A >= T(kExpTableMin))) {
+    for (int g = 0; g < M; ++g) {
+      const T s = node_s(gp, g, M, ts, tc);
+      acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
+    }
   } else {
     for (int g = 0; g < M; ++g) {
       const T s = node_s(gp, g, M, ts, tc);
@@ -166,7 +171,7 @@ static kde_status launch_deposit_t(const kde_domain* dom, int64_t n, const T* x,
   const dim3 grid{unsigned(chunks)}, block{unsigned(kBlock)};
   const double kg = kappa;
   const size_t lds = 2 * size_t(M) * sizeof(T);
-  KDE_RETURN_IF(check_lds(lds + kDepMaxChunk * (sizeof(PGeo<T>) + 2 * sizeof(T)) + kBlock * sizeof(double)));
+  KDE_RETURN_IF(check_lds(lds + sizeof(DepSmem<T>)));
   TimedLaunch timed(KDE_KERNEL_DEPOSIT, s);
   if (M <= kBlock) {
     hipLaunchKernelGGL((deposit_kernel<T, PER, 1>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials);
@@ -258,7 +263,7 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
     return KDE_OK;
   }
   const size_t lds = 3 * size_t(dom->M) * elem_size(dom->prec);
-  KDE_RETURN_IF(check_lds(lds));
+  KDE_RETURN_IF(check_lds(lds + (dom->prec == KDE_F64 ? 256 * sizeof(double) : sizeof(double))));  // + exp table
   TimedLaunch timed(KDE_KERNEL_GATHER, s);
   if (dom->prec == KDE_F64) {
     hipLaunchKernelGGL(gather_kernel<double>, grid, block, lds, s, static_cast<const double*>(x),

@@ -33,15 +33,20 @@ template <typename T>
 struct Flt;
 // ex(a, tab): exp of a kernel exponent a <= 0 (natural in double, with the
 // exponential's table `tab` in LDS; base 2 in float, where tab is unused).
+// ex_in(a, tab): the same for an exponent known to lie in the table
+// exponential's own domain (a >= kExpTableMin), without the clamp.
+constexpr double kExpTableMin = -17592186044416.0;  // -2^44
 template <>
 struct Flt<double> {
   static __device__ __forceinline__ double ex(double a, const double* tab) { return exp_nonpos_table_any(a, tab); }
+  static __device__ __forceinline__ double ex_in(double a, const double* tab) { return exp_nonpos_table(a, tab); }
   static constexpr double unit = 1.0;
   static constexpr double tiny = DBL_MIN;
 };
 template <>
 struct Flt<float> {
   static __device__ __forceinline__ float ex(float a, const double*) { return __builtin_amdgcn_exp2f(a); }
+  static __device__ __forceinline__ float ex_in(float a, const double*) { return __builtin_amdgcn_exp2f(a); }
   static constexpr double unit = 1.4426950408889634;
   static constexpr float tiny = FLT_MIN;
 };
@@ -177,8 +182,10 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
     if (sub < S) {
       SumOf<T> acc;
       for (int p = sub; p < cnt; p += S) {
+        // every lane of a wave takes the same particle, so this test is uniform
         const T s = node_s(sm.pg[p], g, M, ts, tc);
-        const T e = Flt<T>::ex(sm.pA[p] * (s * s), sm.etab);
+        const T A = sm.pA[p];
+        const T e = (A >= T(kExpTableMin)) ? Flt<T>::ex_in(A * (s * s), sm.etab) : Flt<T>::ex(A * (s * s), sm.etab);
         acc.add(PER ? sm.pw[p] * e : e);
       }
       tot = acc.value();
@@ -200,7 +207,7 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
         const int g = tid + k * kBlock;
         if (g < M) {
           const T s = node_s(gp, g, M, ts, tc);
-          const T e = Flt<T>::ex(A * (s * s), sm.etab);
+          const T e = (A >= T(kExpTableMin)) ? Flt<T>::ex_in(A * (s * s), sm.etab) : Flt<T>::ex(A * (s * s), sm.etab);
           acc[k].add(PER ? w * e : e);
         }
       }
