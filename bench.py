@@ -152,6 +152,49 @@ def secondary_rooflines(prec, n, M, kern):
     return out
 
 
+# Issue-rate probes: per instruction kind, the iteration count of one
+# launch (about 10-40 ms on MI355X) and the published peak it is read
+# against (lane-operations per second, an FMA counting as one; the
+# published vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s of which
+# half needs packed instructions; no published figure for exp2 or add).
+PROBES = (("fma_f64", 0, 131072, 78.6e12 / 2), ("fma_f32", 1, 262144, 157.3e12 / 2),
+          ("exp_f32", 2, 32768, None), ("add_f64", 3, 131072, 78.6e12 / 2))
+
+
+def bench_peak(args, kde, torch, dev):
+    """Sustained lane-operation rates of single instruction kinds (8 waves
+    per SIMD, 8 independent chains per lane), timed with the library's HIP
+    events over `steps` launches after one warm-up."""
+    blocks = 2048
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    rates, ratio, ms = {}, {}, {}
+    for name, kind, iters, peak in PROBES:
+        kde.kde_probe_peak(kind, blocks, 4096, out)
+        torch.cuda.synchronize()
+        kde.kde_timing_reset()
+        kde.kde_timing_enable(True)
+        for _ in range(args.steps):
+            kde.kde_probe_peak(kind, blocks, iters, out)
+        torch.cuda.synchronize()
+        kde.kde_timing_enable(False)
+        tot, cnt = kde.kde_timing_read(kde.KDE_KERNEL_PROBE)
+        ops = blocks * 256 * 8 * iters * cnt
+        rates[name] = ops / (tot * 1e-3)
+        ms[name] = tot / cnt
+        ratio[name] = rates[name] / peak if peak else None
+    line = {"metric": "sustained lane-operations/s per instruction kind", "value": rates["fma_f64"],
+            "unit": "lane-ops/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic", "vs_baseline": None,
+            "config": {"workload": "issue-rate probes: 2048 workgroups x 256 threads, 8 dependency chains per "
+                                   "thread, one instruction kind per launch"},
+            "rates": rates, "fraction_of_published_peak": ratio, "ms_per_launch": ms}
+    out_s = json.dumps(line)
+    print(out_s, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out_s + "\n")
+
+
 def host_cores():
     """The host the oracle ran on: logical CPUs, those this process may use,
     and the CPU model."""
@@ -198,14 +241,15 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "fourier", "landau", "copy"],
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "fourier", "landau", "copy", "peak"],
                     default="plain",
                     help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
                          "serve: the request server beside 16 resident PIC sessions; tri: the first-order "
                          "(triangular) shape with a CV-chosen width on the paper-scale positions; fourier: the "
                          "paper-scale pipeline through the Fourier moments (refined kappa*, exact pilot); "
                          "landau: Landau-damping ensembles on resident sessions, standard PIC against KDE; "
-                         "copy: a device copy of known size that calibrates the HBM byte counters")
+                         "copy: a device copy of known size that calibrates the HBM byte counters; "
+                         "peak: issue-rate probes (double and float FMA, float exp2, double add)")
     ap.add_argument("--sets", type=int, default=512)
     ap.add_argument("--requests", type=int, default=2000, help="serve form: requests per load point")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
@@ -232,6 +276,8 @@ def main():
     kde.require_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.form == "peak":
+        return bench_peak(args, kde, torch, dev)
     if args.form == "batch":
         args.prec = args.prec or "f32"
         return bench_batch(args, kde, W, torch, dev)

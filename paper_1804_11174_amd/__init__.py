@@ -105,6 +105,7 @@ _SIGNATURES = {
     "kde_timing_enable": (_i32, [_i32]),
     "kde_timing_reset": (_i32, []),
     "kde_timing_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
+    "kde_probe_peak": (_i32, [_i32, _i32, _i64, _vp, _vp]),
     "kde_tune_set": (_i32, [_i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kde_tune_get": (_i32, [_i32, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kde_batch_plan": (_i32, [ctypes.POINTER(kde_batch_set), _i32, _i32, _i32, ctypes.POINTER(_dbl), _dbl,
@@ -139,7 +140,8 @@ KDE_E_AGAIN, KDE_E_BUDGET = 4, 3
 TUNE_FILE = os.path.join(HERE, "tune_gfx950.json")
 
 KDE_KERNEL_CV_PAIRS, KDE_KERNEL_DEPOSIT, KDE_KERNEL_GATHER, KDE_KERNEL_ADAPT = 0, 1, 2, 3
-KDE_KERNEL_MOMENTS = 4
+KDE_KERNEL_MOMENTS, KDE_KERNEL_PROBE = 4, 5
+KDE_PROBE_FMA_F64, KDE_PROBE_FMA_F32, KDE_PROBE_EXP_F32, KDE_PROBE_ADD_F64 = 0, 1, 2, 3
 
 EXPORTED = tuple(_SIGNATURES)
 
@@ -622,6 +624,17 @@ def kde_timing_read(kernel_id: int) -> Tuple[float, int]:
     n = _i64(0)
     _check(require_library().kde_timing_read(int(kernel_id), ctypes.byref(ms), ctypes.byref(n)), "kde_timing_read")
     return float(ms.value), int(n.value)
+
+
+def kde_probe_peak(kind: int, blocks: int, iters: int, out, stream=None) -> None:
+    """Launch the issue-rate probe: blocks x 256 threads, each running 8
+    dependency chains of ``iters`` steps of one instruction kind; ``out`` is
+    a device tensor of blocks x 256 doubles."""
+    import torch
+    if out.dtype != torch.float64 or out.numel() < blocks * 256 or not out.is_cuda:
+        raise ValueError("out must be a device float64 tensor of at least blocks x 256 elements")
+    _check(require_library().kde_probe_peak(int(kind), int(blocks), int(iters), _ptr(out), _stream(stream)),
+           "kde_probe_peak")
 
 
 # ------------------------------------------------------- workspace helper

@@ -49,6 +49,8 @@ constexpr int kCvTile = 256;              // particles per CV tile (one per thre
 constexpr double kSkipExponent = 70.0;    // terms below exp(-70) of their sum's scale are skipped
 constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int kMaxM = 4096;
+constexpr int kProbeMaxBlocks = 65536;                // kde_probe_peak limits
+constexpr int64_t kProbeMaxIters = int64_t(1) << 30;
 
 // ------------------------------------------------------------ workspace
 

@@ -106,6 +106,17 @@ def test_deposit_gather_adapt_argument_checks(lib):
     assert lib.kde_workspace_size(99, ctypes.byref(d), 10, 0, ctypes.byref(ctypes.c_size_t())) == 1
 
 
+def test_probe_argument_checks(lib):
+    """The issue-rate probe rejects bad arguments before launching anything."""
+    assert lib.kde_probe_peak(0, 8, 64, None, None) == 1            # no output buffer
+    assert lib.kde_probe_peak(0, 0, 64, 1, None) == 1               # no workgroups
+    assert lib.kde_probe_peak(0, 65537, 64, 1, None) == 1           # too many
+    assert lib.kde_probe_peak(0, 8, 6, 1, None) == 1                # not a multiple of 4
+    assert lib.kde_probe_peak(0, 8, (1 << 30) + 4, 1, None) == 1    # too many steps
+    assert lib.kde_probe_peak(7, 8, 64, 1, None) == 1               # unknown kind
+    assert b"kind" in lib.kde_last_error()
+
+
 def test_shape_argument_checks(lib):
     """The triangle shape takes half-widths in (0, L/2]; an unknown shape and
     adaptive widths with the triangle are refused (fake pointers: every case
