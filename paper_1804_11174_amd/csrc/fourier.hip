@@ -25,9 +25,14 @@
 //                       (bessel_series), the ratios multiplied up to rho_m by
 //                       a prefix scan; then all threads form the series in a
 //                       fixed order.
-//   newton_kernel    -- one workgroup: the scan's first minimum, then
-//                       Newton's method on u = log(kappa) with bisection as
-//                       the safeguard. The derivatives come from the same
+//   newton_start_kernel -- three workgroups side by side: the objective
+//                       and its derivatives at the two ends of the bracket
+//                       around the scan's first minimum and at the first
+//                       iterate (the vertex of the parabola through the three
+//                       grid values there).
+//   newton_kernel    -- one workgroup: from those, Newton's method on
+//                       u = log(kappa) with bisection as the safeguard.
+//                       The derivatives come from the same
 //                       recurrence differentiated in kappa:
 //                         r'_k  = r_k^2 (2k / kappa^2 - r'_{k+1}),
 //                         r''_k = 2 r'_k^2 / r_k - r_k^2 (4k / kappa^3 + r''_{k+1}),
@@ -64,6 +69,7 @@ constexpr int64_t kMomBlocks = 4096;    // workgroups a moment launch aims for
 constexpr int kMomPerThread = 8;        // fewest particles per thread of a moment workgroup
 constexpr int kPilotRun = 64;           // rotations between exact phase restarts
 constexpr int kMaxNewton = 100;
+constexpr int kStartEvals = 3;          // refine: bracket ends and first iterate, evaluated side by side
 
 // Concentrations with their series orders (fourier_order of each; the
 // order grows with kappa, so a bracket's upper end bounds it inside).
@@ -114,6 +120,7 @@ struct FourierBufs {
   double* S;         // [2 M] moments (re, im)
   double* rho;       // [B][M + 1] (scan) or [3][M + 1] (refine, pilot)
   double* cvgrid;    // [B]
+  double* start;     // refine: (cv, g, g') at the bracket ends and the first iterate, then that iterate's u
   double* w;         // [2 M] pilot weights
   double* lf;        // [N] log pilot
   double* bpart;     // [blocks][2]
@@ -131,9 +138,12 @@ FourierBufs carve_fourier(Carver& c, int op, int64_t n, int B) {
   b.partials = c.take<double>(size_t(budget) * 2 * M);
   b.colsum = c.take<double>((column_sum_scratch(budget * M, 2) + column_sum_scratch(1, 2 * M)) / sizeof(double) + 1);
   b.S = c.take<double>(size_t(2) * M);
-  const int slots = (op == KDE_OP_CV_FOURIER) ? B : (op == KDE_OP_CV_REFINE ? std::max(B, 3) : 1);
+  const int slots = (op == KDE_OP_CV_FOURIER) ? B : (op == KDE_OP_CV_REFINE ? std::max(B, 3 * kStartEvals) : 1);
   b.rho = c.take<double>(size_t(slots) * (M + 1));
-  if (op == KDE_OP_CV_REFINE) b.cvgrid = c.take<double>(size_t(B));
+  if (op == KDE_OP_CV_REFINE) {
+    b.cvgrid = c.take<double>(size_t(B));
+    b.start = c.take<double>(3 * kStartEvals + 1);
+  }
   if (op == KDE_OP_ADAPT_EXACT) {
     const int64_t blocks = ceil_div(n, kBlock);
     b.w = c.take<double>(size_t(2) * M);
@@ -165,6 +175,27 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) t += red[w];
   return t;
+}
+
+// Six workgroup sums at once, each in block_sum's order (wave sums, then
+// the waves in order), with one exchange through LDS.
+__device__ __forceinline__ void block_sum6(double (&v)[6], double (*red)[6]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w][k];
+    v[k] = t;
+  }
 }
 
 template <typename T>
@@ -219,6 +250,7 @@ struct SeriesSmem {
   double aff[2][kBlock][2];  // affine maps x -> a + b x
   double pre[2][kBlock][3];  // segment totals (product, sum, sum)
   double red[kBlock / 64];
+  double red6[kBlock / 64][6];
 };
 
 __device__ __forceinline__ void mat_mul_norm(const double* a, const double* b, double* c) {
@@ -463,7 +495,6 @@ struct Eval {
 __device__ Eval eval_u(double u, const double* __restrict__ S, int Mk, double n, double L, double* rho, double* d1,
                        double* d2, SeriesSmem& sm) {
   const double kappa = exp(u);
-  double* red = sm.red;
   bessel_series<true>(kappa, Mk, rho, d1, d2, sm);
   double A = 0.0, C = 0.0, A1 = 0.0, C1 = 0.0, A2 = 0.0, C2 = 0.0;
   for (int m = 1 + threadIdx.x; m <= Mk; m += kBlock) {
@@ -478,12 +509,14 @@ __device__ Eval eval_u(double u, const double* __restrict__ S, int Mk, double n,
     A2 = fma(2.0 * fma(r1, r1, r * r2), P, A2);
     C2 = fma(r2, q, C2);
   }
-  A = block_sum(A, red);
-  C = block_sum(C, red);
-  A1 = block_sum(A1, red);
-  C1 = block_sum(C1, red);
-  A2 = block_sum(A2, red);
-  C2 = block_sum(C2, red);
+  double v[6] = {A, C, A1, C1, A2, C2};
+  block_sum6(v, sm.red6);
+  A = v[0];
+  C = v[1];
+  A1 = v[2];
+  C1 = v[3];
+  A2 = v[4];
+  C2 = v[5];
   const double n2 = n * n, nn = n * (n - 1.0);
   Eval e;
   e.cv = (2.0 * A / n2 - 4.0 * C / nn - 1.0) / L;
@@ -495,20 +528,25 @@ __device__ Eval eval_u(double u, const double* __restrict__ S, int Mk, double n,
   return e;
 }
 
-// result: [kappa*, cv(kappa*), dCV/du at kappa*, steps, b*]. Every thread
-// runs the same control flow on the same values (block sums reach all).
-__global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict__ S, int M, double n, double L,
-                                                       FKappas kap, int B, const double* __restrict__ cvgrid,
-                                                       double* __restrict__ rho3, double* __restrict__ result,
-                                                       int32_t* __restrict__ argmin) {
-  __shared__ SeriesSmem sm;
-  double* rho = rho3;
-  double* d1 = rho3 + (M + 1);
-  double* d2 = rho3 + 2 * (M + 1);
-  const int bs = first_min(cvgrid, B);
-  if (argmin && threadIdx.x == 0) *argmin = bs;
-  const int Mk = min(M, kap.order[min(bs + 1, B - 1)]);
-  double klo = kap.k[max(bs - 1, 0)], khi = kap.k[min(bs + 1, B - 1)];
+// The refinement's bracket: the list neighbours of the scan's first
+// minimum bs (the lower one replaced by the first positive kappa when it is
+// 0), the series order Mk of its upper end, and the first Newton iterate:
+// the vertex of the parabola through the three grid values around bs in
+// u = log(kappa) when it lies inside the bracket, else log(kappa_bs), else
+// the bracket's middle. valid is false when there is no bracket of
+// positive concentrations.
+struct Bracket {
+  int bs, Mk;
+  double klo, khi, ul, uh, u0;
+  bool valid;
+};
+
+__device__ Bracket make_bracket(const double* __restrict__ cvgrid, int B, const FKappas& kap, int M) {
+  Bracket r;
+  r.bs = first_min(cvgrid, B);
+  r.Mk = min(M, kap.order[min(r.bs + 1, B - 1)]);
+  double klo = kap.k[max(r.bs - 1, 0)];
+  const double khi = kap.k[min(r.bs + 1, B - 1)];
   if (!(klo > 0.0)) {
     double kp = 0.0;
     for (int t = 0; t < B; ++t)
@@ -518,26 +556,87 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
       }
     klo = kp;
   }
+  r.valid = (klo > 0.0) && (khi > klo);
+  r.klo = klo;
+  r.khi = khi;
+  r.ul = r.valid ? log(klo) : 0.0;
+  r.uh = r.valid ? log(khi) : 0.0;
+  r.u0 = 0.5 * (r.ul + r.uh);
+  const int b = r.bs;
+  if (r.valid && b > 0 && b < B - 1 && kap.k[b] > klo && kap.k[b] < khi) {
+    const double ub = log(kap.k[b]);
+    r.u0 = ub;
+    if (kap.k[b - 1] > 0.0) {
+      const double ua = log(kap.k[b - 1]), uc = log(kap.k[b + 1]);
+      const double p = (ub - ua) * (cvgrid[b] - cvgrid[b + 1]);
+      const double q = (ub - uc) * (cvgrid[b] - cvgrid[b - 1]);
+      const double den = p - q;
+      if (den != 0.0) {
+        const double uv = ub - 0.5 * ((ub - ua) * p - (ub - uc) * q) / den;
+        if (uv > r.ul && uv < r.uh) r.u0 = uv;
+      }
+    }
+  }
+  return r;
+}
+
+// Workgroup w evaluates the objective at the bracket's lower end (w = 0),
+// upper end (1) and first iterate (2), each with its own series arrays
+// (slots 3w .. 3w + 2 of rho); start[3w..3w+2] = (cv, g, g'),
+// start[9] = the first iterate's u.
+__global__ void __launch_bounds__(kBlock) newton_start_kernel(const double* __restrict__ S, int M, double n,
+                                                             double L, FKappas kap, int B,
+                                                             const double* __restrict__ cvgrid,
+                                                             double* __restrict__ rho, double* __restrict__ start) {
+  __shared__ SeriesSmem sm;
+  const Bracket br = make_bracket(cvgrid, B, kap, M);
+  if (!br.valid) return;
+  const int w = blockIdx.x;
+  const double u = (w == 0) ? br.ul : (w == 1) ? br.uh : br.u0;
+  double* r = rho + size_t(3 * w) * (M + 1);
+  const Eval e = eval_u(u, S, br.Mk, n, L, r, r + (M + 1), r + 2 * (M + 1), sm);
+  if (threadIdx.x == 0) {
+    start[3 * w] = e.cv;
+    start[3 * w + 1] = e.g;
+    start[3 * w + 2] = e.gp;
+    if (w == 2) start[3 * kStartEvals] = u;
+  }
+}
+
+// result: [kappa*, cv(kappa*), dCV/du at kappa*, steps, b*], continuing
+// from newton_start_kernel's evaluations. Every thread runs the same
+// control flow on the same values (block sums reach all).
+__global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict__ S, int M, double n, double L,
+                                                       FKappas kap, int B, const double* __restrict__ cvgrid,
+                                                       const double* __restrict__ start, double* __restrict__ rho3,
+                                                       double* __restrict__ result, int32_t* __restrict__ argmin) {
+  __shared__ SeriesSmem sm;
+  double* rho = rho3;
+  double* d1 = rho3 + (M + 1);
+  double* d2 = rho3 + 2 * (M + 1);
+  const Bracket br = make_bracket(cvgrid, B, kap, M);
+  const int bs = br.bs;
+  if (argmin && threadIdx.x == 0) *argmin = bs;
   double k_best = 0.0, cv_best = 0.0, g_best = 0.0;
   int steps = 0;
-  if (!(klo > 0.0) || !(khi > klo)) {
+  if (!br.valid) {
     // no bracket of positive concentrations: the scan's value
     k_best = kap.k[bs];
     cv_best = cvgrid[bs];
     g_best = 0.0;
   } else {
-    double ul = log(klo), uh = log(khi);
-    const Eval el = eval_u(ul, S, Mk, n, L, rho, d1, d2, sm);
-    const Eval eh = eval_u(uh, S, Mk, n, L, rho, d1, d2, sm);
+    double ul = br.ul, uh = br.uh;
+    const Eval el{start[0], start[1], start[2]};
+    const Eval eh{start[3], start[4], start[5]};
     steps = 2;
     if (!(el.g < 0.0 && eh.g > 0.0)) {
       const bool lo_wins = el.cv <= eh.cv;
-      k_best = lo_wins ? klo : khi;
+      k_best = lo_wins ? br.klo : br.khi;
       cv_best = lo_wins ? el.cv : eh.cv;
       g_best = lo_wins ? el.g : eh.g;
     } else {
-      double u = (bs > 0 && bs < B - 1 && kap.k[bs] > klo && kap.k[bs] < khi) ? log(kap.k[bs]) : 0.5 * (ul + uh);
-      Eval e = eval_u(u, S, Mk, n, L, rho, d1, d2, sm);
+      double u = start[3 * kStartEvals];
+      Eval e{start[6], start[7], start[8]};
       ++steps;
       for (int it = 0; it < kMaxNewton && e.g != 0.0; ++it) {
         if (e.g < 0.0)
@@ -548,7 +647,7 @@ __global__ void __launch_bounds__(kBlock) newton_kernel(const double* __restrict
         if (!(e.gp > 0.0) || !(un > ul && un < uh)) un = 0.5 * (ul + uh);
         const bool done = fabs(un - u) <= 1e-14 * fmax(1.0, fabs(un)) || (uh - ul) <= 1e-14 * fmax(1.0, fabs(un));
         u = un;
-        e = eval_u(u, S, Mk, n, L, rho, d1, d2, sm);
+        e = eval_u(u, S, br.Mk, n, L, rho, d1, d2, sm);
         ++steps;
         if (done) break;
       }
@@ -736,8 +835,11 @@ kde_status kde_cv_refine(const kde_domain* dom, int64_t N, const void* x, int32_
   hipLaunchKernelGGL(series_kernel, dim3(B), dim3(kBlock), 0, s, (const double*)b.S, M, double(N), dom->L, kl, B,
                      b.rho, grid, (double*)nullptr);
   KDE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(newton_start_kernel, dim3(kStartEvals), dim3(kBlock), 0, s, (const double*)b.S, M, double(N),
+                     dom->L, kl, B, (const double*)grid, b.rho, b.start);
+  KDE_CHECK_LAUNCH();
   hipLaunchKernelGGL(newton_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)b.S, M, double(N), dom->L, kl, B,
-                     (const double*)grid, b.rho, result, argmin);
+                     (const double*)grid, (const double*)b.start, b.rho, result, argmin);
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }
