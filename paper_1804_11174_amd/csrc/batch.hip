@@ -190,8 +190,8 @@ __global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvCons
     const int b_lo = int(q - p * groups) * gsize;
     int I, J;
     tri_decode(p, I, J);
-    cv_tile_pair<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), uni32(s.cells), I, J, K, b_lo,
-                        min(K.B, b_lo + gsize), uni_ptr(s.partials) + p * 2 * K.B, sm);
+    cv_tile_pair<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), uni32(s.cells), s.L, I, J, K,
+                        b_lo, min(K.B, b_lo + gsize), uni_ptr(s.partials) + p * 2 * K.B, sm);
   }
 }
 
@@ -357,7 +357,7 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.blocks = ceil_div(in.N, kBlock);
     d.g_ad = ceil_div(d.blocks, kSumRows);
     d.hist = c.take<int32_t>(size_t(d.cells) * size_t(d.sblocks));
-    d.packed = b.prec == KDE_F64 ? static_cast<void*>(c.take<double>(2 * size_t(d.n_cv)))
+    d.packed = b.prec == KDE_F64 ? static_cast<void*>(c.take<double>(Packed<double>::per_particle * size_t(d.n_cv)))
                                  : static_cast<void*>(c.take<uint32_t>(size_t(d.n_cv)));
     d.partials = c.take<double>(size_t(d.units) * 2 * b.B);
     d.cv_l1 = c.take<double>(size_t(d.g_cv) * 2 * b.B);

@@ -86,15 +86,15 @@ __global__ void __launch_bounds__(KDE_MAX_KAPPAS) tri_finalize_kernel(const doub
 // Block (tile pair p, concentration group g) with p = blockIdx.x / groups.
 template <typename T, int BC>
 __global__ void __launch_bounds__(kBlock) cv_pairs_kernel(const typename Packed<T>::type* __restrict__ packed,
-                                                         int64_t n, int cells, int groups, int gsize, CvConsts<T> K,
-                                                         double* __restrict__ partials) {
+                                                         int64_t n, int cells, double L, int groups, int gsize,
+                                                         CvConsts<T> K, double* __restrict__ partials) {
   __shared__ CvSmem<T, BC> sm;
   const int64_t p = int64_t(blockIdx.x) / groups;
   const int g = int(int64_t(blockIdx.x) - p * groups);
   int I, J;
   tri_decode(p, I, J);
   const int b_lo = g * gsize;
-  cv_tile_pair<T, BC>(packed, n, cells, I, J, K, b_lo, min(K.B, b_lo + gsize), partials + p * 2 * K.B, sm);
+  cv_tile_pair<T, BC>(packed, n, cells, L, I, J, K, b_lo, min(K.B, b_lo + gsize), partials + p * 2 * K.B, sm);
 }
 
 // raw[0..B): Kbar sums, raw[B..2B): K sums (unnormalised); one block.
@@ -173,7 +173,7 @@ struct CvBuffers {
 static CvBuffers carve_cv(Carver& cv, const CvPlan& p, int64_t n, int B, int prec) {
   CvBuffers b;
   b.hist = cv.take<int32_t>(size_t(p.sort.cells) * p.sort.blocks);
-  b.packed = prec == KDE_F64 ? static_cast<void*>(cv.take<double>(2 * size_t(n)))
+  b.packed = prec == KDE_F64 ? static_cast<void*>(cv.take<double>(Packed<double>::per_particle * size_t(n)))
                              : static_cast<void*>(cv.take<uint32_t>(size_t(n)));
   b.partials = cv.take<double>(size_t(p.units) * 2 * B);
   b.colsum = cv.take<double>(column_sum_scratch(p.units, 2 * B) / sizeof(double) + 1);
@@ -208,15 +208,15 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
     const dim3 grid{unsigned(p.units * groups)}, block{unsigned(kBlock)};
     switch (tp.chunk) {
       case 4:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, groups, gsize, K,
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, groups, gsize, K,
                            buf.partials);
         break;
       case 8:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, groups, gsize, K,
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, groups, gsize, K,
                            buf.partials);
         break;
       default:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, groups, gsize, K,
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, groups, gsize, K,
                            buf.partials);
         break;
     }

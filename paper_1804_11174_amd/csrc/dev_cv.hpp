@@ -10,7 +10,15 @@
 //   Kbar-term exp(-2 kappa (1 - c)) I0e(2 kappa c)        (two-fold convolution)
 // Both exponents are formed without cancellation:
 //   double: from half-angle vectors (a, b) = (cos(pi x/L), sin(pi x/L)),
-//           c = |a_i a_j + b_i b_j|, s = b_i a_j - a_i b_j, 1 - c = s^2 / (1 + c);
+//           c = |a_i a_j + b_i b_j|, s = b_i a_j - a_i b_j, 1 - c = s^2 / (1 + c).
+//           The vectors carry an absolute rounding of about one unit, so for
+//           near-coincident pairs (|s| < 2^-8) s is taken instead from the
+//           exact difference of the wrapped positions, d = w_i - w_j (with
+//           the periodic image when |d| > L/2), as sin(pi d / L) by its
+//           Taylor series: the exponent -2 kappa s^2 then keeps full
+//           relative accuracy at any kappa. A wave computes that only when
+//           one of its pairs is that close, so it costs nothing away from
+//           the diagonal tiles;
 //   float : from 32-bit fixed-point phases, whose wrapped integer difference
 //           gives phi in [-pi/2, pi/2) exactly up to one conversion; then
 //           1 - c = phi^2 R(phi^2) with R the Taylor series of
@@ -114,7 +122,7 @@ struct I0eBounds<float> {
 // packed form: the half-angle vector (cos(pi f), sin(pi f)) with
 // f in [0, 1], the double position fraction, or the 32-bit phase.
 __device__ __forceinline__ double packed_frac(const double* __restrict__ packed, int64_t i) {
-  return atan2(packed[2 * i + 1], packed[2 * i]) * 0.31830988618379067;  // 1/pi
+  return atan2(packed[3 * i + 1], packed[3 * i]) * 0.31830988618379067;  // 1/pi
 }
 __device__ __forceinline__ double packed_frac(const FracPos* __restrict__ packed, int64_t i) { return packed[i].f; }
 __device__ __forceinline__ double packed_frac(const uint32_t* __restrict__ packed, int64_t i) {
@@ -165,6 +173,14 @@ struct Geo {
   T s2, q, c, c2, inv2c, rs2c;
 };
 
+// The period, for the exact separation of near-coincident pairs.
+struct Period {
+  double L, half, pi_over_L;
+};
+__device__ __forceinline__ Period make_period(double L) { return Period{L, 0.5 * L, 3.141592653589793 / L}; }
+
+constexpr double kNearS = 0.00390625;  // 2^-8: |s| below this takes the exact separation
+
 template <typename T>
 __device__ __forceinline__ T c_floor() {
   return T(double(I0eBounds<T>::X0) / (double(I0eBounds<T>::X0) + kSkipExponent));
@@ -175,7 +191,7 @@ template <typename T>
 struct IPart;
 template <>
 struct IPart<double> {
-  double a, b;
+  double a, b, w;
 };
 template <>
 struct IPart<float> {
@@ -183,16 +199,31 @@ struct IPart<float> {
 };
 
 __device__ __forceinline__ IPart<double> load_i(const double* __restrict__ packed, int64_t i, bool valid) {
-  return IPart<double>{valid ? packed[2 * i] : 1.0, valid ? packed[2 * i + 1] : 0.0};
+  return IPart<double>{valid ? packed[3 * i] : 1.0, valid ? packed[3 * i + 1] : 0.0, valid ? packed[3 * i + 2] : 0.0};
 }
 __device__ __forceinline__ IPart<float> load_i(const uint32_t* __restrict__ packed, int64_t i, bool valid) {
   return IPart<float>{valid ? packed[i] : 0u};
 }
 
-__device__ __forceinline__ Geo<double> pair_geo(const IPart<double>& p, const double* __restrict__ tj, int jj) {
-  const double aj = tj[2 * jj], bj = tj[2 * jj + 1];
+__device__ __forceinline__ Geo<double> pair_geo(const IPart<double>& p, const double* __restrict__ tj, int jj,
+                                                const Period& per) {
+  const double aj = tj[3 * jj], bj = tj[3 * jj + 1];
   const double c = fabs(p.a * aj + p.b * bj);
-  const double s = p.b * aj - p.a * bj;
+  double s = p.b * aj - p.a * bj;
+  const bool near = fabs(s) < kNearS;
+  if (__any(near)) {
+    // d exact (Sterbenz) for close w; the image across the period by an
+    // exact shift of the larger position. Only s^2 is used, so the sign
+    // the image flips does not matter. |pi d / L| < 2^-7 here, where the
+    // series' next term is below 1e-24 of the value.
+    const double wj = tj[3 * jj + 2];
+    double d = p.w - wj;
+    d = (d > per.half) ? (p.w - per.L) - wj : ((d < -per.half) ? p.w - (wj - per.L) : d);
+    const double ph = d * per.pi_over_L;
+    const double p2 = ph * ph;
+    const double sn = ph * fma(p2, fma(p2, fma(p2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    s = near ? sn : s;
+  }
   Geo<double> g;
   g.s2 = s * s;
   g.q = g.s2 / (1.0 + c);
@@ -204,7 +235,8 @@ __device__ __forceinline__ Geo<double> pair_geo(const IPart<double>& p, const do
   return g;
 }
 
-__device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint32_t* __restrict__ tj, int jj) {
+__device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint32_t* __restrict__ tj, int jj,
+                                               const Period&) {
   // pi / 2^32 turns a wrapped phase difference into the half-angle difference
   const float phi = float(int32_t(p.u - tj[jj])) * 7.3145904152e-10f;
   const float y = phi * phi;
@@ -232,7 +264,7 @@ struct GeoS {
   T s2, c2;
 };
 __device__ __forceinline__ GeoS<double> pair_geo_small(const IPart<double>& p, const double* __restrict__ tj, int jj) {
-  const double aj = tj[2 * jj], bj = tj[2 * jj + 1];
+  const double aj = tj[3 * jj], bj = tj[3 * jj + 1];
   const double c = p.a * aj + p.b * bj;
   const double s = p.b * aj - p.a * bj;
   return GeoS<double>{s * s, c * c};
@@ -285,12 +317,12 @@ __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* 
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
                                            const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
-                                           const CvConsts<T>& K, const double* __restrict__ etab,
+                                           const CvConsts<T>& K, const Period& per, const double* __restrict__ etab,
                                            Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
   const int nb = min(BC, b_end - b0);
   const T X0 = I0eBounds<T>::X0;
   for (int jj = 0; jj < nj; ++jj) {
-    const Geo<T> g = pair_geo(ip, tj, jj);
+    const Geo<T> g = pair_geo(ip, tj, jj, per);
     bool live = true;
     if (MASKED) live = valid_i && (!diag || jj > int(threadIdx.x));
     // `go` is uniform across the wave: it turns false at the first
@@ -358,9 +390,10 @@ struct CvSmem {
 // the per-term test would skip, so the sums are those of the full loop.
 template <typename T, int BC>
 __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __restrict__ packed, int64_t n,
-                                             int cells, int I, int J, const CvConsts<T>& K, int b_lo, int b_hi,
-                                             double* __restrict__ out, CvSmem<T, BC>& sm) {
-  constexpr int per = Packed<T>::per_particle;
+                                             int cells, double L, int I, int J, const CvConsts<T>& K, int b_lo,
+                                             int b_hi, double* __restrict__ out, CvSmem<T, BC>& sm) {
+  constexpr int pp = Packed<T>::per_particle;
+  const Period per = make_period(L);
   const int tid = threadIdx.x;
   const int64_t i0 = int64_t(I) * kCvTile, j0 = int64_t(J) * kCvTile;
   const int nj = int(min(int64_t(kCvTile), n - j0));
@@ -382,7 +415,7 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
     constexpr double etab_src[256] = KDE_EXP_TABLE;
     for (int k = tid; k < 256; k += kBlock) sm.etab[k] = etab_src[k];
   }
-  for (int k = tid; k < per * nj; k += kBlock) sm.tj[k] = packed[per * j0 + k];
+  for (int k = tid; k < pp * nj; k += kBlock) sm.tj[k] = packed[pp * j0 + k];
   const int64_t i = i0 + tid;
   const bool valid_i = i < n;
   const IPart<T> ip = load_i(packed, i, valid_i);
@@ -408,9 +441,9 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
         pair_chunk_pure<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
     } else {
       if (masked)
-        pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+        pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
       else
-        pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+        pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
     }
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {

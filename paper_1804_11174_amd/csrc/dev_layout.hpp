@@ -5,7 +5,9 @@
 // both users produce the same packed order.
 //
 // Packed forms:
-//   double: the half-angle vector (cos(pi x / L), sin(pi x / L));
+//   double: the half-angle vector (cos(pi w / L), sin(pi w / L)) and the
+//           wrapped position w itself (the difference of two close w is
+//           exact, which the pair kernel uses for near-coincident pairs);
 //   float : the phase as a 32-bit fixed-point fraction of the period,
 //           u = round(x / L * 2^32) mod 2^32. The difference of two phases
 //           in wrapping integer arithmetic is then the exact periodic
@@ -31,18 +33,22 @@ __device__ __forceinline__ int cell_of(T x, double L, int cells) {
   return c < 0 ? 0 : (c >= cells ? cells - 1 : c);
 }
 
-__device__ __forceinline__ void store_packed(double* packed, int64_t dest, double frac) {
+// Store the packed form of a particle at wrapped position w in [0, L).
+__device__ __forceinline__ void store_packed(double* packed, int64_t dest, double w, double L) {
   double sp, cp;
-  sincospi(frac, &sp, &cp);
-  packed[2 * dest] = cp;
-  packed[2 * dest + 1] = sp;
+  sincospi(w / L, &sp, &cp);
+  packed[3 * dest] = cp;
+  packed[3 * dest + 1] = sp;
+  packed[3 * dest + 2] = w;
 }
 
-__device__ __forceinline__ void store_packed(FracPos* packed, int64_t dest, double frac) { packed[dest].f = frac; }
+__device__ __forceinline__ void store_packed(FracPos* packed, int64_t dest, double w, double L) {
+  packed[dest].f = w / L;
+}
 
-__device__ __forceinline__ void store_packed(uint32_t* packed, int64_t dest, double frac) {
-  // frac in [0, 1): the nearest multiple of 2^-32, wrapped
-  const double v = floor(frac * 4294967296.0 + 0.5);
+__device__ __forceinline__ void store_packed(uint32_t* packed, int64_t dest, double w, double L) {
+  // w / L in [0, 1): the nearest multiple of 2^-32, wrapped
+  const double v = floor((w / L) * 4294967296.0 + 0.5);
   packed[dest] = (v >= 4294967296.0) ? 0u : uint32_t(v);
 }
 
@@ -73,7 +79,7 @@ __device__ __forceinline__ void stable_scatter(const T* __restrict__ x, int64_t 
     for (int w = 0; w < kBlock / 64; ++w) {
       if (wave == w && valid) {
         const int64_t dest = int64_t(base[c]) + rank;
-        store_packed(packed, dest, wrap_d(double(xv), L) / L);
+        store_packed(packed, dest, wrap_d(double(xv), L), L);
         if (perm) perm[dest] = int32_t(i);
       }
       __syncthreads();

@@ -130,15 +130,15 @@ SortPlan make_sort_plan(int64_t n);
 
 // ------------------------------------------------------------- launchers
 
-// Packed particle element of the pair kernels: for double, two values per
-// particle (cos(pi x/L), sin(pi x/L)); for float, one 32-bit fixed-point
-// phase round(x/L * 2^32) mod 2^32.
+// Packed particle element of the pair kernels: for double, three values per
+// particle (cos(pi w/L), sin(pi w/L), w) with w the wrapped position; for
+// float, one 32-bit fixed-point phase round(w/L * 2^32) mod 2^32.
 template <typename T>
 struct Packed;
 template <>
 struct Packed<double> {
   using type = double;
-  static constexpr int per_particle = 2;
+  static constexpr int per_particle = 3;
 };
 template <>
 struct Packed<float> {

@@ -165,6 +165,28 @@ def test_bad_arguments_raise(gpu):
         gpu.cv_scan(x.to(torch.int32), 1.0, [1.0])
 
 
+def test_extreme_concentrations(gpu):
+    """Concentrations up to the scan's limit (1e12) on clustered positions
+    (groups of three within 1e-7 L), so that waves stay live where other
+    lanes' exponents reach about -2e12: the exponential's reduction must
+    hold over that whole range. FP64, against the oracle."""
+    L = 4 * math.pi
+    rng = np.random.default_rng(73)
+    base = L * rng.random(100)
+    x = np.concatenate([base, base + 1e-7 * L * rng.random(100), base + 2e-7 * L * rng.random(100)]) % L
+    kap = np.array([1.0, 1e3, 1e6, 1e9, 1e12])
+    announce("cv extreme kappas")
+    cv, sums, am = run_gpu_cv(gpu, x, L, kap, "f64")
+    ref_cv, S1, S2 = ocv.cv_curve(x, L, kap)
+    n, B = len(x), len(kap)
+    assert rel_err(cv, ref_cv).max() <= TOL["f64"], rel_err(cv, ref_cv)
+    from oracle.vonmises import i0e
+    skipped = math.exp(-70.0) * n * n / 2
+    for got, ref, w in ((sums[:B], S1, 1 / (L * i0e(kap) ** 2)), (sums[B:], S2, 1 / (L * i0e(kap)))):
+        assert np.all(np.abs(got - ref) <= TOL["f64"] * np.abs(ref) + skipped * w)
+    assert_argmin_ok(am, ref_cv, TOL["f64"])
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_small_argument_range_boundary(gpu, dtype):
     """Concentrations with 2 kappa below the Bessel fits' switch point

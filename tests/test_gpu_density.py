@@ -61,6 +61,41 @@ def test_deposit_grid_and_particle_counts(gpu, M, n, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_extreme_concentrations(gpu, dtype):
+    """Per-particle concentrations from moderate to far beyond any use (up
+    to 1e300 in double, where the exponent is clamped before the
+    exponential; 1e30 in float) in one deposit and one gather, against the
+    oracle. The floor is the moderate particles' peak density: the narrow
+    kernels vanish at every node a particle does not sit on. In float a
+    term with natural exponent e carries about (1 + |e|) rounding units and
+    exp2 underflows near e = -104, so a value dominated by one narrow kernel
+    is held to 128 units (7.6e-6) instead of 1e-6; in double |e| <= 1000
+    after the clamp keeps every term within 1e-12."""
+    L, M, n = 4 * math.pi, 256, 600
+    rng = np.random.default_rng(74)
+    x = npx(L * rng.random(n), dtype)
+    big = [1e6, 1e12, 1e15, 1e300] if dtype == "f64" else [1e6, 1e12, 1e20, 1e30]
+    kap = npx(rng.choice([5.0, 50.0] + big, n), dtype)
+    announce("extreme kappas", dtype)
+    rho = host(gpu.deposit(to_gpu(x), L, M, kappa_i=to_gpu(kap)))
+    x64, k64 = x.astype(np.float64), kap.astype(np.float64)
+    ref = od.deposit(x64, L, M, kappa_i=k64)
+    from oracle.vonmises import i0e
+    moderate = k64 <= 50.0
+    peak = np.mean(1.0 / (L * i0e(k64[moderate]))) * moderate.mean()
+    floor = (4 * 2.0 ** -24 if dtype == "f32" else 1e-15) * peak
+    rel = TOL[dtype] if dtype == "f64" else 128 * 2.0 ** -24
+    assert np.all(np.isfinite(rho))
+    assert np.all(np.abs(rho - ref) <= rel * np.abs(ref) + floor)
+    F = np.cos(2 * math.pi * np.arange(M) / M) + 1.5
+    G = host(gpu.gather(to_gpu(x), L, to_gpu(F), kappa_i=to_gpu(kap)))
+    ref_G = od.gather(x64, L, F, kappa_i=k64)
+    assert np.all(np.isfinite(G))
+    scale = np.abs(ref_G[moderate]).max()
+    assert np.all(np.abs(G - ref_G) <= rel * np.abs(ref_G) + 4 * TOL[dtype] * scale)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_gather_and_adjointness(gpu, dtype):
     L, M, n = 4 * math.pi, 128, 3000
     rng = np.random.default_rng(12)
