@@ -82,14 +82,26 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
       g = (g + 1 == M) ? 0 : g + 1;
     }
-  } else if (__all(A >= T(kExpTableMin))) {
+  } else if (__all(A >= T(-2.0 * kNearKappa))) {
     for (int g = 0; g < M; ++g) {
       const T s = node_s(gp, g, M, ts, tc);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
     }
-  } else {
+  } else if (__all(A >= T(kExpTableMin))) {
+    // sharp kernels in the wave: near nodes take the exact separation
+    const double dx = L / double(M);
+    const bool sharp = A < T(-2.0 * kNearKappa);
     for (int g = 0; g < M; ++g) {
-      const T s = node_s(gp, g, M, ts, tc);
+      T s = node_s(gp, g, M, ts, tc);
+      if (sharp) s = near_node_s(s, g, dx, gp.w, L);
+      acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
+    }
+  } else {
+    const double dx = L / double(M);
+    const bool sharp = A < T(-2.0 * kNearKappa);
+    for (int g = 0; g < M; ++g) {
+      T s = node_s(gp, g, M, ts, tc);
+      if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
     }
   }

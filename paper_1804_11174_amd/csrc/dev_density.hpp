@@ -78,12 +78,37 @@ constexpr int kDepMaxChunk = 512;
 //           from a table over k. Near nodes have small k and small beta, so s
 //           keeps float relative accuracy where the kernel is largest (the
 //           global form would carry the absolute rounding of a_i, b_i).
+// In double that absolute rounding (about one unit) matters only for a sharp
+// kernel close to a node: through the exponent -2 kappa s^2 it is a term
+// error up to about 6 sqrt(372 kappa) units. So for a particle with
+// kappa_i > kNearKappa, a node with |s| < 2^-8 takes s = sin(pi d / L) from
+// the exact difference d = x_g - w_i (node x_g = g (L/M), w_i the wrapped
+// position; the periodic image by an exact shift of the larger one), by
+// its Taylor series.
 template <typename T>
 struct PGeo;
 template <>
 struct PGeo<double> {
-  double a, b;
+  double a, b, w;
 };
+
+constexpr double kNearKappa = 50.0;
+constexpr double kNearS2 = 0.00390625;  // 2^-8
+
+// s for node g (position g dx, dx = L / M) and particle position w in
+// [0, L) when |s0| (the table form) is below 2^-8; s0 otherwise. Only s^2
+// is used. The node position must be the rounded product that defines the
+// grid, so the product and the difference are not fused into one FMA.
+__device__ __forceinline__ double near_node_s(double s0, int g, double dx, double w, double L) {
+#pragma clang fp contract(off)
+  if (!(fabs(s0) < kNearS2)) return s0;
+  const double xg = double(g) * dx;
+  double d = xg - w;
+  d = (d > 0.5 * L) ? (xg - L) - w : ((d < -0.5 * L) ? xg - (w - L) : d);
+  const double ph = d * (3.141592653589793 / L);
+  const double p2 = ph * ph;
+  return ph * fma(p2, fma(p2, fma(p2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+}
 template <>
 struct PGeo<float> {
   int g0;
@@ -95,6 +120,7 @@ __device__ __forceinline__ void make_geo(double xw, double L, int M, PGeo<double
   sincospi(xw / L, &sp, &cp);
   p.a = cp;
   p.b = sp;
+  p.w = xw;
 }
 
 __device__ __forceinline__ void make_geo(double xw, double L, int M, PGeo<float>& p) {
@@ -167,28 +193,81 @@ __device__ __forceinline__ void node_table(int M, T* ts, T* tc) {
 // M <= 256: S = 256 / M sub-streams share a node, thread t -> node t % M,
 //           sub-stream t / M (threads beyond S*M idle);
 // M  > 256: thread t -> nodes t, t + 256, ... (G per thread).
+// Sum over the chunk's particles p = sub, sub + S, ... at node g. NEAR: the
+// chunk holds a sharp kernel (kappa > kNearKappa), whose near nodes take the
+// exact separation; CLAMP: it holds an exponent factor beyond the table
+// exponential's domain, so exponents are clamped first. Chunks without
+// either (every chunk of ordinary widths) run the plain loop.
+template <typename T, bool PER, bool NEAR, bool CLAMP>
+__device__ __forceinline__ double dep_node_sum(int g, int sub, int S, int cnt, int M, double L, const T* ts,
+                                               const T* tc, const DepSmem<T>& sm) {
+  SumOf<T> acc;
+  const double dx = L / double(M);
+  for (int p = sub; p < cnt; p += S) {
+    T s = node_s(sm.pg[p], g, M, ts, tc);
+    const T A = sm.pA[p];
+    if constexpr (NEAR) {
+      if (A < T(-2.0 * kNearKappa)) s = near_node_s(s, g, dx, sm.pg[p].w, L);
+    }
+    const T e = CLAMP ? Flt<T>::ex(A * (s * s), sm.etab) : Flt<T>::ex_in(A * (s * s), sm.etab);
+    acc.add(PER ? sm.pw[p] * e : e);
+  }
+  return acc.value();
+}
+
+// The same for G nodes per thread (g = tid + k kBlock), all particles.
+template <typename T, bool PER, int G, bool NEAR, bool CLAMP>
+__device__ __forceinline__ void dep_node_sums(int tid, int cnt, int M, double L, const T* ts, const T* tc,
+                                              const DepSmem<T>& sm, SumOf<T> (&acc)[G]) {
+  const double dx = L / double(M);
+  for (int p = 0; p < cnt; ++p) {
+    const PGeo<T> gp = sm.pg[p];
+    const T A = sm.pA[p], w = sm.pw[p];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = tid + k * kBlock;
+      if (g < M) {
+        T s = node_s(gp, g, M, ts, tc);
+        if constexpr (NEAR) {
+          if (A < T(-2.0 * kNearKappa)) s = near_node_s(s, g, dx, gp.w, L);
+        }
+        const T e = CLAMP ? Flt<T>::ex(A * (s * s), sm.etab) : Flt<T>::ex_in(A * (s * s), sm.etab);
+        acc[k].add(PER ? w * e : e);
+      }
+    }
+  }
+}
+
 template <typename T, bool PER, int G>
 __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* __restrict__ kap, double kappa_g,
                                               int M, double L, int64_t lo, int cnt, double* __restrict__ out,
                                               const T* ts, const T* tc, DepSmem<T>& sm) {
   const int tid = threadIdx.x;
-  for (int k = tid; k < cnt; k += kBlock) particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.pg[k], sm.pA[k], sm.pw[k]);
+  int sharp = 0, huge = 0;
+  for (int k = tid; k < cnt; k += kBlock) {
+    particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.pg[k], sm.pA[k], sm.pw[k]);
+    if (std::is_same<T, double>::value && sm.pA[k] < T(-2.0 * kNearKappa)) sharp = 1;
+    if (std::is_same<T, double>::value && !(sm.pA[k] >= T(kExpTableMin))) huge = 1;
+  }
   exp_table_fill<T>(sm.etab);
-  __syncthreads();
+  // one barrier that also tells every thread whether the chunk holds a
+  // sharp kernel or an exponent factor beyond the table's domain
+  const int flags = __syncthreads_or(sharp | (huge << 1)) ? (__syncthreads_or(huge) ? 3 : 1) : 0;
   if (M <= kBlock) {
     const int S = kBlock / M;
     const int g = tid % M, sub = tid / M;
     double tot = 0.0;
     if (sub < S) {
-      SumOf<T> acc;
-      for (int p = sub; p < cnt; p += S) {
-        // every lane of a wave takes the same particle, so this test is uniform
-        const T s = node_s(sm.pg[p], g, M, ts, tc);
-        const T A = sm.pA[p];
-        const T e = (A >= T(kExpTableMin)) ? Flt<T>::ex_in(A * (s * s), sm.etab) : Flt<T>::ex(A * (s * s), sm.etab);
-        acc.add(PER ? sm.pw[p] * e : e);
+      if constexpr (std::is_same<T, double>::value) {
+        if (flags == 0)
+          tot = dep_node_sum<T, PER, false, false>(g, sub, S, cnt, M, L, ts, tc, sm);
+        else if (flags == 1)
+          tot = dep_node_sum<T, PER, true, false>(g, sub, S, cnt, M, L, ts, tc, sm);
+        else
+          tot = dep_node_sum<T, PER, true, true>(g, sub, S, cnt, M, L, ts, tc, sm);
+      } else {
+        tot = dep_node_sum<T, PER, false, false>(g, sub, S, cnt, M, L, ts, tc, sm);
       }
-      tot = acc.value();
     }
     sm.red[tid] = tot;
     __syncthreads();
@@ -199,18 +278,15 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
     }
   } else {
     SumOf<T> acc[G];
-    for (int p = 0; p < cnt; ++p) {
-      const PGeo<T> gp = sm.pg[p];
-      const T A = sm.pA[p], w = sm.pw[p];
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const int g = tid + k * kBlock;
-        if (g < M) {
-          const T s = node_s(gp, g, M, ts, tc);
-          const T e = (A >= T(kExpTableMin)) ? Flt<T>::ex_in(A * (s * s), sm.etab) : Flt<T>::ex(A * (s * s), sm.etab);
-          acc[k].add(PER ? w * e : e);
-        }
-      }
+    if constexpr (std::is_same<T, double>::value) {
+      if (flags == 0)
+        dep_node_sums<T, PER, G, false, false>(tid, cnt, M, L, ts, tc, sm, acc);
+      else if (flags == 1)
+        dep_node_sums<T, PER, G, true, false>(tid, cnt, M, L, ts, tc, sm, acc);
+      else
+        dep_node_sums<T, PER, G, true, true>(tid, cnt, M, L, ts, tc, sm, acc);
+    } else {
+      dep_node_sums<T, PER, G, false, false>(tid, cnt, M, L, ts, tc, sm, acc);
     }
     const double scale = PER ? 1.0 : 1.0 / (L * i0e_f64(kappa_g));
 #pragma unroll

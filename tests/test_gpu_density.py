@@ -95,6 +95,39 @@ def test_extreme_concentrations(gpu, dtype):
     assert np.all(np.abs(G - ref_G) <= rel * np.abs(ref_G) + 4 * TOL[dtype] * scale)
 
 
+def test_sharp_kernels_near_nodes(gpu):
+    """FP64 deposit and gather with sharp kernels (kappa 1e4 .. 1e12) at
+    1e-9 .. 1e-5 L from interior nodes, beside moderate ones: the exponent
+    -2 kappa s^2 needs s with full relative accuracy there, which the
+    half-angle tables alone do not give. Interior nodes only: the oracle's
+    sin(pi (x_g - x) / L) itself loses that accuracy for d near +-L."""
+    L, M = 4 * math.pi, 64
+    dx = L / M
+    rng = np.random.default_rng(75)
+    nodes = rng.choice(np.arange(2, M - 2), 12, replace=False)
+    offs = np.array([1e-9, -1e-9, 1e-7, -1e-7, 1e-5, -1e-5]) * L
+    xs, ks = [], []
+    for k, g in enumerate(nodes):
+        for j, o in enumerate(offs):
+            xs.append(g * dx + o)
+            ks.append([1e4, 1e8, 1e12][(k + j) % 3])
+    xm = L * rng.random(200)
+    x = np.concatenate([np.array(xs), xm])
+    kap = np.concatenate([np.array(ks), np.full(200, 5.0)])
+    announce("sharp kernels near nodes")
+    rho = host(gpu.deposit(to_gpu(x), L, M, kappa_i=to_gpu(kap)))
+    ref = od.deposit(x, L, M, kappa_i=kap)
+    from oracle.vonmises import i0e
+    floor = 1e-15 * 200 / len(x) / (L * i0e(5.0))
+    assert np.all(np.abs(rho - ref) <= TOL["f64"] * np.abs(ref) + floor), rel_err(rho, ref).max()
+    F = np.cos(2 * math.pi * np.arange(M) / M) + 1.5
+    G = host(gpu.gather(to_gpu(x), L, to_gpu(F), kappa_i=to_gpu(kap)))
+    ref_G = od.gather(x, L, F, kappa_i=kap)
+    bound = TOL["f64"] * np.abs(ref_G) + 1e-15 * np.abs(ref_G).max()
+    bad = np.flatnonzero(~(np.abs(G - ref_G) <= bound))
+    assert bad.size == 0, [(int(i), x[i], kap[i], G[i], ref_G[i]) for i in bad[:5]]
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_gather_and_adjointness(gpu, dtype):
     L, M, n = 4 * math.pi, 128, 3000
