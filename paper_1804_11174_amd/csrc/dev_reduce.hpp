@@ -15,7 +15,7 @@ constexpr int kSumRows = 256;
 // Rows are loaded kLoadAhead at a time and then added one by one, in
 // ascending order: the same sum as the plain loop, with the loads of a
 // batch in flight together instead of one dependent load per add.
-constexpr int kLoadAhead = 8;
+constexpr int kLoadAhead = 32;
 
 __device__ __forceinline__ double column_run(const double* __restrict__ in, int64_t r0, int64_t r1, int cols, int c) {
   double s = 0.0;

@@ -17,10 +17,15 @@
 //    A^2 = -N - (1/N) sum_j [(2j - 1) ln u_(j) + (2N - 2j + 1) ln(1 - u_(j))]
 //    over the sorted u (the usual form with the second logarithm's index
 //    reversed), u clamped to [2^-53, 1 - 2^-53]. The positions are sorted by
-//    an LSD radix sort on their bit patterns (non-negative floating-point
-//    values order like their unsigned bit patterns), 8 bits per pass, each
-//    pass a stable counting sort; the terms are summed in double in a fixed
-//    order.
+//    an LSD radix sort, 8 bits per pass, each pass a stable counting sort,
+//    on a 32-bit key that orders like the value: the bit pattern in float
+//    (non-negative floats order like their unsigned bit patterns), and
+//    floor(x 2^32 / L) in double, after which the rare runs of equal keys
+//    (positions within L 2^-32 of each other) are put in order by value, so
+//    the result is the fully sorted array in four passes instead of eight.
+//    Within a pass a wave ranks its lanes by digit from eight ballots and
+//    the waves write side by side at offsets from their digit counts. The
+//    terms are summed in double in a fixed order.
 #include "dev_reduce.hpp"
 #include "kde_internal.hpp"
 
@@ -109,95 +114,152 @@ __global__ void __launch_bounds__(kBlock) push_kernel(T* __restrict__ x, T* __re
 
 // ---------------------------------------------------------- radix sort (AD)
 
-template <typename T>
-struct KeyOf;
-template <>
-struct KeyOf<double> {
-  using K = unsigned long long;
-  static __device__ __forceinline__ K key(double v) { return K(__double_as_longlong(v)); }
-  static constexpr int passes = 8;
-};
-template <>
-struct KeyOf<float> {
-  using K = unsigned int;
-  static __device__ __forceinline__ K key(float v) { return K(__float_as_uint(v)); }
-  static constexpr int passes = 4;
-};
-
-template <typename T>
-__device__ __forceinline__ int digit_of(T v, int pass) {
-  return int((KeyOf<T>::key(v) >> (8 * pass)) & 0xff);
+// 32-bit sort key, ordered like the value: float bit pattern (positions are
+// non-negative), or floor(x kscale) with kscale = 2^32 / L in double (a
+// monotone map; ties are ordered afterwards by radix_fixup_kernel).
+__device__ __forceinline__ uint32_t sort_key(float v, double) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t sort_key(double v, double kscale) {
+  const double q = floor(v * kscale);
+  if (!(q > 0.0)) return 0u;  // also NaN
+  return q >= 4294967295.0 ? 4294967295u : uint32_t(q);
 }
 
 template <typename T>
+__device__ __forceinline__ int digit_of(T v, int pass, double kscale) {
+  return int((sort_key(v, kscale) >> (8 * pass)) & 0xffu);
+}
+
+constexpr int kSortPasses = 4;
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) radix_hist_kernel(const T* __restrict__ in, int64_t n, int64_t chunk, int pass,
-                                                           int32_t* __restrict__ hist) {
+                                                           double kscale, int32_t* __restrict__ hist) {
   __shared__ int32_t lh[256];
   lh[threadIdx.x] = 0;
   __syncthreads();
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int64_t hi = min(n, lo + chunk);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&lh[digit_of(in[i], pass)], 1);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&lh[digit_of(in[i], pass, kscale)], 1);
   __syncthreads();
   hist[int64_t(threadIdx.x) * gridDim.x + blockIdx.x] = lh[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(kBlock) radix_scan_kernel(int32_t* __restrict__ a, int64_t len) {
-  __shared__ int32_t tot[kBlock];
-  const int64_t seg = (len + kBlock - 1) / kBlock;
-  const int64_t lo = int64_t(threadIdx.x) * seg;
-  const int64_t hi = min(len, lo + seg);
-  int32_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += a[i];
-  tot[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int t = 0; t < kBlock; ++t) {
-      const int32_t v = tot[t];
-      tot[t] = run;
-      run += v;
-    }
+// Exclusive prefix of x over the kBlock threads of a workgroup (shuffles
+// within a wave, then the wave totals through wsum); every thread calls it.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t x, int32_t* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t v = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
   }
+  if (lane == 63) wsum[wave] = v;
   __syncthreads();
-  int32_t run = tot[threadIdx.x];
-  for (int64_t i = lo; i < hi; ++i) {
-    const int32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
+  int32_t pre = v - x;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  return pre;
 }
 
-// Stable scatter of one pass (the same wave-rank scheme as the cell sort).
+// One workgroup per digit: exclusive scan, in place, of that digit's row of
+// the [digit][block] histogram (the offsets of each block within the digit),
+// and the digit's total count into totals[digit].
+__global__ void __launch_bounds__(kBlock) radix_scan_kernel(int32_t* __restrict__ hist, int64_t blocks,
+                                                            int32_t* __restrict__ totals) {
+  __shared__ int32_t wsum[kBlock / 64];
+  int32_t* row = hist + int64_t(blockIdx.x) * blocks;
+  const int64_t seg = (blocks + kBlock - 1) / kBlock;
+  const int64_t lo = int64_t(threadIdx.x) * seg;
+  const int64_t hi = min(blocks, lo + seg);
+  int32_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += row[i];
+  int32_t run = block_exclusive_scan(s, wsum);
+  for (int64_t i = lo; i < hi; ++i) {
+    const int32_t x = row[i];
+    row[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == kBlock - 1) totals[blockIdx.x] = run;
+}
+
+// Stable scatter of one pass. Per round of kBlock keys: a lane's peers (the
+// lanes of its wave with the same digit) come from eight ballots, its rank
+// is the number of peers before it; each wave's digit counts go to LDS, and
+// every key lands at base[digit] + (the counts of that digit in the waves
+// before its own) + rank, so the waves write side by side and the order
+// stays that of the input within each digit. base starts as the block's
+// offset within its digit plus the totals of the smaller digits.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) radix_scatter_kernel(const T* __restrict__ in, int64_t n, int64_t chunk,
-                                                              int pass, const int32_t* __restrict__ base_in,
+                                                              int pass, double kscale,
+                                                              const int32_t* __restrict__ base_in,
+                                                              const int32_t* __restrict__ totals,
                                                               T* __restrict__ out) {
+  constexpr int kWaves = kBlock / 64;
   __shared__ int32_t base[256];
-  base[threadIdx.x] = base_in[int64_t(threadIdx.x) * gridDim.x + blockIdx.x];
+  __shared__ int32_t cnt[kWaves][256];
+  __shared__ int32_t wsum[kWaves];
+  const int tid = threadIdx.x;
+  const int32_t below = block_exclusive_scan(totals[tid], wsum);
+  base[tid] = base_in[int64_t(tid) * gridDim.x + blockIdx.x] + below;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int64_t hi = min(n, lo + chunk);
   for (int64_t r0 = lo; r0 < hi; r0 += kBlock) {
-    const int64_t i = r0 + threadIdx.x;
+    const int64_t i = r0 + tid;
     const bool valid = i < hi;
     const T v = valid ? in[i] : T(0);
-    const int d = valid ? digit_of(v, pass) : -1;
-    int rank = 0, after = 0;
-    for (int k = 0; k < 64; ++k) {
-      const int dk = __shfl(d, k, 64);
-      if (dk == d) {
-        if (k < lane) ++rank;
-        if (k > lane) ++after;
-      }
+    const int d = valid ? digit_of(v, pass, kscale) : 0;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
     }
-    for (int w = 0; w < kBlock / 64; ++w) {
-      if (wave == w && valid) out[base[d] + rank] = v;
-      __syncthreads();
-      if (wave == w && valid && after == 0) base[d] += rank + 1;
-      __syncthreads();
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) cnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int off = base[d] + rank;
+      for (int w = 0; w < wave; ++w) off += cnt[w][d];
+      out[off] = v;
     }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      add += cnt[w][tid];
+      cnt[w][tid] = 0;
+    }
+    base[tid] += add;
+    __syncthreads();
+  }
+}
+
+// Double keys map positions within L 2^-32 to one key; after the passes,
+// the first thread of every run of equal keys puts its run in order by value
+// (insertion sort; runs are disjoint, and a neighbour's key does not change
+// while its run is being sorted, so the run boundaries read are stable).
+__global__ void __launch_bounds__(kBlock) radix_fixup_kernel(double* __restrict__ a, int64_t n, double kscale) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = sort_key(a[i], kscale);
+  if (i > 0 && sort_key(a[i - 1], kscale) == k) return;
+  int64_t j = i + 1;
+  while (j < n && sort_key(a[j], kscale) == k) ++j;
+  for (int64_t p = i + 1; p < j; ++p) {
+    const double v = a[p];
+    int64_t q = p - 1;
+    while (q >= i && a[q] > v) {
+      a[q + 1] = a[q];
+      --q;
+    }
+    a[q + 1] = v;
   }
 }
 
@@ -274,9 +336,9 @@ template kde_status launch_push<double>(double*, double*, const double*, int64_t
 template kde_status launch_push<float>(float*, float*, const float*, int64_t, double, double, hipStream_t);
 
 static int64_t ad_blocks(int64_t n) {
-  int64_t b = ceil_div(n, 4096);
+  int64_t b = ceil_div(n, 1024);
   if (b < 1) b = 1;
-  if (b > 256) b = 256;
+  if (b > 1024) b = 1024;
   return b;
 }
 
@@ -287,6 +349,7 @@ size_t ad_workspace_bytes(int64_t n, int prec) {
   c.take<char>(size_t(n) * elem_size(prec));
   c.take<char>(size_t(n) * elem_size(prec));
   c.take<int32_t>(256 * size_t(blocks));
+  c.take<int32_t>(256);
   c.take<double>(size_t(tb));
   c.take<double>(column_sum_scratch(tb, 1) / sizeof(double) + 1);
   c.take<double>(1);
@@ -303,6 +366,7 @@ kde_status launch_ad_statistic(const T* x, int64_t n, double L, double* a2, void
   T* buf0 = c.take<T>(size_t(n));
   T* buf1 = c.take<T>(size_t(n));
   int32_t* hist = c.take<int32_t>(256 * size_t(blocks));
+  int32_t* totals = c.take<int32_t>(256);
   double* parts = c.take<double>(size_t(tb));
   double* scratch = c.take<double>(column_sum_scratch(tb, 1) / sizeof(double) + 1);
   double* sum = c.take<double>(1);
@@ -310,17 +374,23 @@ kde_status launch_ad_statistic(const T* x, int64_t n, double L, double* a2, void
   KDE_TRY_HIP(hipMemcpyAsync(buf0, x, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s));
   T* src = buf0;
   T* dst = buf1;
-  for (int pass = 0; pass < KeyOf<T>::passes; ++pass) {
-    hipLaunchKernelGGL(radix_hist_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, (const T*)src, n, chunk, pass, hist);
+  const double kscale = 4294967296.0 / L;
+  for (int pass = 0; pass < kSortPasses; ++pass) {
+    hipLaunchKernelGGL(radix_hist_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, (const T*)src, n, chunk, pass,
+                       kscale, hist);
     KDE_CHECK_LAUNCH();
-    hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(kBlock), 0, s, hist, int64_t(256) * blocks);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kBlock), 0, s, hist, blocks, totals);
     KDE_CHECK_LAUNCH();
     hipLaunchKernelGGL(radix_scatter_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, (const T*)src, n, chunk, pass,
-                       (const int32_t*)hist, dst);
+                       kscale, (const int32_t*)hist, (const int32_t*)totals, dst);
     KDE_CHECK_LAUNCH();
     T* t = src;
     src = dst;
     dst = t;
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    hipLaunchKernelGGL(radix_fixup_kernel, dim3(unsigned(ceil_div(n, kBlock))), dim3(kBlock), 0, s, src, n, kscale);
+    KDE_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(ad_terms_kernel<T>, dim3(unsigned(tb)), dim3(kBlock), 0, s, (const T*)src, n, L, parts);
   KDE_CHECK_LAUNCH();

@@ -35,6 +35,27 @@ def oracle_session(x0, v0, L, M, dt, kappas, n_cv, steps, alpha=0.5, thr=0.01, r
         hist.append(dict(a2=a2, p=p, fired=fired, kstar=kstar, rho=rho, E=E))
     return x, v, k_i, st, hist
 
+def test_ad_statistic_with_tied_sort_keys(gpu):
+    """Positions in clusters of four 1e-12 L apart, in descending order
+    within each cluster: the double sort keys (L 2^-32 resolution) tie, so
+    the runs of equal keys must be put in order by value. After one step of
+    negligible motion (dt = 1e-15, cold start) the session's A^2 equals the
+    oracle's on the positions it holds."""
+    L, M, n = 4 * math.pi, 64, 4096
+    rng = np.random.default_rng(77)
+    base = L * (0.001 + 0.998 * rng.random(n // 4))
+    x0 = np.concatenate([base + k * 1e-12 * L for k in (3, 2, 1, 0)])
+    v0 = np.zeros(n)
+    announce("AD statistic with tied keys")
+    s = gpu.Session(to_gpu(x0), to_gpu(v0), L, M, 1e-15, W.log_kappas(1.0, 1e3, 8), 1024)
+    try:
+        s.step(1)
+        a2 = s.state()["last_a2"]
+        ref = adtest.ad_statistic(host(s.read(gpu.KDE_SESSION_X)), L)
+        assert abs(a2 - ref) <= 1e-10 * abs(ref), (a2, ref)
+    finally:
+        s.close()
+
 
 @pytest.mark.parametrize("alpha_density", [0.1, 0.01])
 def test_session_steps_match_oracle(gpu, alpha_density):
