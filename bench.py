@@ -651,12 +651,12 @@ def bench_landau(args, kde, W, torch, dev):
     (CV width at t = 0 and the update rule): 2^15 particles, 256 nodes,
     dt = 0.01, 1500 steps, density perturbation 0.02 cos x. Each run's
     damping rate is the slope of log field energy through its first two
-    peaks (kde_damping_rate, = 2 Im(omega)); the theory is the Maxwellian
-    root, and for KDE also the root with the kernel's response rho_1^2 at
-    the kappa* in force between the peaks. Sessions step concurrently, one
+    peaks (kde_damping_rate, = 2 Im(omega)), reported per method as mean,
+    spread and, for KDE, the kappa* in force between the peaks; the
+    comparison with the dispersion relation's roots is made afterwards from
+    this JSON line by tests/landau_table.py. Sessions step concurrently, one
     per worker thread, each on its own stream."""
     import concurrent.futures as cf
-    from oracle import landau as olandau
     vths = [float(v) for v in args.vths.split(",")]
     ens = [W.landau_ensemble(i) for i in range(args.ensembles)]
     e0 = ens[0]
@@ -691,23 +691,16 @@ def bench_landau(args, kde, W, torch, dev):
     wall = time.perf_counter() - t0
     table = []
     for vth in vths:
-        theory = 2 * olandau.landau_root(1.0, vth).imag
-        row = {"v_th": vth, "theory_energy_rate": theory}
+        row = {"v_th": vth}
         for m in ("standard", "kde"):
             r = np.array([res[0] for (i, v, mm), res in zip(jobs, results) if v == vth and mm == m])
             k = np.array([res[1] for (i, v, mm), res in zip(jobs, results) if v == vth and mm == m])
             ok = np.isfinite(r)
-            err = r[ok] - theory
             sd = float(np.std(r[ok], ddof=1)) if ok.sum() > 1 else float("nan")
             entry = {"mean_rate": float(np.mean(r[ok])) if ok.any() else None, "sd": sd,
-                     "abs_error_of_mean": float(abs(np.mean(err))) if ok.any() else None,
-                     "t_stat": float(np.mean(err) / (sd / math.sqrt(ok.sum()))) if ok.sum() > 1 else None,
                      "runs_with_two_peaks": int(ok.sum())}
             if m == "kde":
-                kk = float(np.nanmean(k))
-                entry["mean_kappa_star"] = kk
-                entry["theory_with_kernel_response"] = 2 * olandau.landau_root(
-                    1.0, vth, response=olandau.kernel_response(kk)).imag
+                entry["mean_kappa_star"] = float(np.nanmean(k))
             row[m] = entry
         table.append(row)
     steps = len(jobs) * e0.steps
