@@ -43,11 +43,14 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(const T* __restrict__ x
   deposit_block<T, PER, G>(x, kap, kappa_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, ts, tc, sm);
 }
 
-// One thread per particle, looping over the nodes. Dynamic LDS: the node
-// table (2 M values of T) and the field (M values of T). In the float form
-// the loop runs over k = g - g0, so the table read is a broadcast and the
-// field read is per lane.
-template <typename T>
+// S adjacent lanes per particle (S = 1, 2, 4 or 8, from gather_split), lane
+// j summing the nodes k in [j M / S, (j + 1) M / S) in order; the S partial
+// sums are combined by an xor butterfly, a fixed pairwise tree whose result
+// every lane of the group holds. Dynamic LDS: the node table (2 M values of
+// T) and the field (M values of T). In the float form the loop runs over
+// k = g - g0, so the table read is a broadcast and the field read is per
+// lane.
+template <typename T, int S>
 __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x, const T* __restrict__ kap,
                                                        double kappa_g, bool per, int64_t n, int M, double L,
                                                        const double* __restrict__ field, T* __restrict__ out) {
@@ -65,8 +68,11 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
     tf[k] = T(field[k]);
   }
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
+  const int64_t gid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t i = gid / S;
+  if (i >= n) return;  // a particle's S lanes leave together
+  const int j = int(gid % S);
+  const int k0 = (j * M) / S, k1 = ((j + 1) * M) / S;
   const double xi = double(x[i]);
   const double xw = xi - L * floor(xi / L);
   PGeo<T> gp;
@@ -76,14 +82,15 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   const double w = (L / M) / (L * i0e_f64(kk));
   SumOf<T> acc;
   if constexpr (std::is_same<T, float>::value) {
-    int g = gp.g0;
-    for (int k = 0; k < M; ++k) {
+    int g = gp.g0 + k0;
+    if (g >= M) g -= M;
+    for (int k = k0; k < k1; ++k) {
       const T s = ts[k] * gp.cb - tc[k] * gp.sb;
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
       g = (g + 1 == M) ? 0 : g + 1;
     }
   } else if (__all(A >= T(-2.0 * kNearKappa))) {
-    for (int g = 0; g < M; ++g) {
+    for (int g = k0; g < k1; ++g) {
       const T s = node_s(gp, g, M, ts, tc);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
     }
@@ -91,7 +98,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
     // sharp kernels in the wave: near nodes take the exact separation
     const double dx = L / double(M);
     const bool sharp = A < T(-2.0 * kNearKappa);
-    for (int g = 0; g < M; ++g) {
+    for (int g = k0; g < k1; ++g) {
       T s = node_s(gp, g, M, ts, tc);
       if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
@@ -99,13 +106,16 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   } else {
     const double dx = L / double(M);
     const bool sharp = A < T(-2.0 * kNearKappa);
-    for (int g = 0; g < M; ++g) {
+    for (int g = k0; g < k1; ++g) {
       T s = node_s(gp, g, M, ts, tc);
       if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
     }
   }
-  out[i] = T(w * acc.value());
+  double tot = acc.value();
+#pragma unroll
+  for (int m = 1; m < S; m <<= 1) tot += __shfl_xor(tot, m, 64);
+  if (j == 0) out[i] = T(w * tot);
 }
 
 template <typename T>
@@ -256,6 +266,39 @@ kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* 
   return launch_column_sum(partials, chunks, dom->M, scratch, rho, s, 1.0 / double(n));
 }
 
+// Lanes per particle for the gather: split the node loop while the
+// particles alone would leave the chip short of workgroups (fewer than
+// 1024) and every lane keeps at least 32 nodes.
+static int gather_split(int64_t n, int M) {
+  int S = 1;
+  while (S < 8 && M / (2 * S) >= 32 && ceil_div(n * S, kBlock) < 1024) S *= 2;
+  return S;
+}
+
+template <typename T>
+static kde_status launch_gather_t(const kde_domain* dom, int64_t n, const T* x, const T* kap, double kappa,
+                                  const double* field, T* out, size_t lds, hipStream_t s) {
+  const int S = gather_split(n, dom->M);
+  const dim3 grid{unsigned(ceil_div(n * S, kBlock))}, block{unsigned(kBlock)};
+  const bool per = kap != nullptr;
+  switch (S) {
+    case 1:
+      hipLaunchKernelGGL((gather_kernel<T, 1>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gather_kernel<T, 2>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      break;
+    case 4:
+      hipLaunchKernelGGL((gather_kernel<T, 4>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      break;
+    default:
+      hipLaunchKernelGGL((gather_kernel<T, 8>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      break;
+  }
+  KDE_CHECK_LAUNCH();
+  return KDE_OK;
+}
+
 kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
                   const double* field, void* out, hipStream_t s) {
   const dim3 grid{unsigned(ceil_div(n, kBlock))}, block{unsigned(kBlock)};
@@ -277,16 +320,12 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
   const size_t lds = 3 * size_t(dom->M) * elem_size(dom->prec);
   KDE_RETURN_IF(check_lds(lds + (dom->prec == KDE_F64 ? 256 * sizeof(double) : sizeof(double))));  // + exp table
   TimedLaunch timed(KDE_KERNEL_GATHER, s);
-  if (dom->prec == KDE_F64) {
-    hipLaunchKernelGGL(gather_kernel<double>, grid, block, lds, s, static_cast<const double*>(x),
-                       static_cast<const double*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
-                       static_cast<double*>(out));
-  } else {
-    hipLaunchKernelGGL(gather_kernel<float>, grid, block, lds, s, static_cast<const float*>(x),
-                       static_cast<const float*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
-                       static_cast<float*>(out));
-  }
-  KDE_CHECK_LAUNCH();
+  if (dom->prec == KDE_F64)
+    KDE_RETURN_IF(launch_gather_t<double>(dom, n, static_cast<const double*>(x), static_cast<const double*>(kap),
+                                          kappa, field, static_cast<double*>(out), lds, s));
+  else
+    KDE_RETURN_IF(launch_gather_t<float>(dom, n, static_cast<const float*>(x), static_cast<const float*>(kap),
+                                         kappa, field, static_cast<float*>(out), lds, s));
   return KDE_OK;
 }
 

@@ -148,6 +148,24 @@ def test_gather_and_adjointness(gpu, dtype):
     assert np.abs(Gg - refg).max() <= TOL[dtype] * np.abs(refg).max()
 
 
+@pytest.mark.parametrize("M", [7, 64, 100, 128, 257, 1000])
+@pytest.mark.parametrize("n", [1, 5, 300, 4097, 40000])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gather_grid_and_particle_counts(gpu, M, n, dtype):
+    """Gather at ragged particle counts and grid sizes that give every node
+    split the kernel uses (1, 2, 4 or 8 lanes per particle, each over a
+    contiguous range of nodes), against the oracle, per-particle widths."""
+    L = 2.0
+    rng = np.random.default_rng([21, M, n])
+    x = npx(L * rng.random(n), dtype)
+    kap = npx(10.0 ** rng.uniform(0, 4, n), dtype)
+    F = np.cos(2 * math.pi * np.arange(M) / M) + 0.25 * np.sin(6 * math.pi * np.arange(M) / M) + 1.2
+    announce("gather sizes", M, n, dtype)
+    G = host(gpu.gather(to_gpu(x), L, to_gpu(F), kappa_i=to_gpu(kap)))
+    ref = od.gather(x.astype(np.float64), L, F, kappa_i=kap.astype(np.float64))
+    assert np.all(np.abs(G - ref) <= TOL[dtype] * np.abs(ref).max())
+
+
 def test_gather_of_ones_matches_grid_sum_identity(gpu):
     from scipy import special
     L, M, k = 2 * math.pi, 64, 900.0
