@@ -376,7 +376,7 @@ kde_status kde_batch_destroy(kde_batch* b);
  * population in HBM (inside a caller-owned arena) and advances it by the
  * KDE-PIC cycle of Sec. III.A with the width-update rule of Sec. II.D:
  * deposit with kappa_i -> net charge 1 - L rho -> three-point periodic
- * Poisson equation solved exactly by FFT (the mean mode dropped) ->
+ * Poisson equation solved exactly (the mean charge removed) ->
  * centred field -> gather with kappa_i -> leapfrog push (electrons,
  * q/m = -1; v <- v - E dt, then x <- x + v dt, wrapped) -> Anderson-Darling
  * statistic of x/L against the uniform law, read by the host, whose

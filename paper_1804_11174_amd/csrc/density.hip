@@ -161,9 +161,25 @@ __global__ void __launch_bounds__(kBlock) tri_gather_kernel(const T* __restrict_
   __syncthreads();
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
-  const TriGeo<T> p = tri_geo<T>(double(x[i]), per ? double(hi[i]) : h_g, L, M);
+  const double h = per ? double(hi[i]) : h_g;
+  const TriGeo<T> p = tri_geo<T>(double(x[i]), h, L, M);
   SumOf<T> acc;
-  for (int g = 0; g < M; ++g) acc.add(tf[g] * tri_node(p, g, M));
+  // Nodes beyond h / dx cells of the particle add exact zeros, so a
+  // particle whose support is shorter than the circle visits only the nodes
+  // g0 - r .. g0 + r (one node of margin against the rounding of q), still
+  // in ascending node order: for a finite field the sum is the full
+  // loop's, bit for bit.
+  const int r = int(fmin(ceil(h * (double(M) / L)), double(M))) + 1;
+  if (isfinite(double(p.w)) && 2 * r < M) {
+    const int a = p.g0 - r, b = p.g0 + r;
+    const int lo1 = a < 0 ? 0 : (b >= M ? 0 : a);
+    const int hi1 = a < 0 ? b : (b >= M ? b - M : b);
+    const int lo2 = a < 0 ? a + M : (b >= M ? a : M);
+    for (int g = lo1; g <= hi1; ++g) acc.add(tf[g] * tri_node(p, g, M));
+    for (int g = lo2; g < M; ++g) acc.add(tf[g] * tri_node(p, g, M));
+  } else {
+    for (int g = 0; g < M; ++g) acc.add(tf[g] * tri_node(p, g, M));
+  }
   out[i] = T((L / M) * double(p.w) * acc.value());
 }
 

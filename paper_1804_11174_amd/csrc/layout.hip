@@ -84,16 +84,20 @@ template kde_status launch_pack_sorted_as<double, FracPos>(const double*, int64_
 
 // ------------------------------------------------------ deterministic sums
 
-// Block (row block x, column block y): one column per thread.
-__global__ void __launch_bounds__(kBlock) colsum_level1_kernel(const double* __restrict__ in, int64_t rows, int cols,
-                                                              double* __restrict__ l1) {
-  const int c = int(blockIdx.y) * kBlock + threadIdx.x;
+// Block (row block x, column block y): one column per thread, kSumCols
+// columns per workgroup, so a wide sum spreads its reads over
+// ceil(cols / kSumCols) workgroups per row block.
+constexpr int kSumCols = 64;
+
+__global__ void __launch_bounds__(kSumCols) colsum_level1_kernel(const double* __restrict__ in, int64_t rows,
+                                                                int cols, double* __restrict__ l1) {
+  const int c = int(blockIdx.y) * kSumCols + threadIdx.x;
   if (c < cols) l1[int64_t(blockIdx.x) * cols + c] = colsum_level1(in, rows, cols, blockIdx.x, c);
 }
 
-__global__ void __launch_bounds__(kBlock) colsum_level2_kernel(const double* __restrict__ l1, int64_t g, int cols,
-                                                              double scale, double* __restrict__ out) {
-  const int c = int(blockIdx.x) * kBlock + threadIdx.x;
+__global__ void __launch_bounds__(kSumCols) colsum_level2_kernel(const double* __restrict__ l1, int64_t g, int cols,
+                                                                double scale, double* __restrict__ out) {
+  const int c = int(blockIdx.x) * kSumCols + threadIdx.x;
   if (c < cols) out[c] = colsum_level2(l1, g, cols, c, scale);
 }
 
@@ -104,10 +108,11 @@ size_t column_sum_scratch(int64_t rows, int cols) {
 kde_status launch_column_sum(const double* in, int64_t rows, int cols, double* scratch, double* out, hipStream_t s,
                              double scale) {
   const int64_t g = ceil_div(rows, kSumRows);
-  const unsigned cb = unsigned(ceil_div(cols, kBlock));
-  hipLaunchKernelGGL(colsum_level1_kernel, dim3(unsigned(g), cb), dim3(kBlock), 0, s, in, rows, cols, scratch);
+  const unsigned cb = unsigned(ceil_div(cols, kSumCols));
+  hipLaunchKernelGGL(colsum_level1_kernel, dim3(unsigned(g), cb), dim3(kSumCols), 0, s, in, rows, cols, scratch);
   KDE_CHECK_LAUNCH();
-  hipLaunchKernelGGL(colsum_level2_kernel, dim3(cb), dim3(kBlock), 0, s, (const double*)scratch, g, cols, scale, out);
+  hipLaunchKernelGGL(colsum_level2_kernel, dim3(cb), dim3(kSumCols), 0, s, (const double*)scratch, g, cols, scale,
+                     out);
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }

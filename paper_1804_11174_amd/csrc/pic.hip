@@ -3,10 +3,14 @@
 //
 //  * Poisson and field: net charge rho_q = 1 - L rho (electrons of mean
 //    density 1 on a uniform ion background, plasma frequency 1), the
-//    three-point periodic Poisson equation solved exactly in Fourier space
-//    (mode m is divided by (2 - 2 cos(2 pi m / M)) / dx^2, the mean mode is
-//    dropped), then the centred field E_j = (phi_{j-1} - phi_{j+1}) / (2 dx).
-//    One workgroup: an iterative radix-2 complex FFT in LDS, M a power of two.
+//    three-point periodic Poisson equation phi_{j-1} - 2 phi_j + phi_{j+1}
+//    = -dx^2 (rho_q,j - mean rho_q) (the mean carries no field), and the
+//    centred field E_j = (phi_{j-1} - phi_{j+1}) / (2 dx). Solved exactly
+//    without phi: the half-node fields e_j = (phi_j - phi_{j+1}) / dx obey
+//    e_j - e_{j-1} = dx (rho_q,j - mean) and sum to zero over the period,
+//    so they are the running sums of that right side less their mean, and
+//    E_j = (e_{j-1} + e_j) / 2. One workgroup, three fixed-order block
+//    scans in LDS; M a power of two (the session's grids).
 //  * Push: v <- v - E_i dt, x <- x + v dt, wrapped into [0, L) (electrons,
 //    q/m = -1), one thread per particle.
 //  * Field energy: W = (dx / 2) sum_g E_g^2 (eps0 = 1), one workgroup, the
@@ -31,71 +35,67 @@
 
 namespace kde {
 
-constexpr int kMaxFftM = 2048;
+constexpr int kMaxPoissonM = 2048;  // largest session grid
 
-__device__ __forceinline__ int bit_reverse(int v, int bits) { return int(__brev(unsigned(v)) >> (32 - bits)); }
-
-// In-place radix-2 FFT of (re, im)[M] in LDS by one workgroup; sign = -1
-// forward, +1 inverse (unscaled).
-__device__ void fft_lds(double* re, double* im, int M, int bits, double sign) {
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const int j = bit_reverse(i, bits);
-    if (j > i) {
-      const double tr = re[i], ti = im[i];
-      re[i] = re[j];
-      im[i] = im[j];
-      re[j] = tr;
-      im[j] = ti;
-    }
+// Exclusive prefix of x over the kBlock threads of a workgroup in a fixed
+// order (a shuffle tree within each wave, then the wave totals in wave
+// order); *total gets the workgroup's sum. Every thread calls it; wsum is
+// this call's own.
+__device__ __forceinline__ double block_exclusive_scan_f64(double x, double* wsum, double* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
   }
+  double ex = __shfl_up(v, 1, 64);
+  if (lane == 0) ex = 0.0;
+  if (lane == 63) wsum[wave] = v;
   __syncthreads();
-  for (int len = 2; len <= M; len <<= 1) {
-    const int half = len >> 1;
-    for (int t = threadIdx.x; t < M / 2; t += blockDim.x) {
-      const int grp = t / half, k = t % half;
-      const int i = grp * len + k, j = i + half;
-      double s, c;
-      sincospi(sign * 2.0 * double(k) / double(len), &s, &c);
-      const double xr = re[j] * c - im[j] * s;
-      const double xi = re[j] * s + im[j] * c;
-      re[j] = re[i] - xr;
-      im[j] = im[i] - xi;
-      re[i] += xr;
-      im[i] += xi;
-    }
-    __syncthreads();
+  double pre = 0.0, all = 0.0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w == wave) pre = all;
+    all += wsum[w];
   }
+  *total = all;
+  return pre + ex;
 }
 
-__global__ void __launch_bounds__(kBlock) poisson_field_kernel(const double* __restrict__ rho, int M, int bits,
-                                                              double L, double* __restrict__ E,
-                                                              double* __restrict__ phi_out) {
-  __shared__ double re[kMaxFftM], im[kMaxFftM];
+__global__ void __launch_bounds__(kBlock) poisson_field_kernel(const double* __restrict__ rho, int M, double L,
+                                                              double* __restrict__ E) {
+  __shared__ double e[kMaxPoissonM];
+  __shared__ double w1[kBlock / 64], w2[kBlock / 64], w3[kBlock / 64];
   const double dx = L / M;
-  for (int g = threadIdx.x; g < M; g += kBlock) {
-    re[g] = 1.0 - L * rho[g];
-    im[g] = 0.0;
+  const int seg = (M + kBlock - 1) / kBlock;
+  const int lo = min(M, int(threadIdx.x) * seg), hi = min(M, lo + seg);
+  double s = 0.0;  // this thread's cells of the net charge
+  for (int j = lo; j < hi; ++j) {
+    const double r = 1.0 - L * rho[j];
+    e[j] = r;
+    s += r;
   }
-  __syncthreads();
-  fft_lds(re, im, M, bits, -1.0);
-  for (int m = threadIdx.x; m < M; m += kBlock) {
-    if (m == 0) {
-      re[0] = 0.0;
-      im[0] = 0.0;
-    } else {
-      const double sp = sinpi(double(m) / double(M));   // 2 - 2 cos(2 pi m / M) = 4 sin^2(pi m / M)
-      const double f = dx * dx / (4.0 * sp * sp) / double(M);
-      re[m] *= f;
-      im[m] *= f;
-    }
+  double tot;
+  block_exclusive_scan_f64(s, w1, &tot);
+  const double mean = tot / M;
+  double t = 0.0;  // right side dx (rho_q - mean)
+  for (int j = lo; j < hi; ++j) {
+    const double q = dx * (e[j] - mean);
+    e[j] = q;
+    t += q;
   }
-  __syncthreads();
-  fft_lds(re, im, M, bits, 1.0);
+  double run = block_exclusive_scan_f64(t, w2, &tot);
+  double u = 0.0;  // running sums: e_j up to the constant
+  for (int j = lo; j < hi; ++j) {
+    run += e[j];
+    e[j] = run;
+    u += run;
+  }
+  block_exclusive_scan_f64(u, w3, &tot);  // its barrier also publishes e[]
+  const double c = -tot / M;
   for (int g = threadIdx.x; g < M; g += kBlock) {
     const int gm = (g == 0) ? M - 1 : g - 1;
-    const int gp = (g + 1 == M) ? 0 : g + 1;
-    E[g] = (re[gm] - re[gp]) / (2.0 * dx);
-    if (phi_out) phi_out[g] = re[g];
+    E[g] = 0.5 * ((e[gm] + c) + (e[g] + c));
   }
 }
 
@@ -294,7 +294,7 @@ __global__ void ad_finish_kernel(const double* __restrict__ sum, int64_t n, doub
 
 // ------------------------------------------------------------------ host
 
-size_t poisson_max_m() { return kMaxFftM; }
+size_t poisson_max_m() { return kMaxPoissonM; }
 
 __global__ void __launch_bounds__(kBlock) field_energy_kernel(const double* __restrict__ E, int M, double half_dx,
                                                              double* __restrict__ out) {
@@ -317,11 +317,9 @@ kde_status launch_field_energy(const double* E, int M, double L, double* out, hi
   return KDE_OK;
 }
 
-kde_status launch_poisson_field(const double* rho, int M, double L, double* E, double* phi, hipStream_t s) {
-  int bits = 0;
-  while ((1 << bits) < M) ++bits;
-  if ((1 << bits) != M || M > kMaxFftM || M < 2) return fail(KDE_E_INVALID_ARG, "M must be a power of two in [2, %d]", kMaxFftM);
-  hipLaunchKernelGGL(poisson_field_kernel, dim3(1), dim3(kBlock), 0, s, rho, M, bits, L, E, phi);
+kde_status launch_poisson_field(const double* rho, int M, double L, double* E, hipStream_t s) {
+  if (M < 2 || M > kMaxPoissonM || (M & (M - 1))) return fail(KDE_E_INVALID_ARG, "M must be a power of two in [2, %d]", kMaxPoissonM);
+  hipLaunchKernelGGL(poisson_field_kernel, dim3(1), dim3(kBlock), 0, s, rho, M, L, E);
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }
@@ -336,7 +334,7 @@ template kde_status launch_push<double>(double*, double*, const double*, int64_t
 template kde_status launch_push<float>(float*, float*, const float*, int64_t, double, double, hipStream_t);
 
 static int64_t ad_blocks(int64_t n) {
-  int64_t b = ceil_div(n, 1024);
+  int64_t b = ceil_div(n, kBlock);
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return b;

@@ -43,7 +43,7 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
 kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
                         double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
                         hipStream_t s);
-kde_status launch_poisson_field(const double* rho, int M, double L, double* E, double* phi, hipStream_t s);
+kde_status launch_poisson_field(const double* rho, int M, double L, double* E, hipStream_t s);
 kde_status launch_field_energy(const double* E, int M, double L, double* out, hipStream_t s);
 template <typename T>
 kde_status launch_push(T* x, T* v, const T* E_i, int64_t n, double dt, double L, hipStream_t s);
@@ -229,7 +229,7 @@ static kde_status standard_step_once(kde_session* s) {
   const kde_pic_params& p = s->prm;
   const double dx = p.L / double(p.M);
   KDE_RETURN_IF(deposit(&s->tdom, p.N, s->x, nullptr, dx, s->rho, s->ws, s->ws_bytes, s->s));
-  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, nullptr, s->s));
+  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
   KDE_RETURN_IF(record_energy(s));
   KDE_RETURN_IF(gather(&s->tdom, p.N, s->x, nullptr, dx, s->E, s->Ei, s->s));
   KDE_RETURN_IF(push_any(s));
@@ -241,7 +241,7 @@ static kde_status session_step_once(kde_session* s) {
   const kde_pic_params& p = s->prm;
   if (standard(p)) return standard_step_once(s);
   KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s));
-  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, nullptr, s->s));
+  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
   KDE_RETURN_IF(record_energy(s));
   KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s));
   if (p.prec == KDE_F64) {

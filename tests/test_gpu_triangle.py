@@ -58,6 +58,15 @@ def conditioning_floor(x, L, M, h, dtype):
     return 8 * u * np.sum(cover * ((1 + S / h) / h)[None, :], axis=1) / len(x)
 
 
+def gather_floor(L, M, h, F, dtype):
+    """Per particle: the deposit's per-node bound 8 u (1 + S / h_i) / h_i
+    times dx |F|max over the at most 2 h_i / dx + 2 nodes of its support."""
+    h = np.asarray(h, dtype=np.float64)
+    u, S = (2.0 ** -53, L) if dtype == "f64" else (2.0 ** -24, L / M)
+    dx = L / M
+    return dx * np.abs(F).max() * (2 * h / dx + 2) * 8 * u * (1 + S / h) / h
+
+
 def widths_for(L, M, count):
     """Half-widths from a quarter cell to half the period, ascending; the
     widest ones (> L/4) reach their periodic image."""
@@ -239,3 +248,35 @@ def test_gather_and_adjointness(gpu, dtype):
     Gg = host(gpu.gather(to_gpu(x), L, to_gpu(F), kappa=0.3, shape=shape))
     refg = tri.gather(x.astype(np.float64), L, F, h=0.3)
     assert np.abs(Gg - refg).max() <= TOL[dtype] * np.abs(refg).max()
+
+
+@pytest.mark.parametrize("M", [2, 7, 64, 257, 1000])
+@pytest.mark.parametrize("n", [1, 300, 4097])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gather_sizes_and_support_edges(gpu, M, n, dtype):
+    """Triangle gather over ragged sizes with widths from 0.01 cells to L/2
+    (short supports visit only the nodes near the particle, long ones the
+    whole circle), whole-cell widths whose support ends on a node, and
+    particles on nodes, at half cells and next to the wrap point; then
+    h = dx on a constant field, where the two linear weights sum to one."""
+    L = 3.0
+    dx = L / M
+    rng = np.random.default_rng([23, M, n])
+    x = L * rng.random(n)
+    x[: n // 4] = dx * rng.integers(0, M, n // 4)
+    x[n // 4: n // 3] = dx * (rng.integers(0, M, n // 3 - n // 4) + 0.5)
+    x[n // 3: n // 3 + 4] = [0.0, L * (1 - 1e-12), 1e-12, L - 0.5 * dx][: min(4, n - n // 3)]
+    cells = 10.0 ** rng.uniform(-2, math.log10(max(M / 2, 1.01)), n)
+    cells[::5] = rng.integers(1, max(2, M // 2) + 1, cells[::5].shape)
+    h = np.minimum(0.5 * L, dx * cells)
+    x = npx(x, dtype)
+    h = f32_widths(h, L) if dtype == "f32" else h
+    F = np.cos(2 * math.pi * np.arange(M) / M) + 0.5 * np.sin(10 * math.pi * np.arange(M) / M) + 1.1
+    shape = gpu.KDE_SHAPE_TRIANGLE
+    announce("tri gather sizes", M, n, dtype)
+    G = host(gpu.gather(to_gpu(x), L, to_gpu(F), kappa_i=to_gpu(npx(h, dtype)), shape=shape))
+    h64 = npx(h, dtype).astype(np.float64)
+    ref = tri.gather(x.astype(np.float64), L, F, h_i=h64)
+    assert np.all(np.abs(G - ref) <= TOL[dtype] * np.abs(ref).max() + gather_floor(L, M, h64, F, dtype))
+    G1 = host(gpu.gather(to_gpu(x), L, to_gpu(np.ones(M)), kappa=dx, shape=shape))
+    assert np.abs(G1 - 1.0).max() <= 8 * TOL[dtype]
