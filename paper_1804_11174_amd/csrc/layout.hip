@@ -101,6 +101,15 @@ __global__ void __launch_bounds__(kSumCols) colsum_level2_kernel(const double* _
   if (c < cols) out[c] = colsum_level2(l1, g, cols, c, scale);
 }
 
+// Both levels at once when there is one row block: level 2 over a single
+// level-1 row is 0 + l1, exactly l1, so out[c] = l1 * scale has the
+// two-kernel result's bits.
+__global__ void __launch_bounds__(kSumCols) colsum_single_kernel(const double* __restrict__ in, int64_t rows,
+                                                                int cols, double scale, double* __restrict__ out) {
+  const int c = int(blockIdx.x) * kSumCols + threadIdx.x;
+  if (c < cols) out[c] = colsum_level1(in, rows, cols, 0, c) * scale;
+}
+
 size_t column_sum_scratch(int64_t rows, int cols) {
   return size_t(ceil_div(rows, kSumRows)) * size_t(cols) * sizeof(double);
 }
@@ -109,6 +118,11 @@ kde_status launch_column_sum(const double* in, int64_t rows, int cols, double* s
                              double scale) {
   const int64_t g = ceil_div(rows, kSumRows);
   const unsigned cb = unsigned(ceil_div(cols, kSumCols));
+  if (g == 1) {
+    hipLaunchKernelGGL(colsum_single_kernel, dim3(cb), dim3(kSumCols), 0, s, in, rows, cols, scale, out);
+    KDE_CHECK_LAUNCH();
+    return KDE_OK;
+  }
   hipLaunchKernelGGL(colsum_level1_kernel, dim3(unsigned(g), cb), dim3(kSumCols), 0, s, in, rows, cols, scratch);
   KDE_CHECK_LAUNCH();
   hipLaunchKernelGGL(colsum_level2_kernel, dim3(cb), dim3(kSumCols), 0, s, (const double*)scratch, g, cols, scale,

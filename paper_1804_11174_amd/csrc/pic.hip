@@ -369,23 +369,23 @@ kde_status launch_ad_statistic(const T* x, int64_t n, double L, double* a2, void
   double* scratch = c.take<double>(column_sum_scratch(tb, 1) / sizeof(double) + 1);
   double* sum = c.take<double>(1);
   if (!c.fits()) return fail(KDE_E_WORKSPACE, "AD workspace too small: %zu < %zu", ws_bytes, c.used);
-  KDE_TRY_HIP(hipMemcpyAsync(buf0, x, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s));
-  T* src = buf0;
-  T* dst = buf1;
+  // The first pass reads x itself; the passes then alternate between the
+  // two buffers, the sorted array ending in bufs[(passes - 1) & 1].
+  T* bufs[2] = {buf0, buf1};
   const double kscale = 4294967296.0 / L;
   for (int pass = 0; pass < kSortPasses; ++pass) {
-    hipLaunchKernelGGL(radix_hist_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, (const T*)src, n, chunk, pass,
-                       kscale, hist);
+    const T* in = pass == 0 ? x : bufs[(pass + 1) & 1];
+    T* out = bufs[pass & 1];
+    hipLaunchKernelGGL(radix_hist_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, in, n, chunk, pass, kscale,
+                       hist);
     KDE_CHECK_LAUNCH();
     hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kBlock), 0, s, hist, blocks, totals);
     KDE_CHECK_LAUNCH();
-    hipLaunchKernelGGL(radix_scatter_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, (const T*)src, n, chunk, pass,
-                       kscale, (const int32_t*)hist, (const int32_t*)totals, dst);
+    hipLaunchKernelGGL(radix_scatter_kernel<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, in, n, chunk, pass, kscale,
+                       (const int32_t*)hist, (const int32_t*)totals, out);
     KDE_CHECK_LAUNCH();
-    T* t = src;
-    src = dst;
-    dst = t;
   }
+  T* src = bufs[(kSortPasses - 1) & 1];
   if constexpr (std::is_same<T, double>::value) {
     hipLaunchKernelGGL(radix_fixup_kernel, dim3(unsigned(ceil_div(n, kBlock))), dim3(kBlock), 0, s, src, n, kscale);
     KDE_CHECK_LAUNCH();
