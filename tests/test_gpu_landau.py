@@ -46,6 +46,35 @@ def test_standard_session_matches_oracle(gpu):
         s.close()
 
 
+@pytest.mark.parametrize("M", [2, 4, 512, 2048])
+def test_standard_session_grid_sizes(gpu, M):
+    """The session's field solve over the power-of-two grids it accepts,
+    from two nodes to 2048 (several cells per thread of the solver's
+    workgroup), against the oracle's DFT solve, after two steps; grid values
+    normwise, since small grids and sparse cells hold zeros."""
+    e = W.landau_ensemble(12, n=3000, M=M)
+    x0, v0 = e.x, e.v(0.3)
+    steps, dt = 2, 0.05
+    announce("standard session grid size", M)
+    s = gpu.Session(to_gpu(x0), to_gpu(v0), e.L, e.M, dt, method=gpu.KDE_PIC_STANDARD, history=steps)
+    try:
+        x, v = x0.copy(), v0.copy()
+        for _ in range(steps):
+            x, v, rho, E = landau.field_step_standard(x, v, e.L, e.M, dt)
+        s.step(steps)
+        gE = host(s.read(gpu.KDE_SESSION_E))
+        scale = max(np.abs(E).max(), (e.L / M) * np.abs(1.0 - e.L * rho).max())  # M = 2: E is 0
+        assert np.max(np.abs(gE - E)) <= 1e-11 * scale
+        grho = host(s.read(gpu.KDE_SESSION_RHO))
+        assert np.max(np.abs(grho - rho)) <= 1e-11 * np.abs(rho).max()
+        gx, gv = host(s.read(gpu.KDE_SESSION_X)), host(s.read(gpu.KDE_SESSION_V))
+        d = np.abs(gx - x)
+        assert np.max(np.minimum(d, e.L - d)) <= 1e-11 * e.L
+        assert np.max(np.abs(gv - v)) <= 1e-11 * np.abs(v).max()
+    finally:
+        s.close()
+
+
 def test_kde_session_energy_history_matches_oracle(gpu):
     """The KDE session's recorded energies equal the oracle's field energy of
     the fields its steps compute (history shorter than the run: later steps
