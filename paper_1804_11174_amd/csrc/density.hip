@@ -44,9 +44,10 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(const T* __restrict__ x
 }
 
 // S adjacent lanes per particle (S = 1, 2, 4 or 8, from gather_split), lane
-// j summing the nodes k in [j M / S, (j + 1) M / S) in order; the S partial
-// sums are combined by an xor butterfly, a fixed pairwise tree whose result
-// every lane of the group holds. Dynamic LDS: the node table (2 M values of
+// j summing the nodes k = j, j + S, j + 2S, ... in order (interleaved, so
+// the S lanes read neighbouring LDS words instead of one bank); the S
+// partial sums are combined by an xor butterfly, a fixed pairwise tree
+// whose result every lane of the group holds. Dynamic LDS: the node table (2 M values of
 // T) and the field (M values of T). In the float form the loop runs over
 // k = g - g0, so the table read is a broadcast and the field read is per
 // lane.
@@ -72,7 +73,6 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   const int64_t i = gid / S;
   if (i >= n) return;  // a particle's S lanes leave together
   const int j = int(gid % S);
-  const int k0 = (j * M) / S, k1 = ((j + 1) * M) / S;
   const double xi = double(x[i]);
   const double xw = xi - L * floor(xi / L);
   PGeo<T> gp;
@@ -82,15 +82,16 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   const double w = (L / M) / (L * i0e_f64(kk));
   SumOf<T> acc;
   if constexpr (std::is_same<T, float>::value) {
-    int g = gp.g0 + k0;
+    int g = gp.g0 + j;
     if (g >= M) g -= M;
-    for (int k = k0; k < k1; ++k) {
+    for (int k = j; k < M; k += S) {
       const T s = ts[k] * gp.cb - tc[k] * gp.sb;
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
-      g = (g + 1 == M) ? 0 : g + 1;
+      g += S;
+      if (g >= M) g -= M;
     }
   } else if (__all(A >= T(-2.0 * kNearKappa))) {
-    for (int g = k0; g < k1; ++g) {
+    for (int g = j; g < M; g += S) {
       const T s = node_s(gp, g, M, ts, tc);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
     }
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
     // sharp kernels in the wave: near nodes take the exact separation
     const double dx = L / double(M);
     const bool sharp = A < T(-2.0 * kNearKappa);
-    for (int g = k0; g < k1; ++g) {
+    for (int g = j; g < M; g += S) {
       T s = node_s(gp, g, M, ts, tc);
       if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
@@ -106,7 +107,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   } else {
     const double dx = L / double(M);
     const bool sharp = A < T(-2.0 * kNearKappa);
-    for (int g = k0; g < k1; ++g) {
+    for (int g = j; g < M; g += S) {
       T s = node_s(gp, g, M, ts, tc);
       if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));

@@ -153,8 +153,8 @@ def test_gather_and_adjointness(gpu, dtype):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_gather_grid_and_particle_counts(gpu, M, n, dtype):
     """Gather at ragged particle counts and grid sizes that give every node
-    split the kernel uses (1, 2, 4 or 8 lanes per particle, each over a
-    contiguous range of nodes), against the oracle, per-particle widths."""
+    split the kernel uses (1, 2, 4 or 8 lanes per particle, lane j over the
+    nodes j, j + S, ...), against the oracle, per-particle widths."""
     L = 2.0
     rng = np.random.default_rng([21, M, n])
     x = npx(L * rng.random(n), dtype)
