@@ -1,7 +1,7 @@
 // Fixed-order column sums shared by the one-set launchers and the batched
 // engine, so that both produce bitwise identical results.
 //
-// For in[rows][cols]: level 1 sums each block of 256 consecutive rows,
+// For in[rows][cols]: level 1 sums each block of 128 consecutive rows,
 // rows ascending, into L1[b][c]; level 2 sums the level-1 rows, b
 // ascending, and applies a scale: out[c] = scale * sum_b L1[b][c].
 #pragma once
@@ -10,7 +10,7 @@
 
 namespace kde {
 
-constexpr int kSumRows = 256;
+constexpr int kSumRows = 128;  // rows per level-1 block: the length of one column's add chain
 
 // Rows are loaded kLoadAhead at a time and then added one by one, in
 // ascending order: the same sum as the plain loop, with the loads of a
