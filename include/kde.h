@@ -387,7 +387,11 @@ kde_status kde_batch_destroy(kde_batch* b);
  * Units follow the Birdsall convention (plasma frequency 1). Creation runs
  * the CV scan at t = 0 (h_opt = h_target at its optimum, p_th = 2 thr).
  * Every step waits once for the A^2 value (one 8-byte device-to-host copy)
- * and, when the rule fires, for the scan's argmin.
+ * and, when the rule fires, for the scan's argmin. The part of a step that
+ * is the same every step (for KDE: deposit through the A^2 copy; for
+ * standard PIC: the whole step) is captured into a HIP graph on the
+ * session's stream at the first step and replayed by one graph launch per
+ * step; its kernels are not seen by kde_timing.
  *
  * method KDE_PIC_STANDARD runs the same cycle as standard PIC, the
  * comparison method of Sec. III: linear ("cloud-in-cell") weighting for the

@@ -296,8 +296,12 @@ __global__ void ad_finish_kernel(const double* __restrict__ sum, int64_t n, doub
 
 size_t poisson_max_m() { return kMaxPoissonM; }
 
+// W of the current field into history slot *step (when the slot exists),
+// then *step + 1: the slot index lives on the device, so a captured step
+// replays with the same arguments every time.
 __global__ void __launch_bounds__(kBlock) field_energy_kernel(const double* __restrict__ E, int M, double half_dx,
-                                                             double* __restrict__ out) {
+                                                             double* __restrict__ energy, int64_t history,
+                                                             int64_t* __restrict__ step) {
   __shared__ double red[kBlock / 64];
   double s = 0.0;
   for (int g = threadIdx.x; g < M; g += kBlock) s = fma(E[g], E[g], s);
@@ -307,12 +311,25 @@ __global__ void __launch_bounds__(kBlock) field_energy_kernel(const double* __re
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) t += red[w];
-    *out = half_dx * t;
+    const int64_t st = *step;
+    if (st >= 0 && st < history) energy[st] = half_dx * t;
+    *step = st + 1;
   }
 }
 
-kde_status launch_field_energy(const double* E, int M, double L, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(field_energy_kernel, dim3(1), dim3(kBlock), 0, s, E, M, 0.5 * (L / M), out);
+__global__ void set_step_kernel(int64_t* __restrict__ step, int64_t value) {
+  if (threadIdx.x == 0) *step = value;
+}
+
+kde_status launch_field_energy(const double* E, int M, double L, double* energy, int64_t history, int64_t* step,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(field_energy_kernel, dim3(1), dim3(kBlock), 0, s, E, M, 0.5 * (L / M), energy, history, step);
+  KDE_CHECK_LAUNCH();
+  return KDE_OK;
+}
+
+kde_status launch_set_step(int64_t* step, int64_t value, hipStream_t s) {
+  hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, s, step, value);
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }

@@ -44,7 +44,9 @@ kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const d
                         double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
                         hipStream_t s);
 kde_status launch_poisson_field(const double* rho, int M, double L, double* E, hipStream_t s);
-kde_status launch_field_energy(const double* E, int M, double L, double* out, hipStream_t s);
+kde_status launch_field_energy(const double* E, int M, double L, double* energy, int64_t history, int64_t* step,
+                               hipStream_t s);
+kde_status launch_set_step(int64_t* step, int64_t value, hipStream_t s);
 template <typename T>
 kde_status launch_push(T* x, T* v, const T* E_i, int64_t n, double dt, double L, hipStream_t s);
 template <typename T>
@@ -115,12 +117,16 @@ struct kde_session {
   void *x = nullptr, *v = nullptr, *kap = nullptr, *Ei = nullptr;
   double *rho = nullptr, *E = nullptr, *pilot = nullptr, *cv = nullptr, *a2 = nullptr, *energy = nullptr;
   int32_t* argmin = nullptr;
+  int64_t* step_dev = nullptr;  // history slot of the next field energy
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // pinned host mailbox: [a2, argmin]
   double* mail = nullptr;
+  // the step's fixed launch sequence, captured at the first step
+  hipGraphExec_t fixed = nullptr;
   SessionState st;
   ~kde_session() {
+    if (fixed) (void)hipGraphExecDestroy(fixed);
     if (mail) (void)hipHostFree(mail);
   }
 };
@@ -151,12 +157,14 @@ static size_t carve_session(Carver& c, const kde_pic_params& p, kde_session* s) 
   double* a2 = c.take<double>(1);
   int32_t* am = c.take<int32_t>(1);
   double* energy = c.take<double>(size_t(std::max(p.history, 1)));
+  int64_t* stepd = c.take<int64_t>(1);
   const size_t wsb = session_ws_bytes(p);
   void* ws = c.take<char>(wsb);
   if (s) {
     s->x = x; s->v = v; s->kap = kap; s->Ei = Ei;
     s->rho = rho; s->E = E; s->pilot = pilot; s->cv = cv; s->a2 = a2; s->argmin = am;
     s->energy = energy;
+    s->step_dev = stepd;
     s->ws = ws; s->ws_bytes = wsb;
   }
   return c.used;
@@ -210,9 +218,7 @@ static kde_status session_widths(kde_session* s, double kstar) {
 }
 
 static kde_status record_energy(kde_session* s) {
-  if (s->st.step < s->prm.history)
-    KDE_RETURN_IF(launch_field_energy(s->E, s->prm.M, s->prm.L, s->energy + s->st.step, s->s));
-  return KDE_OK;
+  return launch_field_energy(s->E, s->prm.M, s->prm.L, s->energy, s->prm.history, s->step_dev, s->s);
 }
 
 static kde_status push_any(kde_session* s) {
@@ -224,36 +230,66 @@ static kde_status push_any(kde_session* s) {
                             p.N, p.dt, p.L, s->s);
 }
 
-// Standard PIC: linear weighting both ways, no width update; enqueue only.
-static kde_status standard_step_once(kde_session* s) {
+// The fixed part of a step, the same launches with the same arguments every
+// step. Standard PIC (linear weighting both ways, no width update): the
+// whole step. KDE: deposit with kappa_i, field, energy, gather, push and
+// the A^2 statistic, copied to the host mailbox.
+static kde_status enqueue_fixed(kde_session* s) {
   const kde_pic_params& p = s->prm;
-  const double dx = p.L / double(p.M);
-  KDE_RETURN_IF(deposit(&s->tdom, p.N, s->x, nullptr, dx, s->rho, s->ws, s->ws_bytes, s->s));
+  if (standard(p)) {
+    const double dx = p.L / double(p.M);
+    KDE_RETURN_IF(deposit(&s->tdom, p.N, s->x, nullptr, dx, s->rho, s->ws, s->ws_bytes, s->s));
+    KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
+    KDE_RETURN_IF(record_energy(s));
+    KDE_RETURN_IF(gather(&s->tdom, p.N, s->x, nullptr, dx, s->E, s->Ei, s->s));
+    return push_any(s);
+  }
+  KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s));
   KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
   KDE_RETURN_IF(record_energy(s));
-  KDE_RETURN_IF(gather(&s->tdom, p.N, s->x, nullptr, dx, s->E, s->Ei, s->s));
+  KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s));
   KDE_RETURN_IF(push_any(s));
-  s->st.step += 1;
+  if (p.prec == KDE_F64)
+    KDE_RETURN_IF(launch_ad_statistic<double>(static_cast<const double*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
+  else
+    KDE_RETURN_IF(launch_ad_statistic<float>(static_cast<const float*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(s->mail, s->a2, sizeof(double), hipMemcpyDeviceToHost, s->s));
+  return KDE_OK;
+}
+
+// Enqueue the fixed part: captured into a graph at the first step (all its
+// pointers are the session's own and its launch shapes depend on N and M
+// alone), then one graph launch per step instead of some twenty kernel
+// launches.
+static kde_status run_fixed(kde_session* s) {
+  if (!s->fixed) {
+    KDE_TRY_HIP(hipStreamBeginCapture(s->s, hipStreamCaptureModeRelaxed));
+    const kde_status st = enqueue_fixed(s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->s, &g);
+    if (st != KDE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    KDE_TRY_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&s->fixed, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      s->fixed = nullptr;
+      KDE_TRY_HIP(ei);
+    }
+  }
+  KDE_TRY_HIP(hipGraphLaunch(s->fixed, s->s));
   return KDE_OK;
 }
 
 static kde_status session_step_once(kde_session* s) {
   const kde_pic_params& p = s->prm;
-  if (standard(p)) return standard_step_once(s);
-  KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s));
-  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
-  KDE_RETURN_IF(record_energy(s));
-  KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s));
-  if (p.prec == KDE_F64) {
-    KDE_RETURN_IF(launch_push<double>(static_cast<double*>(s->x), static_cast<double*>(s->v),
-                                      static_cast<const double*>(s->Ei), p.N, p.dt, p.L, s->s));
-    KDE_RETURN_IF(launch_ad_statistic<double>(static_cast<const double*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
-  } else {
-    KDE_RETURN_IF(launch_push<float>(static_cast<float*>(s->x), static_cast<float*>(s->v),
-                                     static_cast<const float*>(s->Ei), p.N, p.dt, p.L, s->s));
-    KDE_RETURN_IF(launch_ad_statistic<float>(static_cast<const float*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
+  KDE_RETURN_IF(run_fixed(s));
+  if (standard(p)) {  // enqueue only: standard steps never wait on the host
+    s->st.step += 1;
+    return KDE_OK;
   }
-  KDE_TRY_HIP(hipMemcpyAsync(s->mail, s->a2, sizeof(double), hipMemcpyDeviceToHost, s->s));
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
   SessionState& st = s->st;
   st.last_a2 = s->mail[0];
@@ -317,6 +353,7 @@ kde_status kde_session_create(const kde_pic_params* p, const void* x0, const voi
   const size_t es = elem_size(p->prec);
   KDE_TRY_HIP(hipMemcpyAsync(s->x, x0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(s->v, v0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
+  KDE_RETURN_IF(launch_set_step(s->step_dev, 0, s->s));
   if (standard(*p)) {
     KDE_TRY_HIP(hipStreamSynchronize(s->s));
     *out_h = s.release();
@@ -440,6 +477,7 @@ kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes)
   if (s->prm.history > 0)
     KDE_TRY_HIP(hipMemcpyAsync(s->energy, p + 3 * pn, size_t(s->prm.history) * sizeof(double), hipMemcpyHostToDevice,
                                s->s));
+  KDE_RETURN_IF(launch_set_step(s->step_dev, s->st.step, s->s));
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
   return KDE_OK;
 }

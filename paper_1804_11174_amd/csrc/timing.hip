@@ -25,6 +25,10 @@ Slot g_slots[KDE_KERNEL_COUNT];
 TimedLaunch::TimedLaunch(int id, hipStream_t s) : id_(id), s_(s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on || id < 0 || id >= KDE_KERNEL_COUNT) return;
+  // a launch being captured into a graph is not timed (its events would be
+  // recorded into the graph, not now)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&start_) != hipSuccess) return;
   if (hipEventCreate(&stop_) != hipSuccess) {
     (void)hipEventDestroy(start_);
