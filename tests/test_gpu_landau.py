@@ -30,7 +30,10 @@ def test_standard_session_matches_oracle(gpu):
         for _ in range(steps):
             x, v, rho, E = landau.field_step_standard(x, v, e.L, e.M, dt)
             energies.append(landau.field_energy(E, e.L))
-        s.step(steps)
+            # one replay of the session's captured step, then an eager read
+            s.step(1)
+            gE = host(s.read(gpu.KDE_SESSION_E))
+            assert np.max(np.abs(gE - E)) <= 1e-11 * np.abs(E).max()
         gx, gv = host(s.read(gpu.KDE_SESSION_X)), host(s.read(gpu.KDE_SESSION_V))
         assert np.max(np.abs(gx - x)) <= 1e-11 * e.L
         assert np.max(np.abs(gv - v)) <= 1e-11 * np.abs(v).max()
