@@ -7,7 +7,8 @@ KDE also the root with the kernel's response rho_1(kappa*)^2 at the mean
 kappa* of the runs (both from the oracle), with the t statistic of each
 mean's error against the plain theory.
 
-    python tests/landau_table.py gpurun_out/bench_landau.json
+    python bench.py --form landau --json-out landau.json
+    python tests/landau_table.py landau.json
 """
 from __future__ import annotations
 
