@@ -3,7 +3,7 @@
 // set's kappa*, adaptive widths, adaptive deposit) in one hipGraph launch.
 //
 // The graph holds one kernel per phase over the work units of every set
-// -- (set), (set, sort block), (set, tile pair, concentration group),
+// -- (set), (set, sort block), (set, pair slot, concentration group),
 // (set, particle chunk) or (set, row block) -- with the sets ordered by
 // decreasing CV cost so that the long pair-sum work starts first. The pair
 // phase runs one workgroup per unit; the light phases run about as many
@@ -47,12 +47,12 @@ struct SetDev {
   const void* x;
   double L;
   int M, cells, chunk, sblocks;  // sblocks: blocks of the cell sort
-  int gsize, groups;              // pair units: concentrations per unit, units per tile pair
+  int gsize, groups;              // pair units: concentrations per unit, units per slot
   int64_t schunk;                 // particles per sort block
-  int64_t units, g_cv, chunks, g_dep, blocks, g_ad;  // units: tile pairs
+  int64_t slots, g_cv, chunks, g_dep, blocks, g_ad;  // slots: rows of CV partial sums (cv_slots)
   int32_t* hist;      // cells x sblocks, cell-major
   void* packed;
-  double* partials;   // units x 2B
+  double* partials;   // slots x 2B
   double* cv_l1;      // g_cv x 2B
   double* dep_part;   // chunks x M (pilot, then adaptive)
   double* dep_l1;     // g_dep x M
@@ -169,13 +169,13 @@ __global__ void __launch_bounds__(kBlock) batch_sort_scatter_kernel(BatchArgs a)
   }
 }
 
-// Pair units [u_lo, u_hi) of the flattened list (one pass-size bucket),
-// one workgroup per unit. The list follows the cost order of the sets, and
+// Pair units [u_lo, u_hi) of the flattened list (one pass-size bucket), a
+// unit being a (set, slot, concentration group), one workgroup per unit. The list follows the cost order of the sets, and
 // workgroups are dispatched in index order, so the largest sets start
 // first without a work counter; a loop over claimed units would keep more
 // registers live and lower the occupancy of this, the heaviest phase.
 template <typename T, int BC>
-__global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvConsts<T> K, int64_t u_lo, int64_t u_hi) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PairWaves<T, BC>::value))) batch_pairs_kernel(BatchArgs a, CvConsts<T> K, int64_t u_lo, int64_t u_hi) {
   using P = typename Packed<T>::type;
   __shared__ CvSmem<T, BC> sm;
   const int64_t* pf = a.prefix + PF_PAIRS * (a.nsets + 1);
@@ -186,12 +186,10 @@ __global__ void __launch_bounds__(kBlock) batch_pairs_kernel(BatchArgs a, CvCons
     const SetDev& s = a.sets[si];
     const int64_t q = u - uni64(pf[si]);
     const int groups = uni32(s.groups), gsize = uni32(s.gsize);
-    const int64_t p = q / groups;
-    const int b_lo = int(q - p * groups) * gsize;
-    int I, J;
-    tri_decode(p, I, J);
-    cv_tile_pair<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), uni32(s.cells), s.L, I, J, K,
-                        b_lo, min(K.B, b_lo + gsize), uni_ptr(s.partials) + p * 2 * K.B, sm);
+    const int64_t r = q / groups;
+    const int b_lo = int(q - r * groups) * gsize;
+    cv_slot<T, BC>(uni_ptr(static_cast<const P*>(s.packed)), uni64(s.n_cv), uni32(s.cells), s.L, r, uni64(s.slots),
+                   K, b_lo, min(K.B, b_lo + gsize), uni_ptr(s.partials) + r * 2 * K.B, sm);
   }
 }
 
@@ -214,7 +212,7 @@ __global__ void __launch_bounds__(kBlock) batch_level1_kernel(BatchArgs a, int p
     int64_t rows;
     int cols;
     if (SRC == SRC_CV) {
-      in = s.partials; l1 = s.cv_l1; rows = s.units; cols = 2 * a.B;
+      in = s.partials; l1 = s.cv_l1; rows = s.slots; cols = 2 * a.B;
     } else if (SRC == SRC_DEP) {
       in = s.dep_part; l1 = s.dep_l1; rows = s.chunks; cols = s.M;
     } else {
@@ -346,12 +344,11 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.sblocks = sp.blocks;
     d.schunk = sp.chunk;
     d.chunk = deposit_chunk(in.N);
-    const int64_t ntiles = ceil_div(d.n_cv, kCvTile);
-    d.units = ntiles * (ntiles + 1) / 2;
+    d.slots = cv_slots(d.n_cv);
     const PairTuning tp = tuned_pass(b.prec, d.n_cv);
     d.gsize = pair_group_size(tp, b.B);
     d.groups = pair_groups(tp, b.B);
-    d.g_cv = ceil_div(d.units, kSumRows);
+    d.g_cv = ceil_div(d.slots, kSumRows);
     d.chunks = ceil_div(in.N, d.chunk);
     d.g_dep = ceil_div(d.chunks, kSumRows);
     d.blocks = ceil_div(in.N, kBlock);
@@ -359,7 +356,7 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.hist = c.take<int32_t>(size_t(d.cells) * size_t(d.sblocks));
     d.packed = b.prec == KDE_F64 ? static_cast<void*>(c.take<double>(Packed<double>::per_particle * size_t(d.n_cv)))
                                  : static_cast<void*>(c.take<uint32_t>(size_t(d.n_cv)));
-    d.partials = c.take<double>(size_t(d.units) * 2 * b.B);
+    d.partials = c.take<double>(size_t(d.slots) * 2 * b.B);
     d.cv_l1 = c.take<double>(size_t(d.g_cv) * 2 * b.B);
     d.dep_part = c.take<double>(size_t(d.chunks) * in.M);
     d.dep_l1 = c.take<double>(size_t(d.g_dep) * in.M);
@@ -373,7 +370,7 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.kstar = c.take<double>(1);
     d.kstar_user = in.kappa_star;
     if (descs) (*descs)[r] = d;
-    const int64_t per[PF_COUNT] = {d.units * d.groups, d.g_cv, d.chunks, d.g_dep, d.blocks, d.g_ad, int64_t(d.sblocks)};
+    const int64_t per[PF_COUNT] = {d.slots * d.groups, d.g_cv, d.chunks, d.g_dep, d.blocks, d.g_ad, int64_t(d.sblocks)};
     for (int k = 0; k < PF_COUNT; ++k) {
       if (prefix) (*prefix)[size_t(k) * (ns + 1) + r] = acc[k];
       acc[k] += per[k];
@@ -572,8 +569,7 @@ kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int
   for (size_t k = 0; k + 1 < im.bucket_begin.size(); ++k) {
     int64_t units = 0;
     for (int r = im.bucket_begin[k]; r < im.bucket_begin[k + 1]; ++r) {
-      const int64_t nt = ceil_div(ncv(im.order[r]), kCvTile);
-      units += nt * (nt + 1) / 2 * pair_groups(tuned_pass(prec, ncv(im.order[r])), B);
+      units += cv_slots(ncv(im.order[r])) * pair_groups(tuned_pass(prec, ncv(im.order[r])), B);
       if (units > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "too many CV pair units for one launch");
     }
   }

@@ -87,6 +87,22 @@ static kde_status check_kappa(const kde_domain* dom, double k, const char* what)
   return KDE_OK;
 }
 
+kde_status check_cv_args(const kde_domain* dom, int64_t N, const void* x, int B, const double* kappas_h,
+                         const double* cv) {
+  KDE_RETURN_IF(check_domain(dom, false));
+  KDE_RETURN_IF(check_n(N, 2));
+  if (B < 1 || B > KDE_MAX_KAPPAS) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d] (got %d)", KDE_MAX_KAPPAS, B);
+  if (!x || !cv) return fail(KDE_E_INVALID_ARG, "x and cv must not be NULL");
+  if (!kappas_h) return fail(KDE_E_INVALID_ARG, "kappas_h is NULL");
+  for (int b = 0; b < B; ++b) {
+    KDE_RETURN_IF(check_kappa(dom, kappas_h[b], "every kappa"));
+    if (dom->shape == KDE_SHAPE_VONMISES && kappas_h[b] > KDE_MAX_CV_KAPPA)
+      return fail(KDE_E_INVALID_ARG, "every kappa must be <= %g (got %g)", KDE_MAX_CV_KAPPA, kappas_h[b]);
+    if (b > 0 && !(kappas_h[b] > kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending (index %d)", b);
+  }
+  return KDE_OK;
+}
+
 }  // namespace kde
 
 using namespace kde;
@@ -176,17 +192,7 @@ kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h, int32_t* grou
 kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t B, const double* kappas_h,
                        double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes, void* stream) {
   clear_error();
-  KDE_RETURN_IF(check_domain(dom, false));
-  KDE_RETURN_IF(check_n(N, 2));
-  if (B < 1 || B > KDE_MAX_KAPPAS) return fail(KDE_E_INVALID_ARG, "B must lie in [1, %d] (got %d)", KDE_MAX_KAPPAS, B);
-  if (!x || !cv) return fail(KDE_E_INVALID_ARG, "x and cv must not be NULL");
-  if (!kappas_h) return fail(KDE_E_INVALID_ARG, "kappas_h is NULL");
-  for (int b = 0; b < B; ++b) {
-    KDE_RETURN_IF(check_kappa(dom, kappas_h[b], "every kappa"));
-    if (dom->shape == KDE_SHAPE_VONMISES && kappas_h[b] > KDE_MAX_CV_KAPPA)
-      return fail(KDE_E_INVALID_ARG, "every kappa must be <= %g (got %g)", KDE_MAX_CV_KAPPA, kappas_h[b]);
-    if (b > 0 && !(kappas_h[b] > kappas_h[b - 1])) return fail(KDE_E_INVALID_ARG, "kappas must be strictly ascending (index %d)", b);
-  }
+  KDE_RETURN_IF(check_cv_args(dom, N, x, B, kappas_h, cv));
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, cv_workspace_bytes(N, B, dom->prec)));
   return cv_scan(dom, N, x, B, kappas_h, cv, sums, argmin, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }

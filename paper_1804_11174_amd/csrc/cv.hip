@@ -17,12 +17,16 @@
 // 1/(L I0e(kappa)^2) are applied once, in double, by the finalize kernel.
 //
 // Work decomposition: particles (sorted by angular cell) are cut into tiles
-// of 256; one workgroup takes one tile pair (I <= J), one i-particle per
-// thread against the J tile staged in LDS (every lane reads the same j:
-// an LDS broadcast). Concentrations are processed in chunks of 16, each
-// with per-thread accumulators; at the end of a chunk the 256 per-thread
-// sums are reduced in double in a fixed order and the workgroup writes its
-// 2B partial sums to its own slot. No floating-point atomics are used.
+// of 256. A tile pair (I <= J) is taken one i-particle per thread against
+// the J tile staged in LDS (every lane reads the same j: an LDS
+// broadcast). Concentrations are processed in chunks of up to 16, each with
+// per-thread accumulators; at the end of a chunk the 256 per-thread sums
+// are reduced in double in a fixed order into the workgroup's running
+// sums. A workgroup owns one slot: the tile pairs k = slot, slot + S, ...
+// of the list ordered by circular tile distance (pair_decode), S =
+// min(tile pairs, 32768), and writes the slot's 2B sums to its own row, so
+// the partial sums take at most 32768 x 2B doubles at any N. No
+// floating-point atomics are used.
 //
 // Terms whose exponent is below -70 are not evaluated: each is below
 // e^-70 (4e-31) times the largest term of its sum (the pair at distance 0
@@ -42,15 +46,15 @@
 
 namespace kde {
 
-// Triangle shape: one workgroup per tile pair.
+// Triangle shape: one workgroup per slot (cv_slots(n) of them), compiled
+// for eight waves per SIMD, which the tile-pair body fits on its own (the
+// loop over a slot's tile pairs otherwise keeps more values live).
 template <typename T, int BC>
-__global__ void __launch_bounds__(kBlock) tri_pairs_kernel(const typename TriPacked<T>::type* __restrict__ packed,
-                                                          int64_t n, int cells, TriConsts<T> K,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) tri_pairs_kernel(const typename TriPacked<T>::type* __restrict__ packed,
+                                                          int64_t n, int cells, int64_t nslots, TriConsts<T> K,
                                                           double* __restrict__ partials) {
   __shared__ TriSmem<T, BC> sm;
-  int I, J;
-  tri_decode(int64_t(blockIdx.x), I, J);
-  tri_tile_pair<T, BC>(packed, n, cells, I, J, K, partials + int64_t(blockIdx.x) * 2 * K.B, sm);
+  tri_slot<T, BC>(packed, n, cells, int64_t(blockIdx.x), nslots, K, partials + int64_t(blockIdx.x) * 2 * K.B, sm);
 }
 
 // raw[0..B): 6 h Tbar sums, raw[B..2B): h T sums; widths h_b. One block.
@@ -83,18 +87,16 @@ __global__ void __launch_bounds__(KDE_MAX_KAPPAS) tri_finalize_kernel(const doub
   }
 }
 
-// Block (tile pair p, concentration group g) with p = blockIdx.x / groups.
+// Block (slot r, concentration group g) with r = blockIdx.x / groups.
 template <typename T, int BC>
-__global__ void __launch_bounds__(kBlock) cv_pairs_kernel(const typename Packed<T>::type* __restrict__ packed,
-                                                         int64_t n, int cells, double L, int groups, int gsize,
-                                                         CvConsts<T> K, double* __restrict__ partials) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PairWaves<T, BC>::value))) cv_pairs_kernel(const typename Packed<T>::type* __restrict__ packed,
+                                                         int64_t n, int cells, double L, int64_t nslots, int groups,
+                                                         int gsize, CvConsts<T> K, double* __restrict__ partials) {
   __shared__ CvSmem<T, BC> sm;
-  const int64_t p = int64_t(blockIdx.x) / groups;
-  const int g = int(int64_t(blockIdx.x) - p * groups);
-  int I, J;
-  tri_decode(p, I, J);
+  const int64_t r = int64_t(blockIdx.x) / groups;
+  const int g = int(int64_t(blockIdx.x) - r * groups);
   const int b_lo = g * gsize;
-  cv_tile_pair<T, BC>(packed, n, cells, L, I, J, K, b_lo, min(K.B, b_lo + gsize), partials + p * 2 * K.B, sm);
+  cv_slot<T, BC>(packed, n, cells, L, r, nslots, K, b_lo, min(K.B, b_lo + gsize), partials + r * 2 * K.B, sm);
 }
 
 // raw[0..B): Kbar sums, raw[B..2B): K sums (unnormalised); one block.
@@ -150,15 +152,13 @@ kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* 
 
 struct CvPlan {
   SortPlan sort;
-  int ntiles;
-  int64_t units;
+  int64_t slots;  // rows of partial sums
 };
 
 static CvPlan make_cv_plan(int64_t n) {
   CvPlan p;
   p.sort = make_sort_plan(n);
-  p.ntiles = int(ceil_div(n, kCvTile));
-  p.units = int64_t(p.ntiles) * (p.ntiles + 1) / 2;
+  p.slots = cv_slots(n);
   return p;
 }
 
@@ -175,8 +175,8 @@ static CvBuffers carve_cv(Carver& cv, const CvPlan& p, int64_t n, int B, int pre
   b.hist = cv.take<int32_t>(size_t(p.sort.cells) * p.sort.blocks);
   b.packed = prec == KDE_F64 ? static_cast<void*>(cv.take<double>(Packed<double>::per_particle * size_t(n)))
                              : static_cast<void*>(cv.take<uint32_t>(size_t(n)));
-  b.partials = cv.take<double>(size_t(p.units) * 2 * B);
-  b.colsum = cv.take<double>(column_sum_scratch(p.units, 2 * B) / sizeof(double) + 1);
+  b.partials = cv.take<double>(size_t(p.slots) * 2 * B);
+  b.colsum = cv.take<double>(column_sum_scratch(p.slots, 2 * B) / sizeof(double) + 1);
   b.raw = cv.take<double>(2 * size_t(B));
   return b;
 }
@@ -202,27 +202,26 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
   CvConsts<T> K = make_consts<T>(kappas, B);
   const PairTuning tp = tuned_pass(dom->prec, n);
   const int groups = pair_groups(tp, B), gsize = pair_group_size(tp, B);
-  if (p.units * groups > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "N too large for one CV launch");
   {
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
-    const dim3 grid{unsigned(p.units * groups)}, block{unsigned(kBlock)};
+    const dim3 grid{unsigned(p.slots * groups)}, block{unsigned(kBlock)};
     switch (tp.chunk) {
       case 4:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, groups, gsize, K,
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
                            buf.partials);
         break;
       case 8:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, groups, gsize, K,
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
                            buf.partials);
         break;
       default:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, groups, gsize, K,
+        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
                            buf.partials);
         break;
     }
   }
   KDE_CHECK_LAUNCH();
-  KDE_RETURN_IF(launch_column_sum(buf.partials, p.units, 2 * B, buf.colsum, buf.raw, s));
+  KDE_RETURN_IF(launch_column_sum(buf.partials, p.slots, 2 * B, buf.colsum, buf.raw, s));
   KappaList kl{};
   for (int b = 0; b < B; ++b) kl.k[b] = kappas[b];
   hipLaunchKernelGGL(cv_finalize_kernel, dim3(1), dim3(KDE_MAX_KAPPAS), 0, s, (const double*)buf.raw, B,
@@ -245,14 +244,13 @@ static kde_status run_cv_tri(const kde_domain* dom, int64_t n, const T* x, int B
   P* packed = static_cast<P*>(buf.packed);
   KDE_RETURN_IF((launch_pack_sorted_as<T, P>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s)));
   const TriConsts<T> K = make_tri_consts<T>(widths, B, dom->L);
-  if (p.units > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "N too large for one CV launch");
   {
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
-    hipLaunchKernelGGL((tri_pairs_kernel<T, kTriPass>), dim3(unsigned(p.units)), dim3(kBlock), 0, s,
-                       (const P*)packed, n, p.sort.cells, K, buf.partials);
+    hipLaunchKernelGGL((tri_pairs_kernel<T, kTriPass>), dim3(unsigned(p.slots)), dim3(kBlock), 0, s,
+                       (const P*)packed, n, p.sort.cells, p.slots, K, buf.partials);
   }
   KDE_CHECK_LAUNCH();
-  KDE_RETURN_IF(launch_column_sum(buf.partials, p.units, 2 * B, buf.colsum, buf.raw, s));
+  KDE_RETURN_IF(launch_column_sum(buf.partials, p.slots, 2 * B, buf.colsum, buf.raw, s));
   KappaList kl{};
   for (int b = 0; b < B; ++b) kl.k[b] = widths[b];
   hipLaunchKernelGGL(tri_finalize_kernel, dim3(1), dim3(KDE_MAX_KAPPAS), 0, s, (const double*)buf.raw, B, double(n),

@@ -27,12 +27,16 @@
 // 1/(L I0e(kappa)^2) are applied once, in double, by the finalize kernel.
 //
 // Work decomposition: particles (sorted by angular cell) are cut into tiles
-// of 256; one workgroup takes one tile pair (I <= J), one i-particle per
-// thread against the J tile staged in LDS (every lane reads the same j:
-// an LDS broadcast). Concentrations are processed in chunks of 16, each
-// with per-thread accumulators; at the end of a chunk the 256 per-thread
-// sums are reduced in double in a fixed order and the workgroup writes its
-// 2B partial sums to its own slot. No floating-point atomics are used.
+// of 256. A tile pair (I <= J) is taken one i-particle per thread against
+// the J tile staged in LDS (every lane reads the same j: an LDS
+// broadcast). Concentrations are processed in chunks of up to 16, each with
+// per-thread accumulators; at the end of a chunk the 256 per-thread sums
+// are reduced in double in a fixed order into the workgroup's running
+// sums. A workgroup owns one slot: the tile pairs k = slot, slot + S, ...
+// of the list ordered by circular tile distance (pair_decode), S =
+// min(tile pairs, 32768), and writes the slot's 2B sums to its own row, so
+// the partial sums take at most 32768 x 2B doubles at any N. No
+// floating-point atomics are used.
 //
 // Terms whose exponent is below -70 are not evaluated: each is below
 // e^-70 (4e-31) times the largest term of its sum (the pair at distance 0
@@ -119,13 +123,15 @@ struct I0eBounds<float> {
 };
 
 // Position of packed particle i as a fraction of the period, from its
-// packed form: the half-angle vector (cos(pi f), sin(pi f)) with
-// f in [0, 1], the double position fraction, or the 32-bit phase.
-__device__ __forceinline__ double packed_frac(const double* __restrict__ packed, int64_t i) {
-  return atan2(packed[3 * i + 1], packed[3 * i]) * 0.31830988618379067;  // 1/pi
+// packed form: the wrapped position w (third component of the double
+// form) times 1/L, the double position fraction, or the 32-bit phase.
+__device__ __forceinline__ double packed_frac(const double* __restrict__ packed, int64_t i, double inv_L) {
+  return packed[3 * i + 2] * inv_L;
 }
-__device__ __forceinline__ double packed_frac(const FracPos* __restrict__ packed, int64_t i) { return packed[i].f; }
-__device__ __forceinline__ double packed_frac(const uint32_t* __restrict__ packed, int64_t i) {
+__device__ __forceinline__ double packed_frac(const FracPos* __restrict__ packed, int64_t i, double) {
+  return packed[i].f;
+}
+__device__ __forceinline__ double packed_frac(const uint32_t* __restrict__ packed, int64_t i, double) {
   return double(packed[i]) * (1.0 / 4294967296.0);
 }
 
@@ -138,12 +144,13 @@ __device__ __forceinline__ double packed_frac(const uint32_t* __restrict__ packe
 // rounds), so two cells of slack are added each way. A position within one
 // phase step of L packs to 0 although it sorts into the last cell, so a
 // tile whose last fraction is below its first reaches the end of the period.
+// The two candidate gaps add up to at most 1, so the bound is at most 1/2.
 template <typename P>
 __device__ __forceinline__ double tile_gap(const P* __restrict__ packed, int64_t i0, int ni, int64_t j0, int nj,
-                                           int cells) {
+                                           int cells, double inv_L) {
   const double c = double(cells);
-  const double fI0 = packed_frac(packed, i0), fI1 = packed_frac(packed, i0 + ni - 1);
-  const double fJ0 = packed_frac(packed, j0), fJ1 = packed_frac(packed, j0 + nj - 1);
+  const double fI0 = packed_frac(packed, i0, inv_L), fI1 = packed_frac(packed, i0 + ni - 1, inv_L);
+  const double fJ0 = packed_frac(packed, j0, inv_L), fJ1 = packed_frac(packed, j0 + nj - 1, inv_L);
   const double loI = (floor(fI0 * c) - 2.0) / c;
   const double hiI = (floor((fI1 < fI0 ? 1.0 : fI1) * c) + 3.0) / c;
   const double loJ = (floor(fJ0 * c) - 2.0) / c;
@@ -151,13 +158,16 @@ __device__ __forceinline__ double tile_gap(const P* __restrict__ packed, int64_t
   return fmin(loJ - hiI, 1.0 + loI - hiJ);
 }
 
-// Decode the J-major triangular index p -> (I, J), I <= J.
-__device__ __forceinline__ void tri_decode(int64_t p, int& I, int& J) {
-  int64_t j = int64_t((sqrt(8.0 * double(p) + 1.0) - 1.0) * 0.5);
-  while (j * (j + 1) / 2 > p) --j;
-  while ((j + 1) * (j + 2) / 2 <= p) ++j;
-  J = int(j);
-  I = int(p - j * (j + 1) / 2);
+// A lower bound on 1 - cos(pi g) = 2 sin^2(pi g / 2) for a gap g in
+// (0, 1/2]: sin y >= y - y^3 / 6 for y >= 0, and y = pi g / 2 <= pi / 4
+// keeps that bound positive (it is below the sine by at most 0.4 %, which
+// only makes the tile test that uses it a little less eager). Two constants
+// instead of a sine's polynomial: the pair kernels keep this test's
+// constants live across their loop over tile pairs.
+__device__ __forceinline__ double one_minus_cos_pi_lower(double g) {
+  const double y = 1.5707963267948966 * g;
+  const double sl = y * fma(y * y, -1.0 / 6.0, 1.0);
+  return 2.0 * sl * sl;
 }
 
 // Geometry of one pair: s^2, q = 1 - c, c, c^2, 1/(2c'), 1/sqrt(2c') with
@@ -382,6 +392,23 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
   }
 }
 
+// Waves per SIMD the pair kernels are compiled for, by (precision, pass
+// size): the occupancy the register use of the tile-pair body allows on
+// its own. Without the hint the loop over a slot's tile pairs lets the
+// compiler keep more values live across it (hoisted constants, scalar
+// values spilled to vector lanes), which costs one to four waves; with it,
+// the few values that no longer fit are reloaded once per tile pair.
+template <typename T, int BC>
+struct PairWaves {
+  static constexpr int value = 4;
+};
+template <> struct PairWaves<double, 4> { static constexpr int value = 6; };
+template <> struct PairWaves<double, 8> { static constexpr int value = 5; };
+template <> struct PairWaves<double, 16> { static constexpr int value = 4; };
+template <> struct PairWaves<float, 4> { static constexpr int value = 8; };
+template <> struct PairWaves<float, 8> { static constexpr int value = 8; };
+template <> struct PairWaves<float, 16> { static constexpr int value = 5; };
+
 // Shared memory of one tile-pair unit.
 template <typename T, int BC>
 struct CvSmem {
@@ -392,26 +419,28 @@ struct CvSmem {
   int b_end;
 };
 
-// One unit of the pair sums: tile I (one i per thread) against tile J
-// (staged in LDS), concentrations [b_lo, b_hi); writes those entries of the
-// tile pair's 2B partial sums [Kbar sums | K sums] at `out`. A tile pair may
-// be split over several units by concentration range: every concentration
-// accumulates the same terms in the same order whatever the range. Used by
-// the one-set kernel and by the batched engine. Ends with a barrier, so the
-// caller may reuse `sm`.
+// One tile pair of the pair sums: tile I (one i per thread) against tile J
+// (staged in LDS), concentrations [b_lo, b_hi); adds this pair's sums into
+// the slot's running sums sm.unit_acc ([Kbar sums | K sums], 2B entries,
+// each one added to in a fixed order: chunk reductions in wave order,
+// tile pairs in the order of the slot's list). The exponential table
+// (double form) must be staged and visible. A tile pair may be split over
+// several units by concentration range: every concentration accumulates
+// the same terms in the same order whatever the range. Ends with a
+// barrier, so the caller may reuse `sm`.
 //
 // Concentrations are ascending, and a pair's K-bar exponent -2 kappa q
 // (q = 1 - cos(pi d / L), growing with the periodic distance d) is the
 // larger of its two exponents. With gap the lower bound on the distance
 // between the two tiles (from `cells`, the sort's cell count), every term
-// of a concentration with kappa q_min > S/2 (q_min = 1 - cos(pi gap), S the
-// skip exponent) is below the skip bound, so the unit stops before the
+// of a concentration with kappa q_min > S/2 (q_min a lower bound on
+// 1 - cos(pi gap), S the skip exponent) is below the skip bound, so the unit stops before the
 // first such concentration; the margin of 1e-6 keeps this a subset of what
 // the per-term test would skip, so the sums are those of the full loop.
 template <typename T, int BC>
 __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __restrict__ packed, int64_t n,
                                              int cells, double L, int I, int J, const CvConsts<T>& K, int b_lo,
-                                             int b_hi, double* __restrict__ out, CvSmem<T, BC>& sm) {
+                                             int b_hi, CvSmem<T, BC>& sm) {
   constexpr int pp = Packed<T>::per_particle;
   const Period per = make_period(L);
   const int tid = threadIdx.x;
@@ -420,20 +449,14 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
   if (tid == 0) {
     int be = b_hi;
     if (I != J) {
-      const double gap = tile_gap(packed, i0, int(min(int64_t(kCvTile), n - i0)), j0, nj, cells);
+      const double gap = tile_gap(packed, i0, int(min(int64_t(kCvTile), n - i0)), j0, nj, cells, 1.0 / L);
       if (gap > 0.0) {
-        const double sh = sinpi(0.5 * gap);
-        const double qmin = 2.0 * sh * sh;
+        const double qmin = one_minus_cos_pi_lower(gap);
         be = b_lo;
-        while (be < b_hi && !(double(K.twok[be]) * qmin > 2.0 * kSkipExponent * (1.0 + 1e-6))) ++be;
+        while (be < b_hi && !(double(K.twok[be]) * qmin > kSkipExponent * (1.0 + 1e-6))) ++be;
       }
     }
     sm.b_end = be;
-  }
-  for (int k = tid; k < 2 * KDE_MAX_KAPPAS; k += kBlock) sm.unit_acc[k] = 0.0;
-  if constexpr (std::is_same<T, double>::value) {
-    constexpr double etab_src[256] = KDE_EXP_TABLE;
-    for (int k = tid; k < 256; k += kBlock) sm.etab[k] = etab_src[k];
   }
   for (int k = tid; k < pp * nj; k += kBlock) sm.tj[k] = packed[pp * j0 + k];
   const int64_t i = i0 + tid;
@@ -481,12 +504,62 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
       if (b0 + bb < bc_end) {
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
-        sm.unit_acc[which * K.B + b0 + bb] = v;
+        sm.unit_acc[which * K.B + b0 + bb] += v;
       }
     }
     __syncthreads();
     b0 = bc_end;
   }
+}
+
+// Item k of the list of the T(T+1)/2 tile pairs of T sorted tiles in
+// order of circular tile distance e = min(J - I, T - (J - I)): band e holds
+// the pairs with J - I = e (I ascending) and then those with J - I = T - e
+// (the pairs that are neighbours across the period), T items per band (the
+// last band T/2 when T is even). Tiles hold equal particle counts of the
+// cell-sorted positions, so the separation of a pair, and with it the work
+// of its tile pair, falls with e: the list runs roughly from the most to
+// the least expensive tile pair.
+__device__ __forceinline__ void pair_decode(int64_t k, int T, int& I, int& J) {
+  const int64_t t = T;
+  const int64_t e = k / t;
+  const int64_t r = k - e * t;
+  if (r < t - e) {
+    I = int(r);
+    J = int(r + e);
+  } else {
+    I = int(r - (t - e));
+    J = int(r);
+  }
+}
+
+// One slot of the pair sums: the tile pairs k = slot, slot + nslots,
+// slot + 2 nslots, ... of the list of pair_decode, in that order, for
+// concentrations [b_lo, b_hi); writes those entries of the slot's row of
+// 2B running sums [Kbar sums | K sums] at `out`. Up to kCvMaxSlots tile
+// pairs every slot holds one, and the workgroups, dispatched in slot order,
+// take the most expensive tile pairs first; beyond that the partial sums
+// stay at kCvMaxSlots rows and each slot takes tile pairs from every band.
+// Used by the one-set kernel and by the batched engine (the same slots and
+// order, so their sums are bitwise equal). Ends with a barrier.
+template <typename T, int BC>
+__device__ __forceinline__ void cv_slot(const typename Packed<T>::type* __restrict__ packed, int64_t n, int cells,
+                                        double L, int64_t slot, int64_t nslots, const CvConsts<T>& K, int b_lo,
+                                        int b_hi, double* __restrict__ out, CvSmem<T, BC>& sm) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < 2 * KDE_MAX_KAPPAS; k += kBlock) sm.unit_acc[k] = 0.0;
+  if constexpr (std::is_same<T, double>::value) {
+    constexpr double etab_src[256] = KDE_EXP_TABLE;
+    for (int k = tid; k < 256; k += kBlock) sm.etab[k] = etab_src[k];
+  }
+  const int ntiles = int((n + kCvTile - 1) / kCvTile);
+  const int64_t items = int64_t(ntiles) * (ntiles + 1) / 2;
+  for (int64_t k = slot; k < items; k += nslots) {
+    int I, J;
+    pair_decode(k, ntiles, I, J);
+    cv_tile_pair<T, BC>(packed, n, cells, L, I, J, K, b_lo, b_hi, sm);
+  }
+  __syncthreads();
   const int nk = b_hi - b_lo;
   for (int k = tid; k < 2 * nk; k += kBlock) {
     const int e = (k / nk) * K.B + b_lo + k % nk;

@@ -143,31 +143,30 @@ __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool 
       if (b_lo + bb < b_hi) {
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
-        sm.unit_acc[which * K.B + b_lo + bb] = v;
+        sm.unit_acc[which * K.B + b_lo + bb] += v;
       }
     }
     __syncthreads();
   }
 }
 
-// One tile pair (I, J) of the triangle pair sums; writes all 2B raw
-// partials [Tbar sums x 6 h | T sums x h] to `out`. `cells` is the cell
-// count of the sort that ordered the packed particles, which bounds the
-// distance between the two tiles from below by `gap` (tile_gap); widths
-// with 2 h <= gap L contribute nothing to the pair, and a pair farther
-// apart than every support is skipped whole.
+// One tile pair (I, J) of the triangle pair sums; adds its 2B raw sums
+// [Tbar sums x 6 h | T sums x h] into the slot's running sums sm.unit_acc.
+// `cells` is the cell count of the sort that ordered the packed particles,
+// which bounds the distance between the two tiles from below by `gap`
+// (tile_gap); widths with 2 h <= gap L contribute nothing to the pair, and
+// a pair farther apart than every support is skipped whole.
 // Ends with a barrier.
 template <typename T, int BC>
 __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type* __restrict__ packed, int64_t n,
-                                              int cells, int I, int J, const TriConsts<T>& K,
-                                              double* __restrict__ out, TriSmem<T, BC>& sm) {
+                                              int cells, int I, int J, const TriConsts<T>& K, TriSmem<T, BC>& sm) {
   using P = typename TriPacked<T>::type;
   const int tid = threadIdx.x;
   const int64_t i0 = int64_t(I) * kCvTile, j0 = int64_t(J) * kCvTile;
   const int ni = int(min(int64_t(kCvTile), n - i0));
   const int nj = int(min(int64_t(kCvTile), n - j0));
   if (tid == 0) {
-    const double gap = tile_gap(packed, i0, ni, j0, nj, cells);
+    const double gap = tile_gap(packed, i0, ni, j0, nj, cells, 0.0);
     int bs = 0;
     if (I != J) {
       if (gap >= K.reach) {
@@ -178,11 +177,9 @@ __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type*
     }
     sm.bstart = bs;
   }
-  for (int k = tid; k < 2 * K.B; k += kBlock) sm.unit_acc[k] = 0.0;
   __syncthreads();
   const int b_start = sm.bstart;
   if (b_start >= K.B) {
-    for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = 0.0;
     __syncthreads();
     return;
   }
@@ -195,6 +192,25 @@ __device__ __forceinline__ void tri_tile_pair(const typename TriPacked<T>::type*
     tri_passes<T, BC, true>(pi, valid_i, diag, nj, b_start, K, sm);
   else
     tri_passes<T, BC, false>(pi, valid_i, diag, nj, b_start, K, sm);
+}
+
+// One slot of the triangle pair sums: the tile pairs slot, slot + nslots,
+// ... of the list of pair_decode (as cv_slot), all widths; writes the
+// slot's 2B raw sums to `out`. Ends with a barrier.
+template <typename T, int BC>
+__device__ __forceinline__ void tri_slot(const typename TriPacked<T>::type* __restrict__ packed, int64_t n, int cells,
+                                         int64_t slot, int64_t nslots, const TriConsts<T>& K, double* __restrict__ out,
+                                         TriSmem<T, BC>& sm) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < 2 * K.B; k += kBlock) sm.unit_acc[k] = 0.0;
+  const int ntiles = int((n + kCvTile - 1) / kCvTile);
+  const int64_t items = int64_t(ntiles) * (ntiles + 1) / 2;
+  for (int64_t k = slot; k < items; k += nslots) {
+    int I, J;
+    pair_decode(k, ntiles, I, J);
+    tri_tile_pair<T, BC>(packed, n, cells, I, J, K, sm);
+  }
+  __syncthreads();
   for (int k = tid; k < 2 * K.B; k += kBlock) out[k] = sm.unit_acc[k];
   __syncthreads();
 }

@@ -46,6 +46,7 @@ void clear_error();
 
 constexpr int kBlock = 256;               // threads per workgroup for every kernel
 constexpr int kCvTile = 256;              // particles per CV tile (one per thread)
+constexpr int64_t kCvMaxSlots = 32768;    // rows of CV partial sums: tile pairs are dealt to this many slots
 constexpr double kSkipExponent = 70.0;    // terms below exp(-70) of their sum's scale are skipped
 constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int kMaxM = 4096;
@@ -98,6 +99,9 @@ kde_status check_domain(const kde_domain* dom, bool need_grid);
 // than the current device provides.
 kde_status check_lds(size_t bytes);
 kde_status check_workspace(void* ws, size_t ws_bytes, size_t need);
+// The argument rules of kde_cv_scan, without its workspace.
+kde_status check_cv_args(const kde_domain* dom, int64_t N, const void* x, int B, const double* kappas_h,
+                         const double* cv);
 size_t elem_size(int prec);
 
 // Launch shape of the pair kernel for (precision, N): `chunk`
@@ -109,6 +113,17 @@ struct PairTuning {
 };
 PairTuning tuned_pass(int prec, int64_t n);
 kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk, const int32_t* group);
+
+// Tile pairs of a CV scan over n particles, and the slots (rows of partial
+// sums, one workgroup per slot and concentration group) they are dealt to.
+inline int64_t cv_tile_pairs(int64_t n) {
+  const int64_t t = (n + kCvTile - 1) / kCvTile;
+  return t * (t + 1) / 2;
+}
+inline int64_t cv_slots(int64_t n) {
+  const int64_t p = cv_tile_pairs(n);
+  return p < kCvMaxSlots ? p : kCvMaxSlots;
+}
 
 // Concentrations per work unit, and units per tile pair, for B values.
 inline int pair_group_size(const PairTuning& t, int B) { return (t.group > 0 && t.group < B) ? t.group : B; }

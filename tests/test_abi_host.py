@@ -186,6 +186,36 @@ def test_ad_pvalue_host_matches_oracle(a2):
     assert abs(kde.kde_ad_pvalue(a2) - adtest.ad_pvalue(a2)) <= 1e-9
 
 
+def test_ad_pvalue_host_published_tail_points():
+    """The host p-value at Anderson and Darling's (1954) printed points,
+    the 2.5 % and 1 % points included: the tail where the width-update rule
+    acts (p <= 0.01 fires it, half of p_th re-fires it)."""
+    import json
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "ad_critical_points.json")))
+    assert len(g["points"]) >= 4
+    for p in g["points"]:
+        assert abs(kde.kde_ad_pvalue(p["a2"]) - p["upper_tail"]) <= p["abs_tol"], p
+
+
+def test_ad_pvalue_host_matches_characteristic_function():
+    """The host p-value against the Gil-Pelaez inversion of the limit law's
+    characteristic function (an independent route), across the tail."""
+    from tests.test_oracle_adapt_pic import ad_upper_tail_charfn
+    for a2 in (2.492, 3.070, 3.0775, 3.857, 3.8781, 4.5, 6.0):
+        assert abs(kde.kde_ad_pvalue(a2) - ad_upper_tail_charfn(a2)) <= 1e-9, a2
+
+
+def test_cv_workspace_is_bounded_in_n():
+    """The CV partial sums take at most 32,768 slot rows whatever N: at
+    N = 2^20 and B = 64 the workspace is the packed positions (24 B per
+    particle), the sort histogram and 32,768 x 128 doubles of slot sums,
+    not 8.4 million tile pairs x 128 doubles."""
+    n = 1 << 20
+    w = kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(), n, 64)
+    assert w <= 24 * n + 8192 * 128 * 4 + 32768 * 128 * 8 + 256 * 128 * 8 + 64 * 1024
+
+
+
 def test_ad_pvalue_edges():
     assert kde.kde_ad_pvalue(0.0) == 1.0
     assert kde.kde_ad_pvalue(-1.0) == 1.0

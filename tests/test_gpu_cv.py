@@ -241,3 +241,46 @@ def test_pass_size_changes_nothing(gpu, dtype):
             gpu.kde_tune_set(prec, [1 << 62], [16])
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_slots_holding_several_tile_pairs(gpu, dtype):
+    """N = 70,001: 274 tiles (the last one ragged) and 37,675 tile pairs
+    dealt to 32,768 slots, so 4,907 slots sum two tile pairs from different
+    bands of separation; against the oracle's Fourier-moment route (pinned
+    to the direct sums on the CPU)."""
+    L = 4 * math.pi
+    x = W.cosine_positions(np.random.default_rng([7, 70001]), 70001, L, 0.3, 0.5)
+    kap = W.log_kappas(1.0, 3e3, 12)
+    if dtype == "f32":
+        x = x.astype(np.float32)
+    announce("cv several tile pairs per slot", dtype, len(x))
+    cv, sums, am = run_gpu_cv(gpu, x, L, kap, dtype)
+    ref_cv, S1, S2 = ocv.cv_curve_fourier(np.asarray(x, dtype=np.float64), L, kap)
+    tol = TOL[dtype]
+    assert rel_err(cv, ref_cv).max() <= tol, rel_err(cv, ref_cv)
+    if dtype == "f64":
+        assert rel_err(sums[:12], S1).max() <= tol
+        assert rel_err(sums[12:], S2).max() <= tol
+    assert_argmin_ok(am, ref_cv, tol)
+
+
+def test_pass_size_changes_nothing_with_several_tile_pairs_per_slot(gpu):
+    """The bitwise invariance of the pass size and concentration split at
+    N = 80,000 (49,141 tile pairs over 32,768 slots), float form."""
+    L = 4 * math.pi
+    x = W.cosine_positions(np.random.default_rng([7, 80000]), 80000, L, 0.3, 0.5).astype(np.float32)
+    kap = W.log_kappas(1.0, 1e4, 20)
+    outs = []
+    announce("cv pass size, several tile pairs per slot")
+    try:
+        for c, g in ((16, 0), (4, 8), (8, 0)):
+            gpu.kde_tune_set(gpu.KDE_F32, [1 << 62], [c], [g])
+            outs.append(run_gpu_cv(gpu, x, L, kap, "f32"))
+    finally:
+        if __import__("os").path.exists(gpu.TUNE_FILE):
+            gpu.load_tuning(gpu.TUNE_FILE)
+        else:
+            gpu.kde_tune_set(gpu.KDE_F32, [1 << 62], [16])
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])

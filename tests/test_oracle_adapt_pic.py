@@ -143,7 +143,38 @@ def test_ad_statistic_matches_scipy():
 def test_ad_published_upper_tail_points():
     g = json.load(open(os.path.join(GOLDEN, "ad_critical_points.json")))
     for p in g["points"]:
-        assert abs(adtest.ad_pvalue(p["a2"]) - p["upper_tail"]) <= g["abs_tol"]
+        assert abs(adtest.ad_pvalue(p["a2"]) - p["upper_tail"]) <= p["abs_tol"]
+
+
+def ad_upper_tail_charfn(x, T=6000.0, h=0.01):
+    """Upper tail of the limiting law of A^2 by Gil-Pelaez inversion of its
+    characteristic function, a route independent of the Anderson-Darling
+    series the oracle sums. The limit law is that of sum_j Y_j^2 / (j(j+1))
+    with Y_j standard normal, so
+        phi(t) = prod_j (1 - 2 i t / (j (j+1)))^(-1/2)
+               = sqrt(-2 pi i t / cos((pi/2) sqrt(1 + 8 i t)))
+    (the roots of j^2 + j - 2 i t and Gamma(1/2 - z) Gamma(1/2 + z) =
+    pi / cos(pi z)); the branch is the continuous one from phi(0) = 1.
+    F(x) = 1/2 - (1/pi) int_0^inf Im(exp(-i t x) phi(t)) / t dt, by
+    Simpson's rule (the integrand is analytic and |phi| ~ exp(-pi sqrt(t)/2),
+    below 1e-50 at T)."""
+    t = np.arange(1, int(round(T / h)) + 1) * h
+    s = np.sqrt(1.0 + 8j * t)
+    lr = np.log(-2j * math.pi * t) - np.log(np.cos(0.5 * math.pi * s))
+    logphi = 0.5 * (lr.real + 1j * np.unwrap(lr.imag))
+    f = np.imag(np.exp(-1j * t * x + logphi)) / t
+    y = np.concatenate([[1.0 - x], f])  # t -> 0 limit: E[A^2] - x = 1 - x
+    if (y.shape[0] - 1) % 2:
+        y = y[:-1]
+    integral = h / 3.0 * (y[0] + y[-1] + 4.0 * y[1:-1:2].sum() + 2.0 * y[2:-1:2].sum())
+    return 0.5 + integral / math.pi
+
+
+@pytest.mark.parametrize("a2", [0.5, 1.933, 2.492, 3.070, 3.857, 3.8781, 5.0, 7.0])
+def test_ad_tail_matches_characteristic_function(a2):
+    """The oracle's p-value against the characteristic-function inversion,
+    through the tail where the width-update rule acts (p <= 0.02)."""
+    assert abs(adtest.ad_pvalue(a2) - ad_upper_tail_charfn(a2)) <= 1e-12
 
 
 def test_ad_limit_law_moments():
