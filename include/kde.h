@@ -185,6 +185,26 @@ kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t 
                        void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * kde_cv_scan_noalloc -- kde_cv_scan without a caller-given workspace, for
+ * callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation. Same
+ * arguments, rules, outputs and kernels as kde_cv_scan (the same bits);
+ * the workspace is an array of KDE_CV_NOALLOC_MAX_BYTES the library holds
+ * in device memory, one per device, from the library's load on that device
+ * until the process ends. The call allocates nothing.
+ *   Limit: a scan whose kde_workspace_size(KDE_OP_CV_SCAN, dom, N, B)
+ *   exceeds KDE_CV_NOALLOC_MAX_BYTES is refused with KDE_E_WORKSPACE before
+ *   anything is enqueued (24 MiB holds N = 65,536 at B = 32 in either
+ *   precision; every scan of N <= 16,384 at B = 64).
+ *   Concurrency: every call on one device uses that device's one array, so
+ *   calls that overlap on a device (other streams or threads) race and give
+ *   undefined results; calls enqueued on one stream are safe.
+ */
+#define KDE_CV_NOALLOC_MAX_BYTES (24u << 20)
+kde_status kde_cv_scan_noalloc(const kde_domain* dom, int64_t N, const void* x, int32_t B, const double* kappas_h,
+                               double* cv, double* sums, int32_t* argmin, void* stream);
+
+/*
  * kde_deposit -- kernel density estimate at the grid nodes (Sec. II.B
  * Eq. kde; with per-particle concentrations the adaptive estimate of
  * Sec. II.C, step 3, each kernel normalised on its own):

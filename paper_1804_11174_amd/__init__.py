@@ -96,6 +96,7 @@ _SIGNATURES = {
     "kde_last_error": (ctypes.c_char_p, []),
     "kde_workspace_size": (_i32, [_i32, _dom_p, _i64, _i32, ctypes.POINTER(_sz)]),
     "kde_cv_scan": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kde_cv_scan_noalloc": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp]),
     "kde_deposit": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _vp, _vp, _sz, _vp]),
     "kde_gather": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _sz, _vp]),
     "kde_adapt_widths": (_i32, [_dom_p, _i64, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -251,6 +252,14 @@ def kde_cv_scan(dom, N, x, kappas_h, cv, sums, argmin, ws, ws_bytes, stream=None
     kp = k.ctypes.data_as(ctypes.POINTER(_dbl))
     _check(lib.kde_cv_scan(ctypes.byref(dom), int(N), _ptr(x), int(k.shape[0]), kp, _ptr(cv), _ptr(sums),
                            _ptr(argmin), ws, int(ws_bytes), _stream(stream)), "kde_cv_scan")
+
+
+def kde_cv_scan_noalloc(dom, N, x, kappas_h, cv, sums, argmin, stream=None):
+    lib = require_library()
+    k = np.ascontiguousarray(np.asarray(kappas_h, dtype=np.float64))
+    kp = k.ctypes.data_as(ctypes.POINTER(_dbl))
+    _check(lib.kde_cv_scan_noalloc(ctypes.byref(dom), int(N), _ptr(x), int(k.shape[0]), kp, _ptr(cv), _ptr(sums),
+                                   _ptr(argmin), _stream(stream)), "kde_cv_scan_noalloc")
 
 
 def kde_cv_scan_fourier(dom, N, x, kappas_h, cv, sums, argmin, ws, ws_bytes, stream=None):

@@ -213,7 +213,23 @@ def test_cv_workspace_is_bounded_in_n():
     n = 1 << 20
     w = kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(), n, 64)
     assert w <= 24 * n + 8192 * 128 * 4 + 32768 * 128 * 8 + 256 * 128 * 8 + 64 * 1024
+    # the allocation-free scan's array holds the paper-scale scan (N = 65,536, B = 32)
+    for prec in (kde.KDE_F64, kde.KDE_F32):
+        assert kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(prec=prec), 65536, 32) <= (24 << 20)
+        assert kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom(prec=prec), 16384, 64) <= (24 << 20)
 
+
+def test_noalloc_scan_refuses_beyond_its_array_on_the_host(lib):
+    """kde_cv_scan_noalloc checks its arguments and its size limit before
+    anything touches the device (the pointers are never dereferenced)."""
+    d = dom()
+    k = np.linspace(1.0, 64.0, 64)
+    kp = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fake = ctypes.c_void_p(4096)
+    st = lib.kde_cv_scan_noalloc(ctypes.byref(d), 1 << 20, fake, 64, kp, fake, None, None, None)
+    assert st == 2 and "holds" in kde.kde_last_error()
+    st = lib.kde_cv_scan_noalloc(ctypes.byref(d), 1, fake, 64, kp, fake, None, None, None)
+    assert st == 1
 
 
 def test_ad_pvalue_edges():
