@@ -257,3 +257,132 @@ def test_server_large_requests_run_alone_in_order(gpu):
     assert start == sorted(start), "large requests must start in arrival order"
     for k in range(len(res) - 1):
         assert end[k] <= start[k + 1] + 5e-4, f"large requests {k} and {k + 1} overlapped"
+
+
+def _session_tolerances(dtype, rho_ref, L, kappa_peak):
+    """Bounds of one session step in the given form, from its arithmetic.
+
+    Deposit: each grid value to ``r`` relative (1e-12 in double; 1e-6 in the
+    float form, plus 4u of the peak kernel value for the exponent rounding of
+    far terms). The charge 1 - L rho cancels most of rho, so its error is
+    L |d rho| absolute; the Poisson solve with the mean removed and the
+    centred difference map a charge error q to a field error of at most
+    2 L max|q| (the half-node fields are running sums of dx (q - mean) with
+    zero sum). The gather weights of a particle sum to about 1, so the
+    gathered field carries that field error plus its own relative rounding;
+    the push then adds dt times that to v, and one rounding of v and of x
+    (and the storage rounding of x after the wrap) in the form's precision."""
+    u = 2.0 ** -24 if dtype == "f32" else 2.0 ** -53
+    r = 1e-6 if dtype == "f32" else 1e-12
+    drho = r * np.asarray(rho_ref) + 4 * u * kappa_peak
+    dE = 2.0 * L * L * drho.max()
+    return dict(u=u, r=r, drho=drho, dE=dE)
+
+
+@pytest.mark.parametrize("dtype,steps", [("f32", 3), ("f64", 2)])
+def test_session_at_serving_shape_matches_oracle_stepwise(gpu, dtype, steps):
+    """A session of the serving form at its own shape (262,144 particles,
+    M = 128, L = 4 pi, dt = 0.1, 16 concentrations in [1, 1e4], CV on the
+    first 65,536, alpha = 0.5, threshold 0.01, rate 0.05), held to the
+    oracle step by step from the session's own state: before each step x,
+    v and kappa_i are read back, the oracle runs one KDE-PIC step (Sec.
+    III.A) and the update rule (Sec. II.D) from them, and the session's
+    deposit, field, positions, velocities, A^2, p-value, rule decision,
+    kappa* and next widths are compared. Step 1 fires the rule here (A^2
+    of the 1 % perturbation is about 4.7), so the in-step CV scan on the
+    pushed positions is held too (argmin equal, or within the float form's
+    tie band). The oracle's CV goes through its Fourier-moment route, which
+    is pinned to the direct pair sums on the CPU."""
+    import torch
+    from oracle import vonmises as vmo
+    s0 = W.pic_session(0)
+    L, M, dt, kappas, n_cv = s0.L, s0.M, s0.dt, s0.kappas, s0.n_cv
+    td = torch.float32 if dtype == "f32" else torch.float64
+    announce("serving-shape session", dtype, len(s0.x))
+    sess = gpu.Session(to_gpu(s0.x, td), to_gpu(s0.v, td), L, M, dt, kappas, n_cv)
+    band = lambda c: 2 * (1e-6 if dtype == "f32" else 1e-12) * np.abs(c).max()
+    try:
+        info = sess.state()
+        x = host(sess.read(gpu.KDE_SESSION_X)).astype(np.float64)
+        # creation: CV scan at t = 0, pilot at its optimum, widths
+        c0, _, _ = ocv.cv_curve_fourier(x[:n_cv], L, kappas)
+        b_or = ocv.cv_argmin(c0)
+        b_gpu = int(np.argmin(np.abs(kappas - info["kappa_star"])))
+        assert kappas[b_gpu] == info["kappa_star"]
+        assert b_gpu == b_or or abs(c0[b_gpu] - c0[b_or]) <= band(c0), (b_gpu, b_or)
+        k_gpu = host(sess.read(gpu.KDE_SESSION_KAPPA)).astype(np.float64)
+        pil = od.deposit(x, L, M, kappa=info["kappa_star"])
+        k_ref, _, _ = od.adapt_widths(x, L, pil, info["kappa_star"], 0.5)
+        tol_k = 3e-6 if dtype == "f32" else 1e-11
+        assert rel_err(k_gpu, k_ref).max() <= tol_k, rel_err(k_gpu, k_ref).max()
+        fired_total = 0
+        for k in range(steps):
+            before = sess.state()
+            x = host(sess.read(gpu.KDE_SESSION_X)).astype(np.float64)
+            v = host(sess.read(gpu.KDE_SESSION_V)).astype(np.float64)
+            ki = host(sess.read(gpu.KDE_SESSION_KAPPA)).astype(np.float64)
+            announce("serving-shape session step", dtype, k + 1)
+            sess.step(1)
+            info = sess.state()
+            rho = od.deposit(x, L, M, kappa_i=ki)
+            E = pic.efield_centered(pic.poisson_fd(pic.charge_from_density(rho, L), L / M), L / M)
+            Ei = od.gather(x, L, E, kappa_i=ki)
+            xr, vr = pic.push(x, v, Ei, dt, L)
+            peak = float(np.mean(1.0 / (L * vmo.i0e(ki))))
+            t = _session_tolerances(dtype, rho, L, peak)
+            g_rho = host(sess.read(gpu.KDE_SESSION_RHO))
+            g_E = host(sess.read(gpu.KDE_SESSION_E))
+            g_x = host(sess.read(gpu.KDE_SESSION_X)).astype(np.float64)
+            g_v = host(sess.read(gpu.KDE_SESSION_V)).astype(np.float64)
+            e_rho = np.abs(g_rho - rho)
+            e_E = np.abs(g_E - E).max()
+            dEi = 1.05 * t["dE"] + 2 * t["r"] * np.abs(E).max()
+            dv = dt * dEi + 2 * t["u"] * (np.abs(v) + np.abs(Ei) * dt)
+            ex = np.abs(g_x - xr)
+            ex = np.minimum(ex, L - ex)
+            dx = dt * dv + 3 * t["u"] * L
+            print(f"[{dtype} step {k + 1}] rho rel {np.max(e_rho / rho):.2e}  E {e_E:.2e} "
+                  f"(bound {t['dE']:.2e}, |E| {np.abs(E).max():.2e})  v {np.max(np.abs(g_v - vr)):.2e}  "
+                  f"x {ex.max():.2e}", flush=True)
+            assert np.all(e_rho <= t["drho"]), np.max(e_rho / t["drho"])
+            assert e_E <= t["dE"], (e_E, t["dE"])
+            assert np.all(np.abs(g_v - vr) <= dv), np.max(np.abs(g_v - vr) / dv)
+            assert np.all(ex <= dx), np.max(ex / dx)
+            # Anderson-Darling on the session's own pushed positions
+            a2 = adtest.ad_statistic(g_x, L)
+            assert abs(info["last_a2"] - a2) <= 1e-10 * abs(a2), (info["last_a2"], a2)
+            p = adtest.ad_pvalue(a2)
+            assert abs(info["last_p"] - p) <= 1e-9
+            # the rule from the session's state before the step
+            st = update.UpdateState(before["p_th"], before["h_opt"], before["h_target"])
+            solved = {}
+
+            def solve():
+                c, _, _ = ocv.cv_curve_fourier(g_x[:n_cv], L, kappas)
+                solved["c"] = c
+                return vmo.width_from_kappa(kappas[ocv.cv_argmin(c)], L)
+
+            st_ref, fired = update.step(st, p, solve, 0.01, 0.05)
+            fired_total += int(fired)
+            assert info["fired"] == fired_total, (info["fired"], fired_total)
+            if fired:
+                c = solved["c"]
+                b_gpu = int(np.argmin(np.abs(vmo.width_from_kappa(kappas, L) - info["h_target"])))
+                assert abs(info["h_target"] - vmo.width_from_kappa(kappas[b_gpu], L)) <= 1e-15 * info["h_target"]
+                b_or = ocv.cv_argmin(c)
+                assert b_gpu == b_or or abs(c[b_gpu] - c[b_or]) <= band(c), (b_gpu, b_or)
+                st_ref = update.UpdateState(st_ref.p_th, 0.05 * info["h_target"] + 0.95 * before["h_opt"],
+                                            info["h_target"])
+            assert abs(info["p_th"] - st_ref.p_th) <= 1e-9
+            assert abs(info["h_target"] - st_ref.h_target) <= 1e-14 * st_ref.h_target
+            assert abs(info["h_opt"] - st_ref.h_opt) <= 1e-14 * st_ref.h_opt
+            kstar = float(vmo.kappa_from_width(st_ref.h_opt, L))
+            assert abs(info["kappa_star"] - kstar) <= 1e-13 * kstar
+            # the next step's widths from the pilot at kappa*
+            pil = od.deposit(g_x, L, M, kappa=info["kappa_star"])
+            k_ref, _, _ = od.adapt_widths(g_x, L, pil, info["kappa_star"], 0.5)
+            k_gpu = host(sess.read(gpu.KDE_SESSION_KAPPA)).astype(np.float64)
+            assert rel_err(k_gpu, k_ref).max() <= tol_k, rel_err(k_gpu, k_ref).max()
+        assert fired_total >= 1
+    finally:
+        sess.close()
