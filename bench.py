@@ -59,10 +59,28 @@ PEAK_HBM = 8.0e12
 #        + two products = 30; two accumulations 2. Total 47.
 #   f32: K term: product 1 + exponential 1 = 2; Kbar term: product 1 +
 #        exponential 1 + argument and factor 2 + degree-5 polynomial 5 +
-#        two products = 11; two accumulations into double (conversion and
-#        add) of 2 = 4. Total 17.
-OPS_PER_TERM = {"f64": 47, "f32": 17}
+#        two products = 11; two compensated (Kahan) accumulations of 4
+#        float operations = 8. Total 21.
+OPS_PER_TERM = {"f64": 47, "f32": 21}
 SKIP_EXPONENT = 70.0
+
+# The planning cost model's ideal pair-evaluation rates, against which the
+# algorithmic pair-evaluation rate B n (n - 1) / 2 / t is also stated: about
+# 70 FP64 operations per pair-evaluation (5e11/s at the FP64 vector peak);
+# in float 4 transcendentals at a quarter of the FMA rate plus about 22
+# other operations (1.0e12/s). The model counts every (pair, kappa) term,
+# while the kernel skips terms below e^-70 of their sum's scale, so a kernel
+# can exceed it; `frac` itself is taken on the evaluated terms.
+PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
+
+# Issue counters of the pair kernel (rocprofv3 --pmc SQ_INSTS_VALU and
+# GRBM_GUI_ACTIVE on the paper-scale scan, one counter per run), as
+# VALU lane-instructions per evaluated term and the engine clock during the
+# launch; the issue fraction is the lane-instructions issued per second
+# over the one-per-four-clocks (double) or one-per-two-clocks (float, not
+# packed) issue rate of 256 CUs x 4 SIMDs x 64 lanes at that clock. Valid
+# only for the kernel sources they were taken on (PAIR_KERNEL_SOURCES).
+PAIR_COUNTERS = {"digest": None}
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
@@ -120,13 +138,13 @@ def count_evaluated_terms(x, L, kappas):
 #        clamp 1, table exponential 14, weight or field product 1,
 #        accumulation 1 = 21;
 #   f32: node index wrap 2, node sine 2, square 1, exponent product 1,
-#        exp2 1, weight or field product 1, accumulation into double 2 = 10.
+#        exp2 1, weight or field product 1, compensated accumulation 4 = 12.
 # Algorithmic HBM bytes per launch: deposit reads the positions (and the
 # widths in the adaptive one; the pipeline runs one of each, so 1.5 arrays
 # on average) and writes its chunk grids (chunks x M doubles); gather reads
 # positions and widths and writes the gathered values; adapt reads the
 # positions twice (log sums, then widths) and writes the widths.
-NODE_OPS = {"f64": 21, "f32": 10}
+NODE_OPS = {"f64": 21, "f32": 12}
 HBM_PEAK = 8e12
 
 
@@ -195,6 +213,58 @@ def bench_peak(args, kde, torch, dev):
             f.write(out_s + "\n")
 
 
+def pair_kernel_digest():
+    h = hashlib.sha256()
+    for f in PAIR_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1804_11174_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pair_kernel_issue(prec, evaluated, kernel_ms):
+    """Issue fraction of the pair kernel from the stored counters, or None
+    once its sources differ from those the counters were taken on."""
+    if PAIR_COUNTERS.get("digest") != pair_kernel_digest() or prec not in PAIR_COUNTERS:
+        return None
+    c = PAIR_COUNTERS[prec]
+    clocks_per_instr = 4.0 if prec == "f64" else 2.0
+    rate = c["valu_lane_instr_per_term"] * evaluated / (kernel_ms * 1e-3)
+    peak = 256 * 4 * 64 / clocks_per_instr * c["engine_clock_ghz"] * 1e9
+    return {"valu_lane_instr_per_term": c["valu_lane_instr_per_term"], "engine_clock_ghz": c["engine_clock_ghz"],
+            "issue_frac": rate / peak, "source": c["source"]}
+
+
+REFERENCE_FILE = os.path.join(ROOT, "tests", "golden", "bench_reference.json")
+
+
+def _rel(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+def plain_errors(prec, cv, kstar, pilot, rho, k_i, G):
+    """Errors of the timed step's results against the FP64 oracle's, stored
+    by tests/golden/make_bench_references.py for the same positions (float32
+    runs: the float32-rounded positions): the CV curve (relative, and
+    relative to its range), the chosen kappa*, and when it agrees the pilot
+    and adaptive densities (relative per node), the widths (relative) and the
+    gathered density (normwise) at every 4096th particle."""
+    with open(REFERENCE_FILE) as f:
+        ref = json.load(f)["paper_scale"][prec]
+    rc = np.asarray(ref["cv"])
+    out = {"reference": "FP64 oracle, tests/golden/bench_reference.json",
+           "cv_rel": _rel(cv, rc), "cv_over_range": float(np.max(np.abs(np.asarray(cv) - rc)) / np.ptp(rc)),
+           "kappa_star_equal": bool(kstar == ref["kappa_star"])}
+    if out["kappa_star_equal"]:
+        e = ref["sample_every"]
+        rg = np.asarray(ref["gather"])
+        out.update({"pilot_rel": _rel(pilot, ref["pilot"]), "rho_rel": _rel(rho, ref["rho"]),
+                    "kappa_i_rel_sampled": _rel(np.asarray(k_i)[::e], ref["kappa_i"]),
+                    "gather_normwise_sampled": float(np.max(np.abs(np.asarray(G)[::e] - rg)) / np.max(np.abs(rg)))})
+    return out
+
+
 def host_cores():
     """The host the oracle ran on: logical CPUs, those this process may use,
     and the CPU model."""
@@ -210,25 +280,70 @@ def host_cores():
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
-def cpu_baseline(x, L, kappas, budget_s=12.0):
-    """The oracle's direct pair sums timed on a bounded sample of the same
-    scan: the first m particles, with m chosen for about budget_s seconds."""
+def _pair_rows_task(args):
+    """One row block of the oracle's direct pair sums (a worker of the
+    all-cores baseline)."""
     from oracle import cv as ocv
-    # calibrate on a small block
+    x, L, kappas, i0, i1 = args
+    return ocv.pair_sums_rows(x, L, kappas, i0, i1)
+
+
+def _oracle_pair_sums(pool, x, L, kappas, block=256):
+    """The oracle's direct pair sums over row blocks of ``block`` rows,
+    spread over the pool's workers and added in row order (the order of the
+    oracle's own loop, so the result is the one-worker result bit for bit)."""
+    n = x.shape[0]
+    tasks = [(x, L, kappas, i0, min(n, i0 + block)) for i0 in range(0, n, block)]
+    parts = pool.map_async(_pair_rows_task, tasks, chunksize=1).get(timeout=300)
+    S1 = np.zeros(len(kappas))
+    S2 = np.zeros(len(kappas))
+    for s1, s2 in parts:
+        S1 += s1
+        S2 += s2
+    return S1, S2
+
+
+def cpu_baseline(x, L, kappas, budget_s=10.0):
+    """The oracle's direct FP64 pair sums of the same scan, timed on a
+    bounded sample (the first m particles, m chosen for about budget_s
+    seconds of wall time): once on one worker and once on every core this
+    process may use (len(sched_getaffinity)), row blocks spread over a pool
+    of spawned worker processes and reduced in row order. Pair-evaluations
+    per second = B m (m - 1) / 2 over the wall time of the sums."""
+    import multiprocessing as mp
+    from oracle import cv as ocv
+    x = np.asarray(x, dtype=np.float64)
+    kappas = np.asarray(kappas, dtype=np.float64)
+    B = len(kappas)
     m0 = 512
     t0 = time.perf_counter()
     ocv.pair_sums(x[:m0], L, kappas)
-    dt0 = time.perf_counter() - t0
-    rate0 = len(kappas) * m0 * (m0 - 1) / 2 / max(dt0, 1e-9)
-    m = int(math.sqrt(2 * budget_s * rate0 / len(kappas)))
-    m = max(m0, min(m, x.shape[0]))
+    rate0 = B * m0 * (m0 - 1) / 2 / max(time.perf_counter() - t0, 1e-9)
+
+    def size_for(rate):
+        return max(m0, min(int(math.sqrt(2 * budget_s * rate / B)), x.shape[0]))
+
+    m1 = size_for(rate0)
     t0 = time.perf_counter()
-    ocv.pair_sums(x[:m], L, kappas)
-    dt = time.perf_counter() - t0
-    evals = len(kappas) * m * (m - 1) / 2
-    return {"value": evals / dt, "unit": "CV pair-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"direct FP64 pair sums (NumPy/SciPy, one thread) over the first {m} particles "
-                      f"x {len(kappas)} kappas: {evals:.3e} pair-evals in {dt:.1f} s",
+    ocv.pair_sums(x[:m1], L, kappas)
+    dt1 = time.perf_counter() - t0
+    rate1 = B * m1 * (m1 - 1) / 2 / dt1
+    P = len(os.sched_getaffinity(0))
+    with mp.get_context("spawn").Pool(P) as pool:
+        _oracle_pair_sums(pool, x[:256 * P], L, kappas)   # start the workers, import the oracle
+        mP = size_for(rate1 * P)
+        t0 = time.perf_counter()
+        _oracle_pair_sums(pool, x[:mP], L, kappas)
+        dtP = time.perf_counter() - t0
+    rateP = B * mP * (mP - 1) / 2 / dtP
+    return {"value": rateP, "unit": "CV pair-evals/s", "cores": P, "kind": "oracle",
+            "sample": f"direct FP64 pair sums (NumPy/SciPy) of the first {mP} particles x {B} kappas on {P} "
+                      f"worker processes (row blocks of 256, reduced in row order): "
+                      f"{B * mP * (mP - 1) / 2:.3e} pair-evals in {dtP:.1f} s",
+            "one_worker": {"value": rate1, "cores": 1,
+                           "sample": f"the first {m1} particles x {B} kappas: {B * m1 * (m1 - 1) / 2:.3e} pair-evals "
+                                     f"in {dt1:.1f} s"},
+            "all_over_one": rateP / rate1,
             "host": host_cores()}
 
 
@@ -241,9 +356,12 @@ def main():
                     help="particle precision (default: f64 for the plain form, f32 for the batching form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "tri", "fourier", "landau", "copy", "peak"],
+    ap.add_argument("--form", choices=["plain", "precision", "batch", "serve", "tri", "fourier", "landau", "copy",
+                                       "peak"],
                     default="plain",
-                    help="plain: the paper-scale pipeline (default); batch: the batching form on 512 sets; "
+                    help="plain: the paper-scale pipeline (default); precision: the float form on the "
+                         "4096-particle plain-small set (float32-rounded positions; CV scan and the density at "
+                         "every concentration) with every result's error against the FP64 oracle; batch: the batching form on 512 sets; "
                          "serve: the request server beside 16 resident PIC sessions; tri: the first-order "
                          "(triangular) shape with a CV-chosen width on the paper-scale positions; fourier: the "
                          "paper-scale pipeline through the Fourier moments (refined kappa*, exact pilot); "
@@ -278,6 +396,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.form == "peak":
         return bench_peak(args, kde, torch, dev)
+    if args.form == "precision":
+        return bench_precision(args, kde, W, torch, dev)
     if args.form == "batch":
         args.prec = args.prec or "f32"
         return bench_batch(args, kde, W, torch, dev)
@@ -362,12 +482,18 @@ def main():
     pair_ms = kern["cv_pairs"]["avg_ms"]
     achieved = evaluated * OPS_PER_TERM[args.prec] / (pair_ms * 1e-3)
     peak = PEAK_LANE_OPS[args.prec]
+    pe_rate = pair_evals / (pair_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": "cv_pairs_kernel", "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "T lane-ops/s (FMA = 1)",
                 "frac": achieved / peak, "traffic": pair_kernel_traffic(args.prec),
                 "traffic_unit": "bytes per launch",
-                "evaluated_terms_per_launch": evaluated, "ops_per_term": OPS_PER_TERM[args.prec],
-                "kernel_avg_ms": pair_ms}
+                "basis": "algorithmic lane-operations per evaluated term (counted from the kernel's formulas) x "
+                         "the terms at or above e^-70 of their sum's scale, counted from the sorted positions",
+                "evaluated_terms_per_launch": evaluated, "evaluated_fraction": evaluated / pair_evals,
+                "ops_per_term": OPS_PER_TERM[args.prec], "kernel_avg_ms": pair_ms,
+                "pair_evals_per_s": pe_rate, "planning_ideal_pair_evals_per_s": PLANNING_IDEAL_PAIR_EVALS[args.prec],
+                "frac_of_planning_ideal": pe_rate / PLANNING_IDEAL_PAIR_EVALS[args.prec],
+                "issue": pair_kernel_issue(args.prec, evaluated, pair_ms)}
     line = {
         "metric": METRIC,
         "value": value,
@@ -392,9 +518,95 @@ def main():
                     "p90": float(np.percentile(t_steps, 90))},
         "roofline": roofline,
         "secondary": secondary,
+        "errors_vs_oracle": plain_errors(args.prec, cv.cpu().numpy(), kstar, pilot.cpu().numpy(),
+                                         rho.cpu().numpy(), k_i.cpu().numpy(), G.cpu().numpy()),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob.x[:n_cv], L, kappas)
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(out + "\n")
+
+
+def precision_errors(cv, sums, am, grids, ref):
+    """Per-result errors of the plain-small form against the oracle's: every
+    grid value (relative; max over nodes, per concentration and overall),
+    every CV value (relative, and relative to the curve's range max - min),
+    the pair sums (relative) and whether the first minimum is the same."""
+    rc = np.asarray(ref["cv"])
+    rg = np.asarray(ref["grids"])
+    g = np.asarray(grids)
+    B = rc.shape[0]
+    grid_rel = np.max(np.abs(g - rg) / np.abs(rg), axis=1)
+    cv_rel = np.abs(np.asarray(cv) - rc) / np.abs(rc)
+    cv_range = np.abs(np.asarray(cv) - rc) / np.ptp(rc)
+    return {"grid_rel_max": float(grid_rel.max()), "grid_rel_per_kappa": grid_rel.tolist(),
+            "cv_rel_max": float(cv_rel.max()), "cv_rel": cv_rel.tolist(),
+            "cv_over_range_max": float(cv_range.max()), "cv_over_range": cv_range.tolist(),
+            "S1_rel_max": _rel(sums[:B], ref["S1"]), "S2_rel_max": _rel(sums[B:], ref["S2"]),
+            "argmin": int(am), "argmin_oracle": int(ref["argmin"]), "argmin_equal": bool(int(am) == ref["argmin"])}
+
+
+def bench_precision(args, kde, W, torch, dev):
+    """The precision form on the plain-small set: the 4096 float64 positions
+    of the plain-small draw rounded to float32, the CV scan over its 8
+    concentrations and the grid density (M = 64) at every one of them, in
+    the float form (float terms, compensated float sums per thread, FP64
+    normalisers, cross-thread reductions and CV combination). Errors against
+    the FP64 oracle (stored by tests/golden/make_bench_references.py) on the
+    same rounded positions (the float form's own error) and on the float64
+    positions (adding the rounding of the input); the float64 path on the
+    float64 positions alongside. A step is the scan plus the 8 deposits."""
+    p = W.plain_small()
+    with open(REFERENCE_FILE) as f:
+        ref = json.load(f)["precision_small"]
+    kappas, L, M, n = p.kappas, p.L, p.M, p.x.shape[0]
+    B = len(kappas)
+    runs = {}
+    for name, td, prec in (("f32", torch.float32, kde.KDE_F32), ("f64", torch.float64, kde.KDE_F64)):
+        x = torch.from_numpy(p.x).to(dev).to(td).contiguous()
+        dom = kde.kde_domain(L, M, prec)
+        wcv, wdep = kde.Workspace(dev), kde.Workspace(dev)
+        p_cv, b_cv = wcv.get(kde.kde_workspace_size(kde.KDE_OP_CV_SCAN, dom, n, B))
+        p_dep, b_dep = wdep.get(kde.kde_workspace_size(kde.KDE_OP_DEPOSIT, dom, n))
+        cv = torch.empty(B, dtype=torch.float64, device=dev)
+        sums = torch.empty(2 * B, dtype=torch.float64, device=dev)
+        am = torch.empty(1, dtype=torch.int32, device=dev)
+        grids = torch.empty((B, M), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream()
+
+        def step():
+            kde.kde_cv_scan(dom, n, x, kappas, cv, sums, am, p_cv, b_cv, stream)
+            for b in range(B):
+                kde.kde_deposit(dom, n, x, None, float(kappas[b]), grids[b], p_dep, b_dep, stream)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        out = (cv.cpu().numpy(), sums.cpu().numpy(), int(am.cpu()[0]), grids.cpu().numpy())
+        runs[name] = {"ms_per_step": ms, "out": out}
+    f32 = runs["f32"]["out"]
+    pair_evals = B * n * (n - 1) / 2
+    ms = runs["f32"]["ms_per_step"]
+    line = {"metric": METRIC, "value": pair_evals / (ms * 1e-3), "unit": "CV pair-evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "precision form of plain-small: N=4096 positions drawn in float64 and rounded to "
+                                   "float32, L=4pi, M=64, 8 kappas in [1,1e3]; CV scan + density at all 8 kappas",
+                       "n": n, "M": M, "B": B, "prec": "f32", "parallelism": "single GPU"},
+            "particles_per_s": n * (B + 1) / (ms * 1e-3),
+            "errors_vs_oracle_same_positions": precision_errors(*f32, ref["f32_positions"]),
+            "errors_vs_oracle_float64_positions": precision_errors(*f32, ref["f64_positions"]),
+            "f64_path": {"ms_per_step": runs["f64"]["ms_per_step"],
+                         "errors_vs_oracle": precision_errors(*runs["f64"]["out"], ref["f64_positions"])},
+            "oracle_reference": "FP64 oracle, tests/golden/bench_reference.json"}
     out = json.dumps(line)
     print(out, flush=True)
     if args.json_out:

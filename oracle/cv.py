@@ -25,27 +25,40 @@ import numpy as np
 from .vonmises import conv2, conv2_at_zero, kernel, bessel_ratio
 
 
+def pair_sums_rows(x, L, kappas, i0, i1):
+    """The part of the unordered pair sums with the first index in rows
+    [i0, i1): ``(S1[b], S2[b])`` over the pairs i in [i0, i1), j in (i, n)."""
+    x = np.asarray(x, dtype=np.float64)
+    kappas = np.atleast_1d(np.asarray(kappas, dtype=np.float64))
+    n = x.shape[0]
+    S1 = np.zeros(kappas.shape[0])
+    S2 = np.zeros(kappas.shape[0])
+    xi = x[i0:i1, None]
+    xj = x[None, i0:]
+    d = xi - xj
+    mask = (np.arange(i0, n)[None, :] > np.arange(i0, i1)[:, None])
+    dd = d[mask]
+    if dd.size == 0:
+        return S1, S2
+    for b, k in enumerate(kappas):
+        S1[b] = conv2(dd, k, L).sum()
+        S2[b] = kernel(dd, k, L).sum()
+    return S1, S2
+
+
 def pair_sums(x, L, kappas, block=256):
     """Direct unordered pair sums ``(S1[b], S2[b])`` over all i < j, for each
-    candidate ``kappas[b]``. O(n^2) per kappa, in row blocks."""
+    candidate ``kappas[b]``. O(n^2) per kappa, in row blocks of ``block``
+    rows, added in row order."""
     x = np.asarray(x, dtype=np.float64)
     kappas = np.atleast_1d(np.asarray(kappas, dtype=np.float64))
     n = x.shape[0]
     S1 = np.zeros(kappas.shape[0])
     S2 = np.zeros(kappas.shape[0])
     for i0 in range(0, n, block):
-        i1 = min(n, i0 + block)
-        # rows i in [i0, i1), columns j in (i, n)
-        xi = x[i0:i1, None]
-        xj = x[None, i0:]
-        d = xi - xj
-        mask = (np.arange(i0, n)[None, :] > np.arange(i0, i1)[:, None])
-        dd = d[mask]
-        if dd.size == 0:
-            continue
-        for b, k in enumerate(kappas):
-            S1[b] += conv2(dd, k, L).sum()
-            S2[b] += kernel(dd, k, L).sum()
+        s1, s2 = pair_sums_rows(x, L, kappas, i0, min(n, i0 + block))
+        S1 += s1
+        S2 += s2
     return S1, S2
 
 

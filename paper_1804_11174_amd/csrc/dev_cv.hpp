@@ -82,14 +82,31 @@ struct Acc<double> {
   __device__ __forceinline__ double value() const { return s; }
 };
 
-// Float terms summed in double: one conversion and one double add per
-// term, fewer instructions than a compensated float sum and more accurate.
+// Float terms in a compensated float sum (Kahan): c carries the part of
+// each addition that the float sum s lost and is taken off the next term,
+// so a thread's sum over one tile (at most 256 terms per chunk) is within
+// about two units of float rounding of the exact sum of its terms. The
+// value is handed on in double (s - c) to the fixed-order reductions across
+// threads, waves and tile pairs, which are FP64. Four float operations per
+// term: on MI355X the float pair kernel takes about 15 % longer than with
+// each term converted to double and added there (a conversion and a double
+// add), the form used before; summing runs of four terms in plain float and
+// folding each run into the compensated sum was no faster (its third
+// register per sum costs occupancy).
 template <>
 struct Acc<float> {
-  double s;
-  __device__ __forceinline__ void zero() { s = 0.0; }
-  __device__ __forceinline__ void add(float v) { s += double(v); }
-  __device__ __forceinline__ double value() const { return s; }
+  float s, c;
+  __device__ __forceinline__ void zero() {
+    s = 0.0f;
+    c = 0.0f;
+  }
+  __device__ __forceinline__ void add(float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return double(s) - double(c); }
 };
 
 // Pair-kernel exponents lie in [-2 kappa, 0] with kappa <= KDE_MAX_CV_KAPPA

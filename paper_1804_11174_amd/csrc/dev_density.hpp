@@ -59,12 +59,18 @@ struct SumOf<double> {
   __device__ __forceinline__ void add(double v) { s += v; }
   __device__ __forceinline__ double value() const { return s; }
 };
-// Float terms summed in double (a conversion and a double add per term).
+// Float terms in a compensated float sum (Kahan, as Acc<float> of the pair
+// kernels); the value is handed on in double for the FP64 reductions.
 template <>
 struct SumOf<float> {
-  double s = 0.0;
-  __device__ __forceinline__ void add(float v) { s += double(v); }
-  __device__ __forceinline__ double value() const { return s; }
+  float s = 0.0f, c = 0.0f;
+  __device__ __forceinline__ void add(float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return double(s) - double(c); }
 };
 
 constexpr int kDepMaxChunk = 512;

@@ -97,7 +97,12 @@ __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool 
   const int lane = tid & 63, wave = tid >> 6;
   for (int b_hi = K.B; b_hi > b_start; b_hi -= BC) {
     const int b_lo = max(b_start, b_hi - BC);
-    SumOf<T> s1[BC], s2[BC];
+    Acc<T> s1[BC], s2[BC];
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      s1[bb].zero();
+      s2[bb].zero();
+    }
     for (int jj = 0; jj < nj; ++jj) {
       const bool live = LIVE_ALL || (valid_i && (!diag || jj > tid));
       const T r = tri_dist(pi, sm.tj[jj]);

@@ -182,3 +182,19 @@ def test_argmin_takes_first_of_ties():
 def test_needs_two_particles():
     with pytest.raises(ValueError):
         cv.cv_curve(np.array([1.0]), 1.0, [1.0])
+
+
+def test_bench_reference_small_case_is_the_oracles():
+    """The plain-small entries of tests/golden/bench_reference.json (read by
+    bench.py's precision form) are what the oracle computes now."""
+    import json
+    import os
+    from oracle import density as od
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bench_reference.json")
+    ref = json.load(open(path))["precision_small"]["f32_positions"]
+    p = W.plain_small()
+    x = p.x.astype(np.float32).astype(np.float64)
+    c, S1, S2 = cv.cv_curve(x, p.L, p.kappas)
+    assert np.array_equal(c, ref["cv"]) and np.array_equal(S1, ref["S1"]) and cv.cv_argmin(c) == ref["argmin"]
+    for k, g in zip(p.kappas, ref["grids"]):
+        assert np.array_equal(od.deposit(x, p.L, p.M, kappa=float(k)), g)
