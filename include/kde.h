@@ -51,7 +51,8 @@
  *   valid once that work has completed. No call synchronises the device.
  * Positions. Positions outside [0, L) are wrapped on the device
  *   (x - L floor(x / L)); they are not rejected. Non-finite positions or
- *   concentrations propagate as NaN into the results.
+ *   per-particle concentrations propagate as NaN into the results and set
+ *   a numeric status word (KDE_NUMERIC_* bits, kde_numeric_check).
  * Errors. Every entry point returns a kde_status. Arguments are checked on
  *   the host before anything is enqueued; on error nothing is enqueued and
  *   kde_last_error() returns a message (thread-local) naming the problem.
@@ -70,7 +71,7 @@
 extern "C" {
 #endif
 
-#define KDE_ABI_VERSION 5
+#define KDE_ABI_VERSION 6
 
 typedef int32_t kde_status;
 
@@ -83,10 +84,20 @@ enum kde_status_code {
   KDE_E_NOT_FOUND = 5,     /* unknown handle or ticket                         */
   KDE_E_HIP = 6,           /* a HIP runtime call failed; message has its text  */
   KDE_E_NUMERIC = 7,       /* non-finite value where a finite one is needed    */
-  KDE_E_INTERNAL = 8       /* broken internal invariant                        */
+  KDE_E_INTERNAL = 8,      /* broken internal invariant                        */
+  KDE_E_CANCELLED = 9      /* request withdrawn before it ran                  */
 };
 
 enum kde_precision { KDE_F64 = 0, KDE_F32 = 1 };
+
+/* Bits of a numeric status word: kernels that read positions or
+ * per-particle concentrations record a non-finite position, and a
+ * per-particle concentration that is non-finite or negative (for the
+ * triangle: a half-width outside (0, L/2]). Such values do not fault and
+ * are not rejected (they cannot be seen before the kernels run); the
+ * results they touch become NaN and the word says so (kde_numeric_check,
+ * kde_session_step, kde_server_poll, kde_batch_status). */
+enum kde_numeric_flag { KDE_NUMERIC_POSITION = 1, KDE_NUMERIC_CONCENTRATION = 2 };
 
 /* Operation codes for kde_workspace_size. */
 enum kde_op {
@@ -130,6 +141,20 @@ const char* kde_status_str(kde_status s);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* kde_last_error(void);
+
+/*
+ * kde_numeric_check -- the numeric status of the plain calls
+ * (kde_cv_scan, kde_cv_scan_noalloc, kde_cv_scan_fourier, kde_cv_refine,
+ * kde_deposit, kde_gather, kde_adapt_widths, kde_adapt_widths_exact). Their
+ * kernels set KDE_NUMERIC_* bits in a status word the library keeps per
+ * device. This call waits for `stream` (hipStream_t or NULL), takes the
+ * word (reads and clears it with one atomic exchange, enqueued on `stream`)
+ * and writes it to *flags_h: KDE_E_NUMERIC if any bit was set since the
+ * previous check on this device, KDE_OK if none. The word is shared by every
+ * stream and thread on the device, so a plain call on another stream may
+ * set it too; sessions, batches and server requests keep words of their own.
+ */
+kde_status kde_numeric_check(void* stream, uint32_t* flags_h);
 
 /*
  * kde_workspace_size -- bytes of device workspace an operation needs.
@@ -354,10 +379,13 @@ kde_status kde_adapt_widths_exact(const kde_domain* dom, int64_t N, const void* 
  * set's first n_cv particles), kde_deposit at the set's kappa* (the pilot),
  * kde_adapt_widths with `alpha`, and kde_deposit with the resulting
  * per-particle concentrations -- in one hipGraph launch. The graph holds one
- * persistent kernel per phase; their workgroups pull work units (a set, a
- * tile pair, a particle chunk, a row block) from per-phase device counters,
- * largest sets first. Each set's outputs are bitwise identical to those of
- * the one-set calls on the same set.
+ * kernel per phase over the work units of every set, sets ordered by CV
+ * cost (largest first): the pair and deposit phases launch one workgroup
+ * per unit (a set's slot of tile pairs and concentration group, or a
+ * particle chunk); the light phases (sort, reductions, finalize, widths)
+ * launch about as many workgroups as the device keeps resident, which pull
+ * units from per-phase device counters. Each set's outputs are bitwise
+ * identical to those of the one-set calls on the same set.
  */
 typedef struct kde_batch_set {
   int64_t N;          /* particles, >= 2                                        */
@@ -389,6 +417,11 @@ kde_status kde_batch_workspace_size(const kde_batch* b, size_t* bytes_h);
  * copy) and captures the graph; later runs with the same workspace only
  * launch the graph. The workspace belongs to the batch between runs. */
 kde_status kde_batch_run(kde_batch* b, void* ws, size_t ws_bytes, void* stream);
+/* Numeric status of the last run: waits for `stream`, then writes each
+ * set's KDE_NUMERIC_* bits to flags_h[k] (nsets words, the sets' order);
+ * KDE_E_NUMERIC if any set met a non-finite position or concentration.
+ * Every run clears the words first. */
+kde_status kde_batch_status(kde_batch* b, uint32_t* flags_h, void* stream);
 kde_status kde_batch_destroy(kde_batch* b);
 
 /*
@@ -449,6 +482,8 @@ typedef struct kde_session_info {
   double kappa_star;     /* concentration of the current pilot                    */
   double last_a2, last_p;/* last A^2 and its p-value                              */
   int64_t fired;         /* CV scans triggered by the rule after t = 0            */
+  uint32_t numeric;      /* KDE_NUMERIC_* bits seen by the session's kernels      */
+  uint32_t reserved;
 } kde_session_info;
 
 enum kde_session_field { KDE_SESSION_X = 0, KDE_SESSION_V = 1, KDE_SESSION_KAPPA = 2, KDE_SESSION_RHO = 3,
@@ -460,11 +495,19 @@ typedef struct kde_session kde_session;
 kde_status kde_session_bytes(const kde_pic_params* p, size_t* bytes_h);
 /* Create a session in `arena`: copies x0 and v0 (device, N values in
  * prec; positions in [0, L)), runs the t = 0 scan and widths, and returns
- * when that work is done. The session owns one HIP stream (default
- * priority). The arena must stay valid until kde_session_destroy. */
+ * when that work is done. The copies are ordered after the work already
+ * enqueued on `stream` (the caller's hipStream_t, or NULL), so x0 and v0
+ * may come from kernels still running there; x0 and v0 may be released
+ * once this call returns. The session owns one HIP stream (default
+ * priority) for its own work. The arena must stay valid until
+ * kde_session_destroy. KDE_E_NUMERIC (and no session) if x0 holds a
+ * non-finite position. */
 kde_status kde_session_create(const kde_pic_params* p, const void* x0, const void* v0, void* arena,
-                              size_t arena_bytes, kde_session** out_h);
-/* Advance nsteps steps (returns when they are done). */
+                              size_t arena_bytes, void* stream, kde_session** out_h);
+/* Advance nsteps steps (returns when they are done). KDE_E_NUMERIC when a
+ * step met a non-finite position or width (kde_session_info.numeric says
+ * which); that step is counted, the rule and the widths are not updated.
+ * KDE_E_INVALID_ARG while the session is attached to a server. */
 kde_status kde_session_step(kde_session* s, int32_t nsteps);
 kde_status kde_session_state(const kde_session* s, kde_session_info* info_h);
 /* Copy a field to `dst` (device): X, V, KAPPA (N values in prec; KAPPA is
@@ -492,26 +535,32 @@ kde_status kde_session_destroy(kde_session* s);
 kde_status kde_damping_rate(const double* energy_h, int64_t n, double dt, double* rate_h, int64_t* peaks_h);
 
 /*
- * Request server (serving form): continuous batching of KDE solves. A
- * request is one particle set (a kde_batch_set: positions, grid, outputs)
- * taken through the whole path like one set of a batch; the CV scan uses
- * min(N, request n_cv, config n_cv) leading particles (0 = no limit).
- * Requests queue in arrival order; a scheduler thread admits them into
- * `nslots` slots (each a HIP stream of default priority) whenever a slot is
- * free and their workspaces fit in the free part of the caller's arena
- * (the HBM budget). A request's estimated work is B n_cv (n_cv - 1) / 2 CV
- * pair terms plus 2 N M deposit terms plus 5e7; it is large from
- * large_terms on. Large requests run alone, at most large_slots at a time,
- * in arrival order. Otherwise the oldest small request heads a batch,
- * joined by up to max_batch - 1 later small ones whose estimated work lies
- * between a quarter and twice the head's; small requests may pass waiting
- * large ones. Slots run concurrently, one workgroup per work unit, so they
- * share the device with each other and with other streams. A request that
- * alone needs more than the whole budget is
- * refused by kde_server_submit with KDE_E_BUDGET. Results are bitwise the
- * same whatever the mix. Latency = completion noticed by the scheduler
- * minus submission, host steady clock. The request's device buffers must
- * stay valid until its ticket completes; the arena until destroy.
+ * Request server (serving form): continuous batching of KDE solves beside
+ * resident PIC sessions. A request is one particle set (a kde_batch_set:
+ * positions, grid, outputs) taken through the whole path like one set of a
+ * batch; the CV scan uses min(N, request n_cv, config n_cv) leading
+ * particles (0 = no limit). Requests queue in arrival order; a scheduler
+ * thread admits them into `nslots` slots (each a HIP stream of default
+ * priority) whenever a slot is free and their workspaces fit in the free
+ * part of the caller's arena (the HBM budget). A request's estimated work is
+ * B n_cv (n_cv - 1) / 2 CV pair terms plus 2 N M deposit terms plus 5e7; it
+ * is large from large_terms on. Large requests run alone, at most
+ * large_slots at a time, in arrival order. Otherwise the oldest small
+ * request heads a group, joined by up to max_batch - 1 later small ones
+ * whose estimated work lies between a quarter and twice the head's; small
+ * requests may pass waiting large ones. Slots run concurrently, one
+ * workgroup per work unit, so they share the device with each other and
+ * with the attached sessions' streams. Attached sessions (kde_server_attach)
+ * are charged their arena bytes against the budget and stepped by the same
+ * thread, one step in flight each, never blocking it. A request that alone
+ * needs more than the whole budget is refused by kde_server_submit with
+ * KDE_E_BUDGET. Results are bitwise the same whatever the mix. A failure
+ * stays with its own work: a group whose device work fails completes its
+ * requests with that status, a session whose step fails completes its
+ * ticket, and the server goes on. Latency = completion noticed by the
+ * scheduler minus submission, host steady clock. The request's device
+ * buffers must stay valid until its ticket completes; the arena until
+ * destroy.
  */
 typedef struct kde_server_config {
   int32_t prec;          /* KDE_F64 or KDE_F32 for every request                  */
@@ -526,9 +575,11 @@ typedef struct kde_server_config {
 } kde_server_config;
 
 typedef struct kde_result {
-  int32_t status;        /* KDE_OK                                                */
+  int32_t status;        /* KDE_OK, KDE_E_NUMERIC (a non-finite position or width
+                            in the set), KDE_E_CANCELLED, KDE_E_HIP             */
   int32_t batch_size;    /* requests admitted together with this one              */
   double latency_s, queue_s, run_s;  /* total, waiting, on the device             */
+  int64_t steps;         /* attached sessions: steps taken                        */
 } kde_result;
 
 typedef struct kde_server_stats_t {
@@ -537,6 +588,9 @@ typedef struct kde_server_stats_t {
   double p50_s, p99_s, mean_s, max_s;  /* latency of completed requests          */
   double wall_s;         /* first submission to last completion                   */
   double requests_per_s, pair_evals, particles;
+  int64_t failed, cancelled;           /* requests that ended otherwise          */
+  int64_t session_steps;               /* steps of attached sessions             */
+  double session_p50_s, session_p99_s; /* their step latency (begin to done)     */
 } kde_server_stats_t;
 
 typedef struct kde_server kde_server;
@@ -544,12 +598,34 @@ typedef struct kde_server kde_server;
 kde_status kde_server_create(const kde_server_config* cfg, void* arena, size_t budget_bytes, kde_server** out_h);
 /* Workspace bytes one request needs when admitted alone. */
 kde_status kde_server_request_bytes(const kde_server* s, const kde_batch_set* req_h, size_t* bytes_h);
-kde_status kde_server_submit(kde_server* s, const kde_batch_set* req_h, uint64_t* ticket_h);
-/* KDE_OK and the result once done, KDE_E_AGAIN while pending. */
+/* Queue a request. Its work follows everything already enqueued on `stream`
+ * (the submitter's hipStream_t, or NULL) at the time of the call, so the
+ * positions may come from kernels still running there. */
+kde_status kde_server_submit(kde_server* s, const kde_batch_set* req_h, void* stream, uint64_t* ticket_h);
+/*
+ * kde_server_attach -- hand a resident session (Sec. III.A step with the
+ * Sec. II.D rule) to the server for nsteps steps: the scheduler thread
+ * advances it beside the requests, one step in flight at a time, charging
+ * the session's arena bytes against the budget while it is attached
+ * (KDE_E_BUDGET if they do not fit in the largest free block). The ticket
+ * completes (kde_server_poll) when the steps are done, or with the status
+ * of a step that failed (KDE_E_NUMERIC for non-finite values). Until then the
+ * caller must not use the session. Step latencies enter kde_server_stats.
+ */
+kde_status kde_server_attach(kde_server* s, kde_session* session, int64_t nsteps, uint64_t* ticket_h);
+/* Withdraw a queued request: KDE_OK (its result is KDE_E_CANCELLED),
+ * KDE_E_AGAIN when it already runs (it will complete), KDE_E_NOT_FOUND
+ * otherwise. */
+kde_status kde_server_cancel(kde_server* s, uint64_t ticket);
+/* KDE_OK and the result once done, KDE_E_AGAIN while pending; a ticket that
+ * ended otherwise returns its status (res_h filled). */
 kde_status kde_server_poll(kde_server* s, uint64_t ticket, kde_result* res_h);
-/* Wait until every submitted request has completed. */
+/* Wait until every submitted request has completed and every attached
+ * session has taken its steps. */
 kde_status kde_server_drain(kde_server* s);
 kde_status kde_server_stats(kde_server* s, kde_server_stats_t* st_h);
+/* Queued requests are dropped; running ones and the attached sessions'
+ * steps in flight finish first. */
 kde_status kde_server_destroy(kde_server* s);
 
 /* Upper-tail p-value of an Anderson-Darling statistic under its limiting
@@ -576,53 +652,6 @@ kde_status kde_ad_pvalue(double a2, double* p_h);
 kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h,
                         const int32_t* group_h);
 kde_status kde_tune_get(int32_t prec, int64_t N, int32_t* chunk_h, int32_t* group_h);
-
-/*
- * Kernel timing (diagnostics). While enabled, the library brackets every
- * launch of the kernels named below with a pair of HIP events recorded on
- * the launching call's stream. kde_timing_read waits for the recorded
- * events, adds their elapsed times to the kernel's running total and
- * returns it with the number of launches; kde_timing_reset clears all
- * totals. Events are host-side HIP objects: no device memory is
- * allocated. Enabling costs two event records per bracketed launch.
- */
-enum kde_kernel_id {
-  KDE_KERNEL_CV_PAIRS = 0,   /* the O(N^2) pair-sum kernel of kde_cv_scan   */
-  KDE_KERNEL_DEPOSIT = 1,    /* the per-chunk grid kernel of kde_deposit     */
-  KDE_KERNEL_GATHER = 2,     /* the per-particle kernel of kde_gather        */
-  KDE_KERNEL_ADAPT = 3,      /* both per-particle passes of kde_adapt_widths */
-  KDE_KERNEL_MOMENTS = 4,    /* the Fourier-moment kernel of the Fourier ops  */
-  KDE_KERNEL_PROBE = 5,      /* the kernel of kde_probe_peak                  */
-  KDE_KERNEL_COUNT = 6
-};
-kde_status kde_timing_enable(int32_t on);
-kde_status kde_timing_reset(void);
-kde_status kde_timing_read(int32_t kernel_id, double* total_ms_h, int64_t* launches_h);
-
-/*
- * kde_probe_peak -- issue-rate probe (diagnostics, for pricing rooflines on
- * the device at hand rather than from its datasheet). Launches `blocks`
- * workgroups of 256 threads; every thread runs 8 independent dependency
- * chains of `iters` steps of one instruction kind and writes the sum of its
- * chains to out[thread]. Timed with kde_timing_* under KDE_KERNEL_PROBE,
- * the sustained rate is blocks x 256 x 8 x iters lane-operations per
- * elapsed second (an FMA counts as one).
- *   kind   : KDE_PROBE_FMA_F64 (double FMA), KDE_PROBE_FMA_F32 (float FMA,
- *            not packed), KDE_PROBE_EXP_F32 (the hardware base-2
- *            exponential), KDE_PROBE_ADD_F64 (double add).
- *   blocks : 1 .. 65536.
- *   iters  : a multiple of 4 in [4, 2^30].
- *   out    : device, blocks x 256 doubles (written; values are meaningless).
- * Errors: KDE_E_INVALID_ARG for an unknown kind, NULL out or sizes out of
- * range (nothing is launched).
- */
-enum kde_probe_kind {
-  KDE_PROBE_FMA_F64 = 0,
-  KDE_PROBE_FMA_F32 = 1,
-  KDE_PROBE_EXP_F32 = 2,
-  KDE_PROBE_ADD_F64 = 3
-};
-kde_status kde_probe_peak(int32_t kind, int32_t blocks, int64_t iters, double* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,8 @@ class kde_pic_params(ctypes.Structure):
 class kde_session_info(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("p_th", ctypes.c_double), ("h_opt", ctypes.c_double),
                 ("h_target", ctypes.c_double), ("kappa_star", ctypes.c_double), ("last_a2", ctypes.c_double),
-                ("last_p", ctypes.c_double), ("fired", ctypes.c_int64)]
+                ("last_p", ctypes.c_double), ("fired", ctypes.c_int64), ("numeric", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class kde_server_config(ctypes.Structure):
@@ -72,7 +73,7 @@ class kde_server_config(ctypes.Structure):
 
 class kde_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("latency_s", ctypes.c_double),
-                ("queue_s", ctypes.c_double), ("run_s", ctypes.c_double)]
+                ("queue_s", ctypes.c_double), ("run_s", ctypes.c_double), ("steps", ctypes.c_int64)]
 
 
 class kde_server_stats_t(ctypes.Structure):
@@ -80,7 +81,9 @@ class kde_server_stats_t(ctypes.Structure):
                 ("launches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("p50_s", ctypes.c_double),
                 ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double),
                 ("wall_s", ctypes.c_double), ("requests_per_s", ctypes.c_double), ("pair_evals", ctypes.c_double),
-                ("particles", ctypes.c_double)]
+                ("particles", ctypes.c_double), ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("session_steps", ctypes.c_int64), ("session_p50_s", ctypes.c_double),
+                ("session_p99_s", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -94,6 +97,7 @@ _SIGNATURES = {
     "kde_abi_version": (_i32, []),
     "kde_status_str": (ctypes.c_char_p, [_i32]),
     "kde_last_error": (ctypes.c_char_p, []),
+    "kde_numeric_check": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
     "kde_workspace_size": (_i32, [_i32, _dom_p, _i64, _i32, ctypes.POINTER(_sz)]),
     "kde_cv_scan": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp, _sz, _vp]),
     "kde_cv_scan_noalloc": (_i32, [_dom_p, _i64, _vp, _i32, ctypes.POINTER(_dbl), _vp, _vp, _vp, _vp]),
@@ -113,9 +117,10 @@ _SIGNATURES = {
                               ctypes.POINTER(_vp)]),
     "kde_batch_workspace_size": (_i32, [_vp, ctypes.POINTER(_sz)]),
     "kde_batch_run": (_i32, [_vp, _vp, _sz, _vp]),
+    "kde_batch_status": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), _vp]),
     "kde_batch_destroy": (_i32, [_vp]),
     "kde_session_bytes": (_i32, [ctypes.POINTER(kde_pic_params), ctypes.POINTER(_sz)]),
-    "kde_session_create": (_i32, [ctypes.POINTER(kde_pic_params), _vp, _vp, _vp, _sz, ctypes.POINTER(_vp)]),
+    "kde_session_create": (_i32, [ctypes.POINTER(kde_pic_params), _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     "kde_session_step": (_i32, [_vp, _i32]),
     "kde_session_state": (_i32, [_vp, ctypes.POINTER(kde_session_info)]),
     "kde_session_read": (_i32, [_vp, _i32, _vp]),
@@ -126,7 +131,9 @@ _SIGNATURES = {
     "kde_damping_rate": (_i32, [ctypes.POINTER(_dbl), _i64, _dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "kde_server_create": (_i32, [ctypes.POINTER(kde_server_config), _vp, _sz, ctypes.POINTER(_vp)]),
     "kde_server_request_bytes": (_i32, [_vp, ctypes.POINTER(kde_batch_set), ctypes.POINTER(_sz)]),
-    "kde_server_submit": (_i32, [_vp, ctypes.POINTER(kde_batch_set), ctypes.POINTER(ctypes.c_uint64)]),
+    "kde_server_submit": (_i32, [_vp, ctypes.POINTER(kde_batch_set), _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "kde_server_attach": (_i32, [_vp, _vp, _i64, ctypes.POINTER(ctypes.c_uint64)]),
+    "kde_server_cancel": (_i32, [_vp, ctypes.c_uint64]),
     "kde_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(kde_result)]),
     "kde_server_drain": (_i32, [_vp]),
     "kde_server_stats": (_i32, [_vp, ctypes.POINTER(kde_server_stats_t)]),
@@ -136,7 +143,9 @@ _SIGNATURES = {
 KDE_SESSION_X, KDE_SESSION_V, KDE_SESSION_KAPPA, KDE_SESSION_RHO, KDE_SESSION_E = 0, 1, 2, 3, 4
 KDE_SESSION_ENERGY = 5
 KDE_PIC_KDE, KDE_PIC_STANDARD = 0, 1
-KDE_E_AGAIN, KDE_E_BUDGET = 4, 3
+KDE_E_INVALID_ARG, KDE_E_WORKSPACE, KDE_E_BUDGET, KDE_E_AGAIN, KDE_E_NOT_FOUND = 1, 2, 3, 4, 5
+KDE_E_HIP, KDE_E_NUMERIC, KDE_E_INTERNAL, KDE_E_CANCELLED = 6, 7, 8, 9
+KDE_NUMERIC_POSITION, KDE_NUMERIC_CONCENTRATION = 1, 2
 
 TUNE_FILE = os.path.join(HERE, "tune_gfx950.json")
 
@@ -236,6 +245,17 @@ def kde_status_str(status: int) -> str:
 
 def kde_last_error() -> str:
     return require_library().kde_last_error().decode()
+
+
+def kde_numeric_check(stream=None) -> int:
+    """Wait for the stream and take the plain calls' numeric status word
+    (KDE_NUMERIC_* bits; 0 when no non-finite value was seen since the last
+    check on this device). Returns the bits; does not raise."""
+    flags = ctypes.c_uint32(0)
+    st = require_library().kde_numeric_check(_stream(stream), ctypes.byref(flags))
+    if st not in (0, KDE_E_NUMERIC):
+        _check(st, "kde_numeric_check")
+    return int(flags.value)
 
 
 def kde_workspace_size(op: int, dom: kde_domain, N: int, B: int = 0) -> int:
@@ -346,6 +366,15 @@ def kde_batch_run(handle: int, ws, ws_bytes: int, stream=None):
     _check(require_library().kde_batch_run(handle, ws, int(ws_bytes), _stream(stream)), "kde_batch_run")
 
 
+def kde_batch_status(handle: int, nsets: int, stream=None):
+    """Per-set KDE_NUMERIC_* bits of the last run (waits for the stream)."""
+    flags = (ctypes.c_uint32 * nsets)()
+    st = require_library().kde_batch_status(handle, flags, _stream(stream))
+    if st not in (0, KDE_E_NUMERIC):
+        _check(st, "kde_batch_status")
+    return [int(f) for f in flags]
+
+
 def kde_batch_destroy(handle: int):
     _check(require_library().kde_batch_destroy(handle), "kde_batch_destroy")
 
@@ -428,10 +457,10 @@ def kde_session_bytes(params) -> int:
     return int(out.value)
 
 
-def kde_session_create(params, x0, v0, arena, arena_bytes) -> int:
+def kde_session_create(params, x0, v0, arena, arena_bytes, stream=None) -> int:
     h = _vp()
     _check(require_library().kde_session_create(ctypes.byref(params), _ptr(x0), _ptr(v0), arena, int(arena_bytes),
-                                                ctypes.byref(h)), "kde_session_create")
+                                                _stream(stream), ctypes.byref(h)), "kde_session_create")
     return h.value
 
 
@@ -542,19 +571,38 @@ def kde_server_request_bytes(handle, req) -> int:
     return int(out.value)
 
 
-def kde_server_submit(handle, req) -> int:
+def kde_server_submit(handle, req, stream=None) -> int:
     t = ctypes.c_uint64(0)
-    _check(require_library().kde_server_submit(handle, ctypes.byref(req), ctypes.byref(t)), "kde_server_submit")
+    _check(require_library().kde_server_submit(handle, ctypes.byref(req), _stream(stream), ctypes.byref(t)),
+           "kde_server_submit")
     return int(t.value)
 
 
+def kde_server_attach(handle, session_handle, nsteps: int) -> int:
+    t = ctypes.c_uint64(0)
+    _check(require_library().kde_server_attach(handle, session_handle, int(nsteps), ctypes.byref(t)),
+           "kde_server_attach")
+    return int(t.value)
+
+
+def kde_server_cancel(handle, ticket: int) -> bool:
+    """True when the queued request was withdrawn, False when it already runs."""
+    st = require_library().kde_server_cancel(handle, ctypes.c_uint64(ticket))
+    if st == KDE_E_AGAIN:
+        return False
+    _check(st, "kde_server_cancel")
+    return True
+
+
 def kde_server_poll(handle, ticket: int):
-    """The result as a dict once done, else None."""
+    """The result as a dict once done (``status`` 0, or the status it ended
+    with: numeric, cancelled, HIP), else None while pending."""
     r = kde_result()
     st = require_library().kde_server_poll(handle, ctypes.c_uint64(ticket), ctypes.byref(r))
     if st == KDE_E_AGAIN:
         return None
-    _check(st, "kde_server_poll")
+    if st not in (0, KDE_E_NUMERIC, KDE_E_CANCELLED, KDE_E_HIP):
+        _check(st, "kde_server_poll")
     return {f: getattr(r, f) for f, _ in kde_result._fields_}
 
 
@@ -595,8 +643,15 @@ class Server:
         return kde_batch_set(int(x.shape[0]), _ptr(x), float(L), int(M), 0, int(n_cv), _ptr(cv), _ptr(pilot),
                              _ptr(rho), _ptr(k_i), _ptr(ks))
 
-    def submit(self, req) -> int:
-        return kde_server_submit(self.handle, req)
+    def submit(self, req, stream=None) -> int:
+        return kde_server_submit(self.handle, req, stream)
+
+    def attach(self, session, nsteps: int) -> int:
+        """Hand a Session to the server for nsteps steps; poll the ticket."""
+        return kde_server_attach(self.handle, session.handle, nsteps)
+
+    def cancel(self, ticket) -> bool:
+        return kde_server_cancel(self.handle, ticket)
 
     def poll(self, ticket):
         return kde_server_poll(self.handle, ticket)

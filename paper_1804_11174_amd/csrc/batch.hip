@@ -65,6 +65,7 @@ struct SetDev {
   double* cv;         // B or NULL
   double* kstar;      // 1
   double* kstar_user; // 1 or NULL
+  uint32_t* status;   // the set's numeric status word (KDE_NUMERIC_* bits)
 };
 
 // Unit prefix sums, one array of nsets + 1 per multi-unit phase.
@@ -74,6 +75,7 @@ struct BatchArgs {
   const SetDev* sets;
   const int64_t* prefix;  // PF_COUNT x (nsets + 1)
   unsigned long long* counters;
+  uint32_t* statuses;     // nsets numeric status words, in the caller's set order
   int nsets;
   int B;
   double alpha;
@@ -114,8 +116,10 @@ __device__ __forceinline__ int64_t claim(unsigned long long* counter, int64_t* s
   return uni64(v);
 }
 
-__global__ void __launch_bounds__(kBlock) batch_zero_kernel(unsigned long long* counters) {
+__global__ void __launch_bounds__(kBlock) batch_zero_kernel(unsigned long long* counters, uint32_t* statuses,
+                                                            int nsets) {
   if (threadIdx.x < kCounters) counters[threadIdx.x] = 0ull;
+  for (int k = threadIdx.x; k < nsets; k += kBlock) statuses[k] = 0u;
 }
 
 // The stable cell sort of every set's CV prefix in three phases, with the
@@ -135,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) batch_sort_hist_kernel(BatchArgs a) {
     const int b = int(u - pf[si]);
     const int64_t lo = int64_t(b) * s.schunk;
     sort_hist_block<T>(static_cast<const T*>(s.x), lo, min(s.n_cv, lo + s.schunk), s.L, s.cells, b, s.sblocks, lh,
-                       s.hist);
+                       s.hist, s.status);
   }
 }
 
@@ -263,7 +267,8 @@ __global__ void __launch_bounds__(kBlock) batch_deposit_kernel(BatchArgs a) {
   const int64_t lo = c * chunk;
   const int cnt = int(min(int64_t(chunk), uni64(s.n) - lo));
   deposit_block<T, PER, G>(uni_ptr(static_cast<const T*>(s.x)), uni_ptr(static_cast<const T*>(s.kappa_i)),
-                           PER ? 0.0 : *s.kstar, M, s.L, lo, cnt, uni_ptr(s.dep_part) + c * M, ts, tc, sm);
+                           PER ? 0.0 : *s.kstar, M, s.L, lo, cnt, uni_ptr(s.dep_part) + c * M, ts, tc, sm,
+                           uni_ptr(s.status));
 }
 
 // Level 2 of every set: the pilot (scaled by 1/N), the log sums, or rho.
@@ -296,7 +301,8 @@ __global__ void __launch_bounds__(kBlock) batch_adapt_log_kernel(BatchArgs a) {
     const int si = find_set(pf, a.nsets, u);
     const SetDev& s = a.sets[si];
     const int64_t b = u - pf[si];
-    adapt_logsum_block<T>(static_cast<const T*>(s.x), s.n, s.M, s.L, s.pilot, b, s.ad_part + 2 * b, r0, r1);
+    adapt_logsum_block<T>(static_cast<const T*>(s.x), s.n, s.M, s.L, s.pilot, b, s.ad_part + 2 * b, r0, r1,
+                          s.status);
   }
 }
 
@@ -321,10 +327,12 @@ __global__ void __launch_bounds__(kBlock) batch_adapt_apply_kernel(BatchArgs a) 
 // Lay out the workspace; with ws == nullptr only sizes it. Fills host
 // images of the descriptors and prefix arrays.
 static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* descs, std::vector<int64_t>* prefix,
-                           unsigned long long** counters, SetDev** dev_sets, int64_t** dev_prefix) {
+                           unsigned long long** counters, SetDev** dev_sets, int64_t** dev_prefix,
+                           uint32_t** statuses_out = nullptr) {
   Carver c(ws, ~size_t(0));
   const int ns = int(b.sets.size());
   unsigned long long* cnt = c.take<unsigned long long>(kCounters);
+  uint32_t* statuses = c.take<uint32_t>(size_t(ns));
   SetDev* ds = c.take<SetDev>(ns);
   int64_t* dp = c.take<int64_t>(size_t(PF_COUNT) * (ns + 1));
   if (descs) descs->assign(ns, SetDev{});
@@ -369,6 +377,7 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
     d.cv = in.cv;
     d.kstar = c.take<double>(1);
     d.kstar_user = in.kappa_star;
+    d.status = statuses + b.order[r];
     if (descs) (*descs)[r] = d;
     const int64_t per[PF_COUNT] = {d.slots * d.groups, d.g_cv, d.chunks, d.g_dep, d.blocks, d.g_ad, int64_t(d.sblocks)};
     for (int k = 0; k < PF_COUNT; ++k) {
@@ -379,6 +388,7 @@ static size_t layout_batch(const BatchPlan& b, void* ws, std::vector<SetDev>* de
   for (int k = 0; k < PF_COUNT; ++k)
     if (prefix) (*prefix)[size_t(k) * (ns + 1) + ns] = acc[k];
   if (counters) *counters = cnt;
+  if (statuses_out) *statuses_out = statuses;
   if (dev_sets) *dev_sets = ds;
   if (dev_prefix) *dev_prefix = dp;
   return c.used;
@@ -423,7 +433,7 @@ static kde_status enqueue_batch(const BatchPlan& b, const BatchArgs& a, const st
   const size_t dep_lds = 2 * size_t(b.max_M) * sizeof(T);
   const size_t pack_lds = size_t(b.max_cells) * sizeof(int);
 
-  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(kBlock), 0, s, a.counters);
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(kBlock), 0, s, a.counters, a.statuses, ns);
   KDE_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_sort_hist_kernel<T>, dim3(launch_grid(b, batch_sort_hist_kernel<T>, pack_lds, total(PF_SORT))),
                      dim3(kBlock), pack_lds, s, a);
@@ -517,8 +527,9 @@ static void batch_images(const BatchPlan& b, void* ws, std::vector<SetDev>& desc
   unsigned long long* counters = nullptr;
   SetDev* dsets = nullptr;
   int64_t* dpref = nullptr;
-  layout_batch(b, ws, &descs, &prefix, &counters, &dsets, &dpref);
-  a = BatchArgs{dsets, dpref, counters, int(b.sets.size()), b.B, b.alpha};
+  uint32_t* statuses = nullptr;
+  layout_batch(b, ws, &descs, &prefix, &counters, &dsets, &dpref, &statuses);
+  a = BatchArgs{dsets, dpref, counters, statuses, int(b.sets.size()), b.B, b.alpha};
 }
 
 kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int B, const double* kappas_h,
@@ -577,9 +588,23 @@ kde_status batch_plan_make(const kde_batch_set* sets_h, int nsets, int prec, int
   return KDE_OK;
 }
 
-size_t batch_staging_bytes(const BatchPlan& b) {
+static size_t staged_status_offset(const BatchPlan& b) {
   const size_t ns = b.sets.size();
-  return ns * sizeof(SetDev) + size_t(PF_COUNT) * (ns + 1) * sizeof(int64_t) + 64;
+  return round_up(ns * sizeof(SetDev) + size_t(PF_COUNT) * (ns + 1) * sizeof(int64_t), 64);
+}
+
+size_t batch_staging_bytes(const BatchPlan& b) {
+  return staged_status_offset(b) + b.sets.size() * sizeof(uint32_t) + 64;
+}
+
+const uint32_t* batch_staged_status(const BatchPlan& b, const void* staging_h) {
+  return reinterpret_cast<const uint32_t*>(static_cast<const char*>(staging_h) + staged_status_offset(b));
+}
+
+uint32_t* batch_status_words(const BatchPlan& b, void* ws) {
+  uint32_t* st = nullptr;
+  layout_batch(b, ws, nullptr, nullptr, nullptr, nullptr, nullptr, &st);
+  return st;
 }
 
 kde_status batch_plan_enqueue(const BatchPlan& b, void* ws, hipStream_t s, void* staging_h) {
@@ -593,7 +618,10 @@ kde_status batch_plan_enqueue(const BatchPlan& b, void* ws, hipStream_t s, void*
   memcpy(st + db, prefix.data(), pb);
   KDE_TRY_HIP(hipMemcpyAsync(const_cast<SetDev*>(a.sets), st, db, hipMemcpyHostToDevice, s));
   KDE_TRY_HIP(hipMemcpyAsync(const_cast<int64_t*>(a.prefix), st + db, pb, hipMemcpyHostToDevice, s));
-  return b.prec == KDE_F64 ? enqueue_batch_t<double>(b, a, prefix, s) : enqueue_batch_t<float>(b, a, prefix, s);
+  KDE_RETURN_IF(b.prec == KDE_F64 ? enqueue_batch_t<double>(b, a, prefix, s) : enqueue_batch_t<float>(b, a, prefix, s));
+  KDE_TRY_HIP(hipMemcpyAsync(st + staged_status_offset(b), a.statuses, b.sets.size() * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+  return KDE_OK;
 }
 
 // Upload descriptors and capture the graph for workspace `ws`.
@@ -663,6 +691,19 @@ kde_status kde_batch_run(kde_batch* b, void* ws, size_t ws_bytes, void* stream) 
   if (!b->graph.exec || b->graph.ws != ws || b->graph.ws_bytes != ws_bytes)
     KDE_RETURN_IF(build_graph(b->graph, im, ws, ws_bytes));
   KDE_TRY_HIP(hipGraphLaunch(b->graph.exec, static_cast<hipStream_t>(stream)));
+  return KDE_OK;
+}
+
+kde_status kde_batch_status(kde_batch* b, uint32_t* flags_h, void* stream) {
+  clear_error();
+  if (!b || !flags_h) return fail(KDE_E_INVALID_ARG, "batch and flags_h must not be NULL");
+  if (!b->graph.exec) return fail(KDE_E_INVALID_ARG, "the batch has not been run");
+  KDE_TRY_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  const size_t ns = b->plan.sets.size();
+  KDE_TRY_HIP(hipMemcpy(flags_h, batch_status_words(b->plan, b->graph.ws), ns * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost));
+  for (size_t k = 0; k < ns; ++k)
+    if (flags_h[k]) return fail(KDE_E_NUMERIC, "set %zu met non-finite values (flags %u)", k, flags_h[k]);
   return KDE_OK;
 }
 

@@ -54,6 +54,13 @@ size_t batch_staging_bytes(const BatchPlan& b);
 // `staging_h` (pinned host memory of batch_staging_bytes, which must stay
 // untouched until the work has completed) by asynchronous copies, then the
 // phase kernels are launched. `ws` holds plan.ws_need bytes.
+// The sets' numeric status words follow the descriptors in the staging:
+// the enqueue ends with their copy to the host, so once the work has
+// completed, batch_staged_status(b, staging_h)[k] is set k's word (caller
+// order).
 kde_status batch_plan_enqueue(const BatchPlan& b, void* ws, hipStream_t s, void* staging_h);
+const uint32_t* batch_staged_status(const BatchPlan& b, const void* staging_h);
+// Device address of the sets' status words inside workspace `ws`.
+uint32_t* batch_status_words(const BatchPlan& b, void* ws);
 
 }  // namespace kde

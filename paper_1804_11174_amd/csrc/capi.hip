@@ -8,20 +8,6 @@
 
 namespace kde {
 
-// implemented in cv.hip / density.hip
-size_t cv_workspace_bytes(int64_t n, int B, int prec);
-kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
-                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s);
-size_t deposit_workspace_bytes(int64_t n, int M);
-size_t adapt_workspace_bytes(int64_t n);
-kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
-                   void* ws, size_t ws_bytes, hipStream_t s);
-kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
-                  const double* field, void* out, hipStream_t s);
-kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
-                        double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
-                        hipStream_t s);
-
 static thread_local char g_err[512];
 
 kde_status fail(kde_status code, const char* fmt, ...) {
@@ -122,6 +108,7 @@ const char* kde_status_str(kde_status s) {
     case KDE_E_HIP: return "HIP runtime error";
     case KDE_E_NUMERIC: return "non-finite value";
     case KDE_E_INTERNAL: return "internal error";
+    case KDE_E_CANCELLED: return "cancelled";
     default: return "unknown status";
   }
 }
@@ -194,7 +181,8 @@ kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t 
   clear_error();
   KDE_RETURN_IF(check_cv_args(dom, N, x, B, kappas_h, cv));
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, cv_workspace_bytes(N, B, dom->prec)));
-  return cv_scan(dom, N, x, B, kappas_h, cv, sums, argmin, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return cv_scan(dom, N, x, B, kappas_h, cv, sums, argmin, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                 plain_numeric_word());
 }
 
 kde_status kde_deposit(const kde_domain* dom, int64_t N, const void* x, const void* kappa_i, double kappa,
@@ -205,7 +193,8 @@ kde_status kde_deposit(const kde_domain* dom, int64_t N, const void* x, const vo
   if (!x || !rho) return fail(KDE_E_INVALID_ARG, "x and rho must not be NULL");
   if (!kappa_i) KDE_RETURN_IF(check_kappa(dom, kappa, "kappa"));
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, deposit_workspace_bytes(N, dom->M)));
-  return deposit(dom, N, x, kappa_i, kappa, rho, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return deposit(dom, N, x, kappa_i, kappa, rho, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                 plain_numeric_word());
 }
 
 kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const void* kappa_i, double kappa,
@@ -217,7 +206,7 @@ kde_status kde_gather(const kde_domain* dom, int64_t N, const void* x, const voi
   KDE_RETURN_IF(check_n(N, 1));
   if (!x || !field || !out) return fail(KDE_E_INVALID_ARG, "x, field and out must not be NULL");
   if (!kappa_i) KDE_RETURN_IF(check_kappa(dom, kappa, "kappa"));
-  return gather(dom, N, x, kappa_i, kappa, field, out, static_cast<hipStream_t>(stream));
+  return gather(dom, N, x, kappa_i, kappa, field, out, static_cast<hipStream_t>(stream), plain_numeric_word());
 }
 
 kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, const double* pilot,
@@ -232,7 +221,7 @@ kde_status kde_adapt_widths(const kde_domain* dom, int64_t N, const void* x, con
   if (!std::isfinite(alpha) || alpha < 0.0) return fail(KDE_E_INVALID_ARG, "alpha must be finite and >= 0 (got %g)", alpha);
   KDE_RETURN_IF(check_workspace(ws, ws_bytes, adapt_workspace_bytes(N)));
   return adapt_widths(dom, N, x, pilot, kappa_star, alpha, kappa_out, log_geomean, n_floored, ws, ws_bytes,
-                      static_cast<hipStream_t>(stream));
+                      static_cast<hipStream_t>(stream), plain_numeric_word());
 }
 
 }  // extern "C"

@@ -191,14 +191,14 @@ size_t cv_workspace_bytes(int64_t n, int B, int prec) {
 template <typename T>
 static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, const double* kappas,
                          double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes,
-                         hipStream_t s) {
+                         hipStream_t s, uint32_t* status) {
   CvPlan p = make_cv_plan(n);
   Carver c(ws, ws_bytes);
   CvBuffers buf = carve_cv(c, p, n, B, dom->prec);
   if (!c.fits()) return fail(KDE_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.used);
   using P = typename Packed<T>::type;
   P* packed = static_cast<P*>(buf.packed);
-  KDE_RETURN_IF(launch_pack_sorted<T>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s));
+  KDE_RETURN_IF(launch_pack_sorted<T>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s, status));
   CvConsts<T> K = make_consts<T>(kappas, B);
   const PairTuning tp = tuned_pass(dom->prec, n);
   const int groups = pair_groups(tp, B), gsize = pair_group_size(tp, B);
@@ -235,14 +235,15 @@ constexpr int kTriPass = 8;
 
 template <typename T>
 static kde_status run_cv_tri(const kde_domain* dom, int64_t n, const T* x, int B, const double* widths,
-                             double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s) {
+                             double* cv, double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s,
+                             uint32_t* status) {
   CvPlan p = make_cv_plan(n);
   Carver c(ws, ws_bytes);
   CvBuffers buf = carve_cv(c, p, n, B, dom->prec);
   if (!c.fits()) return fail(KDE_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.used);
   using P = typename TriPacked<T>::type;
   P* packed = static_cast<P*>(buf.packed);
-  KDE_RETURN_IF((launch_pack_sorted_as<T, P>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s)));
+  KDE_RETURN_IF((launch_pack_sorted_as<T, P>(x, n, dom->L, p.sort, buf.hist, packed, nullptr, s, status)));
   const TriConsts<T> K = make_tri_consts<T>(widths, B, dom->L);
   {
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
@@ -260,15 +261,18 @@ static kde_status run_cv_tri(const kde_domain* dom, int64_t n, const T* x, int B
 }
 
 kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
-                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s) {
+                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s, uint32_t* status) {
   if (dom->shape == KDE_SHAPE_TRIANGLE) {
     if (dom->prec == KDE_F64)
-      return run_cv_tri<double>(dom, n, static_cast<const double*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
-    return run_cv_tri<float>(dom, n, static_cast<const float*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
+      return run_cv_tri<double>(dom, n, static_cast<const double*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s,
+                                status);
+    return run_cv_tri<float>(dom, n, static_cast<const float*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s,
+                             status);
   }
   if (dom->prec == KDE_F64)
-    return run_cv<double>(dom, n, static_cast<const double*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
-  return run_cv<float>(dom, n, static_cast<const float*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s);
+    return run_cv<double>(dom, n, static_cast<const double*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s,
+                          status);
+  return run_cv<float>(dom, n, static_cast<const float*>(x), B, kappas, cv, sums, argmin, ws, ws_bytes, s, status);
 }
 
 }  // namespace kde

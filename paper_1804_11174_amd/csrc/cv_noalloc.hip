@@ -20,10 +20,6 @@
 
 namespace kde {
 
-size_t cv_workspace_bytes(int64_t n, int B, int prec);
-kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
-                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s);
-
 static __device__ __align__(256) unsigned char scratch[KDE_CV_NOALLOC_MAX_BYTES];
 
 namespace {
@@ -65,7 +61,7 @@ kde_status kde_cv_scan_noalloc(const kde_domain* dom, int64_t N, const void* x, 
   void* ws = nullptr;
   KDE_RETURN_IF(scratch_on_current_device(&ws));
   return cv_scan(dom, N, x, B, kappas_h, cv, sums, argmin, ws, size_t(KDE_CV_NOALLOC_MAX_BYTES),
-                 static_cast<hipStream_t>(stream));
+                 static_cast<hipStream_t>(stream), plain_numeric_word());
 }
 
 }  // extern "C"

@@ -32,7 +32,7 @@ namespace kde {
 template <typename T, bool PER, int G>
 __global__ void __launch_bounds__(kBlock) deposit_kernel(const T* __restrict__ x, const T* __restrict__ kap,
                                                         double kappa_g, int64_t n, int M, double L, int chunk,
-                                                        double* __restrict__ partials) {
+                                                        double* __restrict__ partials, uint32_t* status) {
   __shared__ DepSmem<T> sm;
   extern __shared__ __align__(16) unsigned char dyn[];
   T* ts = reinterpret_cast<T*>(dyn);
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(const T* __restrict__ x
   node_table(M, ts, tc);
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int cnt = int(min(int64_t(chunk), n - lo));
-  deposit_block<T, PER, G>(x, kap, kappa_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, ts, tc, sm);
+  deposit_block<T, PER, G>(x, kap, kappa_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, ts, tc, sm, status);
 }
 
 // S adjacent lanes per particle (S = 1, 2, 4 or 8, from gather_split), lane
@@ -54,7 +54,8 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(const T* __restrict__ x
 template <typename T, int S>
 __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x, const T* __restrict__ kap,
                                                        double kappa_g, bool per, int64_t n, int M, double L,
-                                                       const double* __restrict__ field, T* __restrict__ out) {
+                                                       const double* __restrict__ field, T* __restrict__ out,
+                                                       uint32_t* status) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ double etab[std::is_same<T, double>::value ? 256 : 1];
   T* ts = reinterpret_cast<T*>(dyn);
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   PGeo<T> gp;
   make_geo(xw, L, M, gp);
   const double kk = per ? double(kap[i]) : kappa_g;
+  if (j == 0) note_numeric(status, !isfinite(xi), per && !(isfinite(kk) && kk >= 0.0));
   const T A = T(-2.0 * kk * Flt<T>::unit);
   const double w = (L / M) / (L * i0e_f64(kk));
   SumOf<T> acc;
@@ -122,9 +124,9 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
 template <typename T>
 __global__ void __launch_bounds__(kBlock) adapt_logsum_kernel(const T* __restrict__ x, int64_t n, int M, double L,
                                                              const double* __restrict__ pilot,
-                                                             double* __restrict__ partials) {
+                                                             double* __restrict__ partials, uint32_t* status) {
   __shared__ double r0[kBlock / 64], r1[kBlock / 64];
-  adapt_logsum_block<T>(x, n, M, L, pilot, blockIdx.x, partials + 2 * int64_t(blockIdx.x), r0, r1);
+  adapt_logsum_block<T>(x, n, M, L, pilot, blockIdx.x, partials + 2 * int64_t(blockIdx.x), r0, r1, status);
 }
 
 template <typename T>
@@ -145,17 +147,18 @@ __global__ void __launch_bounds__(kBlock) adapt_apply_kernel(const T* __restrict
 template <typename T, bool PER, int G>
 __global__ void __launch_bounds__(kBlock) tri_deposit_kernel(const T* __restrict__ x, const T* __restrict__ hi,
                                                             double h_g, int64_t n, int M, double L, int chunk,
-                                                            double* __restrict__ partials) {
+                                                            double* __restrict__ partials, uint32_t* status) {
   __shared__ TriDepSmem<T> sm;
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int cnt = int(min(int64_t(chunk), n - lo));
-  tri_deposit_block<T, PER, G>(x, hi, h_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, sm);
+  tri_deposit_block<T, PER, G>(x, hi, h_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, sm, status);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) tri_gather_kernel(const T* __restrict__ x, const T* __restrict__ hi,
                                                            double h_g, bool per, int64_t n, int M, double L,
-                                                           const double* __restrict__ field, T* __restrict__ out) {
+                                                           const double* __restrict__ field, T* __restrict__ out,
+                                                           uint32_t* status) {
   extern __shared__ __align__(16) unsigned char dyn[];
   T* tf = reinterpret_cast<T*>(dyn);
   for (int k = threadIdx.x; k < M; k += kBlock) tf[k] = T(field[k]);
@@ -163,6 +166,7 @@ __global__ void __launch_bounds__(kBlock) tri_gather_kernel(const T* __restrict_
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
   const double h = per ? double(hi[i]) : h_g;
+  note_numeric(status, !isfinite(double(x[i])), per && !(h > 0.0 && h <= 0.5 * L));
   const TriGeo<T> p = tri_geo<T>(double(x[i]), h, L, M);
   SumOf<T> acc;
   // Nodes beyond h / dx cells of the particle add exact zeros, so a
@@ -205,7 +209,8 @@ size_t adapt_workspace_bytes(int64_t n) {
 
 template <typename T, bool PER>
 static kde_status launch_deposit_t(const kde_domain* dom, int64_t n, const T* x, const T* kap, double kappa,
-                                   double* rho, double* partials, int chunk, int64_t chunks, hipStream_t s) {
+                                   double* rho, double* partials, int chunk, int64_t chunks, hipStream_t s,
+                                   uint32_t* status) {
   const int M = dom->M;
   const dim3 grid{unsigned(chunks)}, block{unsigned(kBlock)};
   const double kg = kappa;
@@ -213,15 +218,15 @@ static kde_status launch_deposit_t(const kde_domain* dom, int64_t n, const T* x,
   KDE_RETURN_IF(check_lds(lds + sizeof(DepSmem<T>)));
   TimedLaunch timed(KDE_KERNEL_DEPOSIT, s);
   if (M <= kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 1>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((deposit_kernel<T, PER, 1>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else if (M <= 2 * kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 2>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((deposit_kernel<T, PER, 2>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else if (M <= 4 * kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 4>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((deposit_kernel<T, PER, 4>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else if (M <= 8 * kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 8>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((deposit_kernel<T, PER, 8>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 16>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((deposit_kernel<T, PER, 16>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
   }
   KDE_CHECK_LAUNCH();
   return KDE_OK;
@@ -229,28 +234,29 @@ static kde_status launch_deposit_t(const kde_domain* dom, int64_t n, const T* x,
 
 template <typename T, bool PER>
 static kde_status launch_tri_deposit_t(const kde_domain* dom, int64_t n, const T* x, const T* hi, double h,
-                                       double* partials, int chunk, int64_t chunks, hipStream_t s) {
+                                       double* partials, int chunk, int64_t chunks, hipStream_t s,
+                                       uint32_t* status) {
   const int M = dom->M;
   const dim3 grid{unsigned(chunks)}, block{unsigned(kBlock)};
   KDE_RETURN_IF(check_lds(sizeof(TriDepSmem<T>)));
   TimedLaunch timed(KDE_KERNEL_DEPOSIT, s);
   if (M <= kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 1>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 1>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else if (M <= 2 * kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 2>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 2>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else if (M <= 4 * kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 4>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 4>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else if (M <= 8 * kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 8>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 8>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 16>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials);
+    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 16>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
   }
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }
 
 kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
-                   void* ws, size_t ws_bytes, hipStream_t s) {
+                   void* ws, size_t ws_bytes, hipStream_t s, uint32_t* status) {
   const int chunk = deposit_chunk(n);
   const int64_t chunks = ceil_div(n, chunk);
   Carver c(ws, ws_bytes);
@@ -261,24 +267,24 @@ kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* 
     if (dom->prec == KDE_F64) {
       const double* xx = static_cast<const double*>(x);
       const double* hh = static_cast<const double*>(kap);
-      KDE_RETURN_IF((hh ? launch_tri_deposit_t<double, true>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)
-                        : launch_tri_deposit_t<double, false>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)));
+      KDE_RETURN_IF((hh ? launch_tri_deposit_t<double, true>(dom, n, xx, hh, kappa, partials, chunk, chunks, s, status)
+                        : launch_tri_deposit_t<double, false>(dom, n, xx, hh, kappa, partials, chunk, chunks, s, status)));
     } else {
       const float* xx = static_cast<const float*>(x);
       const float* hh = static_cast<const float*>(kap);
-      KDE_RETURN_IF((hh ? launch_tri_deposit_t<float, true>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)
-                        : launch_tri_deposit_t<float, false>(dom, n, xx, hh, kappa, partials, chunk, chunks, s)));
+      KDE_RETURN_IF((hh ? launch_tri_deposit_t<float, true>(dom, n, xx, hh, kappa, partials, chunk, chunks, s, status)
+                        : launch_tri_deposit_t<float, false>(dom, n, xx, hh, kappa, partials, chunk, chunks, s, status)));
     }
   } else if (dom->prec == KDE_F64) {
     const double* xx = static_cast<const double*>(x);
     const double* kk = static_cast<const double*>(kap);
-    KDE_RETURN_IF((kk ? launch_deposit_t<double, true>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s)
-                      : launch_deposit_t<double, false>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s)));
+    KDE_RETURN_IF((kk ? launch_deposit_t<double, true>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s, status)
+                      : launch_deposit_t<double, false>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s, status)));
   } else {
     const float* xx = static_cast<const float*>(x);
     const float* kk = static_cast<const float*>(kap);
-    KDE_RETURN_IF((kk ? launch_deposit_t<float, true>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s)
-                      : launch_deposit_t<float, false>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s)));
+    KDE_RETURN_IF((kk ? launch_deposit_t<float, true>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s, status)
+                      : launch_deposit_t<float, false>(dom, n, xx, kk, kappa, rho, partials, chunk, chunks, s, status)));
   }
   return launch_column_sum(partials, chunks, dom->M, scratch, rho, s, 1.0 / double(n));
 }
@@ -294,22 +300,22 @@ static int gather_split(int64_t n, int M) {
 
 template <typename T>
 static kde_status launch_gather_t(const kde_domain* dom, int64_t n, const T* x, const T* kap, double kappa,
-                                  const double* field, T* out, size_t lds, hipStream_t s) {
+                                  const double* field, T* out, size_t lds, hipStream_t s, uint32_t* status) {
   const int S = gather_split(n, dom->M);
   const dim3 grid{unsigned(ceil_div(n * S, kBlock))}, block{unsigned(kBlock)};
   const bool per = kap != nullptr;
   switch (S) {
     case 1:
-      hipLaunchKernelGGL((gather_kernel<T, 1>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      hipLaunchKernelGGL((gather_kernel<T, 1>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
     case 2:
-      hipLaunchKernelGGL((gather_kernel<T, 2>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      hipLaunchKernelGGL((gather_kernel<T, 2>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
     case 4:
-      hipLaunchKernelGGL((gather_kernel<T, 4>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      hipLaunchKernelGGL((gather_kernel<T, 4>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
     default:
-      hipLaunchKernelGGL((gather_kernel<T, 8>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out);
+      hipLaunchKernelGGL((gather_kernel<T, 8>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
   }
   KDE_CHECK_LAUNCH();
@@ -317,7 +323,7 @@ static kde_status launch_gather_t(const kde_domain* dom, int64_t n, const T* x, 
 }
 
 kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
-                  const double* field, void* out, hipStream_t s) {
+                  const double* field, void* out, hipStream_t s, uint32_t* status) {
   const dim3 grid{unsigned(ceil_div(n, kBlock))}, block{unsigned(kBlock)};
   if (dom->shape == KDE_SHAPE_TRIANGLE) {
     const size_t lds = size_t(dom->M) * elem_size(dom->prec);
@@ -326,11 +332,11 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
     if (dom->prec == KDE_F64)
       hipLaunchKernelGGL(tri_gather_kernel<double>, grid, block, lds, s, static_cast<const double*>(x),
                          static_cast<const double*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
-                         static_cast<double*>(out));
+                         static_cast<double*>(out), status);
     else
       hipLaunchKernelGGL(tri_gather_kernel<float>, grid, block, lds, s, static_cast<const float*>(x),
                          static_cast<const float*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
-                         static_cast<float*>(out));
+                         static_cast<float*>(out), status);
     KDE_CHECK_LAUNCH();
     return KDE_OK;
   }
@@ -339,16 +345,16 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
   TimedLaunch timed(KDE_KERNEL_GATHER, s);
   if (dom->prec == KDE_F64)
     KDE_RETURN_IF(launch_gather_t<double>(dom, n, static_cast<const double*>(x), static_cast<const double*>(kap),
-                                          kappa, field, static_cast<double*>(out), lds, s));
+                                          kappa, field, static_cast<double*>(out), lds, s, status));
   else
     KDE_RETURN_IF(launch_gather_t<float>(dom, n, static_cast<const float*>(x), static_cast<const float*>(kap),
-                                         kappa, field, static_cast<float*>(out), lds, s));
+                                         kappa, field, static_cast<float*>(out), lds, s, status));
   return KDE_OK;
 }
 
 kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
                         double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t* status) {
   const int64_t blocks = ceil_div(n, kBlock);
   Carver c(ws, ws_bytes);
   double* partials = c.take<double>(size_t(blocks) * 2);
@@ -359,10 +365,10 @@ kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const d
   TimedLaunch timed(KDE_KERNEL_ADAPT, s);
   if (dom->prec == KDE_F64) {
     hipLaunchKernelGGL(adapt_logsum_kernel<double>, grid, block, 0, s, static_cast<const double*>(x), n, dom->M,
-                       dom->L, pilot, partials);
+                       dom->L, pilot, partials, status);
   } else {
     hipLaunchKernelGGL(adapt_logsum_kernel<float>, grid, block, 0, s, static_cast<const float*>(x), n, dom->M,
-                       dom->L, pilot, partials);
+                       dom->L, pilot, partials, status);
   }
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(partials, blocks, 2, scratch, sums, s));

@@ -195,7 +195,9 @@ __device__ __forceinline__ void node_table(int M, T* ts, T* tc) {
 
 // One deposit chunk: particles [lo, lo + cnt) onto all M nodes, written to
 // out[M] (the chunk's partial grid, unnormalised by N). The node table must
-// be filled and visible. Ends with a barrier.
+// be filled and visible. Non-finite positions and per-particle
+// concentrations that are non-finite or negative are noted in `status`
+// (may be null). Ends with a barrier.
 // M <= 256: S = 256 / M sub-streams share a node, thread t -> node t % M,
 //           sub-stream t / M (threads beyond S*M idle);
 // M  > 256: thread t -> nodes t, t + 256, ... (G per thread).
@@ -247,10 +249,13 @@ __device__ __forceinline__ void dep_node_sums(int tid, int cnt, int M, double L,
 template <typename T, bool PER, int G>
 __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* __restrict__ kap, double kappa_g,
                                               int M, double L, int64_t lo, int cnt, double* __restrict__ out,
-                                              const T* ts, const T* tc, DepSmem<T>& sm) {
+                                              const T* ts, const T* tc, DepSmem<T>& sm, uint32_t* status) {
   const int tid = threadIdx.x;
   int sharp = 0, huge = 0;
   for (int k = tid; k < cnt; k += kBlock) {
+    const double xi = double(x[lo + k]);
+    const double ki = PER ? double(kap[lo + k]) : 0.0;
+    note_numeric(status, !isfinite(xi), PER && !(isfinite(ki) && ki >= 0.0));
     particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.pg[k], sm.pA[k], sm.pw[k]);
     if (std::is_same<T, double>::value && sm.pA[k] < T(-2.0 * kNearKappa)) sharp = 1;
     if (std::is_same<T, double>::value && !(sm.pA[k] >= T(kExpTableMin))) huge = 1;
@@ -343,17 +348,20 @@ __device__ __forceinline__ double pilot_at(T xv, double L, int M, const double* 
 
 // Block b of the log-sum pass: particles [256 b, 256 b + 256); writes
 // (sum of log f, floored count) to out[0..2). `r0`, `r1`: kBlock/64 doubles
-// of LDS each.
+// of LDS each. Non-finite positions are noted in `status` (may be null).
 template <typename T>
 __device__ __forceinline__ void adapt_logsum_block(const T* __restrict__ x, int64_t n, int M, double L,
                                                    const double* __restrict__ pilot, int64_t b,
-                                                   double* __restrict__ out, double* r0, double* r1) {
+                                                   double* __restrict__ out, double* r0, double* r1,
+                                                   uint32_t* status) {
   const int64_t i = b * kBlock + threadIdx.x;
   double lsum = 0.0, fl = 0.0;
   if (i < n) {
     bool floored;
-    lsum = log(pilot_at<T>(x[i], L, M, pilot, floored));
+    const T xv = x[i];
+    lsum = log(pilot_at<T>(xv, L, M, pilot, floored));
     fl = floored ? 1.0 : 0.0;
+    note_numeric(status, !isfinite(double(xv)), false);
   }
   lsum = wave_sum(lsum);
   fl = wave_sum(fl);

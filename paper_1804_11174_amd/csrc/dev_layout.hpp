@@ -134,12 +134,18 @@ __device__ __forceinline__ void block_scan_global(int32_t* __restrict__ a, int64
 // counted in LDS `lh` (cells ints) with integer atomics, is stored as
 // column b of the cell-major [cells][nblocks] array `hist`, so that one
 // exclusive scan of `hist` gives every block its stable scatter bases.
+// Non-finite positions are noted in `status` (may be null).
 template <typename T>
 __device__ __forceinline__ void sort_hist_block(const T* __restrict__ x, int64_t lo, int64_t hi, double L, int cells,
-                                                int b, int nblocks, int* lh, int32_t* __restrict__ hist) {
+                                                int b, int nblocks, int* lh, int32_t* __restrict__ hist,
+                                                uint32_t* status) {
   for (int c = threadIdx.x; c < cells; c += kBlock) lh[c] = 0;
   __syncthreads();
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&lh[cell_of(x[i], L, cells)], 1);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const T xv = x[i];
+    note_numeric(status, !isfinite(double(xv)), false);
+    atomicAdd(&lh[cell_of(xv, L, cells)], 1);
+  }
   __syncthreads();
   for (int c = threadIdx.x; c < cells; c += kBlock) hist[int64_t(c) * nblocks + b] = lh[c];
 }

@@ -273,10 +273,14 @@ struct TriDepSmem {
 template <typename T, bool PER, int G>
 __device__ __forceinline__ void tri_deposit_block(const T* __restrict__ x, const T* __restrict__ hi, double h_g,
                                                   int M, double L, int64_t lo, int cnt, double* __restrict__ out,
-                                                  TriDepSmem<T>& sm) {
+                                                  TriDepSmem<T>& sm, uint32_t* status) {
   const int tid = threadIdx.x;
-  for (int k = tid; k < cnt; k += kBlock)
-    sm.pg[k] = tri_geo<T>(double(x[lo + k]), PER ? double(hi[lo + k]) : h_g, L, M);
+  for (int k = tid; k < cnt; k += kBlock) {
+    const double xi = double(x[lo + k]);
+    const double h = PER ? double(hi[lo + k]) : h_g;
+    note_numeric(status, !isfinite(xi), PER && !(h > 0.0 && h <= 0.5 * L));
+    sm.pg[k] = tri_geo<T>(xi, h, L, M);
+  }
   __syncthreads();
   const double gscale = PER ? 1.0 : 1.0 / h_g;
   if (M <= kBlock) {

@@ -200,7 +200,8 @@ __device__ __forceinline__ void block_sum6(double (&v)[6], double (*red)[6]) {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) moments_kernel(const T* __restrict__ x, int64_t n, double L, int M,
-                                                        int64_t per_chunk, double* __restrict__ partials) {
+                                                        int64_t per_chunk, double* __restrict__ partials,
+                                                        uint32_t* status) {
   __shared__ double red[kBlock / 64][2 * kMomM];
   const int64_t ch = blockIdx.x;
   const int m0 = 1 + int(blockIdx.y) * kMomM;
@@ -208,7 +209,9 @@ __global__ void __launch_bounds__(kBlock) moments_kernel(const T* __restrict__ x
 #pragma unroll
   for (int k = 0; k < kMomM; ++k) re[k] = im[k] = 0.0;
   const int64_t lo = ch * per_chunk, hi = min(n, lo + per_chunk);
+  uint32_t* const st = blockIdx.y == 0 ? status : nullptr;  // one column of blocks notes the positions
   for (int64_t j = lo + threadIdx.x; j < hi; j += kBlock) {
+    note_numeric(st, !isfinite(double(x[j])), false);
     const double f = wrap_d(double(x[j]), L) / L;
     double c, s, c1, s1;
     phase(m0, f, c, s);
@@ -681,11 +684,13 @@ __global__ void __launch_bounds__(kBlock) pilot_weights_kernel(const double* __r
 template <typename T>
 __global__ void __launch_bounds__(kBlock) pilot_kernel(const T* __restrict__ x, int64_t n, double L, int M,
                                                       const double* __restrict__ w, double floor_v,
-                                                      double* __restrict__ lf, double* __restrict__ bpart) {
+                                                      double* __restrict__ lf, double* __restrict__ bpart,
+                                                      uint32_t* status) {
   __shared__ double red[kBlock / 64];
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   double lsum = 0.0, fl = 0.0;
   if (i < n) {
+    note_numeric(status, !isfinite(double(x[i])), false);
     const double f = wrap_d(double(x[i]), L) / L;
     double c1, s1;
     sincospi(2.0 * f, &s1, &c1);
@@ -741,7 +746,8 @@ kde_status launch_moments(const T* x, int64_t n, double L, int M, const FourierB
   const dim3 grid{unsigned(chunks), unsigned(ceil_div(M, kMomM))};
   {
     TimedLaunch timed(KDE_KERNEL_MOMENTS, s);
-    hipLaunchKernelGGL((moments_kernel<T>), grid, dim3(kBlock), 0, s, x, n, L, M, per, b.partials);
+    hipLaunchKernelGGL((moments_kernel<T>), grid, dim3(kBlock), 0, s, x, n, L, M, per, b.partials,
+                       plain_numeric_word());
   }
   KDE_CHECK_LAUNCH();
   return launch_column_sum(b.partials, chunks, 2 * M, b.colsum, b.S, s);
@@ -867,10 +873,12 @@ kde_status kde_adapt_widths_exact(const kde_domain* dom, int64_t N, const void* 
     TimedLaunch timed(KDE_KERNEL_ADAPT, s);
     if (dom->prec == KDE_F64)
       hipLaunchKernelGGL(pilot_kernel<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(x), N, dom->L, M,
-                         (const double*)b.w, double(std::numeric_limits<double>::min()), b.lf, b.bpart);
+                         (const double*)b.w, double(std::numeric_limits<double>::min()), b.lf, b.bpart,
+                         plain_numeric_word());
     else
       hipLaunchKernelGGL(pilot_kernel<float>, grid, dim3(kBlock), 0, s, static_cast<const float*>(x), N, dom->L, M,
-                         (const double*)b.w, double(std::numeric_limits<float>::min()), b.lf, b.bpart);
+                         (const double*)b.w, double(std::numeric_limits<float>::min()), b.lf, b.bpart,
+                         plain_numeric_word());
   }
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(b.bpart, blocks, 2, b.colsum2, b.sums2, s));

@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "../../include/kde.h"
+#include "../../include/kde_measure.h"
 
 namespace kde {
 
@@ -180,14 +181,31 @@ struct TriPacked<float> {
 
 // Wrap, pack and sort by cell, stably. `packed` receives n elements of P
 // (one P per particle; the double half-angle form takes two doubles).
+// Non-finite positions are noted in `status` (may be null).
 template <typename T, typename P>
 kde_status launch_pack_sorted_as(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist, P* packed,
-                                 int32_t* perm, hipStream_t s);
+                                 int32_t* perm, hipStream_t s, uint32_t* status);
 template <typename T>
 inline kde_status launch_pack_sorted(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist,
-                                     typename Packed<T>::type* packed, int32_t* perm, hipStream_t s) {
-  return launch_pack_sorted_as<T, typename Packed<T>::type>(x, n, L, plan, hist, packed, perm, s);
+                                     typename Packed<T>::type* packed, int32_t* perm, hipStream_t s,
+                                     uint32_t* status) {
+  return launch_pack_sorted_as<T, typename Packed<T>::type>(x, n, L, plan, hist, packed, perm, s, status);
 }
+
+// One-set launchers of the path (cv.hip, density.hip); `status` receives
+// KDE_NUMERIC_* bits (may be null).
+size_t cv_workspace_bytes(int64_t n, int B, int prec);
+kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
+                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s, uint32_t* status);
+size_t deposit_workspace_bytes(int64_t n, int M);
+size_t adapt_workspace_bytes(int64_t n);
+kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
+                   void* ws, size_t ws_bytes, hipStream_t s, uint32_t* status);
+kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
+                  const double* field, void* out, hipStream_t s, uint32_t* status);
+kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
+                        double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
+                        hipStream_t s, uint32_t* status);
 
 // Workspace of the Fourier-moment ops (KDE_OP_CV_FOURIER, _CV_REFINE,
 // _ADAPT_EXACT), sized for the largest series order the ops accept.
@@ -200,6 +218,26 @@ kde_status launch_column_sum(const double* in, int64_t rows, int cols, double* s
 size_t column_sum_scratch(int64_t rows, int cols);
 
 // ----------------------------------------------------------- device helpers
+
+// Numeric status words (KDE_NUMERIC_* bits). Kernels that read positions
+// or per-particle concentrations note non-finite values (and concentrations
+// outside their range) here: one atomic per wave and kind, taken by the
+// wave's first lane that saw one; nothing else changes (outputs carry NaN).
+// A null word records nothing. Lanes that are inactive at the call add
+// nothing to the ballots.
+__device__ __forceinline__ void note_numeric(uint32_t* status, bool bad_position, bool bad_concentration) {
+  if (status == nullptr) return;
+  const uint64_t mp = __ballot(bad_position);
+  const uint64_t mc = __ballot(bad_concentration);
+  const uint64_t any = mp | mc;
+  if (any == 0) return;
+  if (int(threadIdx.x & 63) == __ffsll((unsigned long long)any) - 1)
+    atomicOr(status, (mp ? uint32_t(KDE_NUMERIC_POSITION) : 0u) | (mc ? uint32_t(KDE_NUMERIC_CONCENTRATION) : 0u));
+}
+
+// The plain calls' numeric status word on the current device (numeric.hip),
+// or nullptr when it cannot be looked up (then nothing is recorded).
+uint32_t* plain_numeric_word();
 
 template <typename T>
 __device__ __forceinline__ T wrap_position(T x, T L) {

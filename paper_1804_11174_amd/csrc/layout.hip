@@ -34,10 +34,10 @@ SortPlan make_sort_plan(int64_t n) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) sort_hist_kernel(const T* __restrict__ x, int64_t n, double L,
                                                           int cells, int64_t chunk,
-                                                          int32_t* __restrict__ hist) {
+                                                          int32_t* __restrict__ hist, uint32_t* status) {
   extern __shared__ int32_t lh[];
   const int64_t lo = int64_t(blockIdx.x) * chunk;
-  sort_hist_block<T>(x, lo, min(n, lo + chunk), L, cells, blockIdx.x, gridDim.x, lh, hist);
+  sort_hist_block<T>(x, lo, min(n, lo + chunk), L, cells, blockIdx.x, gridDim.x, lh, hist, status);
 }
 
 __global__ void __launch_bounds__(kBlock) exclusive_scan_kernel(int32_t* __restrict__ a, int64_t len) {
@@ -61,10 +61,10 @@ __global__ void __launch_bounds__(kBlock) sort_scatter_kernel(const T* __restric
 
 template <typename T, typename P>
 kde_status launch_pack_sorted_as(const T* x, int64_t n, double L, const SortPlan& plan, int32_t* hist, P* packed,
-                                 int32_t* perm, hipStream_t s) {
+                                 int32_t* perm, hipStream_t s, uint32_t* status) {
   const size_t lds = size_t(plan.cells) * sizeof(int32_t);
   hipLaunchKernelGGL(sort_hist_kernel<T>, dim3(plan.blocks), dim3(kBlock), lds, s, x, n, L,
-                     plan.cells, plan.chunk, hist);
+                     plan.cells, plan.chunk, hist, status);
   KDE_CHECK_LAUNCH();
   hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kBlock), 0, s, hist,
                      int64_t(plan.cells) * plan.blocks);
@@ -76,11 +76,11 @@ kde_status launch_pack_sorted_as(const T* x, int64_t n, double L, const SortPlan
 }
 
 template kde_status launch_pack_sorted_as<double, double>(const double*, int64_t, double, const SortPlan&, int32_t*,
-                                                          double*, int32_t*, hipStream_t);
+                                                          double*, int32_t*, hipStream_t, uint32_t*);
 template kde_status launch_pack_sorted_as<float, uint32_t>(const float*, int64_t, double, const SortPlan&, int32_t*,
-                                                           uint32_t*, int32_t*, hipStream_t);
+                                                           uint32_t*, int32_t*, hipStream_t, uint32_t*);
 template kde_status launch_pack_sorted_as<double, FracPos>(const double*, int64_t, double, const SortPlan&, int32_t*,
-                                                           FracPos*, int32_t*, hipStream_t);
+                                                           FracPos*, int32_t*, hipStream_t, uint32_t*);
 
 // ------------------------------------------------------ deterministic sums
 

@@ -1,4 +1,4 @@
-// Issue-rate probes (kde_probe_peak in include/kde.h): one kernel per
+// Issue-rate probes (kde_probe_peak in include/kde_measure.h): one kernel per
 // instruction kind in which every thread runs kChains independent
 // dependency chains of `iters` steps, so the device's sustained
 // lane-operation rate for that kind is (threads x kChains x iters) / time.

@@ -20,29 +20,27 @@
 // integrals are done by the trapezoid rule after scaling out the Gaussian
 // factor (the integrand is even and analytic, so the rule converges
 // geometrically).
+//
+// A step is a small state machine, so that one thread can drive many
+// sessions (the request server) without waiting on any: begin (enqueue the
+// fixed part, whose last node copies A^2 and the numeric status word to a
+// pinned mailbox, and record an event), then advance once that event has
+// completed (apply the rule on the host; when it fires, enqueue the CV scan
+// and record the event again; otherwise, or after the scan, enqueue the
+// widths of the next step). kde_session_step runs the same machine,
+// waiting on the event itself.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <vector>
 
-#include "kde_internal.hpp"
+#include "session_internal.hpp"
 
 namespace kde {
 
-// implemented elsewhere in the library
-size_t cv_workspace_bytes(int64_t n, int B, int prec);
-size_t deposit_workspace_bytes(int64_t n, int M);
-size_t adapt_workspace_bytes(int64_t n);
+// implemented in pic.hip
 size_t ad_workspace_bytes(int64_t n, int prec);
-kde_status cv_scan(const kde_domain* dom, int64_t n, const void* x, int B, const double* kappas, double* cv,
-                   double* sums, int32_t* argmin, void* ws, size_t ws_bytes, hipStream_t s);
-kde_status deposit(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa, double* rho,
-                   void* ws, size_t ws_bytes, hipStream_t s);
-kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* kap, double kappa,
-                  const double* field, void* out, hipStream_t s);
-kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const double* pilot, double kappa_star,
-                        double alpha, void* kout, double* log_g, int64_t* nfl, void* ws, size_t ws_bytes,
-                        hipStream_t s);
 kde_status launch_poisson_field(const double* rho, int M, double L, double* E, hipStream_t s);
 kde_status launch_field_energy(const double* E, int M, double L, double* energy, int64_t history, int64_t* step,
                                hipStream_t s);
@@ -107,27 +105,43 @@ static double width_of_kappa(double k, double L) { return (L / (2.0 * M_PI)) / s
 
 using namespace kde;
 
+// Device and pinned-host mailbox of a session: the last A^2, the CV
+// scan's first minimum and the numeric status word of the session's
+// kernels, copied to the host together.
+struct SessionMail {
+  double a2;
+  int32_t argmin;
+  uint32_t status;
+};
+
+enum class StepPhase { Idle, Fixed, Scan };
+
 struct kde_session {
   kde_pic_params prm{};
   std::vector<double> kappas;
   kde_domain dom{};
   kde_domain tdom{};  // triangle of half-width dx (standard sessions)
   hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;  // completion of the part of a step the host waits on
+  size_t arena_bytes = 0;
   // device buffers in the arena
   void *x = nullptr, *v = nullptr, *kap = nullptr, *Ei = nullptr;
-  double *rho = nullptr, *E = nullptr, *pilot = nullptr, *cv = nullptr, *a2 = nullptr, *energy = nullptr;
-  int32_t* argmin = nullptr;
+  double *rho = nullptr, *E = nullptr, *pilot = nullptr, *cv = nullptr, *energy = nullptr;
+  SessionMail* dmail = nullptr;
   int64_t* step_dev = nullptr;  // history slot of the next field energy
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  // pinned host mailbox: [a2, argmin]
-  double* mail = nullptr;
+  SessionMail* mail = nullptr;  // pinned host copy of dmail
   // the step's fixed launch sequence, captured at the first step
   hipGraphExec_t fixed = nullptr;
   SessionState st;
+  uint32_t numeric = 0;  // numeric status seen so far (sticky until a restore)
+  StepPhase phase = StepPhase::Idle;
+  std::chrono::steady_clock::time_point t_begin;
   ~kde_session() {
     if (fixed) (void)hipGraphExecDestroy(fixed);
     if (mail) (void)hipHostFree(mail);
+    if (ev) (void)hipEventDestroy(ev);
   }
 };
 
@@ -154,15 +168,14 @@ static size_t carve_session(Carver& c, const kde_pic_params& p, kde_session* s) 
   double* E = c.take<double>(p.M);
   double* pilot = c.take<double>(p.M);
   double* cv = c.take<double>(standard(p) ? 1 : p.B);
-  double* a2 = c.take<double>(1);
-  int32_t* am = c.take<int32_t>(1);
+  SessionMail* dmail = c.take<SessionMail>(1);
   double* energy = c.take<double>(size_t(std::max(p.history, 1)));
   int64_t* stepd = c.take<int64_t>(1);
   const size_t wsb = session_ws_bytes(p);
   void* ws = c.take<char>(wsb);
   if (s) {
     s->x = x; s->v = v; s->kap = kap; s->Ei = Ei;
-    s->rho = rho; s->E = E; s->pilot = pilot; s->cv = cv; s->a2 = a2; s->argmin = am;
+    s->rho = rho; s->E = E; s->pilot = pilot; s->cv = cv; s->dmail = dmail;
     s->energy = energy;
     s->step_dev = stepd;
     s->ws = ws; s->ws_bytes = wsb;
@@ -195,15 +208,31 @@ static kde_status check_params(const kde_pic_params* p) {
   return KDE_OK;
 }
 
-// CV scan on the first n_cv particles; returns the chosen concentration.
-static kde_status session_cv(kde_session* s, double* kstar) {
+__global__ void session_clear_status_kernel(SessionMail* m) {
+  if (threadIdx.x == 0) m->status = 0u;
+}
+
+static kde_status clear_status(kde_session* s) {
+  hipLaunchKernelGGL(session_clear_status_kernel, dim3(1), dim3(64), 0, s->s, s->dmail);
+  KDE_CHECK_LAUNCH();
+  return KDE_OK;
+}
+
+static uint32_t* status_word(kde_session* s) { return &s->dmail->status; }
+
+// Enqueue the CV scan on the first n_cv particles and the copy of the
+// mailbox (first minimum, status) to the host.
+static kde_status enqueue_cv(kde_session* s) {
   kde_domain d = s->dom;
-  KDE_RETURN_IF(cv_scan(&d, s->prm.n_cv, s->x, s->prm.B, s->kappas.data(), s->cv, nullptr, s->argmin, s->ws,
-                        s->ws_bytes, s->s));
-  KDE_TRY_HIP(hipMemcpyAsync(s->mail + 1, s->argmin, sizeof(int32_t), hipMemcpyDeviceToHost, s->s));
-  KDE_TRY_HIP(hipStreamSynchronize(s->s));
-  int32_t b = 0;
-  memcpy(&b, s->mail + 1, sizeof(int32_t));
+  KDE_RETURN_IF(cv_scan(&d, s->prm.n_cv, s->x, s->prm.B, s->kappas.data(), s->cv, nullptr, &s->dmail->argmin,
+                        s->ws, s->ws_bytes, s->s, status_word(s)));
+  KDE_TRY_HIP(hipMemcpyAsync(s->mail, s->dmail, sizeof(SessionMail), hipMemcpyDeviceToHost, s->s));
+  return KDE_OK;
+}
+
+// The scan's choice, from the host mailbox (its copy has completed).
+static kde_status scanned_kappa(kde_session* s, double* kstar) {
+  const int32_t b = s->mail->argmin;
   if (b < 0 || b >= s->prm.B) return fail(KDE_E_INTERNAL, "argmin out of range");
   *kstar = s->kappas[b];
   return KDE_OK;
@@ -211,9 +240,9 @@ static kde_status session_cv(kde_session* s, double* kstar) {
 
 // Pilot deposit at kappa* and the adaptive widths for the next step.
 static kde_status session_widths(kde_session* s, double kstar) {
-  KDE_RETURN_IF(deposit(&s->dom, s->prm.N, s->x, nullptr, kstar, s->pilot, s->ws, s->ws_bytes, s->s));
+  KDE_RETURN_IF(deposit(&s->dom, s->prm.N, s->x, nullptr, kstar, s->pilot, s->ws, s->ws_bytes, s->s, status_word(s)));
   KDE_RETURN_IF(adapt_widths(&s->dom, s->prm.N, s->x, s->pilot, kstar, s->prm.alpha, s->kap, nullptr, nullptr, s->ws,
-                             s->ws_bytes, s->s));
+                             s->ws_bytes, s->s, status_word(s)));
   return KDE_OK;
 }
 
@@ -233,27 +262,31 @@ static kde_status push_any(kde_session* s) {
 // The fixed part of a step, the same launches with the same arguments every
 // step. Standard PIC (linear weighting both ways, no width update): the
 // whole step. KDE: deposit with kappa_i, field, energy, gather, push and
-// the A^2 statistic, copied to the host mailbox.
+// the A^2 statistic. Both end with the copy of the mailbox (A^2, status)
+// to the host.
 static kde_status enqueue_fixed(kde_session* s) {
   const kde_pic_params& p = s->prm;
   if (standard(p)) {
     const double dx = p.L / double(p.M);
-    KDE_RETURN_IF(deposit(&s->tdom, p.N, s->x, nullptr, dx, s->rho, s->ws, s->ws_bytes, s->s));
+    KDE_RETURN_IF(deposit(&s->tdom, p.N, s->x, nullptr, dx, s->rho, s->ws, s->ws_bytes, s->s, status_word(s)));
     KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
     KDE_RETURN_IF(record_energy(s));
-    KDE_RETURN_IF(gather(&s->tdom, p.N, s->x, nullptr, dx, s->E, s->Ei, s->s));
-    return push_any(s);
+    KDE_RETURN_IF(gather(&s->tdom, p.N, s->x, nullptr, dx, s->E, s->Ei, s->s, status_word(s)));
+    KDE_RETURN_IF(push_any(s));
+  } else {
+    KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s, status_word(s)));
+    KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
+    KDE_RETURN_IF(record_energy(s));
+    KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s, status_word(s)));
+    KDE_RETURN_IF(push_any(s));
+    if (p.prec == KDE_F64)
+      KDE_RETURN_IF(launch_ad_statistic<double>(static_cast<const double*>(s->x), p.N, p.L, &s->dmail->a2, s->ws,
+                                                s->ws_bytes, s->s));
+    else
+      KDE_RETURN_IF(launch_ad_statistic<float>(static_cast<const float*>(s->x), p.N, p.L, &s->dmail->a2, s->ws,
+                                               s->ws_bytes, s->s));
   }
-  KDE_RETURN_IF(deposit(&s->dom, p.N, s->x, s->kap, 0.0, s->rho, s->ws, s->ws_bytes, s->s));
-  KDE_RETURN_IF(launch_poisson_field(s->rho, p.M, p.L, s->E, s->s));
-  KDE_RETURN_IF(record_energy(s));
-  KDE_RETURN_IF(gather(&s->dom, p.N, s->x, s->kap, 0.0, s->E, s->Ei, s->s));
-  KDE_RETURN_IF(push_any(s));
-  if (p.prec == KDE_F64)
-    KDE_RETURN_IF(launch_ad_statistic<double>(static_cast<const double*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
-  else
-    KDE_RETURN_IF(launch_ad_statistic<float>(static_cast<const float*>(s->x), p.N, p.L, s->a2, s->ws, s->ws_bytes, s->s));
-  KDE_TRY_HIP(hipMemcpyAsync(s->mail, s->a2, sizeof(double), hipMemcpyDeviceToHost, s->s));
+  KDE_TRY_HIP(hipMemcpyAsync(s->mail, s->dmail, sizeof(SessionMail), hipMemcpyDeviceToHost, s->s));
   return KDE_OK;
 }
 
@@ -283,31 +316,101 @@ static kde_status run_fixed(kde_session* s) {
   return KDE_OK;
 }
 
-static kde_status session_step_once(kde_session* s) {
+static kde_status numeric_failure(kde_session* s) {
+  return fail(KDE_E_NUMERIC, "session met non-finite %s%s%s (step %lld)",
+              (s->numeric & KDE_NUMERIC_POSITION) ? "positions" : "",
+              (s->numeric & KDE_NUMERIC_POSITION) && (s->numeric & KDE_NUMERIC_CONCENTRATION) ? " and " : "",
+              (s->numeric & KDE_NUMERIC_CONCENTRATION) ? "concentrations" : (s->numeric ? "" : "values"),
+              (long long)s->st.step);
+}
+
+// The end of a step: relax the width, enqueue the next widths.
+static kde_status finish_step(kde_session* s) {
   const kde_pic_params& p = s->prm;
-  KDE_RETURN_IF(run_fixed(s));
-  if (standard(p)) {  // enqueue only: standard steps never wait on the host
-    s->st.step += 1;
-    return KDE_OK;
-  }
-  KDE_TRY_HIP(hipStreamSynchronize(s->s));
   SessionState& st = s->st;
-  st.last_a2 = s->mail[0];
-  st.last_p = ad_upper_tail(st.last_a2);
-  const double thr = p.p_threshold;
-  if (st.last_p > 2.0 * thr) {
-    st.p_th = 2.0 * thr;
-  } else if (st.last_p < 0.5 * st.p_th) {
-    double k = 0.0;
-    KDE_RETURN_IF(session_cv(s, &k));
-    st.h_target = width_of_kappa(k, p.L);
-    st.p_th = st.last_p;
-    st.fired += 1;
-  }
   st.h_opt = p.adjust_rate * st.h_target + (1.0 - p.adjust_rate) * st.h_opt;
   st.kappa_star = kappa_of_width(st.h_opt, p.L);
   KDE_RETURN_IF(session_widths(s, st.kappa_star));
   st.step += 1;
+  s->phase = StepPhase::Idle;
+  return KDE_OK;
+}
+
+kde_status session_begin_step(kde_session* s) {
+  if (s->phase != StepPhase::Idle) return fail(KDE_E_INTERNAL, "a step of this session is in flight");
+  s->t_begin = std::chrono::steady_clock::now();
+  KDE_RETURN_IF(run_fixed(s));
+  KDE_TRY_HIP(hipEventRecord(s->ev, s->s));
+  s->phase = StepPhase::Fixed;
+  return KDE_OK;
+}
+
+kde_status session_advance(kde_session* s, bool* done) {
+  *done = false;
+  const kde_pic_params& p = s->prm;
+  SessionState& st = s->st;
+  if (s->phase == StepPhase::Fixed) {
+    s->numeric |= s->mail->status;
+    if (standard(p)) {
+      st.step += 1;
+      s->phase = StepPhase::Idle;
+      *done = true;
+      return s->numeric ? numeric_failure(s) : KDE_OK;
+    }
+    st.last_a2 = s->mail->a2;
+    // A^2 of positions in [0, L) (logs clamped) is finite: a non-finite one
+    // means the push produced a non-finite position
+    if (!std::isfinite(st.last_a2)) s->numeric |= KDE_NUMERIC_POSITION;
+    if (s->numeric) {
+      // a non-finite position or width reached the step: the rule and the
+      // widths are left as they were, the step is counted
+      st.step += 1;
+      s->phase = StepPhase::Idle;
+      *done = true;
+      return numeric_failure(s);
+    }
+    st.last_p = ad_upper_tail(st.last_a2);
+    const double thr = p.p_threshold;
+    if (st.last_p > 2.0 * thr) {
+      st.p_th = 2.0 * thr;
+    } else if (st.last_p < 0.5 * st.p_th) {
+      KDE_RETURN_IF(enqueue_cv(s));
+      KDE_TRY_HIP(hipEventRecord(s->ev, s->s));
+      s->phase = StepPhase::Scan;
+      return KDE_OK;
+    }
+    KDE_RETURN_IF(finish_step(s));
+    *done = true;
+    return KDE_OK;
+  }
+  if (s->phase == StepPhase::Scan) {
+    s->numeric |= s->mail->status;
+    double k = 0.0;
+    KDE_RETURN_IF(scanned_kappa(s, &k));
+    st.h_target = width_of_kappa(k, p.L);
+    st.p_th = st.last_p;
+    st.fired += 1;
+    KDE_RETURN_IF(finish_step(s));
+    *done = true;
+    return KDE_OK;
+  }
+  return fail(KDE_E_INTERNAL, "no step of this session is in flight");
+}
+
+hipEvent_t session_event(const kde_session* s) { return s->ev; }
+size_t session_arena_bytes(const kde_session* s) { return s->arena_bytes; }
+double session_step_seconds(const kde_session* s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t_begin).count();
+}
+
+// One step on the calling thread, waiting on the session's event.
+static kde_status session_step_once(kde_session* s) {
+  KDE_RETURN_IF(session_begin_step(s));
+  bool done = false;
+  while (!done) {
+    KDE_TRY_HIP(hipEventSynchronize(s->ev));
+    KDE_RETURN_IF(session_advance(s, &done));
+  }
   return KDE_OK;
 }
 
@@ -332,7 +435,7 @@ kde_status kde_session_bytes(const kde_pic_params* p, size_t* bytes_h) {
 }
 
 kde_status kde_session_create(const kde_pic_params* p, const void* x0, const void* v0, void* arena, size_t arena_bytes,
-                              kde_session** out_h) {
+                              void* stream, kde_session** out_h) {
   clear_error();
   if (!out_h) return fail(KDE_E_INVALID_ARG, "out_h is NULL");
   *out_h = nullptr;
@@ -348,20 +451,32 @@ kde_status kde_session_create(const kde_pic_params* p, const void* x0, const voi
   carve_session(c, *p, s.get());
   if (!arena || reinterpret_cast<uintptr_t>(arena) % 256 != 0) return fail(KDE_E_WORKSPACE, "arena must be 256-byte aligned");
   if (!c.fits()) return fail(KDE_E_WORKSPACE, "arena too small: %zu < %zu bytes", arena_bytes, c.used);
+  s->arena_bytes = c.used;
   KDE_TRY_HIP(hipStreamCreateWithFlags(&s->s, hipStreamNonBlocking));
-  KDE_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->mail), 64, hipHostMallocDefault));
+  KDE_TRY_HIP(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
+  KDE_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->mail), sizeof(SessionMail), hipHostMallocDefault));
+  // the copies of x0 and v0 follow the work already enqueued on the caller's stream
+  KDE_TRY_HIP(hipEventRecord(s->ev, static_cast<hipStream_t>(stream)));
+  KDE_TRY_HIP(hipStreamWaitEvent(s->s, s->ev, 0));
   const size_t es = elem_size(p->prec);
   KDE_TRY_HIP(hipMemcpyAsync(s->x, x0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
   KDE_TRY_HIP(hipMemcpyAsync(s->v, v0, size_t(p->N) * es, hipMemcpyDeviceToDevice, s->s));
   KDE_RETURN_IF(launch_set_step(s->step_dev, 0, s->s));
+  KDE_RETURN_IF(clear_status(s.get()));
   if (standard(*p)) {
     KDE_TRY_HIP(hipStreamSynchronize(s->s));
     *out_h = s.release();
     return KDE_OK;
   }
   // initial CV at t = 0: both widths at its optimum, p_th = 2 thr
+  KDE_RETURN_IF(enqueue_cv(s.get()));
+  KDE_TRY_HIP(hipStreamSynchronize(s->s));
+  if (s->mail->status) {
+    s->numeric = s->mail->status;
+    return numeric_failure(s.get());
+  }
   double k0 = 0.0;
-  KDE_RETURN_IF(session_cv(s.get(), &k0));
+  KDE_RETURN_IF(scanned_kappa(s.get(), &k0));
   s->st.p_th = 2.0 * p->p_threshold;
   s->st.h_opt = s->st.h_target = width_of_kappa(k0, p->L);
   s->st.kappa_star = k0;
@@ -375,6 +490,16 @@ kde_status kde_session_step(kde_session* s, int32_t nsteps) {
   clear_error();
   if (!s) return fail(KDE_E_NOT_FOUND, "session is NULL");
   if (nsteps < 0) return fail(KDE_E_INVALID_ARG, "nsteps must be >= 0");
+  if (s->phase != StepPhase::Idle) return fail(KDE_E_INVALID_ARG, "a step of this session is in flight (attached to a server?)");
+  if (standard(s->prm)) {  // enqueue only: standard steps never wait on the host
+    for (int k = 0; k < nsteps; ++k) {
+      KDE_RETURN_IF(run_fixed(s));
+      s->st.step += 1;
+    }
+    KDE_TRY_HIP(hipStreamSynchronize(s->s));
+    s->numeric |= s->mail->status;
+    return s->numeric ? numeric_failure(s) : KDE_OK;
+  }
   for (int k = 0; k < nsteps; ++k) KDE_RETURN_IF(session_step_once(s));
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
   return KDE_OK;
@@ -391,6 +516,8 @@ kde_status kde_session_state(const kde_session* s, kde_session_info* h) {
   h->last_a2 = s->st.last_a2;
   h->last_p = s->st.last_p;
   h->fired = s->st.fired;
+  h->numeric = s->numeric;
+  h->reserved = 0;
   return KDE_OK;
 }
 
@@ -458,6 +585,7 @@ kde_status kde_session_save(kde_session* s, void* blob_h, size_t* bytes_h) {
 kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes) {
   clear_error();
   if (!s || !blob_h) return fail(KDE_E_INVALID_ARG, "session and blob must not be NULL");
+  if (s->phase != StepPhase::Idle) return fail(KDE_E_INVALID_ARG, "a step of this session is in flight");
   const size_t pn = size_t(s->prm.N) * elem_size(s->prm.prec);
   const size_t need = blob_bytes(s);
   if (bytes < need) return fail(KDE_E_INVALID_ARG, "blob too small: %zu < %zu", bytes, need);
@@ -478,6 +606,8 @@ kde_status kde_session_restore(kde_session* s, const void* blob_h, size_t bytes)
     KDE_TRY_HIP(hipMemcpyAsync(s->energy, p + 3 * pn, size_t(s->prm.history) * sizeof(double), hipMemcpyHostToDevice,
                                s->s));
   KDE_RETURN_IF(launch_set_step(s->step_dev, s->st.step, s->s));
+  KDE_RETURN_IF(clear_status(s));
+  s->numeric = 0;
   KDE_TRY_HIP(hipStreamSynchronize(s->s));
   return KDE_OK;
 }

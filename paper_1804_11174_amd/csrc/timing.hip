@@ -1,4 +1,4 @@
-// Optional per-kernel timing with HIP events (kde_timing_* in include/kde.h).
+// Optional per-kernel timing with HIP events (kde_timing_* in include/kde_measure.h).
 // Pending event pairs are kept per kernel id; reading waits for them and
 // folds their durations into running totals.
 #include <mutex>
