@@ -428,8 +428,7 @@ static kde_status enqueue_batch(const BatchPlan& b, const BatchArgs& a, const st
   const int ns = int(b.sets.size());
   auto total = [&](int pf) { return prefix[size_t(pf) * (ns + 1) + ns]; };
   const CvConsts<T> K = make_consts<T>(b.kappas.data(), b.B);
-  KappaList kl{};
-  for (int k = 0; k < b.B; ++k) kl.k[k] = b.kappas[k];
+  const KappaList kl = make_kappa_list<T>(b.kappas.data(), b.B);
   const size_t dep_lds = 2 * size_t(b.max_M) * sizeof(T);
   const size_t pack_lds = size_t(b.max_cells) * sizeof(int);
 

@@ -222,8 +222,7 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
   }
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(buf.partials, p.slots, 2 * B, buf.colsum, buf.raw, s));
-  KappaList kl{};
-  for (int b = 0; b < B; ++b) kl.k[b] = kappas[b];
+  const KappaList kl = make_kappa_list<T>(kappas, B);
   hipLaunchKernelGGL(cv_finalize_kernel, dim3(1), dim3(KDE_MAX_KAPPAS), 0, s, (const double*)buf.raw, B,
                      double(n), dom->L, kl, cv, sums, argmin);
   KDE_CHECK_LAUNCH();

@@ -44,13 +44,18 @@
 // exponent scales with kappa, so once every lane of a wave is below the
 // bound for one concentration, the wave skips the rest for that j.
 //
-// The leading concentrations with 2 kappa < X0 (the small-argument Bessel
-// range covers every pair) run in chunks of their own through a lean loop:
-// no term can reach the skip bound, so there is no vote, and the pair
-// geometry is s^2 and c^2 alone. With only that branch's polynomial live,
-// its coefficients stay in scalar registers instead of being rebuilt for
-// every term. Which loop a concentration takes depends on kappa alone, so
-// the sums still do not depend on the chunk or group size.
+// Concentrations run in chunks of three kinds, each through a loop of its
+// own. The leading ones with 2 kappa < X0 (the small-argument Bessel range
+// covers every pair): no term can reach the skip bound, so there is no
+// vote, and the pair geometry is s^2 and c^2 alone; with only that
+// branch's polynomial live, its coefficients stay in scalar registers
+// instead of being rebuilt for every term. Those up to `nsmall`, where a
+// term may take either Bessel branch. And the rest, where every term that
+// is not skipped takes the large-argument fit: that loop needs two
+// constants per concentration, and leaves the factor 1/sqrt(kappa) of its
+// K-bar terms to the finalize (KappaList::scale). Which loop a
+// concentration takes depends on kappa alone, so the sums still do not
+// depend on the chunk or group size.
 #include "device_bessel.hpp"
 #include "kde_internal.hpp"
 
@@ -61,7 +66,7 @@ template <typename T>
 struct CvConsts {
   T A[KDE_MAX_KAPPAS];     // -2 kappa (double) or -2 kappa log2(e) (float)
   T vk[KDE_MAX_KAPPAS];    // X0 / kappa: v = X0 / (2 kappa c) = vk / (2 c)
-  T rsk[KDE_MAX_KAPPAS];   // 1 / sqrt(kappa)
+  T rsk[KDE_MAX_KAPPAS];   // 1 / sqrt(kappa) (concentrations below nsmall)
   T em2k[KDE_MAX_KAPPAS];  // exp(-2 kappa) for the small-argument branch
   T twok[KDE_MAX_KAPPAS];  // 2 kappa
   T tk[KDE_MAX_KAPPAS];    // (2 kappa / X0)^2: t = (R / X0)^2 = tk c^2
@@ -300,8 +305,8 @@ __device__ __forceinline__ Geo<float> pair_geo(const IPart<float>& p, const uint
   g.s2 = g.q * (2.0f - g.q);
   g.c2 = g.c * g.c;
   const float cf = fmaxf(g.c, c_floor<float>());
-  g.inv2c = __builtin_amdgcn_rcpf(2.0f * cf);
   g.rs2c = __builtin_amdgcn_rsqf(2.0f * cf);
+  g.inv2c = g.rs2c * g.rs2c;
   return g;
 }
 
@@ -361,6 +366,9 @@ __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* 
   }
 }
 
+// Concentrations [b0, b_end) within [npure, nsmall): a term takes the
+// small-argument Bessel branch when 2 kappa c < X0, else the large-argument
+// fit.
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
                                            const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
@@ -388,16 +396,63 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
       if (go) {
         T t2 = exp_unit(A * g.s2, etab);
         T t1;
-        if (b < K.nsmall) {
-          const T R = K.twok[b] * g.c;
-          if (R < X0) {
-            t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
-          } else {
-            t1 = exp_unit(Aq, etab) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
-          }
+        const T R = K.twok[b] * g.c;
+        if (R < X0) {
+          t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
         } else {
           t1 = exp_unit(Aq, etab) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
         }
+        if (MASKED) {
+          t1 = live ? t1 : T(0);
+          t2 = live ? t2 : T(0);
+        }
+        acc1[bb].add(t1);
+        acc2[bb].add(t2);
+      }
+    }
+  }
+}
+
+// Concentrations [b0, b_end) at or above nsmall: a term that is not
+// skipped takes the large-argument fit, exp(-2 kappa q) sqrt(x) I0e(x) /
+// sqrt(x) with x = 2 kappa c; the 1/sqrt(kappa) of 1/sqrt(x) is left out
+// here (the finalize applies it to the sum), so each concentration needs
+// only its exponent factor and X0/kappa. In float with up to 8
+// concentrations per chunk those are read into (scalar) registers once per
+// chunk instead of once per term; elsewhere the registers they would take
+// cost more than the loads.
+template <typename T, int BC, bool MASKED>
+__device__ __forceinline__ void pair_chunk_large(const typename Packed<T>::type* __restrict__ tj, int nj,
+                                                 const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
+                                                 const CvConsts<T>& K, const Period& per,
+                                                 const double* __restrict__ etab, Acc<T> (&acc1)[BC],
+                                                 Acc<T> (&acc2)[BC]) {
+  constexpr bool hold = std::is_same<T, float>::value && BC <= 8;
+  const int nb = min(BC, b_end - b0);
+  T Ab[BC], Vb[BC];
+#pragma unroll
+  for (int bb = 0; bb < BC; ++bb) {
+    Ab[bb] = (hold && bb < nb) ? K.A[b0 + bb] : T(0);
+    Vb[bb] = (hold && bb < nb) ? K.vk[b0 + bb] : T(0);
+  }
+  for (int jj = 0; jj < nj; ++jj) {
+    const Geo<T> g = pair_geo(ip, tj, jj, per);
+    bool live = true;
+    if (MASKED) live = valid_i && (!diag || jj > int(threadIdx.x));
+    bool go = true;
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      go = go && (bb < nb);
+      T A = T(0), Aq = T(0);
+      if (go) {
+        A = hold ? Ab[bb] : K.A[b0 + bb];
+        Aq = A * g.q;
+        go = !__all(!live || Aq < K.skip);
+      }
+      if (go) {
+        const T V = hold ? Vb[bb] : K.vk[b0 + bb];
+        T t2 = exp_unit(A * g.s2, etab);
+        T t1 = exp_unit(Aq, etab) * (i0e_sqrt_large(g.inv2c * V) * g.rs2c);
         if (MASKED) {
           t1 = live ? t1 : T(0);
           t2 = live ? t2 : T(0);
@@ -424,7 +479,7 @@ template <> struct PairWaves<double, 8> { static constexpr int value = 5; };
 template <> struct PairWaves<double, 16> { static constexpr int value = 4; };
 template <> struct PairWaves<float, 4> { static constexpr int value = 8; };
 template <> struct PairWaves<float, 8> { static constexpr int value = 8; };
-template <> struct PairWaves<float, 16> { static constexpr int value = 5; };
+template <> struct PairWaves<float, 16> { static constexpr int value = 4; };
 
 // Shared memory of one tile-pair unit.
 template <typename T, int BC>
@@ -486,8 +541,9 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
 
   const int lane = tid & 63, wave = tid >> 6;
   for (int b0 = b_lo; b0 < b_end;) {
-    // chunks do not straddle the end of the pure small-argument range
-    const int bc_end = min(b0 + BC, b0 < K.npure ? min(b_end, K.npure) : b_end);
+    // chunks do not straddle npure or nsmall
+    const int bc_end =
+        min(b0 + BC, b0 < K.npure ? min(b_end, K.npure) : (b0 < K.nsmall ? min(b_end, K.nsmall) : b_end));
     Acc<T> s1[BC], s2[BC];
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
@@ -499,11 +555,16 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
         pair_chunk_pure<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
       else
         pair_chunk_pure<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
-    } else {
+    } else if (b0 < K.nsmall) {
       if (masked)
         pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
       else
         pair_chunk<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
+    } else {
+      if (masked)
+        pair_chunk_large<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
+      else
+        pair_chunk_large<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
     }
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
@@ -585,6 +646,15 @@ __device__ __forceinline__ void cv_slot(const typename Packed<T>::type* __restri
   __syncthreads();
 }
 
+// Whether a term of concentration k may take the small-argument Bessel
+// branch (2 kappa |c| < X0) without being negligible: such a term carries
+// weight exp(-2 kappa (1 - |c|)) <= exp(-(2 kappa - X0)), below the skip
+// bound once 2 kappa - X0 exceeds it. Decides the chunk kind of k.
+template <typename T>
+inline bool small_branch_live(double k) {
+  return 2.0 * k - double(I0eBounds<T>::X0) <= kSkipExponent;
+}
+
 // Per-concentration constants of the pair kernel, computed on the host.
 template <typename T>
 inline CvConsts<T> make_consts(const double* kappas, int B) {
@@ -603,18 +673,30 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
     K.em2k[b] = T(std::exp(-2.0 * k));
     K.twok[b] = T(2.0 * k);
     K.tk[b] = T((2.0 * k / X0) * (2.0 * k / X0));
-    // an argument 2 kappa |c| below X0 carries weight exp(-2 kappa (1 - |c|))
-    // <= exp(-(2 kappa - X0)); beyond the skip bound it is negligible
-    if (2.0 * k - X0 <= kSkipExponent) K.nsmall = b + 1;
+    if (small_branch_live<T>(k)) K.nsmall = b + 1;
     if (2.0 * k < X0) K.npure = b + 1;
   }
   K.skip = T(-kSkipExponent * unit);
   return K;
 }
 
+// Concentrations of a scan as the finalize takes them, with the factor
+// scale[b] it applies to the raw K-bar sum of b: 1/sqrt(kappa) where the
+// pair loop left it out of the terms (from nsmall on), else 1.
 struct KappaList {
   double k[KDE_MAX_KAPPAS];
+  double scale[KDE_MAX_KAPPAS];
 };
+
+template <typename T>
+inline KappaList make_kappa_list(const double* kappas, int B) {
+  KappaList kl{};
+  for (int b = 0; b < B; ++b) {
+    kl.k[b] = kappas[b];
+    kl.scale[b] = small_branch_live<T>(kappas[b]) ? 1.0 : 1.0 / std::sqrt(kappas[b]);
+  }
+  return kl;
+}
 
 // The objective from the unordered pair sums of one set, by one workgroup
 // (thread b handles concentration b): raw[0..B) = sum_{i<j} exp(-2k(1-c))
@@ -630,7 +712,7 @@ __device__ __forceinline__ void cv_finalize_block(const double* __restrict__ raw
     const double k = kap.k[b];
     const double ik = i0e_f64(k);
     const double i2k = i0e_f64(2.0 * k);
-    const double S1 = raw[b] / (L * ik * ik);
+    const double S1 = raw[b] * kap.scale[b] / (L * ik * ik);
     const double S2 = raw[B + b] / (L * ik);
     const double kbar0 = i2k / (L * ik * ik);
     const double val = (n * kbar0 + 2.0 * S1) / (n * n) - 4.0 * S2 / (n * (n - 1.0));
