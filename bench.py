@@ -374,10 +374,10 @@ def main():
                     help="serve form: offered loads as fractions of the plain path's capacity")
     ap.add_argument("--slots", type=int, default=4, help="serve form: server slots (streams)")
     ap.add_argument("--max-batch", type=int, default=16, help="serve form: requests per launch at most")
-    ap.add_argument("--budget-mb", type=int, default=4096, help="serve form: server arena budget")
+    ap.add_argument("--budget-mb", type=int, default=256,
+                    help="serve form: server arena budget (requests' workspaces and attached sessions' arenas)")
     ap.add_argument("--sessions", type=int, default=16, help="serve form: resident PIC sessions")
-    ap.add_argument("--session-period-ms", type=float, default=100.0,
-                    help="serve form: every session steps once per period")
+    ap.add_argument("--session-steps", type=int, default=200, help="serve form: steps of every session per run")
     ap.add_argument("--ensembles", type=int, default=30, help="landau form: ensembles per thermal velocity")
     ap.add_argument("--vths", default="0.20,0.25,0.30,0.35,0.40,0.45", help="landau form: thermal velocities")
     ap.add_argument("--workers", type=int, default=16, help="landau form: sessions stepping at once")
@@ -1044,54 +1044,41 @@ def _latency_summary(lat, t_end, reqs, B):
             "particles_per_s": float(ns.sum()) / t_end}
 
 
-class _SessionLoad:
-    """Resident PIC sessions stepped in a thread: every session advances one
-    step per period while the load runs."""
+class _SessionThreads:
+    """The plain path's resident sessions: a thread per session steps it
+    `steps` times back to back (each step synchronous, on the session's own
+    stream), recording every step's latency."""
 
-    def __init__(self, sessions, period_s):
+    def __init__(self, sessions, steps):
         import threading
-        self.sessions, self.period = sessions, period_s
-        self.threading = threading
-        self.stop = threading.Event()
-        self.steps, self.step_time = 0, 0.0
-        self.error = None
+        self.sessions, self.nsteps, self.threading = sessions, steps, threading
+        self.lat = [[] for _ in sessions]
+        self.errors = []
 
-    def _run(self):
+    def _run(self, k):
         try:
-            nxt = time.perf_counter()
-            while not self.stop.is_set():
-                for s in self.sessions:
-                    t = time.perf_counter()
-                    s.step(1)
-                    self.step_time += time.perf_counter() - t
-                    self.steps += 1
-                nxt += self.period
-                d = nxt - time.perf_counter()
-                if d > 0:
-                    self.stop.wait(d)
-                else:
-                    nxt = time.perf_counter()
-        except Exception as e:  # reported by the caller
-            self.error = e
+            s, lat = self.sessions[k], self.lat[k]
+            for _ in range(self.nsteps):
+                t = time.perf_counter()
+                s.step(1)
+                lat.append(time.perf_counter() - t)
+        except Exception as e:  # reported by join()
+            self.errors.append(e)
 
-    def __enter__(self):
-        self.steps, self.step_time = 0, 0.0
-        self.stop.clear()
-        self.thread = self.threading.Thread(target=self._run, daemon=True)
-        self.t0 = time.perf_counter()
-        self.thread.start()
-        return self
+    def start(self):
+        self.threads = [self.threading.Thread(target=self._run, args=(k,), daemon=True)
+                        for k in range(len(self.sessions))]
+        for t in self.threads:
+            t.start()
 
-    def __exit__(self, *exc):
-        self.stop.set()
-        self.thread.join()
-        self.wall = time.perf_counter() - self.t0
-        if self.error is not None:
-            raise self.error
-
-    def summary(self):
-        return {"session_steps": self.steps, "session_steps_per_s": self.steps / self.wall,
-                "mean_session_step_ms": self.step_time * 1e3 / max(self.steps, 1)}
+    def join(self):
+        for t in self.threads:
+            t.join()
+        if self.errors:
+            raise self.errors[0]
+        lat = np.concatenate([np.asarray(v) for v in self.lat])
+        return {"session_steps": int(lat.size), "session_step_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "session_step_p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
 
 def bench_serve(args, kde, W, torch, dev):
@@ -1099,23 +1086,30 @@ def bench_serve(args, kde, W, torch, dev):
     log-uniform in [1e3, 1e6], M in {64, 128, 256, 512}, float form, CV on
     min(N, 65536) particles over 16 kappas, then pilot deposit, widths and
     adaptive deposit) beside resident PIC sessions (N = 262,144, M = 128,
-    dt = 0.1) that step on their own streams throughout.
+    dt = 0.1), each of which takes `--session-steps` steps in every run.
 
-    The plain path serves the same arrival trace FIFO through the one-set
-    calls on one stream, one request at a time. Its capacity is measured
-    first (all requests waiting at time 0); each load point then replays the
-    trace at that fraction of the plain capacity through the server and
-    through the plain path. Latency is completion minus arrival on the
-    host's monotonic clock."""
+    Served path: a fresh server per run with an arena of `--budget-mb`
+    (256 MiB by default); the sessions are attached to it at the start of
+    the run (kde_server_attach), so their arenas are charged against the
+    same budget as the requests' workspaces and the scheduler steps them
+    beside the request slots. Plain path: the same arrival trace FIFO
+    through the one-set calls on one stream, one request at a time, while a
+    thread per session steps it back to back on the session's own stream.
+    The plain capacity is measured first (all requests waiting at time 0);
+    each load point then replays the trace at that fraction of it through
+    both paths. Request latency is completion minus arrival on the host's
+    monotonic clock; a run's wall time ends when its requests and its
+    session steps are all done."""
     prec = kde.KDE_F32 if args.prec == "f32" else kde.KDE_F64
     tdt = torch.float32 if args.prec == "f32" else torch.float64
-    R = args.requests
+    R, S = args.requests, args.session_steps
     t_gen = time.perf_counter()
     trace = W.request_stream(R, 1.0)          # arrivals at rate 1, rescaled per load point
     base_arrival = np.array([r.arrival_s for r in trace])
     kappas = trace[0].problem.kappas
     B = len(kappas)
     n_cv_cap = 65536
+    budget = args.budget_mb << 20
     xs = [torch.from_numpy(r.problem.x).to(dev).to(tdt).contiguous() for r in trace]
 
     def outputs():
@@ -1129,6 +1123,7 @@ def bench_serve(args, kde, W, torch, dev):
     sessions = [kde.Session(torch.from_numpy(si.x).to(dev).to(tdt).contiguous(),
                             torch.from_numpy(si.v).to(dev).to(tdt).contiguous(),
                             si.L, si.M, si.dt, si.kappas, si.n_cv) for si in sess_init]
+    session_bytes = sum(kde.kde_session_bytes(s_.params) for s_ in sessions)
     gen_s = time.perf_counter() - t_gen
 
     # ---- plain path: FIFO, one request at a time, one stream
@@ -1161,104 +1156,103 @@ def bench_serve(args, kde, W, torch, dev):
         ks.fill_(kstar)
         stream.synchronize()
 
-    def run_plain(arrival):
+    def wait_until(target):
+        while True:
+            d = target - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 2e-4))
+
+    def run_plain(arrival, steps=S):
         lat = np.empty(R)
+        load = _SessionThreads(sessions, steps)
         t0 = time.perf_counter()
+        load.start()
         with torch.cuda.stream(stream):
             for i in range(R):
                 target = t0 + arrival[i]
-                while True:
-                    d = target - time.perf_counter()
-                    if d <= 0:
-                        break
-                    time.sleep(min(d, 2e-4))
+                wait_until(target)
                 plain_one(i)
                 lat[i] = time.perf_counter() - target
-        t_end = time.perf_counter() - t0
-        return lat, t_end
+        t_req = time.perf_counter() - t0
+        sess = load.join()
+        wall = time.perf_counter() - t0
+        out = _latency_summary(lat, t_req, trace, B)
+        out.update(sess, wall_s=wall, session_steps_per_s=sess["session_steps"] / wall)
+        return out
 
     # ---- served path
-    srv = kde.Server(kappas, prec=prec, budget_bytes=args.budget_mb << 20, nslots=args.slots,
-                     max_batch=args.max_batch, n_cv=n_cv_cap, alpha=0.5, device=dev)
     reqs = [kde.Server.request(xs[i], trace[i].problem.L, trace[i].problem.M, out_srv[i]) for i in range(R)]
 
-    def run_served(arrival, srv=srv):
-        lag = np.empty(R)
-        tickets = []
-        t0 = time.perf_counter()
-        for i in range(R):
-            target = t0 + arrival[i]
-            while True:
-                d = target - time.perf_counter()
-                if d <= 0:
-                    break
-                time.sleep(min(d, 2e-4))
-            lag[i] = time.perf_counter() - target
-            tickets.append(srv.submit(reqs[i]))
-        srv.drain()
-        res = [srv.poll(t) for t in tickets]
-        if any(r is None or r["status"] != 0 for r in res):
-            raise RuntimeError("a served request did not complete")
+    def run_served(arrival, steps=S, **policy):
+        srv = kde.Server(kappas, prec=prec, budget_bytes=budget, nslots=args.slots, max_batch=args.max_batch,
+                         n_cv=n_cv_cap, alpha=0.5, device=dev, **policy)
+        try:
+            lag = np.empty(R)
+            t0 = time.perf_counter()
+            attached = [srv.attach(s_, steps) for s_ in sessions] if steps else []
+            tickets = []
+            for i in range(R):
+                target = t0 + arrival[i]
+                wait_until(target)
+                lag[i] = time.perf_counter() - target
+                tickets.append(srv.submit(reqs[i]))
+            res = [srv.wait(t) for t in tickets]
+            sres = [srv.wait(t) for t in attached]
+            wall = time.perf_counter() - t0
+            if any(r["status"] != 0 for r in res + sres):
+                raise RuntimeError("a served request or session step did not complete")
+            st = srv.stats()
+        finally:
+            srv.close()
         lat = lag + np.array([r["latency_s"] for r in res])
-        t_end = float(np.max(arrival + lat))
-        batch = np.array([r["batch_size"] for r in res], dtype=np.float64)
-        return lat, t_end, float(batch.mean())
+        out = _latency_summary(lat, float(np.max(arrival + lat)), trace, B)
+        out.update(session_steps=int(st["session_steps"]), session_step_p50_ms=st["session_p50_s"] * 1e3,
+                   session_step_p99_ms=st["session_p99_s"] * 1e3, wall_s=wall,
+                   session_steps_per_s=st["session_steps"] / wall,
+                   mean_batch=float(np.mean([r["batch_size"] for r in res])), launches=int(st["launches"]))
+        return out
 
-    load = _SessionLoad(sessions, args.session_period_ms * 1e-3)
     # warm-up: a few requests through both paths and one step of every session
     zero = np.zeros(R)
     for i in range(min(R, 32)):
         plain_one(i)
+    srv = kde.Server(kappas, prec=prec, budget_bytes=budget, nslots=args.slots, max_batch=args.max_batch,
+                     n_cv=n_cv_cap, alpha=0.5, device=dev)
     warm = [srv.submit(reqs[i]) for i in range(min(R, 32))]
-    srv.drain()
-    if any(srv.poll(t) is None for t in warm):
+    if any(srv.wait(t)["status"] != 0 for t in warm):
         raise RuntimeError("a warm-up request did not complete")
+    srv.close()
     for s_ in sessions:
         s_.step(1)
     torch.cuda.synchronize()
 
+    def progress(tag, sv, pl=None):
+        msg = {"point": tag, "served_p99_ms": sv["p99_ms"], "served_req_per_s": sv["requests_per_s"]}
+        if pl:
+            msg.update(plain_p99_ms=pl["p99_ms"], plain_req_per_s=pl["requests_per_s"])
+        print(json.dumps(msg), file=sys.stderr, flush=True)
+
     points = []
-    with load:
-        lat, t_pl = run_plain(zero)
-    cap_plain = R / t_pl
-    sat_pl = _latency_summary(lat, t_pl, trace, B)
-    sat_pl.update(load.summary())
-    with load:
-        lat, t_sv, mb = run_served(zero)
-    sat_sv = _latency_summary(lat, t_sv, trace, B)
-    sat_sv.update(load.summary())
-    sat_sv["mean_batch"] = mb
+    sat_pl = run_plain(zero)
+    cap_plain = sat_pl["requests_per_s"]
+    sat_sv = run_served(zero)
     same = all(torch.equal(out_srv[i][2], out_pl[i][2]) and torch.equal(out_srv[i][3], out_pl[i][3]) and
                torch.equal(out_srv[i][4], out_pl[i][4]) for i in range(R))
+    progress("saturated", sat_sv, sat_pl)
     points.append({"offered_load": "saturated (all requests waiting at t=0)", "served": sat_sv, "plain": sat_pl})
     # the same saturated trace under a throughput policy: no request is
     # large, so every one may batch with requests of similar cost and run
     # concurrently with other batches
-    srv_t = kde.Server(kappas, prec=prec, budget_bytes=args.budget_mb << 20, nslots=args.slots,
-                       max_batch=args.max_batch, n_cv=n_cv_cap, alpha=0.5, device=dev, large_terms=1e300)
-    with load:
-        lat, t_tp, mb = run_served(zero, srv_t)
-    sat_tp = _latency_summary(lat, t_tp, trace, B)
-    sat_tp.update(load.summary())
-    sat_tp["mean_batch"] = mb
-    srv_t.close()
+    sat_tp = run_served(zero, large_terms=1e300)
+    progress("saturated, throughput policy", sat_tp)
     for f in [float(v) for v in args.loads.split(",") if v]:
         rate = f * cap_plain
         arrival = base_arrival / rate
-        with load:
-            lat, t_sv, mb = run_served(arrival)
-        sv = _latency_summary(lat, t_sv, trace, B)
-        sv.update(load.summary())
-        sv["mean_batch"] = mb
-        with load:
-            lat, t_pl = run_plain(arrival)
-        pl = _latency_summary(lat, t_pl, trace, B)
-        pl.update(load.summary())
+        sv = run_served(arrival)
+        pl = run_plain(arrival)
+        progress(f, sv, pl)
         points.append({"offered_load": f, "rate_per_s": rate, "served": sv, "plain": pl})
-        print(json.dumps({"load": f, "served_p99_ms": sv["p99_ms"], "plain_p99_ms": pl["p99_ms"]}),
-              file=sys.stderr, flush=True)
-    stats = srv.stats()
-    srv.close()
     ns = np.array([r.problem.x.shape[0] for r in trace], dtype=np.float64)
     line = {"metric": METRIC, "form": "serve", "value": sat_sv["pair_evals_per_s"], "unit": "CV pair-evals/s",
             "n_gpus": 1, "steps": R, "warmup": 0, "ms_per_step": 1e3 / sat_sv["requests_per_s"],
@@ -1266,16 +1260,18 @@ def bench_serve(args, kde, W, torch, dev):
             "data": "synthetic",
             "config": {"workload": f"serving form: Poisson stream of {R} KDE/CV requests (N log-uniform in "
                                    "[1e3,1e6], M in {64,128,256,512}, CV on min(N,65536), 16 kappas in [1,1e4]) "
-                                   f"beside {len(sessions)} resident PIC sessions (N=262,144, M=128, dt=0.1, "
-                                   f"one step each per {args.session_period_ms:g} ms)",
+                                   f"beside {len(sessions)} resident PIC sessions (N=262,144, M=128, dt=0.1), "
+                                   f"{S} steps each per run",
                        "requests": R, "mean_N": float(ns.mean()), "slots": args.slots, "max_batch": args.max_batch,
-                       "budget_mb": args.budget_mb, "sessions": len(sessions)},
+                       "budget_mb": args.budget_mb, "sessions": len(sessions), "session_steps_per_run": S,
+                       "session_arena_mb": session_bytes / 2**20},
             "plain_capacity_requests_per_s": cap_plain,
             "served_over_plain_throughput": sat_sv["requests_per_s"] / sat_pl["requests_per_s"],
+            "served_over_plain_wall": sat_pl["wall_s"] / sat_sv["wall_s"],
             "saturated_throughput_policy": sat_tp,
             "throughput_policy_over_plain": sat_tp["requests_per_s"] / sat_pl["requests_per_s"],
             "served_equals_plain_bitwise": bool(same),
-            "load_points": points, "server_launches": stats["launches"], "input_generation_s": gen_s}
+            "load_points": points, "input_generation_s": gen_s}
     for s_ in sessions:
         s_.close()
     out = json.dumps(line)

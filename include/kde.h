@@ -615,11 +615,16 @@ kde_status kde_server_submit(kde_server* s, const kde_batch_set* req_h, void* st
 kde_status kde_server_attach(kde_server* s, kde_session* session, int64_t nsteps, uint64_t* ticket_h);
 /* Withdraw a queued request: KDE_OK (its result is KDE_E_CANCELLED),
  * KDE_E_AGAIN when it already runs (it will complete), KDE_E_NOT_FOUND
- * otherwise. */
+ * otherwise. For an attached session's ticket: KDE_OK, the session takes no
+ * further step, and its ticket completes with KDE_E_CANCELLED (steps = those
+ * taken) once the step in flight is done; the caller may then use the
+ * session again. */
 kde_status kde_server_cancel(kde_server* s, uint64_t ticket);
 /* KDE_OK and the result once done, KDE_E_AGAIN while pending; a ticket that
  * ended otherwise returns its status (res_h filled). */
 kde_status kde_server_poll(kde_server* s, uint64_t ticket, kde_result* res_h);
+/* Block until the ticket completes, then as kde_server_poll. */
+kde_status kde_server_wait(kde_server* s, uint64_t ticket, kde_result* res_h);
 /* Wait until every submitted request has completed and every attached
  * session has taken its steps. */
 kde_status kde_server_drain(kde_server* s);

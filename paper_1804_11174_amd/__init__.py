@@ -135,6 +135,7 @@ _SIGNATURES = {
     "kde_server_attach": (_i32, [_vp, _vp, _i64, ctypes.POINTER(ctypes.c_uint64)]),
     "kde_server_cancel": (_i32, [_vp, ctypes.c_uint64]),
     "kde_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(kde_result)]),
+    "kde_server_wait": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(kde_result)]),
     "kde_server_drain": (_i32, [_vp]),
     "kde_server_stats": (_i32, [_vp, ctypes.POINTER(kde_server_stats_t)]),
     "kde_server_destroy": (_i32, [_vp]),
@@ -586,7 +587,8 @@ def kde_server_attach(handle, session_handle, nsteps: int) -> int:
 
 
 def kde_server_cancel(handle, ticket: int) -> bool:
-    """True when the queued request was withdrawn, False when it already runs."""
+    """True when the queued request was withdrawn or the attached session
+    detaches (after its step in flight), False when the request already runs."""
     st = require_library().kde_server_cancel(handle, ctypes.c_uint64(ticket))
     if st == KDE_E_AGAIN:
         return False
@@ -603,6 +605,15 @@ def kde_server_poll(handle, ticket: int):
         return None
     if st not in (0, KDE_E_NUMERIC, KDE_E_CANCELLED, KDE_E_HIP):
         _check(st, "kde_server_poll")
+    return {f: getattr(r, f) for f, _ in kde_result._fields_}
+
+
+def kde_server_wait(handle, ticket: int) -> dict:
+    """Block until the ticket completes; its result as kde_server_poll's."""
+    r = kde_result()
+    st = require_library().kde_server_wait(handle, ctypes.c_uint64(ticket), ctypes.byref(r))
+    if st not in (0, KDE_E_NUMERIC, KDE_E_CANCELLED, KDE_E_HIP):
+        _check(st, "kde_server_wait")
     return {f: getattr(r, f) for f, _ in kde_result._fields_}
 
 
@@ -655,6 +666,9 @@ class Server:
 
     def poll(self, ticket):
         return kde_server_poll(self.handle, ticket)
+
+    def wait(self, ticket):
+        return kde_server_wait(self.handle, ticket)
 
     def drain(self):
         kde_server_drain(self.handle)

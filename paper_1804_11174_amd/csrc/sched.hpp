@@ -12,7 +12,8 @@
 // workspaces fit together in the largest free block of the arena; small
 // requests may pass waiting large ones. A head that does not fit waits.
 // Attached sessions are charged their arena bytes while attached and are
-// stepped one step in flight at a time, beside the slots. A failure is
+// stepped one step in flight at a time, beside the slots; cancelling one
+// detaches it after the step in flight. A failure is
 // kept to the work it belongs to: a group whose launch or device work
 // fails completes its own requests with that status and frees its slot; a
 // session whose step fails completes its ticket with that status.
@@ -158,7 +159,7 @@ class Scheduler {
     uint64_t ticket;
     size_t off, bytes;
     int64_t steps_left, steps_done = 0;
-    bool in_flight = false;
+    bool in_flight = false, cancelled = false;
     Clock::time_point arrival, step_start;
   };
 
@@ -195,12 +196,15 @@ class Scheduler {
       stats_.first = now;
       stats_.have_first = true;
     }
-    sessions_.push_back(Session{ticket, off, bytes, steps, 0, false, now, now});
+    sessions_.push_back(Session{ticket, off, bytes, steps, 0, false, false, now, now});
     return KDE_OK;
   }
 
   // Remove a queued request: KDE_OK (its outcome is KDE_E_CANCELLED),
-  // KDE_E_AGAIN when it already runs, KDE_E_NOT_FOUND otherwise.
+  // KDE_E_AGAIN when it already runs, KDE_E_NOT_FOUND otherwise. An
+  // attached session takes no further step: KDE_OK, and its ticket
+  // completes with KDE_E_CANCELLED once the step in flight (if any) is
+  // done, with the steps taken.
   kde_status cancel(uint64_t ticket, Clock::time_point now) {
     for (auto it = queue_.begin(); it != queue_.end(); ++it) {
       if (it->ticket != ticket) continue;
@@ -217,8 +221,11 @@ class Scheduler {
     for (const Slot& sl : slots_)
       for (const Request& r : sl.reqs)
         if (r.ticket == ticket) return KDE_E_AGAIN;
-    for (const Session& se : sessions_)
-      if (se.ticket == ticket) return KDE_E_AGAIN;
+    for (Session& se : sessions_)
+      if (se.ticket == ticket) {
+        se.cancelled = true;
+        return KDE_OK;
+      }
     return KDE_E_NOT_FOUND;
   }
 
@@ -337,8 +344,9 @@ class Scheduler {
         }
       }
       if (st == KDE_OK && !se.in_flight) {
-        if (se.steps_left <= 0 || closing_) {
+        if (se.steps_left <= 0 || closing_ || se.cancelled) {
           finished = true;
+          if (se.cancelled) st = KDE_E_CANCELLED;
         } else {
           se.step_start = now;
           st = ex_->session_begin(se.ticket);
@@ -352,7 +360,7 @@ class Scheduler {
         o.latency_s = o.run_s = seconds(se.arrival, now);
         o.steps = se.steps_done;
         results_[se.ticket] = o;
-        if (st != KDE_OK) stats_.failed += 1;
+        if (st != KDE_OK && st != KDE_E_CANCELLED) stats_.failed += 1;
         alloc_.release(se.off, se.bytes);
         ex_->forget(se.ticket);
         stats_.last = now;

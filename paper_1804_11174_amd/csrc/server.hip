@@ -296,10 +296,23 @@ kde_status kde_server_cancel(kde_server* s, uint64_t ticket) {
   if (!s) return fail(KDE_E_INVALID_ARG, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   const kde_status st = s->sch->cancel(ticket, Clock::now());
-  if (st == KDE_E_NOT_FOUND) return fail(st, "ticket %llu is not queued", (unsigned long long)ticket);
+  if (st == KDE_E_NOT_FOUND) return fail(st, "ticket %llu is neither queued nor attached", (unsigned long long)ticket);
   if (st == KDE_E_AGAIN) return KDE_E_AGAIN;
   s->cv_done.notify_all();
   return st;
+}
+
+// Fills res_h from a completed ticket's outcome; returns its status.
+static kde_status report(uint64_t ticket, const sched::Outcome& o, kde_result* res_h) {
+  memset(res_h, 0, sizeof *res_h);
+  res_h->status = o.status;
+  res_h->batch_size = o.batch_size;
+  res_h->latency_s = o.latency_s;
+  res_h->queue_s = o.queue_s;
+  res_h->run_s = o.run_s;
+  res_h->steps = o.steps;
+  if (o.status != KDE_OK) return fail(o.status, "ticket %llu ended with %s", (unsigned long long)ticket, kde_status_str(o.status));
+  return KDE_OK;
 }
 
 kde_status kde_server_poll(kde_server* s, uint64_t ticket, kde_result* res_h) {
@@ -310,15 +323,22 @@ kde_status kde_server_poll(kde_server* s, uint64_t ticket, kde_result* res_h) {
   const kde_status st = s->sch->poll(ticket, &o);
   if (st == KDE_E_NOT_FOUND) return fail(st, "unknown ticket %llu", (unsigned long long)ticket);
   if (st == KDE_E_AGAIN) return KDE_E_AGAIN;
-  memset(res_h, 0, sizeof *res_h);
-  res_h->status = o.status;
-  res_h->batch_size = o.batch_size;
-  res_h->latency_s = o.latency_s;
-  res_h->queue_s = o.queue_s;
-  res_h->run_s = o.run_s;
-  res_h->steps = o.steps;
-  if (o.status != KDE_OK) return fail(o.status, "ticket %llu ended with %s", (unsigned long long)ticket, kde_status_str(o.status));
-  return KDE_OK;
+  return report(ticket, o, res_h);
+}
+
+kde_status kde_server_wait(kde_server* s, uint64_t ticket, kde_result* res_h) {
+  clear_error();
+  if (!s || !res_h) return fail(KDE_E_INVALID_ARG, "server and res_h must not be NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  sched::Outcome o;
+  kde_status st = s->sch->poll(ticket, &o);
+  if (st == KDE_E_NOT_FOUND) return fail(st, "unknown ticket %llu", (unsigned long long)ticket);
+  s->cv_work.notify_one();
+  s->cv_done.wait(lk, [&] {
+    st = s->sch->poll(ticket, &o);
+    return st != KDE_E_AGAIN;
+  });
+  return report(ticket, o, res_h);
 }
 
 kde_status kde_server_drain(kde_server* s) {

@@ -216,6 +216,27 @@ static void test_sessions() {
   CHECK(s.free_bytes() == 10000);
 }
 
+// Cancelling an attached session detaches it after the step in flight.
+static void test_session_detach() {
+  FakeDevice d;
+  Scheduler s(cfg(10000, 1, 1), &d);
+  auto now = Clock::now();
+  const uint64_t se = s.new_ticket();
+  CHECK(s.attach(se, 4000, 1000000, now) == KDE_OK);
+  for (int k = 0; k < 20; ++k) {
+    s.tick(now);
+    now += std::chrono::microseconds(10);
+  }
+  CHECK(s.cancel(se, now) == KDE_OK);
+  CHECK(s.cancel(se, now) == KDE_OK);  // still attached until its step ends
+  run(s, now);
+  Outcome o;
+  CHECK(s.poll(se, &o) == KDE_OK && o.status == KDE_E_CANCELLED);
+  CHECK(o.steps >= 1 && o.steps < 1000000 && o.steps == s.stats().session_steps);
+  CHECK(s.cancel(se, now) == KDE_E_NOT_FOUND);
+  CHECK(s.free_bytes() == 10000 && s.stats().failed == 0 && s.stats().cancelled == 0);
+}
+
 static void test_close() {
   FakeDevice d;
   Scheduler s(cfg(1 << 20, 1, 1), &d);
@@ -287,6 +308,7 @@ int main() {
   test_cancel();
   test_failure_isolation_and_numeric();
   test_sessions();
+  test_session_detach();
   test_close();
   test_threads();
   std::printf("sched tests ok\n");

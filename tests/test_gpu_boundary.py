@@ -217,3 +217,42 @@ def test_create_and_submit_follow_the_callers_stream(gpu):
             assert torch.equal(a, b)
     finally:
         srv.close()
+
+
+def test_server_detaches_a_cancelled_session_and_wait_blocks(gpu):
+    """A session attached for unbounded steps detaches when cancelled: its
+    ticket (kde_server_wait) ends with KDE_E_CANCELLED and the steps it took,
+    after which it is where a twin stepped that many times directly is; the
+    request submitted beside it completes through kde_server_wait."""
+    import time
+    import torch
+    L, M, n = 4 * math.pi, 64, 8192
+    kap = W.log_kappas(1.0, 1e3, 8)
+    rng = W.rng_for(5, 97)
+    x0 = to_gpu(W.cosine_positions(rng, n, L, 0.01, 0.5), torch.float32)
+    v0 = to_gpu(W.maxwellian(rng, n, 1.0), torch.float32)
+    a, b = gpu.Session(x0, v0, L, M, 0.1, kap, 2048), gpu.Session(x0, v0, L, M, 0.1, kap, 2048)
+    srv = gpu.Server(kap, prec=gpu.KDE_F32, budget_bytes=64 << 20, nslots=2, max_batch=4)
+    try:
+        announce("attached session detached by cancel")
+        st = srv.attach(a, 1 << 40)
+        x = to_gpu(W.cosine_positions(np.random.default_rng([14, 1]), 5000, L, 0.3, 0.5).astype(np.float32))
+        out = _outs(x, M, 8)
+        res = srv.wait(srv.submit(gpu.Server.request(x, L, M, out)))
+        assert res["status"] == 0
+        t0 = time.monotonic()
+        while srv.stats()["session_steps"] < 3 and time.monotonic() - t0 < 30:
+            time.sleep(0.01)
+        assert srv.cancel(st)
+        res = srv.wait(st)
+        assert res["status"] == gpu.KDE_E_CANCELLED and 3 <= res["steps"] < (1 << 40)
+        assert srv.stats()["failed"] == 0
+        b.step(int(res["steps"]))
+        for f in (gpu.KDE_SESSION_X, gpu.KDE_SESSION_V, gpu.KDE_SESSION_KAPPA):
+            assert torch.equal(a.read(f), b.read(f)), f
+        assert a.state() == b.state()
+        a.step(1)  # the caller owns it again
+    finally:
+        srv.close()
+        a.close()
+        b.close()
