@@ -640,7 +640,8 @@ kde_status kde_ad_pvalue(double a2, double* p_h);
 
 /*
  * Tuning of the CV pair kernel, by particle count: chunk_h[k], the number
- * of concentrations evaluated per pass over a tile pair (4, 8 or 16), and
+ * of concentrations evaluated per pass over a tile pair (4 or 8, or 16 in
+ * double; KDE_E_INVALID_ARG otherwise), and
  * group_h[k], the number of concentrations one workgroup takes on (0 = all
  * of them; else a multiple of chunk_h[k] up to KDE_MAX_KAPPAS), so that a
  * tile pair is split over ceil(B / group) workgroups, which shortens the
@@ -650,9 +651,10 @@ kde_status kde_ad_pvalue(double a2, double* p_h);
  * the same terms in the same order whatever the pass size or split, so
  * results are bitwise equal. The table is process-wide; set it before
  * launching work, not while calls on other threads are running.
- * kde_tune_get returns the entry used for N (group_h may be NULL). The
- * default is (16, 0) for every N until a table is set (the Python binding
- * installs the autotuned table shipped with the package).
+ * kde_tune_get returns the entry used for N (group_h may be NULL). Until a
+ * table is set, the library uses the one its autotuner measured on gfx950
+ * (built in; the Python binding installs the same table from the package's
+ * tune_gfx950.json).
  */
 kde_status kde_tune_set(int32_t prec, int32_t count, const int64_t* n_max_h, const int32_t* chunk_h,
                         const int32_t* group_h);

@@ -448,17 +448,9 @@ static kde_status enqueue_batch(const BatchPlan& b, const BatchArgs& a, const st
     const int64_t hi = prefix[size_t(PF_PAIRS) * (ns + 1) + b.bucket_begin[k + 1]];
     if (hi - lo > int64_t(0x7fffffff)) return fail(KDE_E_INVALID_ARG, "too many pair units for one launch");
     const dim3 grid{unsigned(hi - lo)};
-    switch (b.bucket_bc[k]) {
-      case 4:
-        hipLaunchKernelGGL((batch_pairs_kernel<T, 4>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
-        break;
-      case 8:
-        hipLaunchKernelGGL((batch_pairs_kernel<T, 8>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
-        break;
-      default:
-        hipLaunchKernelGGL((batch_pairs_kernel<T, 16>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
-        break;
-    }
+    with_pass_size<T>(b.bucket_bc[k], [&](auto bc) {
+      hipLaunchKernelGGL((batch_pairs_kernel<T, decltype(bc)::value>), grid, dim3(kBlock), 0, s, a, K, lo, hi);
+    });
     KDE_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(batch_level1_kernel<SRC_CV>,

@@ -115,15 +115,17 @@ __global__ void __launch_bounds__(KDE_MAX_KAPPAS) cv_finalize_kernel(const doubl
 // (kde_tune_set): concentrations per pass and per work unit. The
 // per-concentration sums do not depend on either: each concentration
 // accumulates the same terms in the same order and the skip test is
-// monotone in kappa. Defaults come from the autotuner run on gfx950
-// (paper_1804_11174_amd/autotune.py).
+// monotone in kappa. The defaults are the table the autotuner
+// (paper_1804_11174_amd/autotune.py) measured on gfx950, written by it to
+// tune_gfx950.inc.
 namespace {
 struct TuneEntry {
   int64_t n_max;
   PairTuning t;
 };
 std::mutex g_tune_mu;
-std::vector<TuneEntry> g_tune[2] = {{{INT64_MAX, {16, 0}}}, {{INT64_MAX, {16, 0}}}};
+#include "tune_gfx950.inc"
+std::vector<TuneEntry> g_tune[2] = {KDE_TUNE_F64, KDE_TUNE_F32};
 }  // namespace
 
 PairTuning tuned_pass(int prec, int64_t n) {
@@ -135,8 +137,8 @@ PairTuning tuned_pass(int prec, int64_t n) {
 kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk, const int32_t* group) {
   std::vector<TuneEntry> t;
   for (int k = 0; k < count; ++k) {
-    if (chunk[k] != 4 && chunk[k] != 8 && chunk[k] != 16)
-      return fail(KDE_E_INVALID_ARG, "chunk must be 4, 8 or 16 (entry %d is %d)", k, chunk[k]);
+    if (chunk[k] != 4 && chunk[k] != 8 && !(chunk[k] == 16 && prec == KDE_F64))
+      return fail(KDE_E_INVALID_ARG, "chunk must be 4 or 8, or 16 in double (entry %d is %d)", k, chunk[k]);
     const int g = group ? group[k] : 0;
     if (g < 0 || g > KDE_MAX_KAPPAS || g % chunk[k] != 0)
       return fail(KDE_E_INVALID_ARG, "group must be 0 or a multiple of chunk up to %d (entry %d is %d)",
@@ -205,20 +207,10 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
   {
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
     const dim3 grid{unsigned(p.slots * groups)}, block{unsigned(kBlock)};
-    switch (tp.chunk) {
-      case 4:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 4>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
-                           buf.partials);
-        break;
-      case 8:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 8>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
-                           buf.partials);
-        break;
-      default:
-        hipLaunchKernelGGL((cv_pairs_kernel<T, 16>), grid, block, 0, s, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
-                           buf.partials);
-        break;
-    }
+    with_pass_size<T>(tp.chunk, [&](auto bc) {
+      hipLaunchKernelGGL((cv_pairs_kernel<T, decltype(bc)::value>), grid, block, 0, s, (const P*)packed, n,
+                         p.sort.cells, dom->L, p.slots, groups, gsize, K, buf.partials);
+    });
   }
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(buf.partials, p.slots, 2 * B, buf.colsum, buf.raw, s));

@@ -338,13 +338,22 @@ __device__ __forceinline__ GeoS<float> pair_geo_small(const IPart<float>& p, con
 
 // Concentrations [b0, b_end) with 2 kappa < X0: every term takes the
 // small-argument branch, and no exponent reaches -X0 > -S, so nothing is
-// skipped. Same accumulation order as pair_chunk.
+// skipped. Same accumulation order as pair_chunk. In float the chunk's
+// three constants per concentration sit in (scalar) registers.
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* __restrict__ tj, int nj,
                                                 const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
                                                 const CvConsts<T>& K, const double* __restrict__ etab,
                                                 Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
+  constexpr bool hold = std::is_same<T, float>::value;
   const int nb = min(BC, b_end - b0);
+  T Ab[BC], Eb[BC], Tb[BC];
+#pragma unroll
+  for (int bb = 0; bb < BC; ++bb) {
+    Ab[bb] = (hold && bb < nb) ? K.A[b0 + bb] : T(0);
+    Eb[bb] = (hold && bb < nb) ? K.em2k[b0 + bb] : T(0);
+    Tb[bb] = (hold && bb < nb) ? K.tk[b0 + bb] : T(0);
+  }
   for (int jj = 0; jj < nj; ++jj) {
     const GeoS<T> g = pair_geo_small(ip, tj, jj);
     bool live = true;
@@ -353,8 +362,8 @@ __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* 
     for (int bb = 0; bb < BC; ++bb) {
       if (bb < nb) {
         const int b = b0 + bb;
-        T t2 = exp_unit(K.A[b] * g.s2, etab);
-        T t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
+        T t2 = exp_unit((hold ? Ab[bb] : K.A[b]) * g.s2, etab);
+        T t1 = (hold ? Eb[bb] : K.em2k[b]) * i0_small((hold ? Tb[bb] : K.tk[b]) * g.c2);
         if (MASKED) {
           t1 = live ? t1 : T(0);
           t2 = live ? t2 : T(0);
@@ -417,17 +426,16 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
 // skipped takes the large-argument fit, exp(-2 kappa q) sqrt(x) I0e(x) /
 // sqrt(x) with x = 2 kappa c; the 1/sqrt(kappa) of 1/sqrt(x) is left out
 // here (the finalize applies it to the sum), so each concentration needs
-// only its exponent factor and X0/kappa. In float with up to 8
-// concentrations per chunk those are read into (scalar) registers once per
-// chunk instead of once per term; elsewhere the registers they would take
-// cost more than the loads.
+// only its exponent factor and X0/kappa. In float those are read into
+// (scalar) registers once per chunk instead of once per term; in double
+// the registers they would take cost more than the loads.
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk_large(const typename Packed<T>::type* __restrict__ tj, int nj,
                                                  const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
                                                  const CvConsts<T>& K, const Period& per,
                                                  const double* __restrict__ etab, Acc<T> (&acc1)[BC],
                                                  Acc<T> (&acc2)[BC]) {
-  constexpr bool hold = std::is_same<T, float>::value && BC <= 8;
+  constexpr bool hold = std::is_same<T, float>::value;
   const int nb = min(BC, b_end - b0);
   T Ab[BC], Vb[BC];
 #pragma unroll
@@ -479,7 +487,6 @@ template <> struct PairWaves<double, 8> { static constexpr int value = 5; };
 template <> struct PairWaves<double, 16> { static constexpr int value = 4; };
 template <> struct PairWaves<float, 4> { static constexpr int value = 8; };
 template <> struct PairWaves<float, 8> { static constexpr int value = 8; };
-template <> struct PairWaves<float, 16> { static constexpr int value = 4; };
 
 // Shared memory of one tile-pair unit.
 template <typename T, int BC>

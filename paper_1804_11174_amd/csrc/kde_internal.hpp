@@ -115,6 +115,25 @@ struct PairTuning {
 PairTuning tuned_pass(int prec, int64_t n);
 kde_status set_tuning(int prec, int count, const int64_t* n_max, const int32_t* chunk, const int32_t* group);
 
+// Calls f(std::integral_constant<int, BC>{}) with the pair kernel's pass
+// size for `chunk`: 4, 8, or 16 in double. The float kernel holds a
+// compensated pair of sums per concentration, which at 16 per pass does
+// not fit its registers, so float has no pass of 16 (set_tuning refuses
+// it).
+template <typename T, typename F>
+inline void with_pass_size(int chunk, F&& f) {
+  if (chunk == 4) {
+    f(std::integral_constant<int, 4>{});
+  } else if constexpr (std::is_same<T, double>::value) {
+    if (chunk == 16)
+      f(std::integral_constant<int, 16>{});
+    else
+      f(std::integral_constant<int, 8>{});
+  } else {
+    f(std::integral_constant<int, 8>{});
+  }
+}
+
 // Tile pairs of a CV scan over n particles, and the slots (rows of partial
 // sums, one workgroup per slot and concentration group) they are dealt to.
 inline int64_t cv_tile_pairs(int64_t n) {

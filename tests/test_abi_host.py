@@ -169,6 +169,8 @@ def test_tuning_table_round_trip():
         kde.kde_tune_set(kde.KDE_F64, [10], [8], [12])
     with pytest.raises(kde.KdeError):                           # group beyond the kappa limit
         kde.kde_tune_set(kde.KDE_F64, [10], [16], [80])
+    with pytest.raises(kde.KdeError):                           # float passes are 4 or 8
+        kde.kde_tune_set(kde.KDE_F32, [10], [16])
     # restore the shipped table (or the built-in default)
     if os.path.exists(kde.TUNE_FILE):
         kde.load_tuning(kde.TUNE_FILE)
