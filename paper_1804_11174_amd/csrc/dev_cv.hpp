@@ -52,10 +52,12 @@
 // instead of being rebuilt for every term. Those up to `nsmall`, where a
 // term may take either Bessel branch. And the rest, where every term that
 // is not skipped takes the large-argument fit: that loop needs two
-// constants per concentration, and leaves the factor 1/sqrt(kappa) of its
-// K-bar terms to the finalize (KappaList::scale). Which loop a
-// concentration takes depends on kappa alone, so the sums still do not
-// depend on the chunk or group size.
+// constants per concentration. From npure on, the K-bar terms leave out a
+// factor 1/sqrt(kappa) (the large-argument fit's 1/sqrt(2 kappa c) and the
+// small-argument constant are scaled to match), which the finalize applies
+// to their sums (KappaList::scale). Which loop a concentration takes
+// depends on kappa alone, so the sums still do not depend on the chunk or
+// group size.
 #include "device_bessel.hpp"
 #include "kde_internal.hpp"
 
@@ -66,8 +68,7 @@ template <typename T>
 struct CvConsts {
   T A[KDE_MAX_KAPPAS];     // -2 kappa (double) or -2 kappa log2(e) (float)
   T vk[KDE_MAX_KAPPAS];    // X0 / kappa: v = X0 / (2 kappa c) = vk / (2 c)
-  T rsk[KDE_MAX_KAPPAS];   // 1 / sqrt(kappa) (concentrations below nsmall)
-  T em2k[KDE_MAX_KAPPAS];  // exp(-2 kappa) for the small-argument branch
+  T em2k[KDE_MAX_KAPPAS];  // small-argument branch: exp(-2 kappa), times sqrt(kappa) from npure on
   T twok[KDE_MAX_KAPPAS];  // 2 kappa
   T tk[KDE_MAX_KAPPAS];    // (2 kappa / X0)^2: t = (R / X0)^2 = tk c^2
   int B;
@@ -79,40 +80,59 @@ struct CvConsts {
 template <typename T>
 struct Acc;
 
+// j partners whose terms a float sum adds in plain float before folding
+// them into its compensated sum (a power of two).
+constexpr int kRun = 8;
+
 template <>
 struct Acc<double> {
   double s;
   __device__ __forceinline__ void zero() { s = 0.0; }
   __device__ __forceinline__ void add(double v) { s += v; }
+  __device__ __forceinline__ void fold() {}
   __device__ __forceinline__ double value() const { return s; }
 };
 
-// Float terms in a compensated float sum (Kahan): c carries the part of
-// each addition that the float sum s lost and is taken off the next term,
-// so a thread's sum over one tile (at most 256 terms per chunk) is within
-// about two units of float rounding of the exact sum of its terms. The
-// value is handed on in double (s - c) to the fixed-order reductions across
-// threads, waves and tile pairs, which are FP64. Four float operations per
-// term: on MI355X the float pair kernel takes about 15 % longer than with
-// each term converted to double and added there (a conversion and a double
-// add), the form used before; summing runs of four terms in plain float and
-// folding each run into the compensated sum was no faster (its third
-// register per sum costs occupancy).
+// Float terms in a compensated float sum: the terms of kRun consecutive j
+// partners are added in plain float into r, and each such run is folded
+// into a Kahan sum (s, c), c carrying the part of each addition that s lost,
+// taken off the next run. All terms are positive, so a thread's sum over
+// one tile is within about (kRun + 1) units of float rounding (5.4e-7
+// relative for runs of 8) of the exact sum of its terms. The value is handed
+// on in double (s - c + r) to the fixed-order reductions across threads,
+// waves and tile pairs, which are FP64. Per term that is one float add and
+// a fifth of a fold, against four operations and a register move for a
+// Kahan step per term: on MI355X the float pair kernel at the paper-scale
+// scan takes 17.2 ms instead of 19.9 ms, and its CV and sums move by less
+// than 1e-9 relative (the error of the float terms themselves, about 7e-8,
+// dominates).
 template <>
 struct Acc<float> {
-  float s, c;
+  float s, c, r;
   __device__ __forceinline__ void zero() {
     s = 0.0f;
     c = 0.0f;
+    r = 0.0f;
   }
-  __device__ __forceinline__ void add(float v) {
-    const float y = v - c;
+  __device__ __forceinline__ void add(float v) { r += v; }
+  __device__ __forceinline__ void fold() {
+    const float y = r - c;
     const float t = s + y;
     c = (t - s) - y;
     s = t;
+    r = 0.0f;
   }
-  __device__ __forceinline__ double value() const { return double(s) - double(c); }
+  __device__ __forceinline__ double value() const { return double(s) - double(c) + double(r); }
 };
+
+template <typename T, int BC>
+__device__ __forceinline__ void fold_all(Acc<T> (&a1)[BC], Acc<T> (&a2)[BC]) {
+#pragma unroll
+  for (int bb = 0; bb < BC; ++bb) {
+    a1[bb].fold();
+    a2[bb].fold();
+  }
+}
 
 // Pair-kernel exponents lie in [-2 kappa, 0] with kappa <= KDE_MAX_CV_KAPPA
 // (checked on the host), inside the table exponential's domain; `tab` is
@@ -372,12 +392,14 @@ __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* 
         acc2[bb].add(t2);
       }
     }
+    if ((jj & (kRun - 1)) == kRun - 1) fold_all(acc1, acc2);
   }
+  fold_all(acc1, acc2);
 }
 
 // Concentrations [b0, b_end) within [npure, nsmall): a term takes the
 // small-argument Bessel branch when 2 kappa c < X0, else the large-argument
-// fit.
+// fit (both without the factor 1/sqrt(kappa)).
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
                                            const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
@@ -409,7 +431,7 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
         if (R < X0) {
           t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
         } else {
-          t1 = exp_unit(Aq, etab) * i0e_sqrt_large(g.inv2c * K.vk[b]) * (g.rs2c * K.rsk[b]);
+          t1 = exp_unit(Aq, etab) * (i0e_sqrt_large(g.inv2c * K.vk[b]) * g.rs2c);
         }
         if (MASKED) {
           t1 = live ? t1 : T(0);
@@ -419,7 +441,9 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
         acc2[bb].add(t2);
       }
     }
+    if ((jj & (kRun - 1)) == kRun - 1) fold_all(acc1, acc2);
   }
+  fold_all(acc1, acc2);
 }
 
 // Concentrations [b0, b_end) at or above nsmall: a term that is not
@@ -469,7 +493,9 @@ __device__ __forceinline__ void pair_chunk_large(const typename Packed<T>::type*
         acc2[bb].add(t2);
       }
     }
+    if ((jj & (kRun - 1)) == kRun - 1) fold_all(acc1, acc2);
   }
+  fold_all(acc1, acc2);
 }
 
 // Waves per SIMD the pair kernels are compiled for, by (precision, pass
@@ -486,7 +512,7 @@ template <> struct PairWaves<double, 4> { static constexpr int value = 6; };
 template <> struct PairWaves<double, 8> { static constexpr int value = 5; };
 template <> struct PairWaves<double, 16> { static constexpr int value = 4; };
 template <> struct PairWaves<float, 4> { static constexpr int value = 8; };
-template <> struct PairWaves<float, 8> { static constexpr int value = 8; };
+template <> struct PairWaves<float, 8> { static constexpr int value = 6; };
 
 // Shared memory of one tile-pair unit.
 template <typename T, int BC>
@@ -656,10 +682,18 @@ __device__ __forceinline__ void cv_slot(const typename Packed<T>::type* __restri
 // Whether a term of concentration k may take the small-argument Bessel
 // branch (2 kappa |c| < X0) without being negligible: such a term carries
 // weight exp(-2 kappa (1 - |c|)) <= exp(-(2 kappa - X0)), below the skip
-// bound once 2 kappa - X0 exceeds it. Decides the chunk kind of k.
+// bound once 2 kappa - X0 exceeds it. With pure_branch, decides the chunk
+// kind of k.
 template <typename T>
 inline bool small_branch_live(double k) {
   return 2.0 * k - double(I0eBounds<T>::X0) <= kSkipExponent;
+}
+
+// Whether every term of concentration k takes the small-argument branch
+// (2 kappa < X0, so 2 kappa |c| < X0 for every pair).
+template <typename T>
+inline bool pure_branch(double k) {
+  return 2.0 * k < double(I0eBounds<T>::X0);
 }
 
 // Per-concentration constants of the pair kernel, computed on the host.
@@ -676,12 +710,11 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
     const double k = kappas[b];
     K.A[b] = T(-2.0 * k * unit);
     K.vk[b] = T(X0 / k);
-    K.rsk[b] = T(1.0 / std::sqrt(k));
-    K.em2k[b] = T(std::exp(-2.0 * k));
+    K.em2k[b] = T(std::exp(-2.0 * k) * (pure_branch<T>(k) ? 1.0 : std::sqrt(k)));
     K.twok[b] = T(2.0 * k);
     K.tk[b] = T((2.0 * k / X0) * (2.0 * k / X0));
     if (small_branch_live<T>(k)) K.nsmall = b + 1;
-    if (2.0 * k < X0) K.npure = b + 1;
+    if (pure_branch<T>(k)) K.npure = b + 1;
   }
   K.skip = T(-kSkipExponent * unit);
   return K;
@@ -689,7 +722,7 @@ inline CvConsts<T> make_consts(const double* kappas, int B) {
 
 // Concentrations of a scan as the finalize takes them, with the factor
 // scale[b] it applies to the raw K-bar sum of b: 1/sqrt(kappa) where the
-// pair loop left it out of the terms (from nsmall on), else 1.
+// pair loops left it out of the terms (from npure on), else 1.
 struct KappaList {
   double k[KDE_MAX_KAPPAS];
   double scale[KDE_MAX_KAPPAS];
@@ -700,7 +733,7 @@ inline KappaList make_kappa_list(const double* kappas, int B) {
   KappaList kl{};
   for (int b = 0; b < B; ++b) {
     kl.k[b] = kappas[b];
-    kl.scale[b] = small_branch_live<T>(kappas[b]) ? 1.0 : 1.0 / std::sqrt(kappas[b]);
+    kl.scale[b] = pure_branch<T>(kappas[b]) ? 1.0 : 1.0 / std::sqrt(kappas[b]);
   }
   return kl;
 }

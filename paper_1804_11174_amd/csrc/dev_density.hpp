@@ -59,8 +59,8 @@ struct SumOf<double> {
   __device__ __forceinline__ void add(double v) { s += v; }
   __device__ __forceinline__ double value() const { return s; }
 };
-// Float terms in a compensated float sum (Kahan, as Acc<float> of the pair
-// kernels); the value is handed on in double for the FP64 reductions.
+// Float terms in a compensated float sum (Kahan, one step per term); the
+// value is handed on in double for the FP64 reductions.
 template <>
 struct SumOf<float> {
   float s = 0.0f, c = 0.0f;

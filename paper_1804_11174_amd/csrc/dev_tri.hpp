@@ -132,7 +132,9 @@ __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool 
           }
         }
       }
+      if ((jj & (kRun - 1)) == kRun - 1) fold_all(s1, s2);
     }
+    fold_all(s1, s2);
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       const double v1 = wave_sum(s1[bb].value());
