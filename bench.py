@@ -49,19 +49,24 @@ PEAK_LANE_OPS = {"f64": 78.6e12 / 2, "f32": 157.3e12 / 2}
 PEAK_HBM = 8.0e12
 
 # Algorithmic lane-operations per evaluated (pair, kappa) term of the CV
-# pair sums, large-argument branch, counted from the formulas (the
+# pair sums, large-argument branch, counted from the method's formulas in
+# FMA-issue slots: a multiply, an add or an FMA counts one; the hardware
+# float exp2 counts four (it issues at a quarter of the float FMA rate,
+# measured by `--form peak`); an accumulated sum counts one add per term
+# (compensation of the float sums is overhead); per-pair geometry shared by
+# all concentrations and per-concentration constants are not counted. The
+# basis does not change with the kernel's implementation. (The
 # small-argument branch, a degree-20 fit in double, costs 22 for the Kbar
-# term against 30 here):
+# term against 29 here.)
 #   f64: K term: exponent product 1 + exponential 14 (Tang's table method:
 #        reduction 4, table index 3, polynomial and combination 5, scaling
 #        1, bound 1) = 15; Kbar term: exponent product 1 + exponential 14 +
-#        Bessel argument and square-root factor 2 + degree-11 polynomial 11
-#        + two products = 30; two accumulations 2. Total 47.
-#   f32: K term: product 1 + exponential 1 = 2; Kbar term: product 1 +
-#        exponential 1 + argument and factor 2 + degree-5 polynomial 5 +
-#        two products = 11; two compensated (Kahan) accumulations of 4
-#        float operations = 8. Total 21.
-OPS_PER_TERM = {"f64": 47, "f32": 21}
+#        Bessel argument 1 + degree-11 polynomial 11 + two products = 29;
+#        two accumulations 2. Total 46.
+#   f32: K term: product 1 + exp2 4 = 5; Kbar term: product 1 + exp2 4 +
+#        argument 1 + degree-5 polynomial 5 + two products = 13; two
+#        accumulations 2. Total 20.
+OPS_PER_TERM = {"f64": 46, "f32": 20}
 SKIP_EXPONENT = 70.0
 
 # The planning cost model's ideal pair-evaluation rates, against which the
@@ -73,14 +78,21 @@ SKIP_EXPONENT = 70.0
 # can exceed it; `frac` itself is taken on the evaluated terms.
 PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
 
-# Issue counters of the pair kernel (rocprofv3 --pmc SQ_INSTS_VALU and
-# GRBM_GUI_ACTIVE on the paper-scale scan, one counter per run), as
-# VALU lane-instructions per evaluated term and the engine clock during the
-# launch; the issue fraction is the lane-instructions issued per second
-# over the one-per-four-clocks (double) or one-per-two-clocks (float, not
-# packed) issue rate of 256 CUs x 4 SIMDs x 64 lanes at that clock. Valid
-# only for the kernel sources they were taken on (PAIR_KERNEL_SOURCES).
-PAIR_COUNTERS = {"digest": None}
+# Issue counters of the pair kernel on the paper-scale scan (rocprofv3 --pmc
+# SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_SALU SQ_WAVES SQ_BUSY_CYCLES
+# GRBM_GUI_ACTIVE, one dispatch): VALU lane-instructions and transcendentals
+# per evaluated term, the engine clock during that dispatch (GRBM_GUI_ACTIVE
+# over its duration, per XCD), and the issue fraction in that same run:
+# FMA-issue slots used (each VALU instruction one, a float transcendental
+# four) over those available (256 CUs x 4 SIMDs at one double instruction
+# per four clocks, or one float instruction per two). Valid only for the
+# kernel sources they were taken on (PAIR_KERNEL_SOURCES' digest).
+PAIR_COUNTERS = {"digest": "1c6f95ce0c753c86",
+                 "source": "profiles/cv_pairs_valu_counters_paper_scale.md",
+                 "f64": {"valu_lane_instr_per_term": 48.09, "trans_per_term": 0.0005, "engine_clock_ghz": 2.177,
+                         "issue_frac": 0.945},
+                 "f32": {"valu_lane_instr_per_term": 23.91, "trans_per_term": 1.842, "engine_clock_ghz": 2.142,
+                         "issue_frac": 0.893}}
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
@@ -89,20 +101,16 @@ PAIR_COUNTERS = {"digest": None}
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "device_bessel.hpp", "bessel_coeffs.inc", "dev_layout.hpp",
                        "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "1e29df0d626424dd",
-                "f64": {"fetch_kib": 6643.875, "write_kib": 16448.0},
-                "f32": {"fetch_kib": 1376.4375, "write_kib": 16448.0}}
+PAIR_TRAFFIC = {"digest": "1c6f95ce0c753c86",
+                "f64": {"fetch_kib": 6950.625, "write_kib": 19945.25},
+                "f32": {"fetch_kib": 1652.625, "write_kib": 22528.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
 def pair_kernel_traffic(prec):
     """HBM bytes per pair-kernel launch, or None once its sources differ
     from those the counters were taken on."""
-    h = hashlib.sha256()
-    for f in PAIR_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1804_11174_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != PAIR_TRAFFIC["digest"]:
+    if pair_kernel_digest() != PAIR_TRAFFIC["digest"]:
         return None
     c = PAIR_TRAFFIC[prec]
     return (FETCH_SCALE * c["fetch_kib"] + WRITE_SCALE * c["write_kib"]) * 1024.0
@@ -221,17 +229,12 @@ def pair_kernel_digest():
     return h.hexdigest()[:16]
 
 
-def pair_kernel_issue(prec, evaluated, kernel_ms):
-    """Issue fraction of the pair kernel from the stored counters, or None
-    once its sources differ from those the counters were taken on."""
+def pair_kernel_issue(prec):
+    """The pair kernel's issue counters, or None once its sources differ
+    from those the counters were taken on."""
     if PAIR_COUNTERS.get("digest") != pair_kernel_digest() or prec not in PAIR_COUNTERS:
         return None
-    c = PAIR_COUNTERS[prec]
-    clocks_per_instr = 4.0 if prec == "f64" else 2.0
-    rate = c["valu_lane_instr_per_term"] * evaluated / (kernel_ms * 1e-3)
-    peak = 256 * 4 * 64 / clocks_per_instr * c["engine_clock_ghz"] * 1e9
-    return {"valu_lane_instr_per_term": c["valu_lane_instr_per_term"], "engine_clock_ghz": c["engine_clock_ghz"],
-            "issue_frac": rate / peak, "source": c["source"]}
+    return dict(PAIR_COUNTERS[prec], source=PAIR_COUNTERS["source"])
 
 
 REFERENCE_FILE = os.path.join(ROOT, "tests", "golden", "bench_reference.json")
@@ -487,13 +490,14 @@ def main():
                 "peak": peak / 1e12, "unit": "T lane-ops/s (FMA = 1)",
                 "frac": achieved / peak, "traffic": pair_kernel_traffic(args.prec),
                 "traffic_unit": "bytes per launch",
-                "basis": "algorithmic lane-operations per evaluated term (counted from the kernel's formulas) x "
-                         "the terms at or above e^-70 of their sum's scale, counted from the sorted positions",
+                "basis": "algorithmic lane-operations per evaluated term (the method's formulas in FMA-issue slots, "
+                         "a float exp2 as 4, one add per accumulated sum) x the terms at or above e^-70 of "
+                         "their sum's scale, counted from the sorted positions",
                 "evaluated_terms_per_launch": evaluated, "evaluated_fraction": evaluated / pair_evals,
                 "ops_per_term": OPS_PER_TERM[args.prec], "kernel_avg_ms": pair_ms,
                 "pair_evals_per_s": pe_rate, "planning_ideal_pair_evals_per_s": PLANNING_IDEAL_PAIR_EVALS[args.prec],
                 "frac_of_planning_ideal": pe_rate / PLANNING_IDEAL_PAIR_EVALS[args.prec],
-                "issue": pair_kernel_issue(args.prec, evaluated, pair_ms)}
+                "issue": pair_kernel_issue(args.prec)}
     line = {
         "metric": METRIC,
         "value": value,
@@ -615,11 +619,11 @@ def bench_precision(args, kde, W, torch, dev):
 
 
 # Triangle shape, algorithmic lane-operations per evaluated (pair, width)
-# term: u = r * scale 1; max(0, 2 - u) and max(0, 1 - u) 4; their cubes 4;
-# the spline difference 1 (an FMA); two accumulations: 2 in double, and in
-# float two of 2 (each term converted to double and added). The per-pair
-# distance (3-4 operations) is shared by all widths and not counted.
-TRI_OPS_PER_TERM = {"f64": 12, "f32": 14}
+# term, on the basis of OPS_PER_TERM: u = r * scale 1; max(0, 2 - u) and
+# max(0, 1 - u) 4; their cubes 4; the spline difference 1 (an FMA); two
+# accumulations 2. The per-pair distance (3-4 operations) is shared by all
+# widths and not counted.
+TRI_OPS_PER_TERM = {"f64": 12, "f32": 12}
 
 
 def count_tri_terms(x, L, widths):

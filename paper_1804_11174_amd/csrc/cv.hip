@@ -208,8 +208,9 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
     const dim3 grid{unsigned(p.slots * groups)}, block{unsigned(kBlock)};
     with_pass_size<T>(tp.chunk, [&](auto bc) {
-      hipLaunchKernelGGL((cv_pairs_kernel<T, decltype(bc)::value>), grid, block, 0, s, (const P*)packed, n,
-                         p.sort.cells, dom->L, p.slots, groups, gsize, K, buf.partials);
+      hipExtLaunchKernelGGL((cv_pairs_kernel<T, decltype(bc)::value>), grid, block, 0, s, timed.start(),
+                            timed.stop(), 0, (const P*)packed, n, p.sort.cells, dom->L, p.slots, groups, gsize, K,
+                            buf.partials);
     });
   }
   KDE_CHECK_LAUNCH();
@@ -238,8 +239,9 @@ static kde_status run_cv_tri(const kde_domain* dom, int64_t n, const T* x, int B
   const TriConsts<T> K = make_tri_consts<T>(widths, B, dom->L);
   {
     TimedLaunch timed(KDE_KERNEL_CV_PAIRS, s);
-    hipLaunchKernelGGL((tri_pairs_kernel<T, kTriPass>), dim3(unsigned(p.slots)), dim3(kBlock), 0, s,
-                       (const P*)packed, n, p.sort.cells, p.slots, K, buf.partials);
+    hipExtLaunchKernelGGL((tri_pairs_kernel<T, kTriPass>), dim3(unsigned(p.slots)), dim3(kBlock), 0, s,
+                          timed.start(), timed.stop(), 0, (const P*)packed, n, p.sort.cells, p.slots, K,
+                          buf.partials);
   }
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(buf.partials, p.slots, 2 * B, buf.colsum, buf.raw, s));

@@ -218,15 +218,15 @@ static kde_status launch_deposit_t(const kde_domain* dom, int64_t n, const T* x,
   KDE_RETURN_IF(check_lds(lds + sizeof(DepSmem<T>)));
   TimedLaunch timed(KDE_KERNEL_DEPOSIT, s);
   if (M <= kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 1>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((deposit_kernel<T, PER, 1>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else if (M <= 2 * kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 2>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((deposit_kernel<T, PER, 2>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else if (M <= 4 * kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 4>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((deposit_kernel<T, PER, 4>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else if (M <= 8 * kBlock) {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 8>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((deposit_kernel<T, PER, 8>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kg, n, M, dom->L, chunk, partials, status);
   } else {
-    hipLaunchKernelGGL((deposit_kernel<T, PER, 16>), grid, block, lds, s, x, kap, kg, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((deposit_kernel<T, PER, 16>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kg, n, M, dom->L, chunk, partials, status);
   }
   KDE_CHECK_LAUNCH();
   return KDE_OK;
@@ -241,15 +241,15 @@ static kde_status launch_tri_deposit_t(const kde_domain* dom, int64_t n, const T
   KDE_RETURN_IF(check_lds(sizeof(TriDepSmem<T>)));
   TimedLaunch timed(KDE_KERNEL_DEPOSIT, s);
   if (M <= kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 1>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((tri_deposit_kernel<T, PER, 1>), grid, block, 0, s, timed.start(), timed.stop(), 0, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else if (M <= 2 * kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 2>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((tri_deposit_kernel<T, PER, 2>), grid, block, 0, s, timed.start(), timed.stop(), 0, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else if (M <= 4 * kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 4>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((tri_deposit_kernel<T, PER, 4>), grid, block, 0, s, timed.start(), timed.stop(), 0, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else if (M <= 8 * kBlock) {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 8>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((tri_deposit_kernel<T, PER, 8>), grid, block, 0, s, timed.start(), timed.stop(), 0, x, hi, h, n, M, dom->L, chunk, partials, status);
   } else {
-    hipLaunchKernelGGL((tri_deposit_kernel<T, PER, 16>), grid, block, 0, s, x, hi, h, n, M, dom->L, chunk, partials, status);
+    hipExtLaunchKernelGGL((tri_deposit_kernel<T, PER, 16>), grid, block, 0, s, timed.start(), timed.stop(), 0, x, hi, h, n, M, dom->L, chunk, partials, status);
   }
   KDE_CHECK_LAUNCH();
   return KDE_OK;
@@ -304,18 +304,19 @@ static kde_status launch_gather_t(const kde_domain* dom, int64_t n, const T* x, 
   const int S = gather_split(n, dom->M);
   const dim3 grid{unsigned(ceil_div(n * S, kBlock))}, block{unsigned(kBlock)};
   const bool per = kap != nullptr;
+  TimedLaunch timed(KDE_KERNEL_GATHER, s);
   switch (S) {
     case 1:
-      hipLaunchKernelGGL((gather_kernel<T, 1>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
+      hipExtLaunchKernelGGL((gather_kernel<T, 1>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
     case 2:
-      hipLaunchKernelGGL((gather_kernel<T, 2>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
+      hipExtLaunchKernelGGL((gather_kernel<T, 2>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
     case 4:
-      hipLaunchKernelGGL((gather_kernel<T, 4>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
+      hipExtLaunchKernelGGL((gather_kernel<T, 4>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
     default:
-      hipLaunchKernelGGL((gather_kernel<T, 8>), grid, block, lds, s, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
+      hipExtLaunchKernelGGL((gather_kernel<T, 8>), grid, block, lds, s, timed.start(), timed.stop(), 0, x, kap, kappa, per, n, dom->M, dom->L, field, out, status);
       break;
   }
   KDE_CHECK_LAUNCH();
@@ -330,11 +331,13 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
     KDE_RETURN_IF(check_lds(lds));
     TimedLaunch timed(KDE_KERNEL_GATHER, s);
     if (dom->prec == KDE_F64)
-      hipLaunchKernelGGL(tri_gather_kernel<double>, grid, block, lds, s, static_cast<const double*>(x),
+      hipExtLaunchKernelGGL(tri_gather_kernel<double>, grid, block, lds, s, timed.start(), timed.stop(), 0,
+                         static_cast<const double*>(x),
                          static_cast<const double*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
                          static_cast<double*>(out), status);
     else
-      hipLaunchKernelGGL(tri_gather_kernel<float>, grid, block, lds, s, static_cast<const float*>(x),
+      hipExtLaunchKernelGGL(tri_gather_kernel<float>, grid, block, lds, s, timed.start(), timed.stop(), 0,
+                         static_cast<const float*>(x),
                          static_cast<const float*>(kap), kappa, kap != nullptr, n, dom->M, dom->L, field,
                          static_cast<float*>(out), status);
     KDE_CHECK_LAUNCH();
@@ -342,7 +345,6 @@ kde_status gather(const kde_domain* dom, int64_t n, const void* x, const void* k
   }
   const size_t lds = 3 * size_t(dom->M) * elem_size(dom->prec);
   KDE_RETURN_IF(check_lds(lds + (dom->prec == KDE_F64 ? 256 * sizeof(double) : sizeof(double))));  // + exp table
-  TimedLaunch timed(KDE_KERNEL_GATHER, s);
   if (dom->prec == KDE_F64)
     KDE_RETURN_IF(launch_gather_t<double>(dom, n, static_cast<const double*>(x), static_cast<const double*>(kap),
                                           kappa, field, static_cast<double*>(out), lds, s, status));
@@ -362,24 +364,24 @@ kde_status adapt_widths(const kde_domain* dom, int64_t n, const void* x, const d
   double* sums = c.take<double>(2);
   if (!c.fits()) return fail(KDE_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, c.used);
   const dim3 grid{unsigned(blocks)}, block{unsigned(kBlock)};
-  TimedLaunch timed(KDE_KERNEL_ADAPT, s);
+  TimedLaunch timed(KDE_KERNEL_ADAPT, s);  // from the log sums' start to the widths' end
   if (dom->prec == KDE_F64) {
-    hipLaunchKernelGGL(adapt_logsum_kernel<double>, grid, block, 0, s, static_cast<const double*>(x), n, dom->M,
-                       dom->L, pilot, partials, status);
+    hipExtLaunchKernelGGL(adapt_logsum_kernel<double>, grid, block, 0, s, timed.start(), nullptr, 0,
+                          static_cast<const double*>(x), n, dom->M, dom->L, pilot, partials, status);
   } else {
-    hipLaunchKernelGGL(adapt_logsum_kernel<float>, grid, block, 0, s, static_cast<const float*>(x), n, dom->M,
-                       dom->L, pilot, partials, status);
+    hipExtLaunchKernelGGL(adapt_logsum_kernel<float>, grid, block, 0, s, timed.start(), nullptr, 0,
+                          static_cast<const float*>(x), n, dom->M, dom->L, pilot, partials, status);
   }
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(partials, blocks, 2, scratch, sums, s));
   if (dom->prec == KDE_F64) {
-    hipLaunchKernelGGL(adapt_apply_kernel<double>, grid, block, 0, s, static_cast<const double*>(x), n, dom->M,
-                       dom->L, pilot, kappa_star, alpha, (const double*)sums, static_cast<double*>(kout), log_g,
-                       nfl);
+    hipExtLaunchKernelGGL(adapt_apply_kernel<double>, grid, block, 0, s, nullptr, timed.stop(), 0,
+                          static_cast<const double*>(x), n, dom->M, dom->L, pilot, kappa_star, alpha,
+                          (const double*)sums, static_cast<double*>(kout), log_g, nfl);
   } else {
-    hipLaunchKernelGGL(adapt_apply_kernel<float>, grid, block, 0, s, static_cast<const float*>(x), n, dom->M,
-                       dom->L, pilot, kappa_star, alpha, (const double*)sums, static_cast<float*>(kout), log_g,
-                       nfl);
+    hipExtLaunchKernelGGL(adapt_apply_kernel<float>, grid, block, 0, s, nullptr, timed.stop(), 0,
+                          static_cast<const float*>(x), n, dom->M, dom->L, pilot, kappa_star, alpha,
+                          (const double*)sums, static_cast<float*>(kout), log_g, nfl);
   }
   KDE_CHECK_LAUNCH();
   return KDE_OK;

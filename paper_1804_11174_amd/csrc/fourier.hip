@@ -746,8 +746,8 @@ kde_status launch_moments(const T* x, int64_t n, double L, int M, const FourierB
   const dim3 grid{unsigned(chunks), unsigned(ceil_div(M, kMomM))};
   {
     TimedLaunch timed(KDE_KERNEL_MOMENTS, s);
-    hipLaunchKernelGGL((moments_kernel<T>), grid, dim3(kBlock), 0, s, x, n, L, M, per, b.partials,
-                       plain_numeric_word());
+    hipExtLaunchKernelGGL((moments_kernel<T>), grid, dim3(kBlock), 0, s, timed.start(), timed.stop(), 0, x, n, L,
+                          M, per, b.partials, plain_numeric_word());
   }
   KDE_CHECK_LAUNCH();
   return launch_column_sum(b.partials, chunks, 2 * M, b.colsum, b.S, s);
@@ -869,28 +869,25 @@ kde_status kde_adapt_widths_exact(const kde_domain* dom, int64_t N, const void* 
   KDE_CHECK_LAUNCH();
   const int64_t blocks = ceil_div(N, kBlock);
   const dim3 grid{unsigned(blocks)};
-  {
-    TimedLaunch timed(KDE_KERNEL_ADAPT, s);
-    if (dom->prec == KDE_F64)
-      hipLaunchKernelGGL(pilot_kernel<double>, grid, dim3(kBlock), 0, s, static_cast<const double*>(x), N, dom->L, M,
-                         (const double*)b.w, double(std::numeric_limits<double>::min()), b.lf, b.bpart,
-                         plain_numeric_word());
-    else
-      hipLaunchKernelGGL(pilot_kernel<float>, grid, dim3(kBlock), 0, s, static_cast<const float*>(x), N, dom->L, M,
-                         (const double*)b.w, double(std::numeric_limits<float>::min()), b.lf, b.bpart,
-                         plain_numeric_word());
-  }
+  TimedLaunch timed(KDE_KERNEL_ADAPT, s);  // from the pilot values' start to the widths' end
+  if (dom->prec == KDE_F64)
+    hipExtLaunchKernelGGL(pilot_kernel<double>, grid, dim3(kBlock), 0, s, timed.start(), nullptr, 0,
+                          static_cast<const double*>(x), N, dom->L, M, (const double*)b.w,
+                          double(std::numeric_limits<double>::min()), b.lf, b.bpart, plain_numeric_word());
+  else
+    hipExtLaunchKernelGGL(pilot_kernel<float>, grid, dim3(kBlock), 0, s, timed.start(), nullptr, 0,
+                          static_cast<const float*>(x), N, dom->L, M, (const double*)b.w,
+                          double(std::numeric_limits<float>::min()), b.lf, b.bpart, plain_numeric_word());
   KDE_CHECK_LAUNCH();
   KDE_RETURN_IF(launch_column_sum(b.bpart, blocks, 2, b.colsum2, b.sums2, s));
-  {
-    TimedLaunch timed(KDE_KERNEL_ADAPT, s);
-    if (dom->prec == KDE_F64)
-      hipLaunchKernelGGL(pilot_apply_kernel<double>, grid, dim3(kBlock), 0, s, (const double*)b.lf, N, kappa_star,
-                         alpha, (const double*)b.sums2, static_cast<double*>(kappa_out), log_geomean, n_floored);
-    else
-      hipLaunchKernelGGL(pilot_apply_kernel<float>, grid, dim3(kBlock), 0, s, (const double*)b.lf, N, kappa_star,
-                         alpha, (const double*)b.sums2, static_cast<float*>(kappa_out), log_geomean, n_floored);
-  }
+  if (dom->prec == KDE_F64)
+    hipExtLaunchKernelGGL(pilot_apply_kernel<double>, grid, dim3(kBlock), 0, s, nullptr, timed.stop(), 0,
+                          (const double*)b.lf, N, kappa_star, alpha, (const double*)b.sums2,
+                          static_cast<double*>(kappa_out), log_geomean, n_floored);
+  else
+    hipExtLaunchKernelGGL(pilot_apply_kernel<float>, grid, dim3(kBlock), 0, s, nullptr, timed.stop(), 0,
+                          (const double*)b.lf, N, kappa_star, alpha, (const double*)b.sums2,
+                          static_cast<float*>(kappa_out), log_geomean, n_floored);
   KDE_CHECK_LAUNCH();
   return KDE_OK;
 }

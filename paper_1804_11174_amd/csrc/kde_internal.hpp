@@ -2,6 +2,7 @@
 // plumbing, workspace carving, launch geometry and small device helpers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -77,20 +78,30 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------ timing
 
-// Brackets the launches made during its lifetime with HIP events when
-// kernel timing is enabled (kde_timing_enable); a no-op otherwise.
+// Times one region of kernel launches when kernel timing is enabled
+// (kde_timing_enable): the region's first launch records start() and its
+// last launch stop() itself (hipExtLaunchKernelGGL), so the interval runs
+// from the first kernel's start to the last kernel's end on the device and
+// holds no host time before the first launch. When timing is off (or the
+// stream is being captured) both are null and the launches record nothing.
 class TimedLaunch {
  public:
   TimedLaunch(int id, hipStream_t s);
   ~TimedLaunch();
   TimedLaunch(const TimedLaunch&) = delete;
   TimedLaunch& operator=(const TimedLaunch&) = delete;
+  hipEvent_t start() const { return start_; }
+  // handing out the stop event marks the region as launched
+  hipEvent_t stop() {
+    armed_ = active_;
+    return stop_;
+  }
 
  private:
   int id_;
   hipStream_t s_;
   hipEvent_t start_{}, stop_{};
-  bool active_ = false;
+  bool active_ = false, armed_ = false;
 };
 
 // ----------------------------------------------------- argument checking

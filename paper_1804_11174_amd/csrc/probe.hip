@@ -72,10 +72,10 @@ kde_status kde_probe_peak(int32_t kind, int32_t blocks, int64_t iters, double* o
   const dim3 grid{unsigned(blocks)}, block{unsigned(kBlock)};
   TimedLaunch timed(KDE_KERNEL_PROBE, s);
   switch (kind) {
-    case KDE_PROBE_FMA_F64: hipLaunchKernelGGL(probe_kernel<KDE_PROBE_FMA_F64>, grid, block, 0, s, iters, out); break;
-    case KDE_PROBE_FMA_F32: hipLaunchKernelGGL(probe_kernel<KDE_PROBE_FMA_F32>, grid, block, 0, s, iters, out); break;
-    case KDE_PROBE_EXP_F32: hipLaunchKernelGGL(probe_kernel<KDE_PROBE_EXP_F32>, grid, block, 0, s, iters, out); break;
-    case KDE_PROBE_ADD_F64: hipLaunchKernelGGL(probe_kernel<KDE_PROBE_ADD_F64>, grid, block, 0, s, iters, out); break;
+    case KDE_PROBE_FMA_F64: hipExtLaunchKernelGGL(probe_kernel<KDE_PROBE_FMA_F64>, grid, block, 0, s, timed.start(), timed.stop(), 0, iters, out); break;
+    case KDE_PROBE_FMA_F32: hipExtLaunchKernelGGL(probe_kernel<KDE_PROBE_FMA_F32>, grid, block, 0, s, timed.start(), timed.stop(), 0, iters, out); break;
+    case KDE_PROBE_EXP_F32: hipExtLaunchKernelGGL(probe_kernel<KDE_PROBE_EXP_F32>, grid, block, 0, s, timed.start(), timed.stop(), 0, iters, out); break;
+    case KDE_PROBE_ADD_F64: hipExtLaunchKernelGGL(probe_kernel<KDE_PROBE_ADD_F64>, grid, block, 0, s, timed.start(), timed.stop(), 0, iters, out); break;
     default: break;
   }
   KDE_CHECK_LAUNCH();

@@ -1,6 +1,7 @@
-// Optional per-kernel timing with HIP events (kde_timing_* in include/kde_measure.h).
-// Pending event pairs are kept per kernel id; reading waits for them and
-// folds their durations into running totals.
+// Optional per-kernel timing with HIP events (kde_timing_* in include/kde_measure.h),
+// recorded by the timed launches themselves. Pending event pairs are kept
+// per kernel id; reading waits for them and folds their durations into
+// running totals.
 #include <mutex>
 #include <vector>
 
@@ -29,14 +30,13 @@ TimedLaunch::TimedLaunch(int id, hipStream_t s) : id_(id), s_(s) {
   // recorded into the graph, not now)
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
-  if (hipEventCreate(&start_) != hipSuccess) return;
-  if (hipEventCreate(&stop_) != hipSuccess) {
-    (void)hipEventDestroy(start_);
+  if (hipEventCreate(&start_) != hipSuccess) {
+    start_ = nullptr;
     return;
   }
-  if (hipEventRecord(start_, s_) != hipSuccess) {
+  if (hipEventCreate(&stop_) != hipSuccess) {
     (void)hipEventDestroy(start_);
-    (void)hipEventDestroy(stop_);
+    start_ = stop_ = nullptr;
     return;
   }
   active_ = true;
@@ -45,7 +45,7 @@ TimedLaunch::TimedLaunch(int id, hipStream_t s) : id_(id), s_(s) {
 TimedLaunch::~TimedLaunch() {
   if (!active_) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  if (hipEventRecord(stop_, s_) != hipSuccess) {
+  if (!armed_) {  // nothing was launched with the events
     (void)hipEventDestroy(start_);
     (void)hipEventDestroy(stop_);
     return;
