@@ -219,8 +219,8 @@ kde_status kde_cv_scan(const kde_domain* dom, int64_t N, const void* x, int32_t 
  * until the process ends. The call allocates nothing.
  *   Limit: a scan whose kde_workspace_size(KDE_OP_CV_SCAN, dom, N, B)
  *   exceeds KDE_CV_NOALLOC_MAX_BYTES is refused with KDE_E_WORKSPACE before
- *   anything is enqueued (24 MiB holds N = 65,536 at B = 32 in either
- *   precision; every scan of N <= 16,384 at B = 64).
+ *   anything is enqueued (24 MiB holds N up to 220,191 in double and
+ *   1,015,616 in float at B = 32, up to 54,528 in either at B = 64).
  *   Concurrency: every call on one device uses that device's one array, so
  *   calls that overlap on a device (other streams or threads) race and give
  *   undefined results; calls enqueued on one stream are safe.
