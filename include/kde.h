@@ -623,7 +623,8 @@ kde_status kde_server_cancel(kde_server* s, uint64_t ticket);
 /* KDE_OK and the result once done, KDE_E_AGAIN while pending; a ticket that
  * ended otherwise returns its status (res_h filled). */
 kde_status kde_server_poll(kde_server* s, uint64_t ticket, kde_result* res_h);
-/* Block until the ticket completes, then as kde_server_poll. */
+/* Block until the ticket completes, then as kde_server_poll. The server
+ * must outlive every pending wait (destroy it only after they return). */
 kde_status kde_server_wait(kde_server* s, uint64_t ticket, kde_result* res_h);
 /* Wait until every submitted request has completed and every attached
  * session has taken its steps. */
