@@ -133,20 +133,21 @@ def count_evaluated_terms(x, L, kappas):
         dmax = min(dmax, L / 2)
         hi = np.searchsorted(ext, xs + dmax, side="right")
         cnt = np.minimum(hi - np.arange(n) - 1, n - 1)     # partners ahead within dmax
-        # every unordered pair within dmax is counted once from each side when
-        # the window wraps less than half the circle
+        # an unordered pair within dmax is counted once, from the particle
+        # whose forward arc to the other is the shorter one (dmax <= L/2)
         total += int(cnt.sum())
     return total
 
 
 # Secondary kernels of the plain pipeline, from the library's per-launch
-# HIP-event averages. Algorithmic lane-operations per (particle, node)
-# evaluation of the deposit and gather:
+# event averages. Algorithmic lane-operations per (particle, node)
+# evaluation of the deposit and gather, on the pair kernel's basis (FMA-issue
+# slots, a float exp2 as four, one add per accumulated sum):
 #   f64: node sine from the node table 2, square 1, exponent product 1,
 #        clamp 1, table exponential 14, weight or field product 1,
 #        accumulation 1 = 21;
 #   f32: node index wrap 2, node sine 2, square 1, exponent product 1,
-#        exp2 1, weight or field product 1, compensated accumulation 4 = 12.
+#        exp2 4, weight or field product 1, accumulation 1 = 12.
 # Algorithmic HBM bytes per launch: deposit reads the positions (and the
 # widths in the adaptive one; the pipeline runs one of each, so 1.5 arrays
 # on average) and writes its chunk grids (chunks x M doubles); gather reads
