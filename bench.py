@@ -87,12 +87,12 @@ PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
 # four) over those available (256 CUs x 4 SIMDs at one double instruction
 # per four clocks, or one float instruction per two). Valid only for the
 # kernel sources they were taken on (PAIR_KERNEL_SOURCES' digest).
-PAIR_COUNTERS = {"digest": "df6d2b5b22ac3977",
+PAIR_COUNTERS = {"digest": "f3549f7cd73c0d6a",
                  "source": "profiles/cv_pairs_valu_counters_paper_scale.md",
-                 "f64": {"valu_lane_instr_per_term": 48.09, "trans_per_term": 0.0005, "engine_clock_ghz": 2.155,
-                         "issue_frac": 0.948},
-                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.094,
-                         "issue_frac": 0.890}}
+                 "f64": {"valu_lane_instr_per_term": 48.38, "trans_per_term": 0.0005, "engine_clock_ghz": 2.116,
+                         "issue_frac": 0.935},
+                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.067,
+                         "issue_frac": 0.885}}
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
@@ -101,9 +101,9 @@ PAIR_COUNTERS = {"digest": "df6d2b5b22ac3977",
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "device_bessel.hpp", "bessel_coeffs.inc", "dev_layout.hpp",
                        "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "df6d2b5b22ac3977",
-                "f64": {"fetch_kib": 6953.25, "write_kib": 19895.25},
-                "f32": {"fetch_kib": 1646.3125, "write_kib": 22528.0}}
+PAIR_TRAFFIC = {"digest": "f3549f7cd73c0d6a",
+                "f64": {"fetch_kib": 6909.875, "write_kib": 19935.625},
+                "f32": {"fetch_kib": 1701.125, "write_kib": 22528.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 

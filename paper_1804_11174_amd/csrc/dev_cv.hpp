@@ -51,8 +51,9 @@
 // branch's polynomial live, its coefficients stay in scalar registers
 // instead of being rebuilt for every term. Those up to `nsmall`, where a
 // term may take either Bessel branch. And the rest, where every term that
-// is not skipped takes the large-argument fit: that loop needs two
-// constants per concentration. From npure on, the K-bar terms leave out a
+// is not skipped takes the large-argument fit: in float a loop of its own
+// with two constants per concentration (in double the previous loop, which
+// takes the fit for them). From npure on, the K-bar terms leave out a
 // factor 1/sqrt(kappa) (the large-argument fit's 1/sqrt(2 kappa c) and the
 // small-argument constant are scaled to match), which the finalize applies
 // to their sums (KappaList::scale). Which loop a concentration takes
@@ -398,9 +399,19 @@ __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* 
   fold_all(acc1, acc2);
 }
 
-// Concentrations [b0, b_end) within [npure, nsmall): a term takes the
-// small-argument Bessel branch when 2 kappa c < X0, else the large-argument
-// fit (both without the factor 1/sqrt(kappa)).
+// Whether the concentrations from nsmall on run through a loop of their own
+// (pair_chunk_large) in chunks that do not straddle nsmall. In float that
+// loop holds its constants in scalar registers; in double it has nothing to
+// gain, and the extra chunk boundary would cost a pass over the tile (its
+// pair geometry) whenever the two ranges share a chunk's worth of
+// concentrations: 3 % at 16 concentrations in [1, 1e4].
+template <typename T>
+constexpr bool kSplitLarge = std::is_same<T, float>::value;
+
+// Concentrations [b0, b_end) from npure on (in float, below nsmall): a
+// term of a concentration below nsmall takes the small-argument Bessel
+// branch when 2 kappa c < X0, else the large-argument fit (both without the
+// factor 1/sqrt(kappa)); from nsmall on, always the fit.
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __restrict__ tj, int nj,
                                            const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
@@ -429,7 +440,7 @@ __device__ __forceinline__ void pair_chunk(const typename Packed<T>::type* __res
         T t2 = exp_unit(A * g.s2, etab);
         T t1;
         const T R = K.twok[b] * g.c;
-        if (R < X0) {
+        if ((kSplitLarge<T> || b < K.nsmall) && R < X0) {
           t1 = K.em2k[b] * i0_small(K.tk[b] * g.c2);
         } else {
           t1 = exp_unit(Aq, etab) * (i0e_sqrt_large(g.inv2c * K.vk[b]) * g.rs2c);
@@ -575,9 +586,9 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
 
   const int lane = tid & 63, wave = tid >> 6;
   for (int b0 = b_lo; b0 < b_end;) {
-    // chunks do not straddle npure or nsmall
-    const int bc_end =
-        min(b0 + BC, b0 < K.npure ? min(b_end, K.npure) : (b0 < K.nsmall ? min(b_end, K.nsmall) : b_end));
+    // chunks do not straddle npure, nor in float nsmall
+    const int bc_end = min(b0 + BC, b0 < K.npure ? min(b_end, K.npure)
+                                                 : (kSplitLarge<T> && b0 < K.nsmall ? min(b_end, K.nsmall) : b_end));
     Acc<T> s1[BC], s2[BC];
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
@@ -589,7 +600,7 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
         pair_chunk_pure<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
       else
         pair_chunk_pure<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
-    } else if (b0 < K.nsmall) {
+    } else if (!kSplitLarge<T> || b0 < K.nsmall) {
       if (masked)
         pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
       else
