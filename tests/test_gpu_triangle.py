@@ -3,8 +3,10 @@ kde_cv_scan, kde_deposit and kde_gather with dom.shape = triangle, against
 the oracle's direct sums (oracle/triangle.py).
 
 Tolerances: FP64 path 1e-12 relative per CV value, pair sum and grid value;
-float form 1e-6. Grid values are relative per node plus a bound from the
-kernel's conditioning: the triangle's value t = 1 - r/h has slope 1/h, so
+float form 1e-6 (CV values relative to the larger of the objective's two
+terms, as for the von Mises kernel). Grid values are relative per node
+plus a bound from the kernel's conditioning: the triangle's value
+t = 1 - r/h has slope 1/h, so
 the absolute rounding of the distance r (about u L in double, where
 positions of size L enter; about u dx in float, where the offset from the
 nearest node is rounded) becomes u S / h of absolute error in t, and the
@@ -83,10 +85,18 @@ def check_cv(cv, sums, am, x64, L, widths, tol):
     ref_cv, S1, S2 = tri.cv_curve(x64, L, widths)
     n = len(x64)
     B = len(widths)
-    assert rel_err(cv, ref_cv).max() <= tol, rel_err(cv, ref_cv)
+    first = (n * tri.conv2_at_zero(widths, L) + 2 * S1) / n ** 2
+    if tol < TOL["f32"]:
+        assert rel_err(cv, ref_cv).max() <= tol, rel_err(cv, ref_cv)
+    else:
+        # the float form's error is relative to the larger of the objective's
+        # two terms: its distances carry a float rounding (the phase
+        # difference converted to float, the width's scale), which a CV value
+        # that is the difference of two near-equal terms keeps at their size
+        err = np.abs(cv - ref_cv) / np.maximum(np.abs(ref_cv), first)
+        assert err.max() <= tol, err
     # each pair sum is held to tol of the objective term it enters (a sum of
     # a few edge-of-support terms has no relative accuracy of its own)
-    first = (n * tri.conv2_at_zero(widths, L) + 2 * S1) / n ** 2
     assert np.all(2 * np.abs(sums[:B] - S1) / n ** 2 <= tol * first)
     assert np.all(4 * np.abs(sums[B:] - S2) / (n * (n - 1)) <= tol * first)
     am_ref = ocv.cv_argmin(ref_cv)
