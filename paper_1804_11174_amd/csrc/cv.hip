@@ -57,8 +57,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
   tri_slot<T, BC>(packed, n, cells, int64_t(blockIdx.x), nslots, K, partials + int64_t(blockIdx.x) * 2 * K.B, sm);
 }
 
-// raw[0..B): 6 h Tbar sums, raw[B..2B): h T sums; widths h_b. One block.
-// S1 = raw1 / (6 h), S2 = raw2 / h, Tbar(0) = 2 / (3 h); the objective and
+// raw[0..B): 3 h Tbar / 4 sums, raw[B..2B): h T sums; widths h_b. One
+// block. S1 = raw1 / (3 h / 4), S2 = raw2 / h, Tbar(0) = 2 / (3 h); the objective and
 // its first minimum as for the von Mises kernel.
 __global__ void __launch_bounds__(KDE_MAX_KAPPAS) tri_finalize_kernel(const double* __restrict__ raw, int B,
                                                                      double n, KappaList widths,
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(KDE_MAX_KAPPAS) tri_finalize_kernel(const doub
   __shared__ double v[KDE_MAX_KAPPAS];
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
     const double h = widths.k[b];
-    const double S1 = raw[b] / (6.0 * h);
+    const double S1 = raw[b] / (0.75 * h);
     const double S2 = raw[B + b] / h;
     const double val = (n * (2.0 / (3.0 * h)) + 2.0 * S1) / (n * n) - 4.0 * S2 / (n * (n - 1.0));
     if (cv) cv[b] = val;
@@ -222,12 +222,13 @@ static kde_status run_cv(const kde_domain* dom, int64_t n, const T* x, int B, co
   return KDE_OK;
 }
 
-// Passes of the triangle pair kernel: widths per pass. In float the three
-// registers of each compensated sum make a pass of 8 spill in the pair
-// loop; 4 runs 8 % faster there (6.8 against 7.4 ms at the paper-scale
-// scan), while double keeps 8 (9.7 against 9.9 ms).
+// Passes of the triangle pair kernel: widths per pass, 4 in both
+// precisions. In float the three registers of each compensated sum make a
+// pass of 8 spill at eight waves, and at five or six it runs slower (5.0
+// against 4.4 ms at the paper-scale scan); in double 4 runs 4 % faster
+// than 8 (6.93 against 7.19 ms).
 template <typename T>
-constexpr int kTriPass = std::is_same<T, float>::value ? 4 : 8;
+constexpr int kTriPass = 4;
 
 template <typename T>
 static kde_status run_cv_tri(const kde_domain* dom, int64_t n, const T* x, int B, const double* widths,

@@ -19,25 +19,32 @@
 // Pair distances are periodic and in fractions of the period: from the
 // wrapped position / L in double, or from the 32-bit fixed-point phase in
 // float (the phase difference in wrapping integer arithmetic is the exact
-// periodic separation). Partial sums are raw: sum of B(u) * 6 and sum of
-// max(0, 1 - u); the finalize divides by 6 h and h.
+// periodic separation). With a = max(0, 1 - u/2) and c = max(0, 1 - u),
+// 6 B(u) = 8 (a^3 - c^3 / 2): each of a and c is one multiply-add of the
+// distance clamped to [0, 1]. The image term needs only its a (its u is at
+// least L / (2 h) >= 1), the same multiply-add of the image distance
+// L - d; for h <= L/4 that a is 0. Partial sums are raw: sum of 6 B(u) / 8
+// and sum of max(0, 1 - u); the finalize divides by 3 h / 4 and h.
 #include "dev_cv.hpp"
 #include "dev_density.hpp"
 
 namespace kde {
 
-// Per-width constants of the pair kernel. scale[b] turns a periodic
-// distance in the packed unit into u = d / h_b; `period` is the period in
-// that unit (1 or 2^32); hfrac2[b] = 2 h_b / L is the distance (in
-// fractions of the period) from which width b contributes nothing;
-// `reach` is the largest of them; image bit b is set when h_b > L/4.
+// Per-width constants of the pair kernel, for a periodic distance r in
+// the packed unit (1 or 2^-32 of the period) and s_b = L / h_b in that
+// unit: a = 1 + r ka[b] (ka = -s/2) and c = 1 + r kc[b] (kc = -s), each
+// clamped to [0, 1]; the image's a is 1 + (period - r) ka[b], `period` in
+// the packed unit. hfrac2[b] = 2 h_b / L is the distance (in fractions of
+// the period) from which width b contributes nothing; `reach` is the
+// largest of them; image bit b is set when h_b > L/4 (with ascending
+// widths, the top ones).
 template <typename T>
 struct TriConsts {
   int B;
   uint64_t image;
   double reach;
   T period;
-  T scale[KDE_MAX_KAPPAS];
+  T ka[KDE_MAX_KAPPAS], kc[KDE_MAX_KAPPAS];
   double hfrac2[KDE_MAX_KAPPAS];
 };
 
@@ -49,7 +56,9 @@ inline TriConsts<T> make_tri_consts(const double* widths, int B, double L) {
   K.period = T(1.0 / unit);
   double hmax = 0.0;
   for (int b = 0; b < B; ++b) {
-    K.scale[b] = T(unit * L / widths[b]);
+    const double sb = unit * L / widths[b];
+    K.ka[b] = T(-0.5 * sb);
+    K.kc[b] = T(-sb);
     K.hfrac2[b] = 2.0 * widths[b] / L;
     if (widths[b] > 0.25 * L) K.image |= (uint64_t(1) << b);
     hmax = widths[b] > hmax ? widths[b] : hmax;
@@ -69,14 +78,8 @@ __device__ __forceinline__ float tri_dist(uint32_t a, uint32_t b) {
   return float(m);
 }
 
-// Cubic B-spline times 6 and the triangle's raw value at u >= 0.
-template <typename T>
-__device__ __forceinline__ void tri_terms(T u, T& kb6, T& k1) {
-  const T a = fmax(T(0), T(2) - u);
-  const T c = fmax(T(0), T(1) - u);
-  kb6 = a * a * a - T(4) * (c * c * c);
-  k1 = c;
-}
+__device__ __forceinline__ float clamp01(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
+__device__ __forceinline__ double clamp01(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
 template <typename T, int BC>
 struct TriSmem {
@@ -86,10 +89,93 @@ struct TriSmem {
   int bstart;
 };
 
-// The passes of one tile pair over widths [b_start, B), widest first; per
-// j the wave stops at the first width whose support no lane reaches (the
-// narrower ones are zero as well). LIVE_ALL: every (i, j) of the pair is
-// counted (an off-diagonal pair of full tiles), so no per-term mask.
+// The terms of one (pair, width): a = max(0, 1 - u/2) given, c and the
+// cubic, and with IMG the image's a (r and rp the distance and the
+// image's distance).
+template <typename T, bool LIVE_ALL, bool IMG>
+__device__ __forceinline__ void tri_add(T r, T rp, T a, T kc, T ka, bool live, Acc<T>& s1, Acc<T>& s2) {
+  const T c = clamp01(fma(r, kc, T(1)));
+  T kb = fma(T(-0.5), c * c * c, a * a * a);
+  if (IMG) {
+    const T ai = clamp01(fma(rp, ka, T(1)));
+    kb = fma(ai * ai, ai, kb);
+  }
+  if (LIVE_ALL) {
+    s1.add(kb);
+    s2.add(c);
+  } else {
+    s1.add(live ? kb : T(0));
+    s2.add(live ? c : T(0));
+  }
+}
+
+// Whether the pair kernel votes at every width (double) or once per j and
+// pass (float). A vote lets the wave stop at the first width, widest
+// first, whose support no lane reaches (the narrower ones are zero as
+// well); it costs a compare and about seven scalar instructions and
+// branches. Float terms issue at twice the rate of double ones, and there
+// the scalar issue of a vote per width bounded the loop (7.2 ms against
+// 4.4 ms with one vote per j at the paper-scale scan); in double the
+// terms a vote per width saves are worth more (6.8 ms against 7.4 ms).
+template <typename T>
+constexpr bool kTriVoteEach = std::is_same<T, double>::value;
+
+// One pass of a tile pair over widths [b_lo, b_hi). With a vote per width
+// the wave stops at the first one, widest first, that no lane reaches.
+// With one vote per j, on the pass's widest width, a j that no lane
+// reaches is skipped and otherwise every width of the pass adds its terms,
+// zero outside their supports; a pass narrower than BC evaluates its last
+// width in the spare slots, whose sums are dropped. Either way a skipped
+// term is an exact zero, so the sums do not depend on the voting.
+// LIVE_ALL: every (i, j) of the pair is counted (an off-diagonal pair of
+// full tiles), so no per-term mask. IMG: the pass holds a width that
+// reaches its image; no vote stops such a width, and every width of the
+// pass adds the image term, exactly 0 for those that do not reach their
+// image (a branch per width on the image bit was 9 % slower in double).
+// A pass without one has no image code (as a select per term it cost five
+// instructions in float).
+template <typename T, int BC, bool LIVE_ALL, bool IMG>
+__device__ __forceinline__ void tri_pass(typename TriPacked<T>::type pi, bool valid_i, bool diag, int nj, int b_lo,
+                                         int b_hi, const TriConsts<T>& K, Acc<T> (&s1)[BC], Acc<T> (&s2)[BC],
+                                         const typename TriPacked<T>::type* tj) {
+  const int tid = threadIdx.x;
+  // the pass's constants, read into (scalar) registers once per pass
+  // instead of once per term
+  T ka[BC], kc[BC];
+#pragma unroll
+  for (int bb = 0; bb < BC; ++bb) {
+    const int b = min(b_lo + bb, b_hi - 1);
+    ka[bb] = K.ka[b];
+    kc[bb] = K.kc[b];
+  }
+  const T ktop = K.ka[b_hi - 1];
+  for (int jj = 0; jj < nj; ++jj) {
+    const bool live = LIVE_ALL || (valid_i && (!diag || jj > tid));
+    const T r = tri_dist(pi, tj[jj]);
+    const T rp = K.period - r;  // the image's distance
+    if (kTriVoteEach<T>) {
+      bool go = true;  // uniform across the wave
+#pragma unroll
+      for (int bb = BC - 1; bb >= 0; --bb) {
+        const int b = b_lo + bb;
+        if (b < b_hi && go) {
+          const T a = clamp01(fma(r, ka[bb], T(1)));
+          const bool img = IMG && ((K.image >> b) & 1);
+          go = img || !__all(!live || a == T(0));
+          if (go) tri_add<T, LIVE_ALL, IMG>(r, rp, a, kc[bb], ka[bb], live, s1[bb], s2[bb]);
+        }
+      }
+    } else if (IMG || !__all(!live || clamp01(fma(r, ktop, T(1))) == T(0))) {
+#pragma unroll
+      for (int bb = 0; bb < BC; ++bb)
+        tri_add<T, LIVE_ALL, IMG>(r, rp, clamp01(fma(r, ka[bb], T(1))), kc[bb], ka[bb], live, s1[bb], s2[bb]);
+    }
+    if ((jj & (kRun - 1)) == kRun - 1) fold_all(s1, s2);
+  }
+  fold_all(s1, s2);
+}
+
+// The passes of one tile pair over widths [b_start, B), widest first.
 template <typename T, int BC, bool LIVE_ALL>
 __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool valid_i, bool diag, int nj,
                                            int b_start, const TriConsts<T>& K, TriSmem<T, BC>& sm) {
@@ -103,38 +189,11 @@ __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool 
       s1[bb].zero();
       s2[bb].zero();
     }
-    for (int jj = 0; jj < nj; ++jj) {
-      const bool live = LIVE_ALL || (valid_i && (!diag || jj > tid));
-      const T r = tri_dist(pi, sm.tj[jj]);
-      bool go = true;  // uniform across the wave
-#pragma unroll
-      for (int bb = BC - 1; bb >= 0; --bb) {
-        const int b = b_lo + bb;
-        if (b < b_hi && go) {
-          const T u = r * K.scale[b];
-          const bool img = (K.image >> b) & 1;
-          go = img || !__all(!live || u >= T(2));
-          if (go) {
-            T kb6, k1;
-            tri_terms(u, kb6, k1);
-            if (img) {
-              T kb6i, k1i;
-              tri_terms((K.period - r) * K.scale[b], kb6i, k1i);
-              kb6 += kb6i;
-            }
-            if (LIVE_ALL) {
-              s1[bb].add(kb6);
-              s2[bb].add(k1);
-            } else {
-              s1[bb].add(live ? kb6 : T(0));
-              s2[bb].add(live ? k1 : T(0));
-            }
-          }
-        }
-      }
-      if ((jj & (kRun - 1)) == kRun - 1) fold_all(s1, s2);
-    }
-    fold_all(s1, s2);
+    // ascending widths: the pass reaches an image if its widest width does
+    if ((K.image >> (b_hi - 1)) & 1)
+      tri_pass<T, BC, LIVE_ALL, true>(pi, valid_i, diag, nj, b_lo, b_hi, K, s1, s2, sm.tj);
+    else
+      tri_pass<T, BC, LIVE_ALL, false>(pi, valid_i, diag, nj, b_lo, b_hi, K, s1, s2, sm.tj);
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
       const double v1 = wave_sum(s1[bb].value());
@@ -158,7 +217,7 @@ __device__ __forceinline__ void tri_passes(typename TriPacked<T>::type pi, bool 
 }
 
 // One tile pair (I, J) of the triangle pair sums; adds its 2B raw sums
-// [Tbar sums x 6 h | T sums x h] into the slot's running sums sm.unit_acc.
+// [Tbar sums x 3 h / 4 | T sums x h] into the slot's running sums sm.unit_acc.
 // `cells` is the cell count of the sort that ordered the packed particles,
 // which bounds the distance between the two tiles from below by `gap`
 // (tile_gap); widths with 2 h <= gap L contribute nothing to the pair, and
