@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(kBlock) batch_deposit_kernel(BatchArgs a) {
   __shared__ DepSmem<T> sm;
   extern __shared__ __align__(16) unsigned char dyn[];
   const int64_t* pf = a.prefix + PF_CHUNKS * (a.nsets + 1);
-  T* ts = reinterpret_cast<T*>(dyn);
+  SinCos<T>* tab = reinterpret_cast<SinCos<T>*>(dyn);
   const int64_t u = int64_t(blockIdx.x);
   if (u >= pf[a.nsets]) return;
   const int si = uni32(find_set(pf, a.nsets, u));
@@ -262,12 +262,11 @@ __global__ void __launch_bounds__(kBlock) batch_deposit_kernel(BatchArgs a) {
   const int64_t c = u - uni64(pf[si]);
   const int M = uni32(s.M);
   const int chunk = uni32(s.chunk);
-  T* tc = ts + M;
-  node_table(M, ts, tc);
+  node_table(M, tab);
   const int64_t lo = c * chunk;
   const int cnt = int(min(int64_t(chunk), uni64(s.n) - lo));
   deposit_block<T, PER, G>(uni_ptr(static_cast<const T*>(s.x)), uni_ptr(static_cast<const T*>(s.kappa_i)),
-                           PER ? 0.0 : *s.kstar, M, s.L, lo, cnt, uni_ptr(s.dep_part) + c * M, ts, tc, sm,
+                           PER ? 0.0 : *s.kstar, M, s.L, lo, cnt, uni_ptr(s.dep_part) + c * M, tab, sm,
                            uni_ptr(s.status));
 }
 

@@ -28,29 +28,28 @@
 
 namespace kde {
 
-// Dynamic LDS: the node table, 2 M values of T.
+// Dynamic LDS: the node table, M SinCos<T> (2 M values of T).
 template <typename T, bool PER, int G>
 __global__ void __launch_bounds__(kBlock) deposit_kernel(const T* __restrict__ x, const T* __restrict__ kap,
                                                         double kappa_g, int64_t n, int M, double L, int chunk,
                                                         double* __restrict__ partials, uint32_t* status) {
   __shared__ DepSmem<T> sm;
   extern __shared__ __align__(16) unsigned char dyn[];
-  T* ts = reinterpret_cast<T*>(dyn);
-  T* tc = ts + M;
-  node_table(M, ts, tc);
+  SinCos<T>* tab = reinterpret_cast<SinCos<T>*>(dyn);
+  node_table(M, tab);
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int cnt = int(min(int64_t(chunk), n - lo));
-  deposit_block<T, PER, G>(x, kap, kappa_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, ts, tc, sm, status);
+  deposit_block<T, PER, G>(x, kap, kappa_g, M, L, lo, cnt, partials + int64_t(blockIdx.x) * M, tab, sm, status);
 }
 
 // S adjacent lanes per particle (S = 1, 2, 4 or 8, from gather_split), lane
 // j summing the nodes k = j, j + S, j + 2S, ... in order (interleaved, so
 // the S lanes read neighbouring LDS words instead of one bank); the S
 // partial sums are combined by an xor butterfly, a fixed pairwise tree
-// whose result every lane of the group holds. Dynamic LDS: the node table (2 M values of
-// T) and the field (M values of T). In the float form the loop runs over
-// k = g - g0, so the table read is a broadcast and the field read is per
-// lane.
+// whose result every lane of the group holds. Dynamic LDS: the node table
+// (M SinCos<T>) and the field (M values of T). In the float form the loop
+// runs over k = g - g0, so the table read is a broadcast and the field read
+// is per lane.
 template <typename T, int S>
 __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x, const T* __restrict__ kap,
                                                        double kappa_g, bool per, int64_t n, int M, double L,
@@ -58,17 +57,11 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
                                                        uint32_t* status) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ double etab[std::is_same<T, double>::value ? 256 : 1];
-  T* ts = reinterpret_cast<T*>(dyn);
-  T* tc = ts + M;
-  T* tf = tc + M;
+  SinCos<T>* tab = reinterpret_cast<SinCos<T>*>(dyn);
+  T* tf = reinterpret_cast<T*>(tab + M);
   exp_table_fill<T>(etab);
-  for (int k = threadIdx.x; k < M; k += kBlock) {
-    double sv, cv;
-    sincospi(double(k) / double(M), &sv, &cv);
-    ts[k] = T(sv);
-    tc[k] = T(cv);
-    tf[k] = T(field[k]);
-  }
+  node_table(M, tab);
+  for (int k = threadIdx.x; k < M; k += kBlock) tf[k] = T(field[k]);
   __syncthreads();
   const int64_t gid = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t i = gid / S;
@@ -82,19 +75,34 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
   if (j == 0) note_numeric(status, !isfinite(xi), per && !(isfinite(kk) && kk >= 0.0));
   const T A = T(-2.0 * kk * Flt<T>::unit);
   const double w = (L / M) / (L * i0e_f64(kk));
-  SumOf<T> acc;
+  Acc<T> acc;
+  acc.zero();
   if constexpr (std::is_same<T, float>::value) {
-    int g = gp.g0 + j;
-    if (g >= M) g -= M;
-    for (int k = j; k < M; k += S) {
-      const T s = ts[k] * gp.cb - tc[k] * gp.sb;
-      acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
-      g += S;
-      if (g >= M) g -= M;
+    // node g = g0 + k (mod M); groups of four without a bound test inside
+    // a group keep their LDS reads in flight together (the run folds fall
+    // after every kRun terms either way)
+    auto term = [&](int k) {
+      const SinCos<T> e = tab[k];
+      const T s = e.s * gp.cb - e.c * gp.sb;
+      const int g = gp.g0 + k;
+      return tf[g >= M ? g - M : g] * Flt<T>::ex(A * (s * s), etab);
+    };
+    int k = j, q = 0;
+    for (; k + 3 * S < M; k += 4 * S, q += 4) {
+      T e[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = term(k + u * S);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc.add(e[u]);
+      if (((q + 4) & (kRun - 1)) == 0) acc.fold();
+    }
+    for (; k < M; k += S, ++q) {
+      acc.add(term(k));
+      if ((q & (kRun - 1)) == kRun - 1) acc.fold();
     }
   } else if (__all(A >= T(-2.0 * kNearKappa))) {
     for (int g = j; g < M; g += S) {
-      const T s = node_s(gp, g, M, ts, tc);
+      const T s = node_s(gp, g, M, tab);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
     }
   } else if (__all(A >= T(kExpTableMin))) {
@@ -102,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
     const double dx = L / double(M);
     const bool sharp = A < T(-2.0 * kNearKappa);
     for (int g = j; g < M; g += S) {
-      T s = node_s(gp, g, M, ts, tc);
+      T s = node_s(gp, g, M, tab);
       if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex_in(A * (s * s), etab));
     }
@@ -110,7 +118,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(const T* __restrict__ x,
     const double dx = L / double(M);
     const bool sharp = A < T(-2.0 * kNearKappa);
     for (int g = j; g < M; g += S) {
-      T s = node_s(gp, g, M, ts, tc);
+      T s = node_s(gp, g, M, tab);
       if (sharp) s = near_node_s(s, g, dx, gp.w, L);
       acc.add(tf[g] * Flt<T>::ex(A * (s * s), etab));
     }

@@ -23,6 +23,7 @@
 // - log g)) is written per particle.
 #include <cfloat>
 
+#include "dev_sum.hpp"
 #include "device_bessel.hpp"
 #include "kde_internal.hpp"
 
@@ -56,20 +57,25 @@ struct SumOf;
 template <>
 struct SumOf<double> {
   double s = 0.0;
+  __device__ __forceinline__ void zero() { s = 0.0; }
   __device__ __forceinline__ void add(double v) { s += v; }
+  __device__ __forceinline__ void fold() {}
   __device__ __forceinline__ double value() const { return s; }
 };
 // Float terms in a compensated float sum (Kahan, one step per term); the
-// value is handed on in double for the FP64 reductions.
+// value is handed on in double for the FP64 reductions. Two registers per
+// sum against the three of Acc<float>, for loops that hold many sums.
 template <>
 struct SumOf<float> {
   float s = 0.0f, c = 0.0f;
+  __device__ __forceinline__ void zero() { s = c = 0.0f; }
   __device__ __forceinline__ void add(float v) {
     const float y = v - c;
     const float t = s + y;
     c = (t - s) - y;
     s = t;
   }
+  __device__ __forceinline__ void fold() {}
   __device__ __forceinline__ double value() const { return double(s) - double(c); }
 };
 
@@ -121,6 +127,13 @@ struct PGeo<float> {
   float cb, sb;
 };
 
+// The LDS node table: sin and cos of pi k / M side by side, so that one
+// read (8 or 16 bytes) gives both.
+template <typename T>
+struct __align__(2 * sizeof(T)) SinCos {
+  T s, c;
+};
+
 __device__ __forceinline__ void make_geo(double xw, double L, int M, PGeo<double>& p) {
   double sp, cp;
   sincospi(xw / L, &sp, &cp);
@@ -141,34 +154,45 @@ __device__ __forceinline__ void make_geo(double xw, double L, int M, PGeo<float>
   p.sb = float(sb);
 }
 
+// A deposit chunk's particle as the node loops read it: geometry and the
+// exponent factor in one record (16 bytes in float, one LDS read), the
+// weight apart (read only with per-particle widths).
+template <typename T>
+struct __align__(16) DepRec {
+  PGeo<T> g;
+  T A;
+};
+
 template <typename T, bool PER>
 __device__ __forceinline__ void particle_terms(const T* __restrict__ x, const T* __restrict__ kap, double kappa_g,
-                                               int64_t i, double L, int M, PGeo<T>& g, T& A, T& w) {
+                                               int64_t i, double L, int M, DepRec<T>& r, T& w) {
   const double xi = double(x[i]);
   const double xw = xi - L * floor(xi / L);
-  make_geo(xw, L, M, g);
+  make_geo(xw, L, M, r.g);
   const double k = PER ? double(kap[i]) : kappa_g;
-  A = T(-2.0 * k * Flt<T>::unit);
+  r.A = T(-2.0 * k * Flt<T>::unit);
   w = PER ? T(1.0 / (L * i0e_f64(k))) : T(1);
 }
 
-// s for node g of a particle; `ts`/`tc` hold sin/cos(pi g/M) (double form,
+// s for node g of a particle; `t` holds sin/cos(pi g/M) (double form,
 // indexed by g) or sin/cos(pi k/M) (float form, indexed by k = g - g0 mod M).
-__device__ __forceinline__ double node_s(const PGeo<double>& p, int g, int M, const double* ts, const double* tc) {
-  return ts[g] * p.a - tc[g] * p.b;
+__device__ __forceinline__ double node_s(const PGeo<double>& p, int g, int M, const SinCos<double>* t) {
+  const SinCos<double> e = t[g];
+  return e.s * p.a - e.c * p.b;
 }
-__device__ __forceinline__ float node_s(const PGeo<float>& p, int g, int M, const float* ts, const float* tc) {
+__device__ __forceinline__ float node_s(const PGeo<float>& p, int g, int M, const SinCos<float>* t) {
   int k = g - p.g0;
   k += (k < 0) ? M : 0;
-  return ts[k] * p.cb - tc[k] * p.sb;
+  const SinCos<float> e = t[k];
+  return e.s * p.cb - e.c * p.sb;
 }
 
 // Shared memory of one deposit chunk (the node table is separate: dynamic
-// LDS of 2 M values of T).
+// LDS of M SinCos<T>).
 template <typename T>
 struct DepSmem {
-  PGeo<T> pg[kDepMaxChunk];
-  T pA[kDepMaxChunk], pw[kDepMaxChunk];
+  DepRec<T> rec[kDepMaxChunk];
+  T pw[kDepMaxChunk];
   double red[kBlock];
   double etab[std::is_same<T, double>::value ? 256 : 1];  // exponential table (double form)
 };
@@ -182,14 +206,13 @@ __device__ __forceinline__ void exp_table_fill(double* etab) {
   }
 }
 
-// Fill the node table: ts[k] = sin(pi k/M), tc[k] = cos(pi k/M).
+// Fill the node table: t[k] = (sin(pi k/M), cos(pi k/M)).
 template <typename T>
-__device__ __forceinline__ void node_table(int M, T* ts, T* tc) {
+__device__ __forceinline__ void node_table(int M, SinCos<T>* t) {
   for (int k = threadIdx.x; k < M; k += kBlock) {
     double sv, cv;
     sincospi(double(k) / double(M), &sv, &cv);
-    ts[k] = T(sv);
-    tc[k] = T(cv);
+    t[k] = SinCos<T>{T(sv), T(cv)};
   }
 }
 
@@ -207,41 +230,66 @@ __device__ __forceinline__ void node_table(int M, T* ts, T* tc) {
 // exponential's domain, so exponents are clamped first. Chunks without
 // either (every chunk of ordinary widths) run the plain loop.
 template <typename T, bool PER, bool NEAR, bool CLAMP>
-__device__ __forceinline__ double dep_node_sum(int g, int sub, int S, int cnt, int M, double L, const T* ts,
-                                               const T* tc, const DepSmem<T>& sm) {
-  SumOf<T> acc;
-  const double dx = L / double(M);
-  for (int p = sub; p < cnt; p += S) {
-    T s = node_s(sm.pg[p], g, M, ts, tc);
-    const T A = sm.pA[p];
-    if constexpr (NEAR) {
-      if (A < T(-2.0 * kNearKappa)) s = near_node_s(s, g, dx, sm.pg[p].w, L);
-    }
-    const T e = CLAMP ? Flt<T>::ex(A * (s * s), sm.etab) : Flt<T>::ex_in(A * (s * s), sm.etab);
-    acc.add(PER ? sm.pw[p] * e : e);
+__device__ __forceinline__ T dep_term(int g, int p, int M, double L, const SinCos<T>* tab, const DepSmem<T>& sm) {
+  const DepRec<T> r = sm.rec[p];
+  T s = node_s(r.g, g, M, tab);
+  if constexpr (NEAR) {
+    if (r.A < T(-2.0 * kNearKappa)) s = near_node_s(s, g, L / double(M), r.g.w, L);
+  }
+  const T e = CLAMP ? Flt<T>::ex(r.A * (s * s), sm.etab) : Flt<T>::ex_in(r.A * (s * s), sm.etab);
+  return PER ? sm.pw[p] * e : e;
+}
+
+// The particles in groups of four without a bound test inside a group, so
+// that their LDS reads (the record, then the table entry it points to) are
+// in flight together, then the rest one by one. The sum's run folds fall
+// after every kRun terms either way, so the result is that of the plain
+// loop.
+template <typename T, bool PER, bool NEAR, bool CLAMP>
+__device__ __forceinline__ double dep_node_sum(int g, int sub, int S, int cnt, int M, double L,
+                                               const SinCos<T>* tab, const DepSmem<T>& sm) {
+  static_assert(kRun % 4 == 0, "a run holds whole groups of four");
+  Acc<T> acc;
+  acc.zero();
+  int p = sub, q = 0;
+  for (; p + 3 * S < cnt; p += 4 * S, q += 4) {
+    T e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e[u] = dep_term<T, PER, NEAR, CLAMP>(g, p + u * S, M, L, tab, sm);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc.add(e[u]);
+    if (((q + 4) & (kRun - 1)) == 0) acc.fold();
+  }
+  for (; p < cnt; p += S, ++q) {
+    acc.add(dep_term<T, PER, NEAR, CLAMP>(g, p, M, L, tab, sm));
+    if ((q & (kRun - 1)) == kRun - 1) acc.fold();
   }
   return acc.value();
 }
 
 // The same for G nodes per thread (g = tid + k kBlock), all particles.
-template <typename T, bool PER, int G, bool NEAR, bool CLAMP>
-__device__ __forceinline__ void dep_node_sums(int tid, int cnt, int M, double L, const T* ts, const T* tc,
-                                              const DepSmem<T>& sm, SumOf<T> (&acc)[G]) {
+template <typename T, bool PER, int G, bool NEAR, bool CLAMP, typename Sum>
+__device__ __forceinline__ void dep_node_sums(int tid, int cnt, int M, double L, const SinCos<T>* tab,
+                                              const DepSmem<T>& sm, Sum (&acc)[G]) {
   const double dx = L / double(M);
   for (int p = 0; p < cnt; ++p) {
-    const PGeo<T> gp = sm.pg[p];
-    const T A = sm.pA[p], w = sm.pw[p];
+    const DepRec<T> r = sm.rec[p];
+    const T w = PER ? sm.pw[p] : T(1);
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int g = tid + k * kBlock;
       if (g < M) {
-        T s = node_s(gp, g, M, ts, tc);
+        T s = node_s(r.g, g, M, tab);
         if constexpr (NEAR) {
-          if (A < T(-2.0 * kNearKappa)) s = near_node_s(s, g, dx, gp.w, L);
+          if (r.A < T(-2.0 * kNearKappa)) s = near_node_s(s, g, dx, r.g.w, L);
         }
-        const T e = CLAMP ? Flt<T>::ex(A * (s * s), sm.etab) : Flt<T>::ex_in(A * (s * s), sm.etab);
+        const T e = CLAMP ? Flt<T>::ex(r.A * (s * s), sm.etab) : Flt<T>::ex_in(r.A * (s * s), sm.etab);
         acc[k].add(PER ? w * e : e);
       }
+    }
+    if ((p & (kRun - 1)) == kRun - 1) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) acc[k].fold();
     }
   }
 }
@@ -249,16 +297,16 @@ __device__ __forceinline__ void dep_node_sums(int tid, int cnt, int M, double L,
 template <typename T, bool PER, int G>
 __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* __restrict__ kap, double kappa_g,
                                               int M, double L, int64_t lo, int cnt, double* __restrict__ out,
-                                              const T* ts, const T* tc, DepSmem<T>& sm, uint32_t* status) {
+                                              const SinCos<T>* tab, DepSmem<T>& sm, uint32_t* status) {
   const int tid = threadIdx.x;
   int sharp = 0, huge = 0;
   for (int k = tid; k < cnt; k += kBlock) {
     const double xi = double(x[lo + k]);
     const double ki = PER ? double(kap[lo + k]) : 0.0;
     note_numeric(status, !isfinite(xi), PER && !(isfinite(ki) && ki >= 0.0));
-    particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.pg[k], sm.pA[k], sm.pw[k]);
-    if (std::is_same<T, double>::value && sm.pA[k] < T(-2.0 * kNearKappa)) sharp = 1;
-    if (std::is_same<T, double>::value && !(sm.pA[k] >= T(kExpTableMin))) huge = 1;
+    particle_terms<T, PER>(x, kap, kappa_g, lo + k, L, M, sm.rec[k], sm.pw[k]);
+    if (std::is_same<T, double>::value && sm.rec[k].A < T(-2.0 * kNearKappa)) sharp = 1;
+    if (std::is_same<T, double>::value && !(sm.rec[k].A >= T(kExpTableMin))) huge = 1;
   }
   exp_table_fill<T>(sm.etab);
   // one barrier that also tells every thread whether the chunk holds a
@@ -271,13 +319,13 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
     if (sub < S) {
       if constexpr (std::is_same<T, double>::value) {
         if (flags == 0)
-          tot = dep_node_sum<T, PER, false, false>(g, sub, S, cnt, M, L, ts, tc, sm);
+          tot = dep_node_sum<T, PER, false, false>(g, sub, S, cnt, M, L, tab, sm);
         else if (flags == 1)
-          tot = dep_node_sum<T, PER, true, false>(g, sub, S, cnt, M, L, ts, tc, sm);
+          tot = dep_node_sum<T, PER, true, false>(g, sub, S, cnt, M, L, tab, sm);
         else
-          tot = dep_node_sum<T, PER, true, true>(g, sub, S, cnt, M, L, ts, tc, sm);
+          tot = dep_node_sum<T, PER, true, true>(g, sub, S, cnt, M, L, tab, sm);
       } else {
-        tot = dep_node_sum<T, PER, false, false>(g, sub, S, cnt, M, L, ts, tc, sm);
+        tot = dep_node_sum<T, PER, false, false>(g, sub, S, cnt, M, L, tab, sm);
       }
     }
     sm.red[tid] = tot;
@@ -288,16 +336,21 @@ __device__ __forceinline__ void deposit_block(const T* __restrict__ x, const T* 
       out[tid] = PER ? v : v * (1.0 / (L * i0e_f64(kappa_g)));
     }
   } else {
-    SumOf<T> acc[G];
+    // runs folded into Kahan sums, or for 16 nodes per thread a Kahan step
+    // per term (the runs' third register per sum would cost two waves)
+    using Sum = typename std::conditional<(G <= 8), Acc<T>, SumOf<T>>::type;
+    Sum acc[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[k].zero();
     if constexpr (std::is_same<T, double>::value) {
       if (flags == 0)
-        dep_node_sums<T, PER, G, false, false>(tid, cnt, M, L, ts, tc, sm, acc);
+        dep_node_sums<T, PER, G, false, false>(tid, cnt, M, L, tab, sm, acc);
       else if (flags == 1)
-        dep_node_sums<T, PER, G, true, false>(tid, cnt, M, L, ts, tc, sm, acc);
+        dep_node_sums<T, PER, G, true, false>(tid, cnt, M, L, tab, sm, acc);
       else
-        dep_node_sums<T, PER, G, true, true>(tid, cnt, M, L, ts, tc, sm, acc);
+        dep_node_sums<T, PER, G, true, true>(tid, cnt, M, L, tab, sm, acc);
     } else {
-      dep_node_sums<T, PER, G, false, false>(tid, cnt, M, L, ts, tc, sm, acc);
+      dep_node_sums<T, PER, G, false, false>(tid, cnt, M, L, tab, sm, acc);
     }
     const double scale = PER ? 1.0 : 1.0 / (L * i0e_f64(kappa_g));
 #pragma unroll
