@@ -90,7 +90,7 @@ PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
 # change to these files leaves cv_pairs_kernel's machine code the same
 # (other kernels of cv.hip, comments), the digest is moved on after
 # comparing that code, and the counters are kept.
-PAIR_COUNTERS = {"digest": "e76873457a2a42e8",
+PAIR_COUNTERS = {"digest": "4d3cb9f27d846e1b",
                  "source": "profiles/cv_pairs_valu_counters_paper_scale.md",
                  "f64": {"valu_lane_instr_per_term": 48.38, "trans_per_term": 0.0005, "engine_clock_ghz": 2.116,
                          "issue_frac": 0.935},
@@ -104,7 +104,7 @@ PAIR_COUNTERS = {"digest": "e76873457a2a42e8",
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "dev_sum.hpp", "device_bessel.hpp", "bessel_coeffs.inc",
                        "dev_layout.hpp", "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "e76873457a2a42e8",
+PAIR_TRAFFIC = {"digest": "4d3cb9f27d846e1b",
                 "f64": {"fetch_kib": 6909.875, "write_kib": 19935.625},
                 "f32": {"fetch_kib": 1701.125, "write_kib": 22528.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0

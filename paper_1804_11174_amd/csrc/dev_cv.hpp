@@ -44,21 +44,21 @@
 // exponent scales with kappa, so once every lane of a wave is below the
 // bound for one concentration, the wave skips the rest for that j.
 //
-// Concentrations run in chunks of three kinds, each through a loop of its
-// own. The leading ones with 2 kappa < X0 (the small-argument Bessel range
-// covers every pair): no term can reach the skip bound, so there is no
-// vote, and the pair geometry is s^2 and c^2 alone; with only that
-// branch's polynomial live, its coefficients stay in scalar registers
-// instead of being rebuilt for every term. Those up to `nsmall`, where a
+// Concentrations run in chunks of three kinds. The leading ones with
+// 2 kappa < X0 (the small-argument Bessel range covers every pair): no
+// term can reach the skip bound, so there is no vote, and the pair
+// geometry is s^2 and c^2 alone; with only that branch's polynomial live,
+// its coefficients stay in scalar registers instead of being rebuilt for
+// every term; they have a loop of their own. Those up to `nsmall`, where a
 // term may take either Bessel branch. And the rest, where every term that
 // is not skipped takes the large-argument fit: in float a loop of its own
-// with two constants per concentration (in double the previous loop, which
-// takes the fit for them). From npure on, the K-bar terms leave out a
-// factor 1/sqrt(kappa) (the large-argument fit's 1/sqrt(2 kappa c) and the
-// small-argument constant are scaled to match), which the finalize applies
-// to their sums (KappaList::scale). Which loop a concentration takes
-// depends on kappa alone, so the sums still do not depend on the chunk or
-// group size.
+// with two constants per concentration (in double the previous loop,
+// which takes the fit for them). From npure on, the K-bar terms leave out
+// a factor 1/sqrt(kappa) (the large-argument fit's 1/sqrt(2 kappa c) and
+// the small-argument constant are scaled to match), which the finalize
+// applies to their sums (KappaList::scale). Which loop a concentration
+// takes depends on kappa alone, so the sums still do not depend on the
+// chunk or group size.
 #include "dev_sum.hpp"
 #include "device_bessel.hpp"
 #include "kde_internal.hpp"
