@@ -240,25 +240,25 @@ __device__ __forceinline__ T dep_term(int g, int p, int M, double L, const SinCo
   return PER ? sm.pw[p] * e : e;
 }
 
-// The particles in groups of four without a bound test inside a group, so
+// The particles in groups of eight without a bound test inside a group, so
 // that their LDS reads (the record, then the table entry it points to) are
 // in flight together, then the rest one by one. The sum's run folds fall
 // after every kRun terms either way, so the result is that of the plain
-// loop.
+// loop. (Groups of four: float deposit 9 % slower, double 3 %.)
 template <typename T, bool PER, bool NEAR, bool CLAMP>
 __device__ __forceinline__ double dep_node_sum(int g, int sub, int S, int cnt, int M, double L,
                                                const SinCos<T>* tab, const DepSmem<T>& sm) {
-  static_assert(kRun % 4 == 0, "a run holds whole groups of four");
+  static_assert(kRun % 8 == 0, "a run holds whole groups");
   Acc<T> acc;
   acc.zero();
   int p = sub, q = 0;
-  for (; p + 3 * S < cnt; p += 4 * S, q += 4) {
-    T e[4];
+  for (; p + 7 * S < cnt; p += 8 * S, q += 8) {
+    T e[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) e[u] = dep_term<T, PER, NEAR, CLAMP>(g, p + u * S, M, L, tab, sm);
+    for (int u = 0; u < 8; ++u) e[u] = dep_term<T, PER, NEAR, CLAMP>(g, p + u * S, M, L, tab, sm);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc.add(e[u]);
-    if (((q + 4) & (kRun - 1)) == 0) acc.fold();
+    for (int u = 0; u < 8; ++u) acc.add(e[u]);
+    if (((q + 8) & (kRun - 1)) == 0) acc.fold();
   }
   for (; p < cnt; p += S, ++q) {
     acc.add(dep_term<T, PER, NEAR, CLAMP>(g, p, M, L, tab, sm));
