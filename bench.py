@@ -92,10 +92,10 @@ PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
 # comparing that code, and the counters are kept.
 PAIR_COUNTERS = {"digest": "21286f87a87e68fd",
                  "source": "profiles/cv_pairs_valu_counters_paper_scale.md",
-                 "f64": {"valu_lane_instr_per_term": 48.38, "trans_per_term": 0.0005, "engine_clock_ghz": 2.116,
-                         "issue_frac": 0.935},
-                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.067,
-                         "issue_frac": 0.885}}
+                 "f64": {"valu_lane_instr_per_term": 48.38, "trans_per_term": 0.0005, "engine_clock_ghz": 2.192,
+                         "issue_frac": 0.937},
+                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.119,
+                         "issue_frac": 0.881}}
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
@@ -105,8 +105,8 @@ PAIR_COUNTERS = {"digest": "21286f87a87e68fd",
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "dev_sum.hpp", "device_bessel.hpp", "bessel_coeffs.inc",
                        "dev_layout.hpp", "kde_internal.hpp")
 PAIR_TRAFFIC = {"digest": "21286f87a87e68fd",
-                "f64": {"fetch_kib": 6909.875, "write_kib": 19935.625},
-                "f32": {"fetch_kib": 1701.125, "write_kib": 22528.0}}
+                "f64": {"fetch_kib": 6911.75, "write_kib": 19914.5},
+                "f32": {"fetch_kib": 1710.75, "write_kib": 22528.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
