@@ -176,7 +176,10 @@ __global__ void __launch_bounds__(kBlock) tri_gather_kernel(const T* __restrict_
   const double h = per ? double(hi[i]) : h_g;
   note_numeric(status, !isfinite(double(x[i])), per && !(h > 0.0 && h <= 0.5 * L));
   const TriGeo<T> p = tri_geo<T>(double(x[i]), h, L, M);
+  // a Kahan step per node: a support spans a few nodes, and runs with their
+  // fold test were 15 % slower here in float
   SumOf<T> acc;
+  auto add = [&](T v) { acc.add(v); };
   // Nodes beyond h / dx cells of the particle add exact zeros, so a
   // particle whose support is shorter than the circle visits only the nodes
   // g0 - r .. g0 + r (one node of margin against the rounding of q), still
@@ -188,10 +191,10 @@ __global__ void __launch_bounds__(kBlock) tri_gather_kernel(const T* __restrict_
     const int lo1 = a < 0 ? 0 : (b >= M ? 0 : a);
     const int hi1 = a < 0 ? b : (b >= M ? b - M : b);
     const int lo2 = a < 0 ? a + M : (b >= M ? a : M);
-    for (int g = lo1; g <= hi1; ++g) acc.add(tf[g] * tri_node(p, g, M));
-    for (int g = lo2; g < M; ++g) acc.add(tf[g] * tri_node(p, g, M));
+    for (int g = lo1; g <= hi1; ++g) add(tf[g] * tri_node(p, g, M));
+    for (int g = lo2; g < M; ++g) add(tf[g] * tri_node(p, g, M));
   } else {
-    for (int g = 0; g < M; ++g) acc.add(tf[g] * tri_node(p, g, M));
+    for (int g = 0; g < M; ++g) add(tf[g] * tri_node(p, g, M));
   }
   out[i] = T((L / M) * double(p.w) * acc.value());
 }

@@ -289,7 +289,7 @@ __device__ __forceinline__ void tri_slot(const typename TriPacked<T>::type* __re
 // taken into [-M/2, M/2], which keeps float's relative accuracy near the
 // particle. A half-width outside (0, L/2] gives a NaN weight.
 template <typename T>
-struct TriGeo {
+struct __align__(16) TriGeo {
   int g0;
   T delta, q, w;
 };
@@ -349,10 +349,28 @@ __device__ __forceinline__ void tri_deposit_block(const T* __restrict__ x, const
     const int g = tid % M, sub = tid / M;
     double tot = 0.0;
     if (sub < S) {
-      SumOf<T> acc;
-      for (int p = sub; p < cnt; p += S) {
-        const T t = tri_node(sm.pg[p], g, M);
-        acc.add(PER ? sm.pg[p].w * t : t);
+      // groups of eight particles without a bound test inside a group (their
+      // LDS reads in flight together), runs of kRun terms folded into a
+      // compensated sum, as in the von Mises deposit
+      auto term = [&](int p) {
+        const TriGeo<T> gp = sm.pg[p];
+        const T t = tri_node(gp, g, M);
+        return PER ? gp.w * t : t;
+      };
+      Acc<T> acc;
+      acc.zero();
+      int p = sub, q = 0;
+      for (; p + 7 * S < cnt; p += 8 * S, q += 8) {
+        T e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = term(p + u * S);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc.add(e[u]);
+        if (((q + 8) & (kRun - 1)) == 0) acc.fold();
+      }
+      for (; p < cnt; p += S, ++q) {
+        acc.add(term(p));
+        if ((q & (kRun - 1)) == kRun - 1) acc.fold();
       }
       tot = acc.value();
     }
@@ -364,7 +382,12 @@ __device__ __forceinline__ void tri_deposit_block(const T* __restrict__ x, const
       out[tid] = v * gscale;
     }
   } else {
-    SumOf<T> acc[G];
+    // runs folded into Kahan sums, or for 16 nodes per thread a Kahan step
+    // per term (registers)
+    using Sum = typename std::conditional<(G <= 8), Acc<T>, SumOf<T>>::type;
+    Sum acc[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[k].zero();
     for (int p = 0; p < cnt; ++p) {
       const TriGeo<T> gp = sm.pg[p];
 #pragma unroll
@@ -374,6 +397,10 @@ __device__ __forceinline__ void tri_deposit_block(const T* __restrict__ x, const
           const T t = tri_node(gp, g, M);
           acc[k].add(PER ? gp.w * t : t);
         }
+      }
+      if ((p & (kRun - 1)) == kRun - 1) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) acc[k].fold();
       }
     }
 #pragma unroll
