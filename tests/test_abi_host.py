@@ -188,6 +188,21 @@ def test_ad_pvalue_host_matches_oracle(a2):
     assert abs(kde.kde_ad_pvalue(a2) - adtest.ad_pvalue(a2)) <= 1e-9
 
 
+def test_ad_pvalue_host_across_the_range():
+    """The host p-value at 60 points log-spaced over A^2 in [0.02, 40]
+    against the oracle's adaptive quadrature of the same series (1e-12
+    absolute), and non-increasing in A^2 on a finer grid up to A^2 = 20
+    (p above 1e-10; beyond, 1 - P(A^2 <= z) is below the resolution of
+    the series' sum): the trapezoid step follows the width of the
+    integrands' analytic strip, so no part of the range may lose accuracy."""
+    import numpy as np
+    from oracle import adtest
+    for a2 in np.geomspace(0.02, 40.0, 60):
+        assert abs(kde.kde_ad_pvalue(float(a2)) - adtest.ad_pvalue(float(a2))) <= 1e-12, a2
+    p = [kde.kde_ad_pvalue(float(a2)) for a2 in np.geomspace(0.02, 20.0, 2000)]
+    assert all(q <= r + 1e-15 for r, q in zip(p, p[1:]))
+
+
 def test_ad_pvalue_host_published_tail_points():
     """The host p-value at Anderson and Darling's (1954) printed points,
     the 2.5 % and 1 % points included: the tail where the width-update rule
