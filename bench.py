@@ -44,7 +44,7 @@ METRIC = "CV pair-evals/s, particles/s at 1e-6 rel err; p50/p99 solve latency vs
 # a multiply, an add, a min or a transcendental each count one) that is
 # 39.3e12/s in double (256 CUs x 64 lanes x 2.4 GHz) and 78.6e12/s in float
 # (twice the lanes per clock, reached with packed FP32 instructions, which
-# this build does not emit). HBM3E 8 TB/s.
+# the library's kernels are compiled not to emit). HBM3E 8 TB/s.
 PEAK_LANE_OPS = {"f64": 78.6e12 / 2, "f32": 157.3e12 / 2}
 PEAK_HBM = 8.0e12
 
