@@ -48,25 +48,37 @@ METRIC = "CV pair-evals/s, particles/s at 1e-6 rel err; p50/p99 solve latency vs
 PEAK_LANE_OPS = {"f64": 78.6e12 / 2, "f32": 157.3e12 / 2}
 PEAK_HBM = 8.0e12
 
-# Algorithmic lane-operations per evaluated (pair, kappa) term of the CV
-# pair sums, large-argument branch, counted from the method's formulas in
-# FMA-issue slots: a multiply, an add or an FMA counts one; the hardware
-# float exp2 counts four (it issues at a quarter of the float FMA rate,
-# measured by `--form peak`); an accumulated sum counts one add per term
-# (compensation of the float sums is overhead); per-pair geometry shared by
-# all concentrations and per-concentration constants are not counted. The
-# basis does not change with the kernel's implementation. (The
-# small-argument branch, a degree-20 fit in double, costs 22 for the Kbar
-# term against 29 here.)
+# Algorithmic lane-operations of the CV pair sums, counted from the method's
+# formulas in FMA-issue slots: a multiply, an add or an FMA counts one; the
+# hardware float exp2 counts four (it issues at a quarter of the float FMA
+# rate, measured by `--form peak`); an accumulated sum counts one add per
+# term (compensation of the float sums is overhead); per-pair geometry and
+# per-concentration constants are not counted.
+# Terms of concentrations from X0/2 on (X0 = 16 in double, 8 in float, the
+# split point of the Bessel fits), priced at the large-argument branch:
 #   f64: K term: exponent product 1 + exponential 14 (Tang's table method:
 #        reduction 4, table index 3, polynomial and combination 5, scaling
 #        1, bound 1) = 15; Kbar term: exponent product 1 + exponential 14 +
 #        Bessel argument 1 + degree-11 polynomial 11 + two products = 29;
-#        two accumulations 2. Total 46.
+#        two accumulations 2. Total 46 per evaluated term.
 #   f32: K term: product 1 + exp2 4 = 5; Kbar term: product 1 + exp2 4 +
 #        argument 1 + degree-5 polynomial 5 + two products = 13; two
-#        accumulations 2. Total 20.
+#        accumulations 2. Total 20 per evaluated term.
+# Concentrations below X0/2 take the small-argument branch for every pair,
+# and none of their terms is skipped:
+#   f64: K term 15 and its accumulation 1 = 16 per term; the Kbar terms of
+#        all these concentrations together 41 per pair: their terms are one
+#        degree-20 polynomial of the pair's c^2 with per-concentration
+#        scales, so the pair sums need only the power sums of c^2 (twenty
+#        multiplies forming c^2 ... c^40 and twenty-one adds); the
+#        polynomials are applied to the power sums once per thread and
+#        tile pair, not per pair.
+#   f32: K term 5 + Kbar term (argument 1 + degree-10 polynomial 10 +
+#        product 1) 12 + two accumulations 2 = 19 per term.
 OPS_PER_TERM = {"f64": 46, "f32": 20}
+BESSEL_X0 = {"f64": 16.0, "f32": 8.0}
+PURE_TERM_OPS = {"f64": 16, "f32": 19}
+PURE_PAIR_OPS = {"f64": 41, "f32": 0}
 SKIP_EXPONENT = 70.0
 
 # The planning cost model's ideal pair-evaluation rates, against which the
@@ -90,12 +102,12 @@ PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
 # change to these files leaves cv_pairs_kernel's machine code the same
 # (other kernels of cv.hip, comments), the digest is moved on after
 # comparing that code, and the counters are kept.
-PAIR_COUNTERS = {"digest": "21286f87a87e68fd",
+PAIR_COUNTERS = {"digest": "6af8e855c776de8a",
                  "source": "profiles/cv_pairs_valu_counters_paper_scale.md",
-                 "f64": {"valu_lane_instr_per_term": 48.38, "trans_per_term": 0.0005, "engine_clock_ghz": 2.192,
-                         "issue_frac": 0.937},
-                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.119,
-                         "issue_frac": 0.881}}
+                 "f64": {"valu_lane_instr_per_term": 42.32, "trans_per_term": 0.0005, "engine_clock_ghz": 2.213,
+                         "issue_frac": 0.922},
+                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.138,
+                         "issue_frac": 0.884}}
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
@@ -104,9 +116,9 @@ PAIR_COUNTERS = {"digest": "21286f87a87e68fd",
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "dev_sum.hpp", "device_bessel.hpp", "bessel_coeffs.inc",
                        "dev_layout.hpp", "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "21286f87a87e68fd",
-                "f64": {"fetch_kib": 6911.75, "write_kib": 19914.5},
-                "f32": {"fetch_kib": 1710.75, "write_kib": 22528.0}}
+PAIR_TRAFFIC = {"digest": "6af8e855c776de8a",
+                "f64": {"fetch_kib": 7029.8125, "write_kib": 29054.0},
+                "f32": {"fetch_kib": 1710.625, "write_kib": 22528.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
@@ -141,6 +153,19 @@ def count_evaluated_terms(x, L, kappas):
         total += int(cnt.sum())
     return total
 
+
+
+def pair_kernel_ops(x, L, kappas, prec):
+    """Algorithmic lane-operations of one CV pair-sum launch over positions x
+    on the basis above; returns (ops, evaluated terms, small-argument terms)."""
+    n = int(np.asarray(x).shape[0])
+    pairs = n * (n - 1) // 2
+    evaluated = count_evaluated_terms(x, L, kappas)
+    npure = sum(1 for k in kappas if 2.0 * float(k) < BESSEL_X0[prec])
+    pure = npure * pairs
+    ops = ((evaluated - pure) * OPS_PER_TERM[prec] + pure * PURE_TERM_OPS[prec]
+           + (pairs * PURE_PAIR_OPS[prec] if npure else 0))
+    return ops, evaluated, pure
 
 # Secondary kernels of the plain pipeline, from the library's per-launch
 # event averages. Algorithmic lane-operations per (particle, node)
@@ -491,20 +516,23 @@ def main():
 
     pair_evals = B * n_cv * (n_cv - 1) / 2
     value = pair_evals / (ms_step * 1e-3)
-    evaluated = count_evaluated_terms(prob.x[:n_cv], L, kappas)
+    ops, evaluated, pure_terms = pair_kernel_ops(prob.x[:n_cv], L, kappas, args.prec)
     pair_ms = kern["cv_pairs"]["avg_ms"]
-    achieved = evaluated * OPS_PER_TERM[args.prec] / (pair_ms * 1e-3)
+    achieved = ops / (pair_ms * 1e-3)
     peak = PEAK_LANE_OPS[args.prec]
     pe_rate = pair_evals / (pair_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": "cv_pairs_kernel", "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "T lane-ops/s (FMA = 1)",
                 "frac": achieved / peak, "traffic": pair_kernel_traffic(args.prec),
                 "traffic_unit": "bytes per launch",
-                "basis": "algorithmic lane-operations per evaluated term (the method's formulas in FMA-issue slots, "
-                         "a float exp2 as 4, one add per accumulated sum) x the terms at or above e^-70 of "
-                         "their sum's scale, counted from the sorted positions",
+                "basis": "algorithmic lane-operations of the method's formulas in FMA-issue slots (a float exp2 "
+                         "as 4, one add per accumulated sum) over the terms at or above e^-70 of their sum's "
+                         "scale, counted from the sorted positions: large-argument terms at ops_per_term, "
+                         "small-argument terms (2 kappa below the Bessel split) at their own formulas",
                 "evaluated_terms_per_launch": evaluated, "evaluated_fraction": evaluated / pair_evals,
-                "ops_per_term": OPS_PER_TERM[args.prec], "kernel_avg_ms": pair_ms,
+                "small_argument_terms_per_launch": pure_terms, "ops_per_launch": ops,
+                "ops_per_term": OPS_PER_TERM[args.prec], "ops_per_evaluated_term": ops / evaluated,
+                "kernel_avg_ms": pair_ms,
                 "pair_evals_per_s": pe_rate, "planning_ideal_pair_evals_per_s": PLANNING_IDEAL_PAIR_EVALS[args.prec],
                 "frac_of_planning_ideal": pe_rate / PLANNING_IDEAL_PAIR_EVALS[args.prec],
                 "issue": pair_kernel_issue(args.prec)}

@@ -47,9 +47,14 @@
 // Concentrations run in chunks of three kinds. The leading ones with
 // 2 kappa < X0 (the small-argument Bessel range covers every pair): no
 // term can reach the skip bound, so there is no vote, and the pair
-// geometry is s^2 and c^2 alone; with only that branch's polynomial live,
-// its coefficients stay in scalar registers instead of being rebuilt for
-// every term; they have a loop of their own. Those up to `nsmall`, where a
+// geometry is s^2 and c^2 alone; they have a loop of their own. In float,
+// with only that branch's polynomial live, its coefficients stay in scalar
+// registers instead of being rebuilt for every term. In double, whose
+// polynomial has 21 coefficients, the K-bar terms are summed through the
+// power sums of c^2 (pair_chunk_pure_f64): the polynomials of these
+// concentrations differ only by a power of a per-concentration scale, so a
+// thread sums the powers of c^2 over its pairs once and forms each
+// concentration's sum from them. Those up to `nsmall`, where a
 // term may take either Bessel branch. And the rest, where every term that
 // is not skipped takes the large-argument fit: in float a loop of its own
 // with two constants per concentration (in double the previous loop,
@@ -303,15 +308,86 @@ __device__ __forceinline__ GeoS<float> pair_geo_small(const IPart<float>& p, con
   return GeoS<float>{q * (2.0f - q), c * c};
 }
 
+// Double concentrations [b0, b_end) with 2 kappa < X0 (see
+// pair_chunk_pure). Their K-bar terms are one polynomial, em2k Q(tk c^2),
+// of every pair's c^2, with coefficients q_m common to all of these
+// concentrations and only the scale tk differing; so the sum over j of a
+// thread's terms is em2k sum_m q_m tk^m W_m with W_m = sum_j c^2m, the same
+// sum reassociated. A first pass over the tile adds each pair's powers
+// c^2m (m = 0..20: twenty multiplies and twenty-one adds per pair, however
+// many such concentrations the chunk holds, against a 21-coefficient
+// Horner per pair and concentration), then each concentration's sum is
+// formed once from the W_m. Every product q_m tk^m W_m is positive but the
+// one of m = 19, which is below 2e-5 of the total, so the reassociation
+// adds no cancellation. The K terms take a second pass over the tile, in
+// the order of the per-term loop. The W_m depend on the pairs alone, so
+// the sums do not depend on the chunk or group size. (The float form keeps
+// the per-term loop: its power sums, eleven compensated float sums, cost
+// registers that the float kernel's eight waves do not have, and measured
+// no faster.)
+template <int BC, bool MASKED>
+__device__ __forceinline__ void pair_chunk_pure_f64(const double* __restrict__ tj, int nj, const IPart<double>& ip,
+                                                    bool valid_i, bool diag, int b0, int b_end,
+                                                    const CvConsts<double>& K, const double* __restrict__ etab,
+                                                    Acc<double> (&acc1)[BC], Acc<double> (&acc2)[BC]) {
+  constexpr int NS = KDE_I0E_F64_NSMALL;
+  constexpr double q[NS] = KDE_I0E_F64_SMALL;
+  const int nb = min(BC, b_end - b0);
+  double W[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) W[m] = 0.0;
+  for (int jj = 0; jj < nj; ++jj) {
+    const double c = ip.a * tj[3 * jj] + ip.b * tj[3 * jj + 1];
+    const double c2 = c * c;
+    double p = 1.0;
+    if (MASKED) p = (valid_i && (!diag || jj > int(threadIdx.x))) ? 1.0 : 0.0;
+    W[0] += p;
+#pragma unroll
+    for (int m = 1; m < NS; ++m) {
+      p *= c2;
+      W[m] += p;
+    }
+  }
+#pragma unroll
+  for (int bb = 0; bb < BC; ++bb) {
+    if (bb < nb) {
+      const double tk = K.tk[b0 + bb];
+      double r = q[NS - 1] * W[NS - 1];
+#pragma unroll
+      for (int m = NS - 2; m >= 0; --m) r = fma(r, tk, q[m] * W[m]);
+      acc1[bb].add(K.em2k[b0 + bb] * r);
+    }
+  }
+  for (int jj = 0; jj < nj; ++jj) {
+    const double s = ip.b * tj[3 * jj] - ip.a * tj[3 * jj + 1];
+    const double s2 = s * s;
+    bool live = true;
+    if (MASKED) live = valid_i && (!diag || jj > int(threadIdx.x));
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+      if (bb < nb) {
+        double t2 = exp_unit(K.A[b0 + bb] * s2, etab);
+        if (MASKED) t2 = live ? t2 : 0.0;
+        acc2[bb].add(t2);
+      }
+    }
+  }
+}
+
 // Concentrations [b0, b_end) with 2 kappa < X0: every term takes the
 // small-argument branch, and no exponent reaches -X0 > -S, so nothing is
 // skipped. Same accumulation order as pair_chunk. In float the chunk's
-// three constants per concentration sit in (scalar) registers.
+// three constants per concentration sit in (scalar) registers; the double
+// form sums its K-bar terms through power sums (pair_chunk_pure_f64).
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* __restrict__ tj, int nj,
                                                 const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
                                                 const CvConsts<T>& K, const double* __restrict__ etab,
                                                 Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
+  if constexpr (std::is_same<T, double>::value) {
+    pair_chunk_pure_f64<BC, MASKED>(tj, nj, ip, valid_i, diag, b0, b_end, K, etab, acc1, acc2);
+    return;
+  }
   constexpr bool hold = std::is_same<T, float>::value;
   const int nb = min(BC, b_end - b0);
   T Ab[BC], Eb[BC], Tb[BC];

@@ -54,3 +54,28 @@ def test_triangle_terms_match_brute_force(bench, seed):
     for h in widths:
         brute += n * (n - 1) // 2 if 2 * h >= L / 2 else int(np.count_nonzero(d < 2 * h))
     assert bench.count_tri_terms(x, L, widths) == brute
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_kernel_ops_prices_each_branch(bench, prec):
+    # small-argument concentrations (2 kappa below the Bessel split) have
+    # every pair's term at their own price plus the per-pair power sums; the
+    # rest are priced per evaluated term; counts by brute force
+    rng = np.random.default_rng([11174, 97, 0 if prec == "f64" else 1])
+    L = 4 * math.pi
+    x = rng.uniform(0.0, L, 300)
+    kappas = [0.5, 3.0, 7.9, 8.0, 50.0, 3e3]
+    d = _distances(x, L)
+    pairs = len(d)
+    x0 = {"f64": 16.0, "f32": 8.0}[prec]
+    pure_k = [k for k in kappas if 2.0 * k < x0]
+    rest = sum(int(np.count_nonzero(-2.0 * k * (1.0 - np.cos(math.pi * d / L)) >= -bench.SKIP_EXPONENT))
+               for k in kappas if 2.0 * k >= x0)
+    per_term = {"f64": 46, "f32": 20}[prec]
+    pure_term = {"f64": 15 + 1, "f32": 5 + 12 + 2}[prec]
+    per_pair = {"f64": 20 + 21, "f32": 0}[prec]
+    want = rest * per_term + len(pure_k) * pairs * pure_term + pairs * per_pair
+    ops, evaluated, pure = bench.pair_kernel_ops(x, L, kappas, prec)
+    assert pure == len(pure_k) * pairs
+    assert evaluated == rest + pure
+    assert ops == want
