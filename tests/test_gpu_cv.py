@@ -223,27 +223,32 @@ def test_small_argument_range_boundary(gpu, dtype):
 def test_pass_size_changes_nothing(gpu, dtype):
     """The tuned pass size (concentrations per pass) and the split of a
     tile pair over workgroups by concentration range must not change any
-    bit (20 concentrations, so the last group is ragged)."""
+    bit (20 and 32 concentrations, so the last group is ragged and the
+    small-argument concentrations are split over groups)."""
     import torch
     p = W.plain_small()
     prec = gpu.KDE_F64 if dtype == "f64" else gpu.KDE_F32
     x = p.x if dtype == "f64" else p.x.astype(np.float32)
-    kap = W.log_kappas(1.0, 1e4, 20)
-    outs = []
     shapes = [(4, 0), (8, 0), (16, 0), (4, 4), (4, 8), (8, 8), (16, 16), (8, 24)]
     if dtype == "f32":  # float passes are 4 or 8
         shapes = [(c, g) for c, g in shapes if c != 16]
-    try:
-        for c, g in shapes:
-            gpu.kde_tune_set(prec, [1 << 62], [c], [g])
-            outs.append(run_gpu_cv(gpu, x, p.L, kap, dtype))
-    finally:
-        if __import__("os").path.exists(gpu.TUNE_FILE):
-            gpu.load_tuning(gpu.TUNE_FILE)
-        else:
-            gpu.kde_tune_set(prec, [1 << 62], [8])
-    for o in outs[1:]:
-        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    # 20 concentrations: 3 below the float Bessel split (2 kappa < 8) and 5
+    # below the double one (2 kappa < 16); 32: 5 and 7, so groups of 4
+    # split the small-argument concentrations of both forms over units
+    for count in (20, 32):
+        kap = W.log_kappas(1.0, 1e4, count)
+        outs = []
+        try:
+            for c, g in shapes:
+                gpu.kde_tune_set(prec, [1 << 62], [c], [g])
+                outs.append(run_gpu_cv(gpu, x, p.L, kap, dtype))
+        finally:
+            if __import__("os").path.exists(gpu.TUNE_FILE):
+                gpu.load_tuning(gpu.TUNE_FILE)
+            else:
+                gpu.kde_tune_set(prec, [1 << 62], [8])
+        for o in outs[1:]:
+            assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
