@@ -54,7 +54,7 @@ PEAK_HBM = 8.0e12
 # rate, measured by `--form peak`); an accumulated sum counts one add per
 # term (compensation of the float sums is overhead); per-pair geometry and
 # per-concentration constants are not counted.
-# Terms of concentrations from X0/2 on (X0 = 16 in double, 8 in float, the
+# Terms of the other concentrations (X0 = 16 in double, 8 in float, the
 # split point of the Bessel fits), priced at the large-argument branch:
 #   f64: K term: exponent product 1 + exponential 14 (Tang's table method:
 #        reduction 4, table index 3, polynomial and combination 5, scaling
@@ -64,8 +64,9 @@ PEAK_HBM = 8.0e12
 #   f32: K term: product 1 + exp2 4 = 5; Kbar term: product 1 + exp2 4 +
 #        argument 1 + degree-5 polynomial 5 + two products = 13; two
 #        accumulations 2. Total 20 per evaluated term.
-# Concentrations below X0/2 take the small-argument branch for every pair,
-# and none of their terms is skipped:
+# Concentrations with 2 kappa below X0 (1.01 X0 in double, where the
+# small-argument fit holds its accuracy to there) take the small-argument
+# branch for every pair, and none of their terms is skipped:
 #   f64: K term 15 and its accumulation 1 = 16 per term; the Kbar terms of
 #        all these concentrations together 41 per pair: their terms are one
 #        degree-20 polynomial of the pair's c^2 with per-concentration
@@ -77,6 +78,7 @@ PEAK_HBM = 8.0e12
 #        product 1) 12 + two accumulations 2 = 19 per term.
 OPS_PER_TERM = {"f64": 46, "f32": 20}
 BESSEL_X0 = {"f64": 16.0, "f32": 8.0}
+PURE_REACH = {"f64": 1.01, "f32": 1.0}
 PURE_TERM_OPS = {"f64": 16, "f32": 19}
 PURE_PAIR_OPS = {"f64": 41, "f32": 0}
 SKIP_EXPONENT = 70.0
@@ -161,7 +163,7 @@ def pair_kernel_ops(x, L, kappas, prec):
     n = int(np.asarray(x).shape[0])
     pairs = n * (n - 1) // 2
     evaluated = count_evaluated_terms(x, L, kappas)
-    npure = sum(1 for k in kappas if 2.0 * float(k) < BESSEL_X0[prec])
+    npure = sum(1 for k in kappas if 2.0 * float(k) < PURE_REACH[prec] * BESSEL_X0[prec])
     pure = npure * pairs
     ops = ((evaluated - pure) * OPS_PER_TERM[prec] + pure * PURE_TERM_OPS[prec]
            + (pairs * PURE_PAIR_OPS[prec] if npure else 0))

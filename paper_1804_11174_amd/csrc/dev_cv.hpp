@@ -45,7 +45,8 @@
 // bound for one concentration, the wave skips the rest for that j.
 //
 // Concentrations run in chunks of three kinds. The leading ones with
-// 2 kappa < X0 (the small-argument Bessel range covers every pair): no
+// 2 kappa below X0 (1.01 X0 in double; pure_branch), where the small-argument
+// fit covers every pair: no
 // term can reach the skip bound, so there is no vote, and the pair
 // geometry is s^2 and c^2 alone; they have a loop of their own. In float,
 // with only that branch's polynomial live, its coefficients stay in scalar
@@ -79,7 +80,7 @@ struct CvConsts {
   T twok[KDE_MAX_KAPPAS];  // 2 kappa
   T tk[KDE_MAX_KAPPAS];    // (2 kappa / X0)^2: t = (R / X0)^2 = tk c^2
   int B;
-  int npure;   // leading concentrations with 2 kappa < X0: every term takes the small-argument branch
+  int npure;   // leading concentrations with pure_branch: every term takes the small-argument branch
   int nsmall;  // leading concentrations that may need the small-argument I0e branch
   T skip;      // exponent bound (in the unit of A)
 };
@@ -308,7 +309,7 @@ __device__ __forceinline__ GeoS<float> pair_geo_small(const IPart<float>& p, con
   return GeoS<float>{q * (2.0f - q), c * c};
 }
 
-// Double concentrations [b0, b_end) with 2 kappa < X0 (see
+// Double concentrations [b0, b_end) with 2 kappa < 1.01 X0 (see
 // pair_chunk_pure). Their K-bar terms are one polynomial, em2k Q(tk c^2),
 // of every pair's c^2, with coefficients q_m common to all of these
 // concentrations and only the scale tk differing; so the sum over j of a
@@ -374,9 +375,9 @@ __device__ __forceinline__ void pair_chunk_pure_f64(const double* __restrict__ t
   }
 }
 
-// Concentrations [b0, b_end) with 2 kappa < X0: every term takes the
-// small-argument branch, and no exponent reaches -X0 > -S, so nothing is
-// skipped. Same accumulation order as pair_chunk. In float the chunk's
+// Concentrations [b0, b_end) with pure_branch (2 kappa below X0, 1.01 X0
+// in double): every term takes the small-argument branch, and no exponent
+// reaches -1.01 X0 > -S, so nothing is skipped. Same accumulation order as pair_chunk. In float the chunk's
 // three constants per concentration sit in (scalar) registers; the double
 // form sums its K-bar terms through power sums (pair_chunk_pure_f64).
 template <typename T, int BC, bool MASKED>
@@ -722,11 +723,29 @@ inline bool small_branch_live(double k) {
   return 2.0 * k - double(I0eBounds<T>::X0) <= kSkipExponent;
 }
 
-// Whether every term of concentration k takes the small-argument branch
-// (2 kappa < X0, so 2 kappa |c| < X0 for every pair).
+// The double small-argument fit keeps its accuracy a little past t = 1: up
+// to x = 1.01 X0 (t = 1.0201) Horner's rule stays within 1.5e-15 relative,
+// as on [0, X0] (against mpmath; pinned by a CPU test of the coefficient
+// table). The float fit grows to 5.3e-7 there against 3.5e-7 on [0, X0],
+// too close to the float form's bound, so it keeps X0.
+template <typename T>
+struct PureReach {
+  static constexpr double value = 1.0;
+};
+template <>
+struct PureReach<double> {
+  static constexpr double value = 1.01;
+};
+
+// Whether every term of concentration k takes the small-argument branch:
+// 2 kappa < reach X0, so 2 kappa |c| < reach X0 for every pair and t =
+// (2 kappa c / X0)^2 stays where the fit holds. (In double, without the
+// stretch a concentration just above X0/2, such as 10^(28/31) = 8.0003 of
+// 32 values log-spaced in [1, 1e4], would take the general loop: per term
+// a skip vote, the reciprocal geometry and either branch.)
 template <typename T>
 inline bool pure_branch(double k) {
-  return 2.0 * k < double(I0eBounds<T>::X0);
+  return 2.0 * k < PureReach<T>::value * double(I0eBounds<T>::X0);
 }
 
 // Per-concentration constants of the pair kernel, computed on the host.

@@ -58,16 +58,17 @@ def test_triangle_terms_match_brute_force(bench, seed):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_pair_kernel_ops_prices_each_branch(bench, prec):
-    # small-argument concentrations (2 kappa below the Bessel split) have
+    # small-argument concentrations (2 kappa below the Bessel split, 1.01
+    # times it in double: 8.05 is one there, 8.1 is not) have
     # every pair's term at their own price plus the per-pair power sums; the
     # rest are priced per evaluated term; counts by brute force
     rng = np.random.default_rng([11174, 97, 0 if prec == "f64" else 1])
     L = 4 * math.pi
     x = rng.uniform(0.0, L, 300)
-    kappas = [0.5, 3.0, 7.9, 8.0, 50.0, 3e3]
+    kappas = [0.5, 3.0, 7.9, 8.05, 8.1, 50.0, 3e3]
     d = _distances(x, L)
     pairs = len(d)
-    x0 = {"f64": 16.0, "f32": 8.0}[prec]
+    x0 = {"f64": 16.0 * 1.01, "f32": 8.0}[prec]  # the small-argument fits' reach
     pure_k = [k for k in kappas if 2.0 * k < x0]
     rest = sum(int(np.count_nonzero(-2.0 * k * (1.0 - np.cos(math.pi * d / L)) >= -bench.SKIP_EXPONENT))
                for k in kappas if 2.0 * k >= x0)
