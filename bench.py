@@ -73,7 +73,10 @@ PEAK_HBM = 8.0e12
 #        scales, so the pair sums need only the power sums of c^2 (twenty
 #        multiplies forming c^2 ... c^40 and twenty-one adds); the
 #        polynomials are applied to the power sums once per thread and
-#        tile pair, not per pair.
+#        tile pair, not per pair. The same holds, tile pair by tile pair,
+#        for larger concentrations on two tiles far enough apart that every
+#        pair's 2 kappa c stays below 1.01 X0 (power_sum_route counts them
+#        as the kernel decides them; the rest at 46 per evaluated term).
 #   f32: K term 5 + Kbar term (argument 1 + degree-10 polynomial 10 +
 #        product 1) 12 + two accumulations 2 = 19 per term.
 OPS_PER_TERM = {"f64": 46, "f32": 20}
@@ -157,16 +160,87 @@ def count_evaluated_terms(x, L, kappas):
 
 
 
+CV_TILE = 256
+
+
+def power_sum_route(x, L, kappas, detail=None):
+    """The double pair kernel's power-sum route over the tile pairs of the
+    cell-sorted positions, as the kernel decides it: per tile pair the
+    concentrations with 2 kappa < 1.01 X0, and, on two tiles at least a gap
+    g apart (the kernel's cell bound), also those with 2 kappa (cos(pi g) +
+    1e-12) < 1.01 X0, up to the first concentration the tile test prunes.
+    Returns (terms on the route, those of them at or above the skip bound,
+    pairs of the tile pairs that form power sums); a list passed as
+    `detail` receives (indices of tile I, indices of tile J, concentrations
+    on the route) per tile pair that has any."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    k2 = 2.0 * np.asarray(kappas, dtype=np.float64)
+    reach = PURE_REACH["f64"] * BESSEL_X0["f64"]
+    cells = min(max(n // 32, 1), 8192)
+    w = x - L * np.floor(x / L)
+    w[w >= L] = 0.0
+    cell = np.clip((w * cells / L).astype(np.int64), 0, cells - 1)
+    order = np.lexsort((np.arange(n), cell))
+    f = w[order] * (1.0 / L)
+    ntiles = (n + CV_TILE - 1) // CV_TILE
+    first = f[np.arange(ntiles) * CV_TILE]
+    last = f[np.minimum(np.arange(ntiles) * CV_TILE + CV_TILE, n) - 1]
+    lo = (np.floor(first * cells) - 2.0) / cells
+    hi = (np.floor(np.where(last < first, 1.0, last) * cells) + 3.0) / cells
+    npure = int(np.count_nonzero(k2 < reach))
+    terms = evaluated = wpairs = 0
+    for I in range(ntiles):
+        ni = min(CV_TILE, n - I * CV_TILE)
+        for J in range(I, ntiles):
+            nj = min(CV_TILE, n - J * CV_TILE)
+            pe, tp = npure, (ni * (ni - 1) // 2 if I == J else ni * nj)
+            gap = -1.0 if I == J else min(lo[J] - hi[I], 1.0 + lo[I] - hi[J])
+            if gap > 0.0:
+                y = 0.5 * math.pi * gap
+                qmin = 2.0 * (y * (1.0 - y * y / 6.0)) ** 2
+                pruned = k2 * qmin > SKIP_EXPONENT * (1.0 + 1e-6)
+                be = int(np.argmax(pruned)) if pruned.any() else len(k2)
+                cmax = math.cos(math.pi * gap) + 1e-12
+                while pe < be and k2[pe] * cmax < reach:
+                    pe += 1
+                pe = min(pe, be)
+            if pe == 0:
+                continue
+            if detail is not None:
+                detail.append((order[I * CV_TILE:I * CV_TILE + ni], order[J * CV_TILE:J * CV_TILE + nj], pe))
+            terms += pe * tp
+            wpairs += tp
+            for b in range(pe):
+                if k2[b] <= SKIP_EXPONENT:
+                    evaluated += tp
+                else:
+                    fi = f[I * CV_TILE:I * CV_TILE + ni]
+                    fj = f[J * CV_TILE:J * CV_TILE + nj]
+                    d = np.abs(fi[:, None] - fj[None, :])
+                    d = np.minimum(d, 1.0 - d)
+                    ok = -k2[b] * (1.0 - np.cos(math.pi * d)) >= -SKIP_EXPONENT
+                    if I == J:
+                        ok = np.triu(ok, 1)
+                    evaluated += int(np.count_nonzero(ok))
+    return terms, evaluated, wpairs
+
+
 def pair_kernel_ops(x, L, kappas, prec):
     """Algorithmic lane-operations of one CV pair-sum launch over positions x
-    on the basis above; returns (ops, evaluated terms, small-argument terms)."""
+    on the basis above; returns (ops, evaluated terms, terms summed through
+    power sums in double / small-argument terms in float)."""
     n = int(np.asarray(x).shape[0])
     pairs = n * (n - 1) // 2
     evaluated = count_evaluated_terms(x, L, kappas)
+    if prec == "f64":
+        route, route_evaluated, wpairs = power_sum_route(x, L, kappas)
+        ops = ((evaluated - route_evaluated) * OPS_PER_TERM[prec] + route * PURE_TERM_OPS[prec]
+               + wpairs * PURE_PAIR_OPS[prec])
+        return ops, evaluated, route
     npure = sum(1 for k in kappas if 2.0 * float(k) < PURE_REACH[prec] * BESSEL_X0[prec])
     pure = npure * pairs
-    ops = ((evaluated - pure) * OPS_PER_TERM[prec] + pure * PURE_TERM_OPS[prec]
-           + (pairs * PURE_PAIR_OPS[prec] if npure else 0))
+    ops = (evaluated - pure) * OPS_PER_TERM[prec] + pure * PURE_TERM_OPS[prec]
     return ops, evaluated, pure
 
 # Secondary kernels of the plain pipeline, from the library's per-launch

@@ -52,10 +52,12 @@
 // with only that branch's polynomial live, its coefficients stay in scalar
 // registers instead of being rebuilt for every term. In double, whose
 // polynomial has 21 coefficients, the K-bar terms are summed through the
-// power sums of c^2 (pair_chunk_pure_f64): the polynomials of these
+// power sums of c^2 (power_sums_f64): the polynomials of these
 // concentrations differ only by a power of a per-concentration scale, so a
 // thread sums the powers of c^2 over its pairs once and forms each
-// concentration's sum from them. Those up to `nsmall`, where a
+// concentration's sum from them; on two tiles far enough apart, larger
+// concentrations whose every pair there takes the small-argument branch
+// join them. Those up to `nsmall`, where a
 // term may take either Bessel branch. And the rest, where every term that
 // is not skipped takes the large-argument fit: in float a loop of its own
 // with two constants per concentration (in double the previous loop,
@@ -71,6 +73,20 @@
 
 namespace kde {
 
+
+// The double small-argument fit keeps its accuracy a little past t = 1: up
+// to x = 1.01 X0 (t = 1.0201) Horner's rule stays within 1.5e-15 relative,
+// as on [0, X0] (against mpmath; pinned by a CPU test of the coefficient
+// table). The float fit grows to 5.3e-7 there against 3.5e-7 on [0, X0],
+// too close to the float form's bound, so it keeps X0.
+template <typename T>
+struct PureReach {
+  static constexpr double value = 1.0;
+};
+template <>
+struct PureReach<double> {
+  static constexpr double value = 1.01;
+};
 
 template <typename T>
 struct CvConsts {
@@ -309,32 +325,31 @@ __device__ __forceinline__ GeoS<float> pair_geo_small(const IPart<float>& p, con
   return GeoS<float>{q * (2.0f - q), c * c};
 }
 
-// Double concentrations [b0, b_end) with 2 kappa < 1.01 X0 (see
-// pair_chunk_pure). Their K-bar terms are one polynomial, em2k Q(tk c^2),
-// of every pair's c^2, with coefficients q_m common to all of these
-// concentrations and only the scale tk differing; so the sum over j of a
-// thread's terms is em2k sum_m q_m tk^m W_m with W_m = sum_j c^2m, the same
-// sum reassociated. A first pass over the tile adds each pair's powers
-// c^2m (m = 0..20: twenty multiplies and twenty-one adds per pair, however
-// many such concentrations the chunk holds, against a 21-coefficient
-// Horner per pair and concentration), then each concentration's sum is
-// formed once from the W_m. Every product q_m tk^m W_m is positive but the
-// one of m = 19, which is below 2e-5 of the total, so the reassociation
-// adds no cancellation. The K terms take a second pass over the tile, in
-// the order of the per-term loop. The W_m depend on the pairs alone, so
-// the sums do not depend on the chunk or group size. (The float form keeps
-// the per-term loop: its power sums, eleven compensated float sums, cost
+// Double concentrations whose every pair of a tile pair takes the
+// small-argument branch: those with pure_branch (2 kappa < 1.01 X0), and on
+// a tile pair whose two tiles are at least a gap g apart, also those with
+// 2 kappa cos(pi g) < 1.01 X0 (c = |cos(pi d / L)| <= cos(pi g) there). Their
+// K-bar terms are one polynomial, em2k Q(tk c^2), of every pair's c^2, with
+// coefficients q_m common to all of these concentrations and only the
+// scale tk (and em2k) differing; so the sum over j of a thread's terms is
+// em2k sum_m q_m tk^m W_m with W_m = sum_j c^2m, the same sum reassociated.
+// power_sums_f64 adds each pair's powers c^2m once per tile pair (m =
+// 0..20: twenty multiplies and twenty-one adds per pair, however many such
+// concentrations the tile pair has, against a 21-coefficient Horner per
+// pair and concentration); pair_chunk_sums_f64 takes a pass of them: their
+// K terms over the tile, in the order of the per-term loop, then each
+// concentration's K-bar sum from the W_m. Every product q_m tk^m W_m is
+// positive but the one of m = 19, which is below 2e-5 of the total, so the
+// reassociation adds no cancellation. Which concentrations take this route
+// on a tile pair depends on the tile pair and kappa alone, so the sums do
+// not depend on the chunk or group size. (The float form keeps the
+// per-term loop: its power sums, eleven compensated float sums, cost
 // registers that the float kernel's eight waves do not have, and measured
 // no faster.)
-template <int BC, bool MASKED>
-__device__ __forceinline__ void pair_chunk_pure_f64(const double* __restrict__ tj, int nj, const IPart<double>& ip,
-                                                    bool valid_i, bool diag, int b0, int b_end,
-                                                    const CvConsts<double>& K, const double* __restrict__ etab,
-                                                    Acc<double> (&acc1)[BC], Acc<double> (&acc2)[BC]) {
+template <bool MASKED>
+__device__ __forceinline__ void power_sums_f64(const double* __restrict__ tj, int nj, const IPart<double>& ip,
+                                               bool valid_i, bool diag, double (&W)[KDE_I0E_F64_NSMALL]) {
   constexpr int NS = KDE_I0E_F64_NSMALL;
-  constexpr double q[NS] = KDE_I0E_F64_SMALL;
-  const int nb = min(BC, b_end - b0);
-  double W[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) W[m] = 0.0;
   for (int jj = 0; jj < nj; ++jj) {
@@ -349,16 +364,30 @@ __device__ __forceinline__ void pair_chunk_pure_f64(const double* __restrict__ t
       W[m] += p;
     }
   }
+}
+
+// The K-bar sum of concentration b from the power sums, per thread:
+// em2k sum_m q_m tk^m W_m by Horner's rule in tk.
+__device__ __forceinline__ double kbar_from_sums_f64(int b, const CvConsts<double>& K,
+                                                     const double (&W)[KDE_I0E_F64_NSMALL]) {
+  constexpr int NS = KDE_I0E_F64_NSMALL;
+  constexpr double q[NS] = KDE_I0E_F64_SMALL;
+  const double tk = K.tk[b];
+  double r = q[NS - 1] * W[NS - 1];
 #pragma unroll
-  for (int bb = 0; bb < BC; ++bb) {
-    if (bb < nb) {
-      const double tk = K.tk[b0 + bb];
-      double r = q[NS - 1] * W[NS - 1];
+  for (int m = NS - 2; m >= 0; --m) r = fma(r, tk, q[m] * W[m]);
+  return K.em2k[b] * r;
+}
+
+// The K terms of concentrations [b0, b_end) (at most BC) over the tile,
+// per thread, in the order of the per-term loop.
+template <int BC, bool MASKED>
+__device__ __forceinline__ void k_terms_f64(const double* __restrict__ tj, int nj, const IPart<double>& ip,
+                                            bool valid_i, bool diag, int b0, int b_end, const CvConsts<double>& K,
+                                            const double* __restrict__ etab, double (&v2)[BC]) {
+  const int nb = min(BC, b_end - b0);
 #pragma unroll
-      for (int m = NS - 2; m >= 0; --m) r = fma(r, tk, q[m] * W[m]);
-      acc1[bb].add(K.em2k[b0 + bb] * r);
-    }
-  }
+  for (int bb = 0; bb < BC; ++bb) v2[bb] = 0.0;
   for (int jj = 0; jj < nj; ++jj) {
     const double s = ip.b * tj[3 * jj] - ip.a * tj[3 * jj + 1];
     const double s2 = s * s;
@@ -369,26 +398,22 @@ __device__ __forceinline__ void pair_chunk_pure_f64(const double* __restrict__ t
       if (bb < nb) {
         double t2 = exp_unit(K.A[b0 + bb] * s2, etab);
         if (MASKED) t2 = live ? t2 : 0.0;
-        acc2[bb].add(t2);
+        v2[bb] += t2;
       }
     }
   }
 }
 
-// Concentrations [b0, b_end) with pure_branch (2 kappa below X0, 1.01 X0
-// in double): every term takes the small-argument branch, and no exponent
-// reaches -1.01 X0 > -S, so nothing is skipped. Same accumulation order as pair_chunk. In float the chunk's
-// three constants per concentration sit in (scalar) registers; the double
-// form sums its K-bar terms through power sums (pair_chunk_pure_f64).
+// Float concentrations [b0, b_end) with pure_branch (2 kappa < X0): every
+// term takes the small-argument branch, and no exponent reaches -X0 > -S,
+// so nothing is skipped. Same accumulation order as pair_chunk. The
+// chunk's three constants per concentration sit in (scalar) registers. (The
+// double form sums its K-bar terms through power sums: power_sums_f64.)
 template <typename T, int BC, bool MASKED>
 __device__ __forceinline__ void pair_chunk_pure(const typename Packed<T>::type* __restrict__ tj, int nj,
                                                 const IPart<T>& ip, bool valid_i, bool diag, int b0, int b_end,
                                                 const CvConsts<T>& K, const double* __restrict__ etab,
                                                 Acc<T> (&acc1)[BC], Acc<T> (&acc2)[BC]) {
-  if constexpr (std::is_same<T, double>::value) {
-    pair_chunk_pure_f64<BC, MASKED>(tj, nj, ip, valid_i, diag, b0, b_end, K, etab, acc1, acc2);
-    return;
-  }
   constexpr bool hold = std::is_same<T, float>::value;
   const int nb = min(BC, b_end - b0);
   T Ab[BC], Eb[BC], Tb[BC];
@@ -555,8 +580,45 @@ struct CvSmem {
   double red[kBlock / 64][2 * BC];
   double unit_acc[2 * KDE_MAX_KAPPAS];
   double etab[std::is_same<T, double>::value ? 256 : 1];  // exponential table (double form)
+  // double: per-wave K-bar sums of the power-sum route, by concentration
+  double kbar_red[kBlock / 64][std::is_same<T, double>::value ? KDE_MAX_KAPPAS : 1];
   int b_end;
+  int p_end;  // double: concentrations [b_lo, p_end) take the power-sum route on this tile pair
 };
+
+// The workgroup's sums of one pass, concentrations [b0, bc_end): each
+// thread's sums v1 (K-bar) and v2 (K) in double (WHICH: 1 the K-bar sums
+// only, 2 the K sums only, 3 both), reduced over the wave by a fixed
+// butterfly, over the waves in wave order, and added to the slot's running
+// sums sm.unit_acc. Ends with a barrier.
+template <typename T, int BC, int WHICH = 3>
+__device__ __forceinline__ void reduce_chunk_values(const double (&v1)[BC], const double (&v2)[BC], int b0,
+                                                    int bc_end, int B, CvSmem<T, BC>& sm) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int bb = 0; bb < BC; ++bb) {
+    if (WHICH & 1) {
+      const double w1 = wave_sum(v1[bb]);
+      if (lane == 0) sm.red[wave][bb] = w1;
+    }
+    if (WHICH & 2) {
+      const double w2 = wave_sum(v2[bb]);
+      if (lane == 0) sm.red[wave][BC + bb] = w2;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * BC) {
+    const int bb = tid % BC;
+    const int which = tid / BC;  // 0: Kbar sums, 1: K sums
+    if (b0 + bb < bc_end && (WHICH & (1 << which))) {
+      double v = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
+      sm.unit_acc[which * B + b0 + bb] += v;
+    }
+  }
+  __syncthreads();
+}
 
 // One tile pair of the pair sums: tile I (one i per thread) against tile J
 // (staged in LDS), concentrations [b_lo, b_hi); adds this pair's sums into
@@ -587,15 +649,23 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
   const int nj = int(min(int64_t(kCvTile), n - j0));
   if (tid == 0) {
     int be = b_hi;
+    int pe = max(b_lo, min(K.npure, b_hi));
     if (I != J) {
       const double gap = tile_gap(packed, i0, int(min(int64_t(kCvTile), n - i0)), j0, nj, cells, 1.0 / L);
       if (gap > 0.0) {
         const double qmin = one_minus_cos_pi_lower(gap);
         be = b_lo;
         while (be < b_hi && !(double(K.twok[be]) * qmin > kSkipExponent * (1.0 + 1e-6))) ++be;
+        if constexpr (std::is_same<T, double>::value) {
+          // every pair has c <= cos(pi gap) (gap <= 1/2); the margin covers
+          // the rounding of c itself
+          const double cmax = cospi(gap) + 1e-12;
+          while (pe < be && double(K.twok[pe]) * cmax < PureReach<double>::value * double(I0eBounds<double>::X0)) ++pe;
+        }
       }
     }
     sm.b_end = be;
+    sm.p_end = min(pe, be);
   }
   for (int k = tid; k < pp * nj; k += kBlock) sm.tj[k] = packed[pp * j0 + k];
   const int64_t i = i0 + tid;
@@ -606,8 +676,44 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
   __syncthreads();
   const int b_end = sm.b_end;
 
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int b0 = b_lo; b0 < b_end;) {
+  int b0 = b_lo;
+  if constexpr (std::is_same<T, double>::value) {
+    const int p_end = sm.p_end;
+    if (b0 < p_end) {
+      double W[KDE_I0E_F64_NSMALL];
+      if (masked)
+        power_sums_f64<true>(sm.tj, nj, ip, valid_i, diag, W);
+      else
+        power_sums_f64<false>(sm.tj, nj, ip, valid_i, diag, W);
+      // the K-bar sums of the whole range first, with no barrier between
+      // them, so that the power sums are dead before the K terms' passes:
+      // per concentration the thread's sum, its wave's sum into LDS; then
+      // the waves' sums in wave order into the running sums
+      const int lane = tid & 63, wave = tid >> 6;
+      for (int b = b0; b < p_end; ++b) {
+        const double w = wave_sum(kbar_from_sums_f64(b, K, W));
+        if (lane == 0) sm.kbar_red[wave][b] = w;
+      }
+      __syncthreads();
+      for (int b = b0 + tid; b < p_end; b += kBlock) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += sm.kbar_red[w][b];
+        sm.unit_acc[b] += v;
+      }
+      __syncthreads();
+    }
+    while (b0 < p_end) {
+      const int bc_end = min(b0 + BC, p_end);
+      double v2[BC];
+      if (masked)
+        k_terms_f64<BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, v2);
+      else
+        k_terms_f64<BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, v2);
+      reduce_chunk_values<T, BC, 2>(v2, v2, b0, bc_end, K.B, sm);
+      b0 = bc_end;
+    }
+  }
+  for (; b0 < b_end;) {
     // chunks do not straddle npure, nor in float nsmall
     const int bc_end = min(b0 + BC, b0 < K.npure ? min(b_end, K.npure)
                                                  : (kSplitLarge<T> && b0 < K.nsmall ? min(b_end, K.nsmall) : b_end));
@@ -617,11 +723,13 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
       s1[bb].zero();
       s2[bb].zero();
     }
-    if (b0 < K.npure) {
-      if (masked)
-        pair_chunk_pure<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
-      else
-        pair_chunk_pure<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+    if (b0 < K.npure) {  // float only: in double these took the power-sum route above
+      if constexpr (std::is_same<T, float>::value) {
+        if (masked)
+          pair_chunk_pure<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+        else
+          pair_chunk_pure<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, sm.etab, s1, s2);
+      }
     } else if (!kSplitLarge<T> || b0 < K.nsmall) {
       if (masked)
         pair_chunk<T, BC, true>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
@@ -633,26 +741,13 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
       else
         pair_chunk_large<T, BC, false>(sm.tj, nj, ip, valid_i, diag, b0, bc_end, K, per, sm.etab, s1, s2);
     }
+    double v1[BC], v2[BC];
 #pragma unroll
     for (int bb = 0; bb < BC; ++bb) {
-      double v1 = wave_sum(s1[bb].value());
-      double v2 = wave_sum(s2[bb].value());
-      if (lane == 0) {
-        sm.red[wave][bb] = v1;
-        sm.red[wave][BC + bb] = v2;
-      }
+      v1[bb] = s1[bb].value();
+      v2[bb] = s2[bb].value();
     }
-    __syncthreads();
-    if (tid < 2 * BC) {
-      const int bb = tid % BC;
-      const int which = tid / BC;  // 0: Kbar sums, 1: K sums
-      if (b0 + bb < bc_end) {
-        double v = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) v += sm.red[w][tid];
-        sm.unit_acc[which * K.B + b0 + bb] += v;
-      }
-    }
-    __syncthreads();
+    reduce_chunk_values<T, BC>(v1, v2, b0, bc_end, K.B, sm);
     b0 = bc_end;
   }
 }
@@ -722,20 +817,6 @@ template <typename T>
 inline bool small_branch_live(double k) {
   return 2.0 * k - double(I0eBounds<T>::X0) <= kSkipExponent;
 }
-
-// The double small-argument fit keeps its accuracy a little past t = 1: up
-// to x = 1.01 X0 (t = 1.0201) Horner's rule stays within 1.5e-15 relative,
-// as on [0, X0] (against mpmath; pinned by a CPU test of the coefficient
-// table). The float fit grows to 5.3e-7 there against 3.5e-7 on [0, X0],
-// too close to the float form's bound, so it keeps X0.
-template <typename T>
-struct PureReach {
-  static constexpr double value = 1.0;
-};
-template <>
-struct PureReach<double> {
-  static constexpr double value = 1.01;
-};
 
 // Whether every term of concentration k takes the small-argument branch:
 // 2 kappa < reach X0, so 2 kappa |c| < reach X0 for every pair and t =

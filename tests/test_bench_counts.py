@@ -80,3 +80,35 @@ def test_pair_kernel_ops_prices_each_branch(bench, prec):
     assert pure == len(pure_k) * pairs
     assert evaluated == rest + pure
     assert ops == want
+
+
+def test_power_sum_route_is_safe_and_counted(bench):
+    # four tight clusters a quarter period apart: tiles of far clusters take
+    # concentrations above X0/2 on the power-sum route; every pair on the
+    # route must have 2 kappa |cos(pi d / L)| below 1.01 X0 (the fit's reach),
+    # and the route's evaluated terms are counted by brute force
+    rng = np.random.default_rng([11174, 96])
+    L = 2 * math.pi
+    x = np.concatenate([rng.normal(c * L / 4, 0.01, 512) for c in range(4)])
+    kappas = [1.0, 4.0, 9.0, 12.0, 20.0, 36.0, 500.0]
+    detail = []
+    terms, evaluated, wpairs = bench.power_sum_route(x, L, kappas, detail)
+    xs = np.asarray(x) % L
+    n = len(x)
+    npure = sum(1 for k in kappas if 2 * k < 1.01 * 16.0)
+    assert terms > npure * n * (n - 1) // 2  # the route reaches past the small concentrations
+    want_terms = want_eval = want_pairs = 0
+    for ti, tj, pe in detail:
+        d = np.abs(xs[ti][:, None] - xs[tj][None, :])
+        d = np.minimum(d, L - d)
+        same = ti[0] == tj[0]
+        live = np.triu(np.ones_like(d, dtype=bool), 1) if same else np.ones_like(d, dtype=bool)
+        c = np.abs(np.cos(math.pi * d / L))
+        for b in range(pe):
+            k = kappas[b]
+            if 2 * k >= 1.01 * 16.0:
+                assert np.all(2 * k * c[live] < 1.01 * 16.0)
+            want_eval += int(np.count_nonzero(live & (-2 * k * (1 - c) >= -bench.SKIP_EXPONENT)))
+        want_terms += pe * int(np.count_nonzero(live))
+        want_pairs += int(np.count_nonzero(live))
+    assert (terms, evaluated, wpairs) == (want_terms, want_eval, want_pairs)
