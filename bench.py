@@ -107,12 +107,12 @@ PLANNING_IDEAL_PAIR_EVALS = {"f64": 5.0e11, "f32": 1.0e12}
 # change to these files leaves cv_pairs_kernel's machine code the same
 # (other kernels of cv.hip, comments), the digest is moved on after
 # comparing that code, and the counters are kept.
-PAIR_COUNTERS = {"digest": "470ddc6d688a12ba",
+PAIR_COUNTERS = {"digest": "9257d2c5f950ec86",
                  "source": "profiles/cv_pairs_valu_counters_paper_scale.md",
-                 "f64": {"valu_lane_instr_per_term": 40.53, "trans_per_term": 0.0005, "engine_clock_ghz": 2.166,
-                         "issue_frac": 0.931},
-                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.138,
-                         "issue_frac": 0.884}}
+                 "f64": {"valu_lane_instr_per_term": 38.51, "trans_per_term": 0.0005, "engine_clock_ghz": 2.213,
+                         "issue_frac": 0.940},
+                 "f32": {"valu_lane_instr_per_term": 23.60, "trans_per_term": 1.842, "engine_clock_ghz": 2.135,
+                         "issue_frac": 0.882}}
 
 # HBM bytes per launch of the pair kernel on the paper-scale scan, from the
 # FETCH_SIZE and WRITE_SIZE counters (rocprofv3 --pmc, one counter per run)
@@ -121,9 +121,9 @@ PAIR_COUNTERS = {"digest": "470ddc6d688a12ba",
 # taken on, identified by PAIR_KERNEL_SOURCES' digest.
 PAIR_KERNEL_SOURCES = ("cv.hip", "dev_cv.hpp", "dev_sum.hpp", "device_bessel.hpp", "bessel_coeffs.inc",
                        "dev_layout.hpp", "kde_internal.hpp")
-PAIR_TRAFFIC = {"digest": "470ddc6d688a12ba",
-                "f64": {"fetch_kib": 7038.0625, "write_kib": 28990.625},
-                "f32": {"fetch_kib": 1710.625, "write_kib": 22528.0}}
+PAIR_TRAFFIC = {"digest": "9257d2c5f950ec86",
+                "f64": {"fetch_kib": 8690.375, "write_kib": 191780.125},
+                "f32": {"fetch_kib": 1711.5, "write_kib": 22528.0}}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
@@ -167,8 +167,9 @@ def power_sum_route(x, L, kappas, detail=None):
     """The double pair kernel's power-sum route over the tile pairs of the
     cell-sorted positions, as the kernel decides it: per tile pair the
     concentrations with 2 kappa < 1.01 X0, and, on two tiles at least a gap
-    g apart (the kernel's cell bound), also those with 2 kappa (cos(pi g) +
-    1e-12) < 1.01 X0, up to the first concentration the tile test prunes.
+    g apart (the kernel's cell bound), also those with 2 kappa (C + 1e-12)
+    < 1.01 X0, C = 1 - x^2/2 + x^4/24 >= cos(x), x = pi g, up to the first
+    concentration the tile test prunes.
     Returns (terms on the route, those of them at or above the skip bound,
     pairs of the tile pairs that form power sums); a list passed as
     `detail` receives (indices of tile I, indices of tile J, concentrations
@@ -201,7 +202,8 @@ def power_sum_route(x, L, kappas, detail=None):
                 qmin = 2.0 * (y * (1.0 - y * y / 6.0)) ** 2
                 pruned = k2 * qmin > SKIP_EXPONENT * (1.0 + 1e-6)
                 be = int(np.argmax(pruned)) if pruned.any() else len(k2)
-                cmax = math.cos(math.pi * gap) + 1e-12
+                x2 = (math.pi * gap) ** 2
+                cmax = 1.0 + x2 * (-0.5 + x2 / 24.0) + 1e-12  # the kernel's bound on cos(pi gap)
                 while pe < be and k2[pe] * cmax < reach:
                     pe += 1
                 pe = min(pe, be)

@@ -657,9 +657,12 @@ __device__ __forceinline__ void cv_tile_pair(const typename Packed<T>::type* __r
         be = b_lo;
         while (be < b_hi && !(double(K.twok[be]) * qmin > kSkipExponent * (1.0 + 1e-6))) ++be;
         if constexpr (std::is_same<T, double>::value) {
-          // every pair has c <= cos(pi gap) (gap <= 1/2); the margin covers
-          // the rounding of c itself
-          const double cmax = cospi(gap) + 1e-12;
+          // every pair has c <= cos(pi gap) (gap <= 1/2) <= 1 - x^2/2 + x^4/24
+          // with x = pi gap (the cosine's Taylor bound from above, a few
+          // operations instead of a library call); the margin covers the
+          // rounding of c itself
+          const double x2 = (3.141592653589793 * gap) * (3.141592653589793 * gap);
+          const double cmax = fma(x2, fma(x2, 1.0 / 24.0, -0.5), 1.0) + 1e-12;
           while (pe < be && double(K.twok[pe]) * cmax < PureReach<double>::value * double(I0eBounds<double>::X0)) ++pe;
         }
       }
