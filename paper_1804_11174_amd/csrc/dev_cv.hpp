@@ -45,8 +45,8 @@
 // bound for one concentration, the wave skips the rest for that j.
 //
 // Concentrations run in chunks of three kinds. The leading ones with
-// 2 kappa below X0 (1.01 X0 in double; pure_branch), where the small-argument
-// fit covers every pair: no
+// 2 kappa below X0 (1.01 X0 in double; pure_branch), where the
+// small-argument fit covers every pair: no
 // term can reach the skip bound, so there is no vote, and the pair
 // geometry is s^2 and c^2 alone; they have a loop of their own. In float,
 // with only that branch's polynomial live, its coefficients stay in scalar
@@ -336,16 +336,16 @@ __device__ __forceinline__ GeoS<float> pair_geo_small(const IPart<float>& p, con
 // power_sums_f64 adds each pair's powers c^2m once per tile pair (m =
 // 0..20: twenty multiplies and twenty-one adds per pair, however many such
 // concentrations the tile pair has, against a 21-coefficient Horner per
-// pair and concentration); pair_chunk_sums_f64 takes a pass of them: their
-// K terms over the tile, in the order of the per-term loop, then each
-// concentration's K-bar sum from the W_m. Every product q_m tk^m W_m is
-// positive but the one of m = 19, which is below 2e-5 of the total, so the
-// reassociation adds no cancellation. Which concentrations take this route
-// on a tile pair depends on the tile pair and kappa alone, so the sums do
-// not depend on the chunk or group size. (The float form keeps the
-// per-term loop: its power sums, eleven compensated float sums, cost
-// registers that the float kernel's eight waves do not have, and measured
-// no faster.)
+// pair and concentration); kbar_from_sums_f64 forms each concentration's
+// K-bar sum from the W_m; k_terms_f64 then takes their K terms over the
+// tile, a pass at a time, in the order of the per-term loop. Every product
+// q_m tk^m W_m is positive but the one of m = 19, which is below 2e-5 of
+// the total, so the reassociation adds no cancellation. Which
+// concentrations take this route on a tile pair depends on the tile pair
+// and kappa alone, so the sums do not depend on the chunk or group size.
+// (The float form keeps the per-term loop: its power sums, eleven
+// compensated float sums, cost registers that the float kernel's eight
+// waves do not have, and were not a consistent gain.)
 template <bool MASKED>
 __device__ __forceinline__ void power_sums_f64(const double* __restrict__ tj, int nj, const IPart<double>& ip,
                                                bool valid_i, bool diag, double (&W)[KDE_I0E_F64_NSMALL]) {
