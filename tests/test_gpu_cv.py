@@ -105,6 +105,28 @@ def test_many_kappas_and_odd_domain(gpu, dtype):
     assert_argmin_ok(am, ref_cv, TOL[dtype])
 
 
+def test_power_sums_on_far_tile_pairs(gpu):
+    """Four clusters a quarter period apart, 1024 particles each (4096: 16
+    tiles): on tile pairs of clusters half a period apart every pair has c
+    near 0, so concentrations up to about 40 take the double kernel's
+    power-sum route there, on neighbouring clusters up to about 11, and on
+    near tile pairs only those below 8.08; the K-bar and K sums and the
+    objective against the oracle's direct sums."""
+    L = 2 * math.pi
+    rng = np.random.default_rng([11174, 4, 4])
+    x = np.concatenate([rng.normal(c * L / 4, 0.02, 1024) for c in range(4)])
+    kap = np.array([1.0, 6.0, 8.05, 9.0, 11.0, 15.0, 25.0, 34.0, 39.0, 41.0, 60.0, 300.0])
+    announce("cv power sums on far tile pairs", len(x))
+    cv, sums, am = run_gpu_cv(gpu, x, L, kap, "f64")
+    from oracle.vonmises import wrap
+    ref_cv, S1, S2 = ocv.cv_curve(wrap(x, L), L, kap)
+    assert rel_err(cv, ref_cv).max() <= TOL["f64"]
+    B = len(kap)
+    assert rel_err(sums[:B], S1).max() <= TOL["f64"]
+    assert rel_err(sums[B:], S2).max() <= TOL["f64"]
+    assert_argmin_ok(am, ref_cv, TOL["f64"])
+
+
 def test_coincident_and_antipodal_points(gpu):
     # pairs at distance 0 (c = 1) and L/2 (c = 0) exercise both I0e regimes
     L = 2 * math.pi
