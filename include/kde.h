@@ -201,7 +201,9 @@ kde_status kde_workspace_size(int32_t op, const kde_domain* dom, int64_t N, int3
  *              kde_workspace_size(KDE_OP_CV_SCAN, dom, N, B) bytes.
  *   stream   : hipStream_t or NULL.
  * Terms whose exponent lies below -70 (each smaller than e^-70 times the
- * largest term of its sum) are not evaluated. For the triangle, pairs
+ * largest term of its sum) may be left out: the kernel skips them where
+ * that saves work and keeps them where it does not (the sums differ from
+ * the full ones by at most that bound per term). For the triangle, pairs
  * outside the support of a width (d >= 2 h) contribute exactly 0 and are
  * skipped.
  */
