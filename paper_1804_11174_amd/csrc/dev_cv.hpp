@@ -38,11 +38,12 @@
 // the partial sums take at most 32768 x 2B doubles at any N. No
 // floating-point atomics are used.
 //
-// Terms whose exponent is below -70 are not evaluated: each is below
+// Terms whose exponent is below -70 need not be evaluated: each is below
 // e^-70 (4e-31) times the largest term of its sum (the pair at distance 0
 // has exponent 0 and I0e <= 1). Concentrations are ascending and the
 // exponent scales with kappa, so once every lane of a wave is below the
-// bound for one concentration, the wave skips the rest for that j.
+// bound for one concentration, the wave skips the rest for that j (the
+// power-sum route below skips nothing: its terms cost nothing each).
 //
 // Concentrations run in chunks of three kinds. The leading ones with
 // 2 kappa below X0 (1.01 X0 in double; pure_branch), where the
