@@ -43,7 +43,8 @@
 // has exponent 0 and I0e <= 1). Concentrations are ascending and the
 // exponent scales with kappa, so once every lane of a wave is below the
 // bound for one concentration, the wave skips the rest for that j (the
-// power-sum route below skips nothing: its terms cost nothing each).
+// power-sum route below skips none of its terms: its K-bar terms cost
+// nothing per term, and its K terms are taken for every pair).
 //
 // Concentrations run in chunks of three kinds. The leading ones with
 // 2 kappa below X0 (1.01 X0 in double; pure_branch), where the
