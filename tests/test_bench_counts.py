@@ -112,3 +112,23 @@ def test_power_sum_route_is_safe_and_counted(bench):
         want_terms += pe * int(np.count_nonzero(live))
         want_pairs += int(np.count_nonzero(live))
     assert (terms, evaluated, wpairs) == (want_terms, want_eval, want_pairs)
+
+
+def test_basis_constants_follow_the_kernel_sources(bench):
+    # the route and skip rules bench.py replays are the kernel's own: the
+    # double small-argument reach, the Bessel split points and the skip bound
+    import re
+    csrc = os.path.join(ROOT, "paper_1804_11174_amd", "csrc")
+    dev_cv = open(os.path.join(csrc, "dev_cv.hpp")).read()
+    internal = open(os.path.join(csrc, "kde_internal.hpp")).read()
+    coeffs = open(os.path.join(csrc, "bessel_coeffs.inc")).read()
+    reach = re.search(r"struct PureReach<double> \{\s*static constexpr double value = ([0-9.]+);", dev_cv)
+    assert reach and float(reach.group(1)) == bench.PURE_REACH["f64"]
+    assert bench.PURE_REACH["f32"] == 1.0
+    skip = re.search(r"constexpr double kSkipExponent = ([0-9.]+);", internal)
+    assert skip and float(skip.group(1)) == bench.SKIP_EXPONENT
+    for prec, macro in (("f64", "KDE_I0E_F64_X0"), ("f32", "KDE_I0E_F32_X0")):
+        x0 = re.search(r"#define %s ([0-9.]+)f?" % macro, coeffs)
+        assert x0 and float(x0.group(1)) == bench.BESSEL_X0[prec]
+    tile = re.search(r"constexpr int kCvTile = (\d+);", internal)
+    assert tile and int(tile.group(1)) == bench.CV_TILE
