@@ -132,3 +132,6 @@ def test_basis_constants_follow_the_kernel_sources(bench):
         assert x0 and float(x0.group(1)) == bench.BESSEL_X0[prec]
     tile = re.search(r"constexpr int kCvTile = (\d+);", internal)
     assert tile and int(tile.group(1)) == bench.CV_TILE
+    # the cell count of the sort that orders the tiles: n / 32, clamped to [1, 8192]
+    layout = open(os.path.join(csrc, "layout.hip")).read()
+    assert "int64_t cells = n / 32;" in layout and "if (cells > 8192) cells = 8192;" in layout
